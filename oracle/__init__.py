@@ -1,0 +1,328 @@
+"""CPU oracle for the adaptive event-camera path tracer (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library: the C sources under ``oracle/src`` implement
+the written definitions independently (Philox keying, scene at an instant,
+camera, watertight intersection, the path estimator, FP64 statistics, the
+Student t CDF, and Algorithm 1 of the paper for one pair of instants).
+
+Functions without an independent pin are flagged "parity unpinned" in their
+docstrings; see the oracle tests for the pins of the others.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MODE_ADAPTIVE_1T, MODE_FIXED, MODE_ADAPTIVE_2T, MODE_MEAN_ONLY = 0, 1, 2, 3
+DF_STUDENT, DF_WELCH = 0, 1
+REF_LOCKSTEP, REF_FULL = 0, 1
+NO_PRIM = 0xFFFFFFFF
+
+_f32p = ctypes.POINTER(ctypes.c_float)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class _SceneDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_mat", ctypes.c_uint32), ("albedo", _f32p), ("emission", _f32p),
+        ("n_vert", ctypes.c_uint32), ("xyz", _f32p),
+        ("n_tri", ctypes.c_uint32), ("tri_idx", _u32p), ("tri_mat", _u32p),
+        ("n_mesh", ctypes.c_uint32), ("mesh_tri_off", _u32p),
+        ("n_inst", ctypes.c_uint32), ("inst_mesh", _u32p), ("inst_key_off", _u32p),
+        ("key_t", _f64p), ("key_xform", _f64p),
+        ("n_plight", ctypes.c_uint32), ("pl_pos", _f32p), ("pl_intensity", _f32p),
+        ("width", ctypes.c_uint32), ("height", ctypes.c_uint32), ("vfov_deg", ctypes.c_double),
+        ("cam_nkeys", ctypes.c_uint32), ("cam_t", _f64p), ("cam_elu", _f64p),
+    ]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("seed", ctypes.c_uint64),
+        ("spp_init", ctypes.c_uint32), ("spp_batch", ctypes.c_uint32), ("spp_max", ctypes.c_uint32),
+        ("max_depth", ctypes.c_uint32), ("rr_start_depth", ctypes.c_uint32),
+        ("minibatch", ctypes.c_uint32), ("log_eps", ctypes.c_double),
+        ("C", ctypes.c_float), ("alpha", ctypes.c_float),
+        ("nee", ctypes.c_uint8), ("jitter", ctypes.c_uint8), ("mode", ctypes.c_uint8),
+        ("df_mode", ctypes.c_uint8), ("ref_mode", ctypes.c_uint8),
+    ]
+
+
+class _PixelOut(ctypes.Structure):
+    _fields_ = [
+        ("polarity", ctypes.c_int8), ("decided_early", ctypes.c_uint8),
+        ("near_crit", ctypes.c_uint8), ("pad", ctypes.c_uint8),
+        ("n_paths", ctypes.c_uint32), ("n_paths_ref", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+        ("mean", ctypes.c_double * 2), ("var", ctypes.c_double * 2),
+        ("mean_radiance", ctypes.c_double * 2), ("t_last", ctypes.c_double),
+        ("crit_margin", ctypes.c_double),
+    ]
+
+
+def lib():
+    """Load liboracle.so (building it with gcc first if it is absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build
+        _build.build()
+    L = ctypes.CDLL(_LIB_PATH)
+    L.evo_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    L.evo_u01.argtypes = [ctypes.c_uint32]
+    L.evo_u01.restype = ctypes.c_float
+    for name, nargs in (("evo_t_cdf", 2), ("evo_t_ppf", 2), ("evo_ibeta", 3)):
+        fn = getattr(L, name)
+        fn.argtypes = [ctypes.c_double] * nargs
+        fn.restype = ctypes.c_double
+    L.evo_scene_new.argtypes = [ctypes.POINTER(_SceneDesc)]
+    L.evo_scene_new.restype = ctypes.c_void_p
+    L.evo_scene_free.argtypes = [ctypes.c_void_p]
+    L.evo_frame_new.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    L.evo_frame_new.restype = ctypes.c_void_p
+    L.evo_frame_free.argtypes = [ctypes.c_void_p]
+    L.evo_frame_num_tris.argtypes = [ctypes.c_void_p]
+    L.evo_frame_num_tris.restype = ctypes.c_uint32
+    L.evo_frame_world_tris.argtypes = [ctypes.c_void_p, ctypes.c_int, _f32p, _u32p]
+    L.evo_frame_camera.argtypes = [ctypes.c_void_p, ctypes.c_int, _f32p, _f32p, _f32p, _f32p, _f32p]
+    L.evo_closest_hit.argtypes = [ctypes.c_void_p, ctypes.c_int, _f32p, _f32p, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_uint32, ctypes.c_int, _f32p, _u32p]
+    L.evo_any_hit.argtypes = [ctypes.c_void_p, ctypes.c_int, _f32p, _f32p, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_uint32, ctypes.c_int]
+    L.evo_path_radiance.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32,
+                                    ctypes.c_int, ctypes.c_uint32]
+    L.evo_path_radiance.restype = ctypes.c_float
+    L.evo_paths_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32,
+                                  _u32p, _u8p, _u32p, _f32p, ctypes.c_int]
+    L.evo_decide.argtypes = [_f64p, ctypes.c_uint32, _f64p, ctypes.c_uint32, ctypes.c_float,
+                             ctypes.c_float, ctypes.c_int, ctypes.c_int, _f64p, _f64p, _f64p,
+                             ctypes.POINTER(ctypes.c_int)]
+    L.evo_render.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _u32p, ctypes.c_uint32,
+                             ctypes.c_int, ctypes.POINTER(_PixelOut)]
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+# ---------------------------------------------------------------------------
+# Small pure functions.
+
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of one 4-word counter under a 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().evo_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32), _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def u01(x: int) -> float:
+    return float(lib().evo_u01(int(x)))
+
+
+def t_cdf(t: float, df: float) -> float:
+    return float(lib().evo_t_cdf(float(t), float(df)))
+
+
+def t_ppf(p: float, df: float) -> float:
+    return float(lib().evo_t_ppf(float(p), float(df)))
+
+
+def ibeta(a: float, b: float, x: float) -> float:
+    return float(lib().evo_ibeta(float(a), float(b), float(x)))
+
+
+def decide(x0, x1, C: float, alpha: float, df_mode: int = DF_STUDENT,
+           mode: int = MODE_ADAPTIVE_1T) -> Dict[str, float]:
+    """t statistic (Eq. 7), lower-tail p-value, degrees of freedom and the
+    stop decision for two sets of log-luminance samples."""
+    a = np.ascontiguousarray(x0, dtype=np.float64)
+    b = np.ascontiguousarray(x1, dtype=np.float64)
+    t = ctypes.c_double()
+    p = ctypes.c_double()
+    df = ctypes.c_double()
+    stop = ctypes.c_int()
+    rc = lib().evo_decide(_ptr(a, ctypes.c_double), len(a), _ptr(b, ctypes.c_double), len(b),
+                          float(C), float(alpha), int(df_mode), int(mode), ctypes.byref(t),
+                          ctypes.byref(p), ctypes.byref(df), ctypes.byref(stop))
+    if rc != 0:
+        raise ValueError("decide needs at least two samples per instant")
+    return dict(t=t.value, p=p.value, df=df.value, stop=bool(stop.value))
+
+
+def make_params(**kw) -> Params:
+    base = dict(seed=0, spp_init=16, spp_batch=16, spp_max=256, max_depth=4, rr_start_depth=2,
+                minibatch=4, log_eps=1e-4, C=0.2, alpha=0.01, nee=1, jitter=1, mode=0,
+                df_mode=0, ref_mode=0)
+    base.update(kw)
+    p = Params()
+    for k, v in base.items():
+        setattr(p, k, v)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Scene and frame.
+
+class Frame:
+    """The scene at the two instants (t0, t1) of one event frame."""
+
+    def __init__(self, scene, t0: float = 0.0, t1: float = 1.0, use_bvh: bool = True):
+        L = lib()
+        self.scene = scene
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        d = _SceneDesc()
+        albedo = arr(scene.albedo, np.float32)
+        emission = arr(scene.emission, np.float32)
+        xyz = arr(scene.xyz, np.float32)
+        tri_idx = arr(scene.tri_idx, np.uint32)
+        tri_mat = arr(scene.tri_mat, np.uint32)
+        mesh_off = arr(scene.mesh_tri_off, np.uint32)
+        inst_mesh = arr(scene.inst_mesh, np.uint32)
+        inst_off = arr(scene.inst_key_off, np.uint32)
+        key_t = arr(scene.key_t, np.float64)
+        key_x = arr(scene.key_xform, np.float64)
+        pl_pos = arr(scene.pl_pos, np.float32)
+        pl_int = arr(scene.pl_intensity, np.float32)
+        cam_t = arr(scene.cam_t, np.float64)
+        cam_elu = arr(scene.cam_elu, np.float64)
+        d.n_mat = len(albedo)
+        d.albedo = _ptr(albedo, ctypes.c_float)
+        d.emission = _ptr(emission, ctypes.c_float)
+        d.n_vert = len(xyz)
+        d.xyz = _ptr(xyz, ctypes.c_float)
+        d.n_tri = len(tri_idx)
+        d.tri_idx = _ptr(tri_idx, ctypes.c_uint32)
+        d.tri_mat = _ptr(tri_mat, ctypes.c_uint32)
+        d.n_mesh = len(mesh_off) - 1
+        d.mesh_tri_off = _ptr(mesh_off, ctypes.c_uint32)
+        d.n_inst = len(inst_mesh)
+        d.inst_mesh = _ptr(inst_mesh, ctypes.c_uint32)
+        d.inst_key_off = _ptr(inst_off, ctypes.c_uint32)
+        d.key_t = _ptr(key_t, ctypes.c_double)
+        d.key_xform = _ptr(key_x, ctypes.c_double)
+        d.n_plight = len(pl_int)
+        d.pl_pos = _ptr(pl_pos, ctypes.c_float)
+        d.pl_intensity = _ptr(pl_int, ctypes.c_float)
+        d.width = scene.width
+        d.height = scene.height
+        d.vfov_deg = scene.vfov_deg
+        d.cam_nkeys = len(cam_t)
+        d.cam_t = _ptr(cam_t, ctypes.c_double)
+        d.cam_elu = _ptr(cam_elu, ctypes.c_double)
+        self._scene = L.evo_scene_new(ctypes.byref(d))
+        self._keep = []
+        self._frame = L.evo_frame_new(self._scene, float(t0), float(t1), int(bool(use_bvh)))
+        self.n_tri = int(L.evo_frame_num_tris(self._frame))
+
+    def close(self) -> None:
+        if getattr(self, "_frame", None):
+            lib().evo_frame_free(self._frame)
+            self._frame = None
+        if getattr(self, "_scene", None):
+            lib().evo_scene_free(self._scene)
+            self._scene = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def world_tris(self, instant: int):
+        xyz = np.zeros((self.n_tri, 3, 3), dtype=np.float32)
+        mat = np.zeros(self.n_tri, dtype=np.uint32)
+        lib().evo_frame_world_tris(self._frame, int(instant), _ptr(xyz, ctypes.c_float),
+                                   _ptr(mat, ctypes.c_uint32))
+        return xyz, mat
+
+    def camera(self, instant: int):
+        bufs = [np.zeros(3, np.float32) for _ in range(4)] + [np.zeros(2, np.float32)]
+        lib().evo_frame_camera(self._frame, int(instant), *[_ptr(b, ctypes.c_float) for b in bufs])
+        return dict(eye=bufs[0], fwd=bufs[1], right=bufs[2], up=bufs[3], sxy=bufs[4])
+
+    def closest_hit(self, instant, o, d, tmin=1e-4, tmax=np.inf, skip=NO_PRIM, brute=False):
+        o = np.ascontiguousarray(o, np.float32)
+        d = np.ascontiguousarray(d, np.float32)
+        t = ctypes.c_float()
+        p = ctypes.c_uint32()
+        hit = lib().evo_closest_hit(self._frame, int(instant), _ptr(o, ctypes.c_float),
+                                    _ptr(d, ctypes.c_float), float(tmin), float(tmax), int(skip),
+                                    int(bool(brute)), ctypes.byref(t), ctypes.byref(p))
+        return (bool(hit), np.float32(t.value), int(p.value))
+
+    def any_hit(self, instant, o, d, tmin=1e-4, tmax=np.inf, skip=NO_PRIM, brute=False) -> bool:
+        o = np.ascontiguousarray(o, np.float32)
+        d = np.ascontiguousarray(d, np.float32)
+        return bool(lib().evo_any_hit(self._frame, int(instant), _ptr(o, ctypes.c_float),
+                                      _ptr(d, ctypes.c_float), float(tmin), float(tmax), int(skip),
+                                      int(bool(brute))))
+
+    def path_radiance(self, params: Params, pixel: int, instant: int, sample: int) -> np.float32:
+        return np.float32(lib().evo_path_radiance(self._frame, ctypes.byref(params), int(pixel),
+                                                  int(instant), int(sample)))
+
+    def paths(self, params: Params, pixel, instant, sample, threads: int = 0) -> np.ndarray:
+        """Per-path radiance for arrays of (pixel, instant, sample)."""
+        px = np.ascontiguousarray(pixel, np.uint32).reshape(-1)
+        it = np.ascontiguousarray(np.broadcast_to(instant, px.shape), np.uint8)
+        sm = np.ascontiguousarray(np.broadcast_to(sample, px.shape), np.uint32)
+        out = np.zeros(px.shape, np.float32)
+        lib().evo_paths_batch(self._frame, ctypes.byref(params), len(px), _ptr(px, ctypes.c_uint32),
+                              _ptr(it, ctypes.c_uint8), _ptr(sm, ctypes.c_uint32),
+                              _ptr(out, ctypes.c_float), int(threads))
+        return out
+
+    def render(self, params: Params, pixels: Optional[np.ndarray] = None,
+               threads: int = 0) -> Dict[str, np.ndarray]:
+        """Algorithm 1 for one pair of instants on a pixel subset (default:
+        every pixel).  Returns per-pixel arrays."""
+        if pixels is None:
+            pixels = np.arange(self.scene.width * self.scene.height, dtype=np.uint32)
+        px = np.ascontiguousarray(pixels, np.uint32)
+        out = (_PixelOut * max(1, len(px)))()
+        rc = lib().evo_render(self._frame, ctypes.byref(params), _ptr(px, ctypes.c_uint32),
+                              len(px), int(threads), out)
+        if rc != 0:
+            raise ValueError("invalid render parameters")
+        raw = np.ctypeslib.as_array(out)[: len(px)]
+        return dict(
+            pixels=px.copy(),
+            polarity=raw["polarity"].astype(np.int8),
+            decided_early=raw["decided_early"].astype(bool),
+            near_crit=raw["near_crit"].astype(bool),
+            n_paths=raw["n_paths"].astype(np.uint32),
+            n_paths_ref=raw["n_paths_ref"].astype(np.uint32),
+            rounds=raw["rounds"].astype(np.uint32),
+            mean=raw["mean"].astype(np.float64).copy(),
+            var=raw["var"].astype(np.float64).copy(),
+            mean_radiance=raw["mean_radiance"].astype(np.float64).copy(),
+            t_last=raw["t_last"].astype(np.float64),
+            crit_margin=raw["crit_margin"].astype(np.float64),
+        )

@@ -1,0 +1,140 @@
+/*
+ * evo.h -- CPU oracle for the adaptive event-camera path tracer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the plain, slow, independent
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.
+ * It shares no code, header, table or constant generator with the GPU
+ * library; both sides implement the same written definitions separately.
+ *
+ * What it computes (paper: "Monte Carlo Path Tracing and Statistical Event
+ * Detection for Event Camera Simulation", arXiv 2408.07996):
+ *   - per-path Monte Carlo radiance at a pixel and a time instant (the
+ *     tracePaths subroutine of Algorithm 1 and Sec. 3.3), as a plain
+ *     unidirectional path tracer with next-event estimation;
+ *   - log-luminance samples and their mean/variance (Eq. 3-4, calcMeanVar
+ *     of Algorithm 1) in FP64 by the two-pass formula;
+ *   - the one-tailed t-test of Eq. 7 and Sec. 3.2 on the lower tail, with the
+ *     p-value from the Student t CDF (regularized incomplete beta, Lentz
+ *     continued fraction), and the event rule of Algorithm 1 / Eq. 1.
+ *
+ * Precision: path radiance in FP32 (the renderer's radiance type), every
+ * statistic and the test in FP64.
+ */
+#ifndef EVO_H
+#define EVO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EVO_NO_PRIM 0xffffffffu
+
+enum { EVO_MODE_ADAPTIVE_1T = 0, EVO_MODE_FIXED = 1, EVO_MODE_ADAPTIVE_2T = 2, EVO_MODE_MEAN_ONLY = 3 };
+enum { EVO_DF_STUDENT = 0, EVO_DF_WELCH = 1 };
+enum { EVO_REF_LOCKSTEP = 0, EVO_REF_FULL = 1 };
+
+/* Flat scene description.  All arrays are read during evo_scene_new and
+ * deep-copied.  Vertex indices in tri_idx are global (into xyz). */
+typedef struct {
+    uint32_t n_mat;
+    const float *albedo;      /* [n_mat]  Lambertian albedo a in [0,1)        */
+    const float *emission;    /* [n_mat]  emitted radiance Le >= 0 (one-sided) */
+    uint32_t n_vert;
+    const float *xyz;         /* [n_vert][3] object-space vertices             */
+    uint32_t n_tri;
+    const uint32_t *tri_idx;  /* [n_tri][3]                                    */
+    const uint32_t *tri_mat;  /* [n_tri]                                       */
+    uint32_t n_mesh;
+    const uint32_t *mesh_tri_off; /* [n_mesh+1] triangle range of each mesh    */
+    uint32_t n_inst;
+    const uint32_t *inst_mesh;    /* [n_inst]                                  */
+    const uint32_t *inst_key_off; /* [n_inst+1] key range of each instance     */
+    const double *key_t;          /* [total keys]                              */
+    const double *key_xform;      /* [total keys][12] row-major 3x4            */
+    uint32_t n_plight;
+    const float *pl_pos;          /* [n_plight][3]                             */
+    const float *pl_intensity;    /* [n_plight]                                */
+    uint32_t width, height;
+    double vfov_deg;
+    uint32_t cam_nkeys;
+    const double *cam_t;          /* [cam_nkeys]                               */
+    const double *cam_elu;        /* [cam_nkeys][9] eye, look-at, up           */
+} evo_scene_desc;
+
+typedef struct {
+    uint64_t seed;
+    uint32_t spp_init, spp_batch, spp_max;
+    uint32_t max_depth, rr_start_depth, minibatch;
+    double log_eps;
+    float C, alpha;
+    uint8_t nee, jitter, mode, df_mode, ref_mode;
+} evo_params;
+
+typedef struct {
+    int8_t polarity;
+    uint8_t decided_early;   /* 1 when the t-test stopped sampling        */
+    uint8_t near_crit;       /* 1 when any executed decision was within
+                                the exemption band of its critical value  */
+    uint8_t pad;
+    uint32_t n_paths;        /* paths traced per instant (reference holds
+                                n_paths_ref in REF_FULL mode)             */
+    uint32_t n_paths_ref;
+    uint32_t rounds;
+    double mean[2], var[2];  /* logL mean and unbiased variance           */
+    double mean_radiance[2]; /* mean of the mini-batch radiance Y         */
+    double t_last;
+    double crit_margin;      /* min |t - critical value| over decisions   */
+} evo_pixel_out;
+
+typedef struct evo_scene evo_scene;
+typedef struct evo_frame evo_frame;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void evo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+float evo_u01(uint32_t x);
+
+/* Student t distribution, FP64. */
+double evo_ibeta(double a, double b, double x);
+double evo_t_cdf(double t, double df);
+double evo_t_ppf(double p, double df);
+
+evo_scene *evo_scene_new(const evo_scene_desc *d);
+void evo_scene_free(evo_scene *s);
+
+/* Scene state at the two instants of one event frame. use_bvh=0 makes every
+ * ray query brute force over all triangles. */
+evo_frame *evo_frame_new(const evo_scene *s, double t0, double t1, int use_bvh);
+void evo_frame_free(evo_frame *f);
+uint32_t evo_frame_num_tris(const evo_frame *f);
+void evo_frame_world_tris(const evo_frame *f, int instant, float *xyz9, uint32_t *mat);
+void evo_frame_camera(const evo_frame *f, int instant, float *eye3, float *fwd3,
+                      float *right3, float *up3, float *sxy2);
+
+int evo_closest_hit(const evo_frame *f, int instant, const float o[3], const float d[3],
+                    float tmin, float tmax, uint32_t skip, int brute,
+                    float *t_out, uint32_t *prim_out);
+int evo_any_hit(const evo_frame *f, int instant, const float o[3], const float d[3],
+                float tmin, float tmax, uint32_t skip, int brute);
+
+float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
+                        int instant, uint32_t sample);
+
+/* Decision on given logL sample sets (m0 samples at the reference instant,
+ * m1 at the second); writes t, the p-value and the stop flag. */
+int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
+               float C, float alpha, int df_mode, int mode,
+               double *t_out, double *p_out, double *df_out, int *stop_out);
+
+int evo_paths_batch(const evo_frame *f, const evo_params *p, uint32_t n, const uint32_t *pixel,
+                    const uint8_t *instant, const uint32_t *sample, float *out, int n_threads);
+
+int evo_render(const evo_frame *f, const evo_params *p, const uint32_t *pixels,
+               uint32_t n_pixels, int n_threads, evo_pixel_out *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,418 @@
+"""Seeded synthetic scene generators.
+
+This module produces plain NumPy arrays describing an animated triangle
+scene (materials, meshes, keyframed rigid instances, optional point lights,
+a keyframed pinhole camera).  It holds none of the renderer's arithmetic:
+no instance transform is applied here, no ray is traced, nothing is
+sampled.  The same arrays feed both the GPU library and the CPU oracle.
+
+The paper evaluates on four scenes (two made in Blender, two public pbrt
+scenes; Sec. 4) that are not available here, so these procedural scenes
+stand in for them:
+
+* ``tiny_box``   -- an open box with a ceiling light and a small moving cube
+  (stands in for the paper's "two boxes"), 64x64.
+* ``sensor``     -- a displaced heightfield floor with 20 icospheres moving
+  rigidly and three area lights (an occluder-rich stand-in for the paper's
+  larger scenes), 640x480, ~98k triangles.
+* closed-form test scenes (white furnace, plane under a point light, plane
+  under a triangle area light) and random triangle soups.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Scene:
+    albedo: np.ndarray          # float32 [n_mat]
+    emission: np.ndarray        # float32 [n_mat]
+    xyz: np.ndarray             # float32 [n_vert, 3] object-space vertices
+    tri_idx: np.ndarray         # uint32 [n_tri, 3] (global vertex indices)
+    tri_mat: np.ndarray         # uint32 [n_tri]
+    mesh_tri_off: np.ndarray    # uint32 [n_mesh + 1]
+    inst_mesh: np.ndarray       # uint32 [n_inst]
+    inst_key_off: np.ndarray    # uint32 [n_inst + 1]
+    key_t: np.ndarray           # float64 [n_keys]
+    key_xform: np.ndarray       # float64 [n_keys, 3, 4]
+    pl_pos: np.ndarray          # float32 [n_plight, 3]
+    pl_intensity: np.ndarray    # float32 [n_plight]
+    width: int
+    height: int
+    vfov_deg: float
+    cam_t: np.ndarray           # float64 [n_cam_keys]
+    cam_elu: np.ndarray         # float64 [n_cam_keys, 9] eye, look-at, up
+
+    @property
+    def n_tri_world(self) -> int:
+        per_mesh = np.diff(self.mesh_tri_off.astype(np.int64))
+        return int(per_mesh[self.inst_mesh.astype(np.int64)].sum()) if len(self.inst_mesh) else 0
+
+    @property
+    def n_pixels(self) -> int:
+        return self.width * self.height
+
+
+class SceneBuilder:
+    """Accumulates meshes, instances, materials and the camera."""
+
+    def __init__(self) -> None:
+        self.albedo: List[float] = []
+        self.emission: List[float] = []
+        self.verts: List[np.ndarray] = []
+        self.tris: List[np.ndarray] = []
+        self.mats: List[np.ndarray] = []
+        self.mesh_off = [0]
+        self.n_vert = 0
+        self.inst_mesh: List[int] = []
+        self.inst_keys: List[tuple] = []
+        self.pl_pos: List[Sequence[float]] = []
+        self.pl_int: List[float] = []
+        self.camera = None
+
+    def material(self, albedo: float, emission: float = 0.0) -> int:
+        self.albedo.append(float(albedo))
+        self.emission.append(float(emission))
+        return len(self.albedo) - 1
+
+    def mesh(self, verts: np.ndarray, tris: np.ndarray, mat) -> int:
+        verts = np.asarray(verts, dtype=np.float32).reshape(-1, 3)
+        tris = np.asarray(tris, dtype=np.int64).reshape(-1, 3)
+        mats = np.broadcast_to(np.asarray(mat, dtype=np.uint32), (len(tris),)).copy()
+        self.verts.append(verts)
+        self.tris.append((tris + self.n_vert).astype(np.uint32))
+        self.mats.append(mats)
+        self.n_vert += len(verts)
+        self.mesh_off.append(self.mesh_off[-1] + len(tris))
+        return len(self.mesh_off) - 2
+
+    def instance(self, mesh_id: int, key_t: Sequence[float], xforms: Sequence[np.ndarray]) -> int:
+        kt = np.asarray(key_t, dtype=np.float64).reshape(-1)
+        kx = np.asarray(xforms, dtype=np.float64).reshape(-1, 3, 4)
+        assert len(kt) == len(kx) and len(kt) >= 1
+        assert np.all(np.diff(kt) > 0)
+        self.inst_mesh.append(mesh_id)
+        self.inst_keys.append((kt, kx))
+        return len(self.inst_mesh) - 1
+
+    def static(self, mesh_id: int) -> int:
+        return self.instance(mesh_id, [0.0], [identity()])
+
+    def point_light(self, pos, intensity: float) -> None:
+        self.pl_pos.append(list(pos))
+        self.pl_int.append(float(intensity))
+
+    def set_camera(self, width: int, height: int, vfov_deg: float, key_t, eye_look_up) -> None:
+        kt = np.asarray(key_t, dtype=np.float64).reshape(-1)
+        elu = np.asarray(eye_look_up, dtype=np.float64).reshape(-1, 9)
+        assert len(kt) == len(elu)
+        self.camera = (int(width), int(height), float(vfov_deg), kt, elu)
+
+    def build(self) -> Scene:
+        assert self.camera is not None
+        key_t = [k[0] for k in self.inst_keys]
+        key_x = [k[1] for k in self.inst_keys]
+        off = np.zeros(len(self.inst_keys) + 1, dtype=np.uint32)
+        off[1:] = np.cumsum([len(k) for k in key_t])
+        w, h, fov, ct, celu = self.camera
+        return Scene(
+            albedo=np.asarray(self.albedo, dtype=np.float32),
+            emission=np.asarray(self.emission, dtype=np.float32),
+            xyz=np.concatenate(self.verts).astype(np.float32) if self.verts else np.zeros((0, 3), np.float32),
+            tri_idx=np.concatenate(self.tris) if self.tris else np.zeros((0, 3), np.uint32),
+            tri_mat=np.concatenate(self.mats) if self.mats else np.zeros((0,), np.uint32),
+            mesh_tri_off=np.asarray(self.mesh_off, dtype=np.uint32),
+            inst_mesh=np.asarray(self.inst_mesh, dtype=np.uint32),
+            inst_key_off=off,
+            key_t=np.concatenate(key_t) if key_t else np.zeros((0,), np.float64),
+            key_xform=np.concatenate(key_x) if key_x else np.zeros((0, 3, 4), np.float64),
+            pl_pos=np.asarray(self.pl_pos, dtype=np.float32).reshape(-1, 3),
+            pl_intensity=np.asarray(self.pl_int, dtype=np.float32),
+            width=w, height=h, vfov_deg=fov, cam_t=ct, cam_elu=celu,
+        )
+
+
+# ---------------------------------------------------------------------------
+# Small geometry helpers (input construction only).
+
+def identity() -> np.ndarray:
+    return np.hstack([np.eye(3), np.zeros((3, 1))])
+
+
+def translation(v) -> np.ndarray:
+    m = identity()
+    m[:, 3] = np.asarray(v, dtype=np.float64)
+    return m
+
+
+def rotation_axis_angle(axis, angle_rad: float) -> np.ndarray:
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    k = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(angle_rad) * k + (1 - math.cos(angle_rad)) * (k @ k)
+
+
+def compose(r3: np.ndarray, t, scale: float = 1.0) -> np.ndarray:
+    """3x4 matrix x -> R (scale * x) + t."""
+    m = np.zeros((3, 4))
+    m[:, :3] = r3 * scale
+    m[:, 3] = np.asarray(t, dtype=np.float64)
+    return m
+
+
+def oriented_quad(corners, normal):
+    """Two triangles over 4 corners (in perimeter order), wound so that
+    cross(v1 - v0, v2 - v0) points along ``normal``."""
+    c = np.asarray(corners, dtype=np.float64)
+    tris = np.array([[0, 1, 2], [0, 2, 3]])
+    n = np.cross(c[1] - c[0], c[2] - c[0])
+    if np.dot(n, np.asarray(normal, dtype=np.float64)) < 0:
+        tris = tris[:, ::-1]
+    return c.astype(np.float32), tris
+
+
+def box_mesh(lo, hi, outward: bool = True, faces=("-x", "+x", "-y", "+y", "-z", "+z")):
+    """Axis-aligned box faces (two triangles each), normals outward or inward."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    verts, tris = [], []
+    for f in faces:
+        ax = "xyz".index(f[1])
+        sgn = 1.0 if f[0] == "+" else -1.0
+        u, v = [a for a in range(3) if a != ax]
+        val = hi[ax] if sgn > 0 else lo[ax]
+        cs = []
+        for (a, b) in ((lo[u], lo[v]), (hi[u], lo[v]), (hi[u], hi[v]), (lo[u], hi[v])):
+            p = np.zeros(3)
+            p[ax] = val
+            p[u] = a
+            p[v] = b
+            cs.append(p)
+        nrm = np.zeros(3)
+        nrm[ax] = sgn if outward else -sgn
+        c, t = oriented_quad(cs, nrm)
+        tris.append(t + 4 * len(verts))
+        verts.append(c)
+    return np.concatenate(verts), np.concatenate(tris)
+
+
+def icosphere(subdiv: int):
+    """Unit icosphere: an icosahedron with each face split in four
+    ``subdiv`` times, new vertices projected to the sphere; outward winding."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t),
+         (0, -1, -t), (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+             (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+             (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdiv):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                p = verts[a] + verts[b]
+                verts.append(p / np.linalg.norm(p))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for (a, b, c) in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    V = np.array(verts)
+    F = np.array(faces, dtype=np.int64)
+    n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    flip = np.einsum("ij,ij->i", n, V[F].mean(axis=1)) < 0
+    F[flip] = F[flip][:, ::-1]
+    return V.astype(np.float32), F
+
+
+# ---------------------------------------------------------------------------
+# Benchmark scenes.
+
+def tiny_box(seed: int = 0, width: int = 64, height: int = 64) -> Scene:
+    """64x64 open box: floor, ceiling, back, left and right faces (10 inward
+    triangles; albedo U[0.2, 0.8] per face, in that order, seed 0), a 0.5 x 0.5
+    ceiling light at y = 1.98 facing down (Le = 10, albedo 0), and a 0.5-unit
+    cube centred at (-0.2, 0.25, -0.2) that moves by +0.05 along x between
+    t = 0 and t = 1.  Pinhole camera at (0, 1, 3.4) looking at (0, 1, 0),
+    40 degree vertical field of view."""
+    rng = np.random.default_rng(seed)
+    draws = rng.uniform(0.2, 0.8, size=6)
+    b = SceneBuilder()
+    face_specs = [("-y", (0, 1, 0)), ("+y", (0, -1, 0)), ("-z", (0, 0, 1)),
+                  ("-x", (1, 0, 0)), ("+x", (-1, 0, 0))]
+    for k, (face, _) in enumerate(face_specs):
+        m = b.material(draws[k])
+        v, t = box_mesh((-1, 0, -1), (1, 2, 1), outward=False, faces=(face,))
+        b.static(b.mesh(v, t, m))
+    light = b.material(0.0, 10.0)
+    lv, lt = oriented_quad([(-0.25, 1.98, -0.25), (0.25, 1.98, -0.25), (0.25, 1.98, 0.25),
+                            (-0.25, 1.98, 0.25)], (0, -1, 0))
+    b.static(b.mesh(lv, lt, light))
+    cube_m = b.material(draws[5])
+    cv, ct = box_mesh((-0.25, -0.25, -0.25), (0.25, 0.25, 0.25), outward=True)
+    cube = b.mesh(cv, ct, cube_m)
+    c0 = np.array([-0.2, 0.25, -0.2])
+    b.instance(cube, [0.0, 1.0], [translation(c0), translation(c0 + [0.05, 0, 0])])
+    b.set_camera(width, height, 40.0, [0.0], [[0, 1, 3.4, 0, 1, 0, 0, 1, 0]])
+    return b.build()
+
+
+def heightfield_y(x, z, phi1: float, phi2: float):
+    return 0.05 * np.sin(1.7 * x + phi1) * np.cos(2.3 * z + phi2)
+
+
+def sensor(seed: int = 0, width: int = 640, height: int = 480, n_spheres: int = 20,
+           grid: int = 190, subdiv: int = 3) -> Scene:
+    """640x480: a 190x190-quad displaced floor on [-4, 4]^2 (72,200 triangles,
+    h = 0.05 sin(1.7x + phi1) cos(2.3z + phi2)), 20 icospheres (subdivision 3,
+    1,280 triangles each) of radius U[0.1, 0.5] resting on the floor at
+    centres U[-3, 3]^2, albedo U[0.1, 0.9] per object, three 1x1 area lights
+    at y = 4 facing down (Le = 10).  Between t = 0 and t = 1 every sphere
+    moves rigidly by a translation U[-0.02, 0.02]^3 and a rotation of U[0, 2]
+    degrees about a random axis through its centre.  Static camera at
+    (0, 2.5, 7) looking at (0, 0.3, 0), 40 degree vertical field of view."""
+    rng = np.random.default_rng(seed)
+    phi1, phi2 = rng.uniform(0, 2 * math.pi, size=2)
+    b = SceneBuilder()
+    floor_m = b.material(rng.uniform(0.1, 0.9))
+    g = grid
+    xs = np.linspace(-4.0, 4.0, g + 1)
+    X, Z = np.meshgrid(xs, xs, indexing="ij")
+    Y = heightfield_y(X, Z, phi1, phi2)
+    fv = np.stack([X, Y, Z], axis=-1).reshape(-1, 3)
+    i = np.arange(g)[:, None]
+    j = np.arange(g)[None, :]
+    v00 = (i * (g + 1) + j).reshape(-1)
+    v10 = ((i + 1) * (g + 1) + j).reshape(-1)
+    v01 = (i * (g + 1) + j + 1).reshape(-1)
+    v11 = ((i + 1) * (g + 1) + j + 1).reshape(-1)
+    ft = np.stack([np.stack([v00, v01, v11], 1), np.stack([v00, v11, v10], 1)], 1).reshape(-1, 3)
+    b.static(b.mesh(fv, ft, floor_m))
+    sv, st = icosphere(subdiv)
+    for _ in range(n_spheres):
+        m = b.material(rng.uniform(0.1, 0.9))
+        mesh = b.mesh(sv, st, m)
+        r = rng.uniform(0.1, 0.5)
+        cx, cz = rng.uniform(-3.0, 3.0, size=2)
+        c = np.array([cx, float(heightfield_y(cx, cz, phi1, phi2)) + r, cz])
+        dt = rng.uniform(-0.02, 0.02, size=3)
+        axis = rng.normal(size=3)
+        ang = math.radians(rng.uniform(0.0, 2.0))
+        rot = rotation_axis_angle(axis, ang)
+        b.instance(mesh, [0.0, 1.0], [compose(np.eye(3), c, r), compose(rot, c + dt, r)])
+    light_m = b.material(0.0, 10.0)
+    for (lx, lz) in ((-2.0, -1.0), (0.0, 1.0), (2.0, -0.5)):
+        lv, lt = oriented_quad([(lx - 0.5, 4.0, lz - 0.5), (lx + 0.5, 4.0, lz - 0.5),
+                                (lx + 0.5, 4.0, lz + 0.5), (lx - 0.5, 4.0, lz + 0.5)], (0, -1, 0))
+        b.static(b.mesh(lv, lt, light_m))
+    b.set_camera(width, height, 40.0, [0.0], [[0, 2.5, 7.0, 0, 0.3, 0, 0, 1, 0]])
+    return b.build()
+
+
+# ---------------------------------------------------------------------------
+# Closed-form and structural test scenes.
+
+def furnace(albedo: float, emission: float, width: int = 16, height: int = 16) -> Scene:
+    """Closed cube [-1, 1]^3 of inward triangles that all have the same albedo
+    and emission, camera inside at the centre."""
+    b = SceneBuilder()
+    m = b.material(albedo, emission)
+    v, t = box_mesh((-1, -1, -1), (1, 1, 1), outward=False)
+    b.static(b.mesh(v, t, m))
+    b.set_camera(width, height, 60.0, [0.0], [[0.0, 0.0, 0.0, 0.3, 0.1, -1.0, 0, 1, 0]])
+    return b.build()
+
+
+def plane_point_light(albedo: float = 0.7, intensity: float = 5.0, h: float = 1.5,
+                      width: int = 24, height: int = 16) -> Scene:
+    """Plane y = 0 (two triangles, 100 units wide) under a point light at
+    (0.3, h, -0.2); the camera at (0, 2, 3) looks at the origin."""
+    b = SceneBuilder()
+    m = b.material(albedo)
+    v, t = oriented_quad([(-50, 0, -50), (50, 0, -50), (50, 0, 50), (-50, 0, 50)], (0, 1, 0))
+    b.static(b.mesh(v, t, m))
+    b.point_light((0.3, h, -0.2), intensity)
+    b.set_camera(width, height, 50.0, [0.0], [[0.0, 2.0, 3.0, 0, 0, 0, 0, 1, 0]])
+    return b.build()
+
+
+def plane_area_light(albedo: float = 0.6, emission: float = 4.0, width: int = 8,
+                     height: int = 8) -> Scene:
+    """Plane y = 0 under one triangular emitter at y = 1 facing down."""
+    b = SceneBuilder()
+    m = b.material(albedo)
+    v, t = oriented_quad([(-50, 0, -50), (50, 0, -50), (50, 0, 50), (-50, 0, 50)], (0, 1, 0))
+    b.static(b.mesh(v, t, m))
+    lm = b.material(0.0, emission)
+    tri = np.array([[-0.4, 1.0, -0.3], [0.5, 1.0, -0.2], [0.0, 1.0, 0.6]], dtype=np.float64)
+    n = np.cross(tri[1] - tri[0], tri[2] - tri[0])
+    if n[1] > 0:
+        tri = tri[[0, 2, 1]]
+    b.static(b.mesh(tri.astype(np.float32), np.array([[0, 1, 2]]), lm))
+    b.set_camera(width, height, 30.0, [0.0], [[0.0, 2.5, 2.5, 0, 0, 0, 0, 1, 0]])
+    return b.build()
+
+
+def triangle_soup(n_tri: int, seed: int = 0, extent: float = 2.0, size: float = 0.4,
+                  width: int = 32, height: int = 32, moving: bool = False,
+                  emitters: int = 0) -> Scene:
+    """Random triangles in [-extent, extent]^3 (plus some coplanar pairs that
+    share an edge), optionally with a moving half and a few emitters."""
+    rng = np.random.default_rng(seed)
+    b = SceneBuilder()
+    mats = [b.material(rng.uniform(0.1, 0.9)) for _ in range(4)]
+    emit_m = b.material(0.0, 5.0) if emitters else None
+    cen = rng.uniform(-extent, extent, size=(n_tri, 1, 3))
+    tri = cen + rng.uniform(-size, size, size=(n_tri, 3, 3))
+    half = n_tri // 2
+    tm = rng.integers(0, 4, size=n_tri)
+    if emitters:
+        tm[:emitters] = -1
+    mat_ids = np.array([emit_m if x < 0 else mats[x] for x in tm], dtype=np.uint32)
+    idx = np.arange(3 * n_tri).reshape(-1, 3)
+    s = b.mesh(tri[:half].reshape(-1, 3), idx[:half], mat_ids[:half])
+    d = b.mesh(tri[half:].reshape(-1, 3), idx[half:] - 3 * half, mat_ids[half:])
+    b.static(s)
+    if moving:
+        rot = rotation_axis_angle(rng.normal(size=3), math.radians(3.0))
+        b.instance(d, [0.0, 1.0], [identity(), compose(rot, (0.05, -0.03, 0.02))])
+    else:
+        b.static(d)
+    b.set_camera(width, height, 45.0, [0.0], [[0.0, 0.0, 6.0, 0, 0, 0, 0, 1, 0]])
+    return b.build()
+
+
+def empty(width: int = 8, height: int = 8) -> Scene:
+    """No geometry at all: every path escapes."""
+    b = SceneBuilder()
+    b.material(0.5)
+    b.set_camera(width, height, 40.0, [0.0], [[0, 0, 5, 0, 0, 0, 0, 1, 0]])
+    return b.build()
+
+
+# ---------------------------------------------------------------------------
+# Render parameter presets for the two plain-method workloads.
+
+TINY_PARAMS = dict(seed=0, spp_init=16, spp_batch=16, spp_max=256, max_depth=4,
+                   rr_start_depth=2, minibatch=4, log_eps=1e-4, C=0.2, alpha=0.01,
+                   nee=1, jitter=1, mode=0, df_mode=0, ref_mode=0)
+
+SENSOR_PARAMS = dict(seed=0, spp_init=64, spp_batch=16, spp_max=1024, max_depth=8,
+                     rr_start_depth=2, minibatch=4, log_eps=1e-4, C=0.15, alpha=0.01,
+                     nee=1, jitter=1, mode=0, df_mode=0, ref_mode=0)
+
+
+def subset_every(width: int, height: int, step: int = 8) -> np.ndarray:
+    """Pixel indices of every ``step``-th pixel in x and y (row-major)."""
+    ys = np.arange(0, height, step)
+    xs = np.arange(0, width, step)
+    return (ys[:, None] * width + xs[None, :]).reshape(-1).astype(np.uint32)

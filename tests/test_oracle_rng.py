@@ -1,0 +1,107 @@
+"""Pins of the oracle's counter-based RNG (Philox4x32-10) and uniform map."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TORCH_INC = None
+try:
+    import torch.utils.cpp_extension as _ce
+    TORCH_INC = _ce.include_paths()[0]
+except Exception:  # pragma: no cover
+    pass
+
+
+def _kat():
+    rows = []
+    with open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x, 16) for x in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("ctr,key,expect", _kat())
+def test_philox_known_answers(ctr, key, expect):
+    assert list(oracle.philox(ctr, key)) == expect
+
+
+def _random_cases(n=64, seed=7):
+    rng = np.random.default_rng(seed)
+    cases = rng.integers(0, 2**32, size=(n, 6), dtype=np.uint64)
+    cases[:8, :4] = [[0, 0, 0, 0], [1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0],
+                     [0, 0, 0, 1], [4095, 255, 0x010203, 0], [2**32 - 1, 0, 7, 9], [5, 6, 7, 8]]
+    return cases.astype(np.uint32)
+
+
+def _run_ref(exe, cases):
+    inp = "\n".join(" ".join(str(int(x)) for x in row) for row in cases) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    return np.array([[int(x) for x in line.split()] for line in out.strip().splitlines()],
+                    dtype=np.uint64)
+
+
+@pytest.fixture(scope="module")
+def ref_dir():
+    d = tempfile.mkdtemp(prefix="philox_ref_")
+    yield d
+    shutil.rmtree(d, ignore_errors=True)
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_matches_rocrand(ref_dir):
+    exe = os.path.join(ref_dir, "roc")
+    subprocess.run(["hipcc", "-O1", "-o", exe, os.path.join(HERE, "philox_ref_rocrand.cpp")],
+                   check=True, capture_output=True)
+    cases = _random_cases()
+    ref = _run_ref(exe, cases)
+    mine = np.array([oracle.philox(c[:4], c[4:]) for c in cases], dtype=np.uint64)
+    np.testing.assert_array_equal(mine, ref)
+
+
+@pytest.mark.skipif(TORCH_INC is None or shutil.which("g++") is None, reason="no torch headers")
+def test_philox_matches_aten(ref_dir):
+    exe = os.path.join(ref_dir, "aten")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I", TORCH_INC, "-o", exe,
+                    os.path.join(HERE, "philox_ref_aten.cpp")], check=True, capture_output=True)
+    cases = _random_cases(seed=11)
+    ref = _run_ref(exe, cases)
+    mine = np.array([oracle.philox(c[:4], c[4:]) for c in cases], dtype=np.uint64)
+    np.testing.assert_array_equal(mine, ref)
+
+
+def test_u01_endpoints_and_exactness():
+    assert oracle.u01(0) == 0.0
+    assert oracle.u01(0xFFFFFFFF) == 1.0 - 2.0**-24
+    assert oracle.u01(0x100) == 2.0**-24
+    # The low 8 bits are dropped; values are exact multiples of 2^-24.
+    for x in (0x12345678, 0xDEADBEEF, 0x80000000):
+        v = oracle.u01(x)
+        assert v == (x >> 8) * 2.0**-24
+        assert oracle.u01(x | 0xFF) == v
+
+
+def test_u01_uniformity_chi_square():
+    from scipy import stats
+    n = 1 << 15
+    vals = []
+    for i in range(n):
+        vals.extend(oracle.philox([i, 3, 0x01000102, 0], [0x1234, 0x5678]))
+    u = np.array([oracle.u01(int(v)) for v in vals])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    counts, _ = np.histogram(u, bins=64, range=(0.0, 1.0))
+    chi2 = ((counts - len(u) / 64) ** 2 / (len(u) / 64)).sum()
+    # 63 degrees of freedom; reject only far in the tail.
+    assert stats.chi2.sf(chi2, 63) > 1e-4
+    # Words of one block are not correlated.
+    a = np.array(vals, dtype=np.float64).reshape(-1, 4) / 2.0**32
+    c = np.corrcoef(a.T)
+    assert np.abs(c - np.eye(4)).max() < 0.03
