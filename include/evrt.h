@@ -1,0 +1,244 @@
+/*
+ * evrt.h -- C ABI of the MI355X (gfx950) adaptive event-camera path tracer.
+ *
+ * Implements the method of "Monte Carlo Path Tracing and Statistical Event
+ * Detection for Event Camera Simulation" (arXiv 2408.07996) for one pair of
+ * time instants per call: every pixel is path traced at instants t0 and t1,
+ * the log-luminance of 4-path mini-batches is accumulated per pixel and
+ * instant (Eq. 3-4), and a pixel keeps being sampled only until the
+ * one-tailed t-test of Eq. 7 (Sec. 3.2, Sec. 3.3, Algorithm 1) decides that
+ * |mean logL(t1) - mean logL(t0)| is significantly below the event
+ * threshold C, or the maximum sample count is reached; then the event rule
+ * of Algorithm 1 (|gap| > C, polarity = sign(gap)) is applied.
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an int status: EVRT_OK (0) or a negative
+ *     EVRT_E_* code.  No C++ exception crosses this boundary.  On failure
+ *     evrt_last_error() describes the cause.
+ *   - Argument errors are detected on the host before any device work is
+ *     enqueued.  HIP runtime failures are reported as EVRT_E_DEVICE.
+ *   - Host arrays passed to scene functions are deep-copied; the caller
+ *     keeps ownership and may free them when the call returns.
+ *   - Output pointers of render calls are caller-allocated DEVICE memory on
+ *     the context's device, row-major pixels (pixel = y * width + x, y = 0
+ *     at the top of the image).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Render calls enqueue their kernels on it and return after the work
+ *     they enqueued has completed (they read per-round active counts).
+ *   - A context belongs to one device and must not be used from two host
+ *     threads at once.
+ */
+#ifndef EVRT_H
+#define EVRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EVRT_ABI_VERSION 1
+
+enum {
+    EVRT_OK = 0,
+    EVRT_E_INVALID = -1,     /* bad argument or inconsistent scene            */
+    EVRT_E_NOMEM = -2,       /* host or device allocation failed              */
+    EVRT_E_DEVICE = -3,      /* HIP runtime error or no device in the context */
+    EVRT_E_STATE = -4,       /* call out of order (e.g. render before commit) */
+    EVRT_E_UNSUPPORTED = -5  /* valid request that this build does not serve  */
+};
+
+/* Sampling modes (Sec. 3.2 and its ablation). */
+enum {
+    EVRT_MODE_ADAPTIVE_1T = 0, /* stop when p_lower(t) < alpha: no event         */
+    EVRT_MODE_FIXED = 1,       /* trace spp_max everywhere (the baseline, Sec. 4) */
+    EVRT_MODE_ADAPTIVE_2T = 2, /* stop on either tail at alpha/2                  */
+    EVRT_MODE_MEAN_ONLY = 3    /* stop once |gap| <= C                            */
+};
+enum { EVRT_DF_STUDENT = 0, EVRT_DF_WELCH = 1 };
+/* LOCKSTEP: both instants hold the same sample count.  REF_FULL: the first
+ * instant is rendered at spp_max and only the second one is adaptive (the
+ * first frame of Algorithm 1 is rendered at the full count). */
+enum { EVRT_REF_LOCKSTEP = 0, EVRT_REF_FULL = 1 };
+
+typedef struct evrt_ctx evrt_ctx;
+
+/* Returns EVRT_ABI_VERSION. */
+int evrt_abi_version(void);
+
+/* Creates a context on HIP device `hip_device` (>= 0).  hip_device = -1
+ * creates a host-only context: scene calls and argument validation work,
+ * anything that needs the device returns EVRT_E_DEVICE.  *out receives the
+ * context (NULL on failure). */
+int evrt_create(int hip_device, evrt_ctx **out);
+void evrt_destroy(evrt_ctx *ctx);
+
+/* Message of the last failure on ctx (or of the last evrt_create failure on
+ * this thread when ctx is NULL).  Valid until the next call on ctx. */
+const char *evrt_last_error(const evrt_ctx *ctx);
+
+/* ---- Scene --------------------------------------------------------------
+ * Grey Lambertian materials: albedo in [0, 1), emitted radiance >= 0.  An
+ * emitter radiates from its front side only (front = the side toward which
+ * cross(v1 - v0, v2 - v0) points); reflection is two-sided. */
+int evrt_scene_set_materials(evrt_ctx *ctx, const float *albedo, const float *emission,
+                             uint32_t n_mat);
+
+/* Mesh `mesh_id` (ids must end up dense 0..n-1): nv object-space vertices
+ * (xyz[nv][3]) and nt triangles (tri_idx[nt][3] into this mesh's vertices,
+ * tri_mat[nt] material ids).  Replaces a mesh with the same id. */
+int evrt_scene_set_mesh(evrt_ctx *ctx, uint32_t mesh_id, const float *xyz, uint32_t nv,
+                        const uint32_t *tri_idx, const uint32_t *tri_mat, uint32_t nt);
+
+/* Instance `inst_id` of mesh `mesh_id` (ids dense 0..n-1) with n_keys
+ * keyframes: strictly increasing times key_t[n_keys] and row-major 3x4
+ * object-to-world matrices xform3x4[n_keys][12].  At time t the matrix is
+ * the first key before the first key time, the last key after the last key
+ * time, and otherwise the entry-wise FP64 interpolation
+ * M_k + w (M_{k+1} - M_k), w = (t - t_k) / (t_{k+1} - t_k).  World vertices
+ * are computed in FP64 as ((m0 x + m1 y) + m2 z) + m3 and rounded to FP32.
+ * World triangles are numbered instance by instance, mesh triangle order
+ * within an instance; that number breaks ties between equal hit distances. */
+int evrt_scene_set_instance(evrt_ctx *ctx, uint32_t inst_id, uint32_t mesh_id, uint32_t n_keys,
+                            const double *key_t, const double *xform3x4);
+
+/* Point lights (n may be 0): positions pos_xyz[n][3], intensities
+ * intensity[n].  Reached through next-event estimation only. */
+int evrt_scene_set_point_lights(evrt_ctx *ctx, const float *pos_xyz, const float *intensity,
+                                uint32_t n);
+
+/* Pinhole camera: image width x height, vertical field of view vfov_deg,
+ * keyframed (eye, look-at, up) eye_look_up[n_keys][9], interpolated like
+ * instance matrices.  The ray through pixel (x, y) with sub-pixel offset
+ * (u, v) has direction f + (2 (x + u) / W - 1) s_x r + (1 - 2 (y + v) / H) s_y u'
+ * (normalized), with s_y = tan(vfov / 2), s_x = s_y W / H, f, r, u' the
+ * forward, right and up unit vectors of the camera. */
+int evrt_scene_set_camera(evrt_ctx *ctx, uint32_t width, uint32_t height, double vfov_deg,
+                          uint32_t n_keys, const double *key_t, const double *eye_look_up);
+
+/* Clears the pending scene description (materials, meshes, instances,
+ * lights, camera).  The committed scene stays current until the next
+ * successful evrt_scene_commit. */
+int evrt_scene_reset(evrt_ctx *ctx);
+
+/* Validates the scene (dense ids, indices in range, finite values) and
+ * makes it current.  Geometry and BVHs for an instant are built on first
+ * use and cached. */
+int evrt_scene_commit(evrt_ctx *ctx);
+
+/* ---- Rendering ---------------------------------------------------------- */
+typedef struct {
+    uint64_t seed;           /* Philox key (low word, high word)                   */
+    uint32_t max_depth;      /* surface vertices per path (>= 1), default 4        */
+    uint32_t rr_start_depth; /* first vertex with Russian roulette, default 2      */
+    uint32_t minibatch;      /* paths per log-luminance sample: 1, 2, 4 or 8 (4)   */
+    double log_eps;          /* x = ln(Y + log_eps), default 1e-4                  */
+    uint8_t nee;             /* next-event estimation on (1, default) or off (0)   */
+    uint8_t jitter;          /* random sub-pixel offset (1, default) or centre (0) */
+    uint8_t mode;            /* EVRT_MODE_*                                        */
+    uint8_t df_mode;         /* EVRT_DF_*                                          */
+    uint8_t ref_mode;        /* EVRT_REF_*                                         */
+    uint8_t profile;         /* 1: time traversal launches with HIP events         */
+    uint8_t count_work;      /* 1: count BVH node visits and triangle tests        */
+    uint8_t reserved0;
+    uint32_t ray_batch;      /* max paths in flight per wavefront piece (0: auto)  */
+    uint32_t reserved1;
+} evrt_render_opts;
+
+/* Fills *opts with the defaults listed above (seed 0). */
+void evrt_default_opts(evrt_render_opts *opts);
+
+/* Per-pixel outputs, caller-owned device arrays with width*height entries
+ * (two per pixel, [pixel][instant], where marked x2).  Optional arrays may
+ * be NULL. */
+typedef struct {
+    int8_t *polarity;        /* -1, 0, +1                                  */
+    uint32_t *n_paths;       /* paths traced per instant (second instant)  */
+    double *mean;            /* x2: mean logL per instant                  */
+    double *var;             /* x2: unbiased variance of logL per instant  */
+    double *t_last;          /* optional: t of the last decision           */
+    double *mean_radiance;   /* optional x2: mean of the mini-batch radiance */
+    uint8_t *flags;          /* optional: bit 0 = stopped by the test      */
+} evrt_frame_out;
+
+/* Renders one event frame for the instants (t0, t1) with threshold C >= 0,
+ * significance 0 < alpha < 1 and the schedule spp_init, spp_init +
+ * spp_batch, ... (clamped to spp_max) paths per instant.  spp_init,
+ * spp_batch and spp_max must be multiples of opts->minibatch, spp_init at
+ * least two mini-batches and at most spp_max.  opts NULL = defaults.
+ * FIXED mode traces spp_max paths everywhere and applies only the event
+ * rule. */
+int evrt_render_event_frame(evrt_ctx *ctx, double t0, double t1, float C, float alpha,
+                            uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
+                            const evrt_render_opts *opts, const evrt_frame_out *out,
+                            void *stream);
+
+/* Counters of the last render call on ctx. */
+typedef struct {
+    uint64_t camera_rays, extension_rays, shadow_rays; /* rays traced        */
+    uint64_t node_visits, tri_tests;  /* closest-hit traversal, when
+                                         count_work was set (else 0)         */
+    uint64_t node_visits_shadow, tri_tests_shadow; /* any-hit traversal      */
+    uint64_t paths;                   /* camera paths traced                 */
+    uint32_t rounds;                  /* decision rounds                     */
+    uint32_t pieces;                  /* wavefront pieces launched           */
+    uint32_t n_closest_launches, n_shadow_launches;
+    double ms_wall;                   /* host wall time of the call          */
+    double ms_closest, ms_shadow;     /* HIP-event time of traversal launches
+                                         (when profile was set, else 0)      */
+    double ms_build;                  /* geometry/BVH build done in the call */
+    uint32_t active_after_round[64];  /* active pixels after rounds 0..63    */
+} evrt_frame_stats;
+
+int evrt_get_frame_stats(const evrt_ctx *ctx, evrt_frame_stats *out);
+
+/* ---- Test and measurement hooks ----------------------------------------- */
+
+/* Traces n caller rays against the scene at time t with the renderer's
+ * traversal kernels.  rays: device float[n][8] = (ox, oy, oz, tmin, dx, dy,
+ * dz, tmax); skip: device uint32[n] primitive to ignore (0xffffffff: none)
+ * or NULL.  any_hit = 0: t_out[i] = closest distance and prim_out[i] = its
+ * primitive, (tmax, 0xffffffff) when nothing is hit; any_hit = 1: prim_out[i]
+ * = 1 if anything is hit in (tmin, tmax) else 0, t_out unused (may be NULL). */
+int evrt_trace_rays(evrt_ctx *ctx, double t, uint32_t n, const float *rays,
+                    const uint32_t *skip, int any_hit, float *t_out, uint32_t *prim_out,
+                    void *stream);
+
+/* Radiance of every path sample s in [0, spp) of the listed pixels at both
+ * instants (the tracePaths estimator of Algorithm 1), written to device
+ * L_out[n_pixels][2][spp].  pixels: device uint32[n_pixels]. */
+int evrt_render_paths(evrt_ctx *ctx, double t0, double t1, uint32_t n_pixels,
+                      const uint32_t *pixels, uint32_t spp, const evrt_render_opts *opts,
+                      float *L_out, void *stream);
+
+/* Runs the accumulator and decision kernels on caller log-luminance
+ * samples: x0, x1 device double[n_pixels][m] (m >= 2).  Writes t_out[n]
+ * (Eq. 7), stop_out[n] (1 when the rule of `mode` stops sampling) and
+ * polarity_out[n] (event rule).  Student degrees of freedom 2m - 2. */
+int evrt_decide_stats(evrt_ctx *ctx, const double *x0, const double *x1, uint32_t n_pixels,
+                      uint32_t m, float C, float alpha, uint8_t mode, double *t_out,
+                      uint8_t *stop_out, int8_t *polarity_out, void *stream);
+
+/* Host-side build of the scene at time t (world triangles and BVH2, no
+ * device work) with a structural check of the BVH: every primitive in
+ * exactly one leaf, every vertex inside its padded leaf box, every node
+ * reachable once, depth within the traversal stack.  Works on host-only
+ * contexts.  Returns EVRT_E_INVALID (message in evrt_last_error) when a
+ * check fails. */
+typedef struct {
+    uint32_t n_tri, n_nodes, n_lds, depth, n_emit;
+    float box_pad;
+    double sah_cost;
+} evrt_scene_info;
+
+int evrt_scene_info_at(evrt_ctx *ctx, double t, evrt_scene_info *out);
+
+/* Host-side Student t quantile used for the critical values: the value q
+ * with P(T_df <= q) = p, for integer df >= 1.  Returns NaN on bad input. */
+double evrt_t_quantile(double p, uint32_t df);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EVRT_H */

@@ -1,0 +1,156 @@
+// evrt_host.h -- host-side state of the library (internal).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/evrt.h"
+#include "evrt_kernels.h"
+
+namespace evrt {
+
+// Thrown inside the library, converted to a status at the ABI boundary.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+
+// Device allocation that only grows.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    void ensure(size_t n);
+    void upload(const void *src, size_t n, hipStream_t s);
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+struct MeshDesc {
+    bool set = false;
+    std::vector<float> xyz;
+    std::vector<uint32_t> idx, mat;
+};
+
+struct InstanceDesc {
+    bool set = false;
+    uint32_t mesh = 0;
+    std::vector<double> kt, kx;  // keys, 12 doubles per key
+};
+
+struct CameraDesc {
+    bool set = false;
+    uint32_t width = 0, height = 0;
+    double vfov = 0.0;
+    std::vector<double> kt, elu;  // 9 doubles per key
+};
+
+struct SceneDesc {
+    std::vector<float> albedo, emission;
+    std::vector<MeshDesc> meshes;
+    std::vector<InstanceDesc> instances;
+    std::vector<float> pl_pos, pl_int;
+    CameraDesc cam;
+};
+
+// World-space geometry of one instant, built on the host and uploaded.
+struct HostInstant {
+    std::vector<float> tri;      // [n][9] world vertices in primitive order
+    std::vector<float4> prim;    // [n] (unit normal, material bits)
+    std::vector<float> area;     // [n]
+    std::vector<uint32_t> emit_prim;
+    std::vector<float> emit_cdf;
+    float emit_S = 0.0f;
+    DevCamera cam;
+    // BVH
+    std::vector<float4> nodes;   // 4 per inner node
+    std::vector<float4> tris;    // 3 per triangle in leaf order
+    int32_t root = kEmptyRef;
+    uint32_t n_lds = 0;
+    uint32_t depth = 0;
+    double sah_cost = 0.0;
+};
+
+struct DevInstantBufs {
+    DevBuf nodes, tris, prim, emit_cdf, emit;
+    DevInstant view{};
+    HostInstant host;  // kept for statistics and validation
+};
+
+// World geometry at time t (primitive order, FP64 transform, FP32 round).
+void build_world(const SceneDesc &sd, double t, HostInstant &out);
+// BVH2 over out.tri (binned SAH), LDS treelet of up to n_lds_max nodes first.
+void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad);
+// Validates structural invariants of a built BVH; returns an empty string
+// when they hold.
+std::string check_bvh(const HostInstant &h, float pad);
+// Padding of node boxes for a scene (see the box test in the kernels).
+float bvh_padding(const SceneDesc &sd, const HostInstant &a, const HostInstant &b);
+
+FastDiv make_fastdiv(uint32_t d);
+
+// Student t quantile (integer df) and its memoized critical values.
+double t_quantile(double p, uint32_t df);
+
+struct FrameBuffers {
+    DevBuf wf_n, wf_mean, wf_m2, wf_ysum, act0, act1;
+    DevBuf cnt, stat;
+    DevBuf q_o[2], q_d[2], q_skip[2], hit;
+    DevBuf sh_o, sh_meta, sh_dir, sh_c;
+    DevBuf rad;
+    DevBuf hook_tm;
+    uint32_t queue_cap = 0, shadow_slots = 0;
+};
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace evrt
+
+struct evrt_ctx {
+    int device = -1;
+    bool host_only = true;
+    std::string err;
+    evrt::SceneDesc pending;
+    evrt::SceneDesc scene;
+    bool committed = false;
+    uint64_t scene_version = 0;
+    std::map<double, std::shared_ptr<evrt::DevInstantBufs>> cache;
+    std::vector<double> cache_order;
+    evrt::DevBuf mat, plights;
+    evrt::FrameBuffers fb;
+    uint32_t *h_pinned = nullptr;            // pinned readback words
+    unsigned long long *h_stat = nullptr;    // pinned stat readback
+    std::vector<evrt::EventPair> events;
+    std::map<std::pair<uint64_t, uint32_t>, double> crit_cache;
+    evrt_frame_stats stats{};
+    uint32_t cu_count = 0;
+    uint32_t trace_blocks_per_cu = 0;
+    uint32_t shade_blocks_per_cu = 0;
+};
+
+namespace evrt {
+// Geometry of instant t on the device (built and cached on first use).
+std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s, double *ms_build);
+DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b);
+void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
+                  uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o,
+                  const evrt_frame_out &out, hipStream_t s);
+void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const uint32_t *pixels,
+                  uint32_t spp, const evrt_render_opts &o, float *L_out, hipStream_t s);
+void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip, int any,
+                float *t_out, uint32_t *p_out, hipStream_t s);
+void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
+                  float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
+                  hipStream_t s);
+void validate_opts(const evrt_render_opts &o);
+}  // namespace evrt

@@ -1,0 +1,66 @@
+// evrt_kernels.h -- launch interface between the host scheduler and the
+// gfx950 kernels (internal to the library).
+#pragma once
+
+#include "evrt_types.h"
+
+namespace evrt {
+
+// Layout of the uint32 device counter array.
+constexpr int kCntMaxDepth = 64;                   // max_depth limit
+constexpr int kCntRay0 = 0;                        // [0, 64]: rays to trace per bounce
+constexpr int kCntShadow0 = kCntRay0 + kCntMaxDepth + 1;  // [65, 129]: shadow entries
+constexpr int kCntActive = 200;                    // [200, 201]: compaction counts (alternating rounds)
+constexpr int kCntSize = 256;
+
+// Decision constants of one round.
+struct Decide {
+    double C;
+    double crit_lo, crit_hi;   // t critical values (lower tail, upper tail)
+    uint32_t mode;             // EVRT_MODE_*
+    uint32_t final_round;      // 1 at spp_max: event rule only
+    uint32_t minibatch;
+    uint32_t cnt_slot;         // which of the two compaction counters this round uses
+};
+
+// Caller output arrays (device).
+struct Outputs {
+    int8_t *polarity;
+    uint32_t *n_paths;
+    double *mean, *var, *t_last, *mean_radiance;
+    uint8_t *flags;
+};
+
+void launch_init_frame(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                       double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat);
+void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const RenderParams &rp,
+                   const RayQueue &q, uint32_t *cnt);
+void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
+                          const RayQueue &q, const uint32_t *cnt_in, float2 *hit, int stat_kind,
+                          unsigned long long *stat);
+void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
+                         const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, float *rad,
+                         unsigned long long *stat);
+void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
+                  const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
+                  const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
+                  uint32_t *cnt_sh, uint32_t depth);
+void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
+                       double *wf_mean, double *wf_m2, double *wf_ysum);
+void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_in, uint32_t nA,
+                           uint32_t *act_out, uint32_t *cnt, const uint32_t *wf_n,
+                           const double *wf_mean, const double *wf_m2, const double *wf_ysum,
+                           const Outputs &out);
+void launch_hook_rays(hipStream_t s, uint32_t n, const float *rays, const uint32_t *skip,
+                      const RayQueue &q, float *tminmax, uint32_t *cnt);
+void launch_hook_trace(hipStream_t s, uint32_t blocks, bool any, const DevScene &sc, const RayQueue &q,
+                       const float *tminmax, uint32_t n, float *t_out, uint32_t *p_out);
+void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint32_t n, uint32_t m,
+                        const Decide &dc, double *t_out, uint8_t *stop_out, int8_t *pol_out);
+
+void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu);
+int traverse_block_threads();
+int lds_treelet_nodes();
+int traverse_max_depth();
+
+}  // namespace evrt

@@ -1,0 +1,110 @@
+// evrt_types.h -- plain data exchanged between the host scheduler and the
+// gfx950 kernels of the adaptive event renderer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace evrt {
+
+constexpr uint32_t kNoPrim = 0xffffffffu;
+constexpr float kRayTmin = 1e-4f;        // self-intersection offset (scene units)
+constexpr float kShadowScale = 0.9999f;  // shadow segment ends short of the light
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr double kTwoPi = 6.283185307179586476925;
+constexpr uint32_t kInstBit = 0x80000000u;  // instant flag in queue path words
+
+// BVH2 node: 64 bytes = four float4.  Child boxes are stored side by side;
+// child references are int32: >= 0 an inner node, < 0 a leaf whose
+// complement packs (first_triangle << 3) | (count - 1).
+//   n[0] = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)
+//   n[1] = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
+//   n[2] = (R.lo.z, R.hi.x, R.hi.y, R.hi.z)
+//   n[3] = (ref L, ref R, 0, 0) as int bits
+constexpr int kLeafCountBits = 3;
+constexpr uint32_t kMaxLeafTris = 1u << kLeafCountBits;
+constexpr int32_t kEmptyRef = -1;  // ~0: a leaf with zero triangles is never built
+
+// Unsigned division by a runtime constant for n < 2^31 (round-up method):
+// q = (umulhi(n, m) + n) >> s.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+struct DevCamera {
+    float eye[3], fwd[3], right[3], up[3];
+    float sx, sy;
+};
+
+// Geometry of the scene at one instant, device pointers.
+struct DevInstant {
+    const float4 *nodes;     // 4 per inner node
+    const float4 *tris;      // 3 per triangle in leaf order: (v0, prim bits), (v1, 0), (v2, 0)
+    const float4 *prim;      // per primitive: (unit normal xyz, material bits)
+    const float *emit_cdf;   // per emitter
+    const float4 *emit;      // 4 per emitter: v0, v1, v2, (unit normal xyz, prim bits)
+    int32_t root;            // root reference (kEmptyRef: no geometry)
+    uint32_t n_nodes, n_lds, n_emit;
+    float emit_S;            // sum over emitters of area * Le
+    DevCamera cam;
+};
+
+struct DevScene {
+    DevInstant inst[2];
+    const float2 *mat;       // (albedo, emission)
+    const float4 *plights;   // (position xyz, intensity)
+    uint32_t n_plights;
+    uint32_t width, height;
+    FastDiv div_w;
+};
+
+struct RenderParams {
+    uint32_t key0, key1;     // Philox key
+    uint32_t max_depth, rr_start;
+    uint32_t nee, jitter;
+    uint32_t minibatch;
+    uint32_t n_slots;        // shadow rays per shade vertex: 1 + point lights
+    double log_eps;
+};
+
+// A piece of a round: samples [s0, s0 + bp) of nA pixels (the active list)
+// at n_inst instants starting at inst_base.  Piece-local path id
+// p = (ii * nA + a) * bp + s; its radiance goes to rad[a*rs_a + ii*rs_i + s].
+struct Piece {
+    const uint32_t *act;
+    uint32_t nA, bp, n_inst, inst_base, s0;
+    uint32_t n_paths;
+    FastDiv div_bp, div_nA;
+    float *rad;
+    uint32_t rs_a, rs_i;
+};
+
+// Ray queue (SoA of float4): o = (origin xyz, throughput beta),
+// d = (direction xyz, path word = p | instant << 31), skip = origin primitive.
+struct RayQueue {
+    float4 *o;
+    float4 *d;
+    uint32_t *skip;
+};
+
+// Shadow queue: one entry per shaded vertex with at least one shadow ray;
+// n_slots rays share the origin.  o = (P xyz, radiance index bits),
+// meta = skip primitive | instant << 31; slot k of entry e lives at
+// [k * cap + e]: dir = (wi xyz, tmax), c = contribution (0: slot unused).
+struct ShadowQueue {
+    float4 *o;
+    uint32_t *meta;
+    float4 *dir;
+    float *c;
+    uint32_t cap;
+};
+
+// Device counters (uint64): rays by kind and optional work counts.
+enum StatIndex : int {
+    kStatCamera = 0, kStatExtension = 1, kStatShadow = 2,
+    kStatNodes = 3, kStatTris = 4,          // closest-hit traversal
+    kStatNodesShadow = 5, kStatTrisShadow = 6,  // any-hit traversal
+    kStatCount = 8
+};
+
+}  // namespace evrt

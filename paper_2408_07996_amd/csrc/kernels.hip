@@ -1,0 +1,867 @@
+// kernels.hip -- gfx950 kernels of the adaptive event renderer.
+//
+// Wavefront path tracer for one piece of a sampling round (raygen, BVH2
+// closest-hit and any-hit traversal, shading with next-event estimation
+// and Russian roulette), the per-pixel FP64 Welford accumulator of the
+// mini-batch log-luminance, and the fused t-test / decision kernel with
+// wave-ballot compaction of the pixels that stay undecided.
+//
+// Floating point: the whole file is compiled without FMA contraction; the
+// only fused multiply-adds are the explicit ones in the (conservative) box
+// test.  Path arithmetic is FP32 in the order documented next to each
+// step; sin, cos and log are evaluated in FP64 (sin/cos rounded to FP32)
+// and statistics are FP64.
+#include <algorithm>
+
+#include "evrt_kernels.h"
+
+namespace evrt {
+namespace {
+
+// ------------------------------------------------------------------------
+// Small helpers.
+
+__device__ __forceinline__ uint32_t fdiv(const FastDiv &f, uint32_t n)
+{
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+__device__ __forceinline__ uint32_t fbits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ float bitsf(uint32_t x) { return __uint_as_float(x); }
+
+// Philox4x32-10 (Salmon et al., SC'11): per round the counter becomes
+// (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key
+// advances by the two Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// Random block for (pixel, sample, instant, vertex, block).
+__device__ __forceinline__ uint4 rng_block(const RenderParams &rp, uint32_t pixel, uint32_t sample,
+                                           uint32_t inst, uint32_t vertex, uint32_t block)
+{
+    return philox10(make_uint4(pixel, sample, (inst << 24) | (vertex << 8) | block, 0u), rp.key0,
+                    rp.key1);
+}
+
+// Uniform in [0, 1 - 2^-24].
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
+
+__device__ __forceinline__ float dot3f(float ax, float ay, float az, float bx, float by, float bz)
+{
+    return (ax * bx + ay * by) + az * bz;
+}
+
+__device__ __forceinline__ float sel3(float4 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+// Appends one element per lane with pred set; returns the lane's slot.
+// One atomic per wave; must be called by every active lane of the wave.
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter)
+{
+    const unsigned long long mask = __ballot(pred);
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    const uint32_t total = (uint32_t)__popcll(mask);
+    uint32_t base = 0;
+    if (total) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        if ((int)__lane_id() == leader) base = atomicAdd(counter, total);
+        base = __shfl(base, leader);
+    }
+    return base + rank;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ------------------------------------------------------------------------
+// Ray preparation shared by both traversal kinds.
+
+struct TRay {
+    float ox, oy, oz;       // origin
+    float ix, iy, iz;       // reciprocal direction (tiny components clamped)
+    float nox, noy, noz;    // -origin * reciprocal, for the fused slab test
+    float okx, oky, okz;    // origin permuted into the watertight frame
+    float Sx, Sy, Sz;       // shear constants
+    int kx, ky, kz;
+};
+
+__device__ __forceinline__ float safe_dir(float d)
+{
+    return fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
+}
+
+// Watertight ray frame (Woop, Benthin, Wald 2013): z = axis of the largest
+// |d| (ties to the lower axis), x and y cyclic after it, swapped when
+// d_z < 0; shear Sx = d_x / d_z, Sy = d_y / d_z, Sz = 1 / d_z.
+__device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx, float dy, float dz)
+{
+    TRay r;
+    r.ox = ox; r.oy = oy; r.oz = oz;
+    r.ix = 1.0f / safe_dir(dx);
+    r.iy = 1.0f / safe_dir(dy);
+    r.iz = 1.0f / safe_dir(dz);
+    r.nox = -(ox * r.ix);
+    r.noy = -(oy * r.iy);
+    r.noz = -(oz * r.iz);
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int kz = 0;
+    float m = ax;
+    if (ay > m) { kz = 1; m = ay; }
+    if (az > m) { kz = 2; }
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    const float4 d4 = make_float4(dx, dy, dz, 0.0f);
+    const float dkz = sel3(d4, kz);
+    if (dkz < 0.0f) { const int tmp = kx; kx = ky; ky = tmp; }
+    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.Sx = sel3(d4, kx) / dkz;
+    r.Sy = sel3(d4, ky) / dkz;
+    r.Sz = 1.0f / dkz;
+    const float4 o4 = make_float4(ox, oy, oz, 0.0f);
+    r.okx = sel3(o4, kx);
+    r.oky = sel3(o4, ky);
+    r.okz = sel3(o4, kz);
+    return r;
+}
+
+// Watertight test against (v0, v1, v2); on a hit stores t = T / det.
+__device__ __forceinline__ bool tri_test(const TRay &r, float4 v0, float4 v1, float4 v2, float &t)
+{
+    const float ax = sel3(v0, r.kx) - r.okx, ay = sel3(v0, r.ky) - r.oky, az = sel3(v0, r.kz) - r.okz;
+    const float bx = sel3(v1, r.kx) - r.okx, by = sel3(v1, r.ky) - r.oky, bz = sel3(v1, r.kz) - r.okz;
+    const float cx = sel3(v2, r.kx) - r.okx, cy = sel3(v2, r.ky) - r.oky, cz = sel3(v2, r.kz) - r.okz;
+    const float Ax = ax - r.Sx * az, Ay = ay - r.Sy * az;
+    const float Bx = bx - r.Sx * bz, By = by - r.Sy * bz;
+    const float Cx = cx - r.Sx * cz, Cy = cy - r.Sy * cz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = (U + V) + W;
+    if (det == 0.0f) return false;
+    const float Az = r.Sz * az, Bz = r.Sz * bz, Cz = r.Sz * cz;
+    const float T = (U * Az + V * Bz) + W * Cz;
+    t = T / det;
+    return true;
+}
+
+// Slab test of both children.  Boxes are padded on the host by more than
+// the rounding of the fused products, so no triangle the exact test hits
+// is culled.  Returns entry distances; a miss gives +inf.
+__device__ __forceinline__ void box2(const TRay &r, float4 n0, float4 n1, float4 n2, float tmin,
+                                     float tfar, float &tl, float &tr)
+{
+    const float lx0 = __builtin_fmaf(n0.x, r.ix, r.nox), lx1 = __builtin_fmaf(n0.w, r.ix, r.nox);
+    const float ly0 = __builtin_fmaf(n0.y, r.iy, r.noy), ly1 = __builtin_fmaf(n1.x, r.iy, r.noy);
+    const float lz0 = __builtin_fmaf(n0.z, r.iz, r.noz), lz1 = __builtin_fmaf(n1.y, r.iz, r.noz);
+    const float rx0 = __builtin_fmaf(n1.z, r.ix, r.nox), rx1 = __builtin_fmaf(n2.y, r.ix, r.nox);
+    const float ry0 = __builtin_fmaf(n1.w, r.iy, r.noy), ry1 = __builtin_fmaf(n2.z, r.iy, r.noy);
+    const float rz0 = __builtin_fmaf(n2.x, r.iz, r.noz), rz1 = __builtin_fmaf(n2.w, r.iz, r.noz);
+    const float lnear = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fmaxf(fminf(lz0, lz1), tmin));
+    const float lfar = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fminf(fmaxf(lz0, lz1), tfar));
+    const float rnear = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fmaxf(fminf(rz0, rz1), tmin));
+    const float rfar = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fminf(fmaxf(rz0, rz1), tfar));
+    tl = lnear <= lfar ? lnear : INFINITY;
+    tr = rnear <= rfar ? rnear : INFINITY;
+}
+
+struct InstSel {
+    const float4 *nodes;
+    const float4 *tris;
+    int32_t root;
+    uint32_t n_lds;
+};
+
+__device__ __forceinline__ InstSel select_inst(const DevScene &sc, uint32_t inst)
+{
+    InstSel s;
+    s.nodes = inst ? sc.inst[1].nodes : sc.inst[0].nodes;
+    s.tris = inst ? sc.inst[1].tris : sc.inst[0].tris;
+    s.root = inst ? sc.inst[1].root : sc.inst[0].root;
+    s.n_lds = inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
+    return s;
+}
+
+// Traversal block shape: kTB threads, a top treelet of kLdsNodes nodes per
+// instant staged in LDS, and a per-lane stack whose first kStackLds entries
+// live in LDS (deeper entries spill to private memory).
+constexpr int kTB = 256;
+constexpr int kLdsNodes = 64;
+constexpr int kStackLds = 16;
+constexpr int kStackMax = 64;
+
+template <bool ANY, bool COUNT>
+__device__ __forceinline__ bool traverse(const InstSel &is, const float4 *lds_nodes,
+                                         uint32_t *lds_stack, const TRay &r, float tmin, float tmax,
+                                         uint32_t skip, float &best_t, uint32_t &best_p,
+                                         uint32_t &visits, uint32_t &tests)
+{
+    best_t = tmax;
+    best_p = kNoPrim;
+    if (is.root == kEmptyRef) return false;
+    int32_t spill[kStackMax - kStackLds];
+    int sp = 0;
+    int32_t ref = is.root;
+    for (;;) {
+        if (ref >= 0) {
+            float4 n0, n1, n2, n3;
+            if ((uint32_t)ref < is.n_lds) {
+                const float4 *p = lds_nodes + 4 * ref;
+                n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+            } else {
+                const float4 *p = is.nodes + 4 * (size_t)ref;
+                n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+            }
+            if (COUNT) ++visits;
+            float tl, tr;
+            box2(r, n0, n1, n2, tmin, best_t, tl, tr);
+            const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+            const bool hl = tl != INFINITY, hr = tr != INFINITY;
+            if (hl && hr) {
+                const bool lfirst = tl <= tr;
+                const int32_t far = lfirst ? cr : cl;
+                ref = lfirst ? cl : cr;
+                if (sp < kStackLds) lds_stack[sp * kTB] = (uint32_t)far;
+                else spill[sp - kStackLds] = far;
+                ++sp;
+                continue;
+            }
+            if (hl || hr) {
+                ref = hl ? cl : cr;
+                continue;
+            }
+        } else {
+            const uint32_t packed = ~(uint32_t)ref;
+            const uint32_t first = packed >> kLeafCountBits;
+            const uint32_t count = (packed & (kMaxLeafTris - 1)) + 1;
+            for (uint32_t k = 0; k < count; ++k) {
+                const float4 *tp = is.tris + 3 * (size_t)(first + k);
+                const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
+                const uint32_t prim = fbits(v0.w);
+                if (prim == skip) continue;
+                if (COUNT) ++tests;
+                float t;
+                if (!tri_test(r, v0, v1, v2, t)) continue;
+                if (!(t > tmin) || !(t < tmax)) continue;
+                if (ANY) {
+                    best_t = t;
+                    best_p = prim;
+                    return true;
+                }
+                if (t < best_t || (t == best_t && prim < best_p)) {
+                    best_t = t;
+                    best_p = prim;
+                }
+            }
+        }
+        // pop
+        if (sp == 0) break;
+        --sp;
+        ref = sp < kStackLds ? (int32_t)lds_stack[sp * kTB] : spill[sp - kStackLds];
+    }
+    return best_p != kNoPrim;
+}
+
+__device__ __forceinline__ void load_treelets(const DevScene &sc, float4 *s_nodes)
+{
+    for (int inst = 0; inst < 2; ++inst) {
+        const uint32_t n = inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
+        const float4 *src = inst ? sc.inst[1].nodes : sc.inst[0].nodes;
+        for (uint32_t i = threadIdx.x; i < 4 * n; i += kTB) s_nodes[inst * 4 * kLdsNodes + i] = src[i];
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------
+// Kernels.
+
+// Clears the per-pixel accumulators, fills the active list with every
+// pixel and clears the frame counters.
+__global__ void k_init_frame(uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                             double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * npx) {
+        wf_n[i] = 0;
+        wf_mean[i] = 0.0;
+        wf_m2[i] = 0.0;
+        wf_ysum[i] = 0.0;
+    }
+    if (i < npx) act[i] = i;
+    if (i == 0) {
+        cnt[kCntActive] = 0;
+        cnt[kCntActive + 1] = 0;
+        for (int k = 0; k < kStatCount; ++k) stat[k] = 0;
+    }
+}
+
+// Camera rays of a piece: pinhole through (x + u, y + v), (u, v) from the
+// vertex-0 random block or the pixel centre.
+__global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uint32_t *cnt)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        cnt[kCntRay0] = pc.n_paths;
+        for (int k = 1; k < kCntMaxDepth + 1; ++k) cnt[kCntRay0 + k] = 0;
+        for (int k = 0; k < kCntMaxDepth + 1; ++k) cnt[kCntShadow0 + k] = 0;
+    }
+    if (p >= pc.n_paths) return;
+    const uint32_t qq = fdiv(pc.div_bp, p);
+    const uint32_t s = p - qq * pc.bp;
+    const uint32_t ii = fdiv(pc.div_nA, qq);
+    const uint32_t a = qq - ii * pc.nA;
+    const uint32_t pixel = pc.act[a];
+    const uint32_t inst = pc.inst_base + ii;
+    const uint32_t sample = pc.s0 + s;
+    const DevCamera &cam = inst ? sc.inst[1].cam : sc.inst[0].cam;
+    const uint32_t py = fdiv(sc.div_w, pixel);
+    const uint32_t px = pixel - py * sc.width;
+    float j0 = 0.5f, j1 = 0.5f;
+    if (rp.jitter) {
+        const uint4 rb = rng_block(rp, pixel, sample, inst, 0, 0);
+        j0 = u01(rb.x);
+        j1 = u01(rb.y);
+    }
+    const float fx = (float)px + j0, fy = (float)py + j1;
+    const float nx = (2.0f * fx) / (float)sc.width - 1.0f;
+    const float ny = 1.0f - (2.0f * fy) / (float)sc.height;
+    const float ca = nx * cam.sx, cb = ny * cam.sy;
+    float dx = (cam.fwd[0] + ca * cam.right[0]) + cb * cam.up[0];
+    float dy = (cam.fwd[1] + ca * cam.right[1]) + cb * cam.up[1];
+    float dz = (cam.fwd[2] + ca * cam.right[2]) + cb * cam.up[2];
+    const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
+    dx = dx / len; dy = dy / len; dz = dz / len;
+    q.o[p] = make_float4(cam.eye[0], cam.eye[1], cam.eye[2], 1.0f);
+    q.d[p] = make_float4(dx, dy, dz, bitsf(p | (inst << 31)));
+    q.skip[p] = kNoPrim;
+    pc.rad[a * pc.rs_a + ii * pc.rs_i + s] = 0.0f;
+}
+
+// Closest hit of the queued rays; hit[i] = (t, prim bits), prim = kNoPrim on
+// a miss.  Persistent grid-stride over the device-side queue count.
+template <bool COUNT>
+__global__ __launch_bounds__(kTB) void k_trace_closest(DevScene sc, RayQueue q, const uint32_t *cnt_in,
+                                                       float2 *hit, int stat_kind,
+                                                       unsigned long long *stat)
+{
+    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ uint32_t s_stack[kStackLds * kTB];
+    load_treelets(sc, s_nodes);
+    const uint32_t n = *cnt_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(stat + stat_kind, (unsigned long long)n);
+    uint32_t visits = 0, tests = 0;
+    for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
+        const float4 o = q.o[i], d = q.d[i];
+        const uint32_t skip = q.skip[i];
+        const uint32_t inst = fbits(d.w) >> 31;
+        const InstSel is = select_inst(sc, inst);
+        const TRay r = make_tray(o.x, o.y, o.z, d.x, d.y, d.z);
+        float bt;
+        uint32_t bp;
+        traverse<false, COUNT>(is, s_nodes + inst * 4 * kLdsNodes, s_stack + threadIdx.x, r, kRayTmin,
+                               INFINITY, skip, bt, bp, visits, tests);
+        hit[i] = make_float2(bt, bitsf(bp));
+    }
+    if (COUNT) {
+        const unsigned long long v = wave_sum_u64(visits), t = wave_sum_u64(tests);
+        if (__lane_id() == 0) {
+            atomicAdd(stat + kStatNodes, v);
+            atomicAdd(stat + kStatTris, t);
+        }
+    }
+}
+
+// Shadow rays: every unoccluded slot adds its contribution; the sum over
+// the entry's slots (in slot order) is added to the path radiance.
+template <bool COUNT>
+__global__ __launch_bounds__(kTB) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
+                                                      const uint32_t *cnt_in, float *rad,
+                                                      unsigned long long *stat)
+{
+    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ uint32_t s_stack[kStackLds * kTB];
+    load_treelets(sc, s_nodes);
+    const uint32_t n = *cnt_in;
+    uint32_t visits = 0, tests = 0, rays = 0;
+    for (uint32_t e = blockIdx.x * kTB + threadIdx.x; e < n; e += gridDim.x * kTB) {
+        const float4 o = sq.o[e];
+        const uint32_t meta = sq.meta[e];
+        const uint32_t inst = meta >> 31;
+        const uint32_t skip = meta & ~kInstBit;
+        const InstSel is = select_inst(sc, inst);
+        float sum = 0.0f;
+        for (uint32_t k = 0; k < n_slots; ++k) {
+            const float c = sq.c[k * sq.cap + e];
+            if (!(c > 0.0f)) continue;
+            const float4 w = sq.dir[k * sq.cap + e];
+            const TRay r = make_tray(o.x, o.y, o.z, w.x, w.y, w.z);
+            float bt;
+            uint32_t bp;
+            ++rays;
+            if (!traverse<true, COUNT>(is, s_nodes + inst * 4 * kLdsNodes, s_stack + threadIdx.x, r,
+                                       kRayTmin, w.w, skip, bt, bp, visits, tests))
+                sum = sum + c;
+        }
+        const uint32_t ri = fbits(o.w);
+        rad[ri] = rad[ri] + sum;
+    }
+    const unsigned long long rs = wave_sum_u64(rays);
+    if (__lane_id() == 0 && rs) atomicAdd(stat + kStatShadow, rs);
+    if (COUNT) {
+        const unsigned long long v = wave_sum_u64(visits), t = wave_sum_u64(tests);
+        if (__lane_id() == 0) {
+            atomicAdd(stat + kStatNodesShadow, v);
+            atomicAdd(stat + kStatTrisShadow, t);
+        }
+    }
+}
+
+// Point light k seen from P with shading normal ns: contribution
+// ((beta * fr) * I) * cos / r^2 and the shadow segment, or c = 0.
+__device__ __forceinline__ float point_light_slot(const DevScene &sc, uint32_t k, float Px, float Py,
+                                                  float Pz, float nsx, float nsy, float nsz,
+                                                  float beta, float fr, float4 &dir)
+{
+    const float4 L = sc.plights[k];
+    const float wx = L.x - Px, wy = L.y - Py, wz = L.z - Pz;
+    const float r2 = dot3f(wx, wy, wz, wx, wy, wz);
+    if (!(r2 > 0.0f)) return 0.0f;
+    const float rl = sqrtf(r2);
+    const float wix = wx / rl, wiy = wy / rl, wiz = wz / rl;
+    const float cx = dot3f(nsx, nsy, nsz, wix, wiy, wiz);
+    if (!(cx > 0.0f)) return 0.0f;
+    dir = make_float4(wix, wiy, wiz, rl * kShadowScale);
+    return (((beta * fr) * L.w) * cx) / r2;
+}
+
+// Shading of vertex `depth` for every queued ray: emission, next-event
+// estimation (area emitters picked in proportion to area * Le, uniform
+// point on the triangle; point lights), Russian roulette, cosine-weighted
+// continuation.  Emits compacted shadow entries and extension rays.
+__global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderParams rp, RayQueue qin,
+                                               const uint32_t *cnt_in, const float2 *hit,
+                                               RayQueue qout, uint32_t *cnt_out, ShadowQueue sq,
+                                               uint32_t *cnt_sh, uint32_t depth)
+{
+    const uint32_t n = *cnt_in;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float2 h = hit[i];
+        const uint32_t prim = fbits(h.y);
+        bool want_shadow = false, want_ext = false;
+        float Px = 0.0f, Py = 0.0f, Pz = 0.0f;
+        float nsx = 0.0f, nsy = 0.0f, nsz = 0.0f, beta = 0.0f, fr = 0.0f, beta_v = 0.0f;
+        float ndx = 0.0f, ndy = 0.0f, ndz = 0.0f;
+        float c0 = 0.0f;
+        float4 d0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        uint32_t pword = 0, ri = 0, inst = 0;
+        if (prim != kNoPrim) {
+            const float4 o = qin.o[i], d = qin.d[i];
+            pword = fbits(d.w);
+            inst = pword >> 31;
+            const uint32_t p = pword & ~kInstBit;
+            const uint32_t qq = fdiv(pc.div_bp, p);
+            const uint32_t s = p - qq * pc.bp;
+            const uint32_t ii = fdiv(pc.div_nA, qq);
+            const uint32_t a = qq - ii * pc.nA;
+            const uint32_t pixel = pc.act[a];
+            const uint32_t sample = pc.s0 + s;
+            ri = a * pc.rs_a + ii * pc.rs_i + s;
+            beta = o.w;
+            const float t = h.x;
+            Px = o.x + t * d.x;
+            Py = o.y + t * d.y;
+            Pz = o.z + t * d.z;
+            const float4 pr = inst ? sc.inst[1].prim[prim] : sc.inst[0].prim[prim];
+            const float2 mt = sc.mat[fbits(pr.w)];
+            const float alb = mt.x, Le = mt.y;
+            const float cosi = dot3f(pr.x, pr.y, pr.z, d.x, d.y, d.z);
+            nsx = cosi < 0.0f ? pr.x : -pr.x;
+            nsy = cosi < 0.0f ? pr.y : -pr.y;
+            nsz = cosi < 0.0f ? pr.z : -pr.z;
+            if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee)) pc.rad[ri] = pc.rad[ri] + beta * Le;
+            if (alb > 0.0f) {
+                const uint4 r0 = rng_block(rp, pixel, sample, inst, depth, 0);
+                fr = alb * kInvPi;
+                beta_v = beta;
+                if (rp.nee) {
+                    const uint32_t n_emit = inst ? sc.inst[1].n_emit : sc.inst[0].n_emit;
+                    if (n_emit > 0) {
+                        const float ul = u01(r0.x);
+                        const float *cdf = inst ? sc.inst[1].emit_cdf : sc.inst[0].emit_cdf;
+                        // first j with ul < cdf[j] (cdf is non-decreasing, last = 1)
+                        uint32_t lo = 0, hi = n_emit - 1;
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (ul < cdf[mid]) hi = mid; else lo = mid + 1;
+                        }
+                        const float4 *E = (inst ? sc.inst[1].emit : sc.inst[0].emit) + 4 * (size_t)lo;
+                        const float4 v0 = E[0], v1 = E[1], v2 = E[2], en = E[3];
+                        const float su = sqrtf(u01(r0.y));
+                        const float u2 = u01(r0.z);
+                        const float w0 = 1.0f - su, w1 = su * (1.0f - u2), w2 = su * u2;
+                        const float wx = ((w0 * v0.x + w1 * v1.x) + w2 * v2.x) - Px;
+                        const float wy = ((w0 * v0.y + w1 * v1.y) + w2 * v2.y) - Py;
+                        const float wz = ((w0 * v0.z + w1 * v1.z) + w2 * v2.z) - Pz;
+                        const float r2 = dot3f(wx, wy, wz, wx, wy, wz);
+                        if (r2 > 0.0f) {
+                            const float rl = sqrtf(r2);
+                            const float wix = wx / rl, wiy = wy / rl, wiz = wz / rl;
+                            const float cx = dot3f(nsx, nsy, nsz, wix, wiy, wiz);
+                            const float cy = -dot3f(en.x, en.y, en.z, wix, wiy, wiz);
+                            if (cx > 0.0f && cy > 0.0f) {
+                                const float S = inst ? sc.inst[1].emit_S : sc.inst[0].emit_S;
+                                c0 = ((((beta * fr) * cx) * cy) * S) / r2;
+                                d0 = make_float4(wix, wiy, wiz, rl * kShadowScale);
+                            }
+                        }
+                    }
+                    want_shadow = c0 > 0.0f;
+                    for (uint32_t k = 0; k < sc.n_plights; ++k) {
+                        float4 dk;
+                        want_shadow |= point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta, fr, dk) > 0.0f;
+                    }
+                }
+                bool cont = depth < rp.max_depth;
+                if (cont && depth >= rp.rr_start) {
+                    const float qs = fminf(1.0f, beta);
+                    if (u01(r0.w) >= qs) cont = false;
+                    else beta = beta / qs;
+                }
+                if (cont) {
+                    const uint4 r1 = rng_block(rp, pixel, sample, inst, depth, 1);
+                    const float e0 = u01(r1.x), e1 = u01(r1.y);
+                    const float rr = sqrtf(e0);
+                    const double ph = kTwoPi * (double)e1;
+                    const float cph = (float)cos(ph), sph = (float)sin(ph);
+                    const float lx = rr * cph, ly = rr * sph, lz = sqrtf(fmaxf(0.0f, 1.0f - e0));
+                    // Orthonormal basis around ns (Duff et al. 2017).
+                    const float sg = copysignf(1.0f, nsz);
+                    const float aa = -1.0f / (sg + nsz);
+                    const float bb = (nsx * nsy) * aa;
+                    const float tx = 1.0f + ((sg * nsx) * nsx) * aa, ty = sg * bb, tz = (-sg) * nsx;
+                    const float bx = bb, by = sg + (nsy * nsy) * aa, bz = -nsy;
+                    ndx = (tx * lx + bx * ly) + nsx * lz;
+                    ndy = (ty * lx + by * ly) + nsy * lz;
+                    ndz = (tz * lx + bz * ly) + nsz * lz;
+                    beta = beta * alb;
+                    want_ext = true;
+                }
+            }
+        }
+        const uint32_t se = wave_append(want_shadow, cnt_sh);
+        if (want_shadow) {
+            sq.o[se] = make_float4(Px, Py, Pz, bitsf(ri));
+            sq.meta[se] = prim | (inst << 31);
+            sq.c[se] = c0;
+            if (c0 > 0.0f) sq.dir[se] = d0;
+            for (uint32_t k = 0; k < sc.n_plights; ++k) {
+                float4 dk = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float ck = point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta_v, fr, dk);
+                sq.c[(k + 1) * sq.cap + se] = ck;
+                if (ck > 0.0f) sq.dir[(k + 1) * sq.cap + se] = dk;
+            }
+        }
+        const uint32_t xe = wave_append(want_ext, cnt_out);
+        if (want_ext) {
+            qout.o[xe] = make_float4(Px, Py, Pz, beta);
+            qout.d[xe] = make_float4(ndx, ndy, ndz, bitsf(pword));
+            qout.skip[xe] = prim;
+        }
+    }
+}
+
+// Pairwise mini-batch mean (FP32) of mb consecutive path radiances.
+__device__ __forceinline__ float minibatch_mean(const float *v, uint32_t mb)
+{
+    if (mb == 1) return v[0];
+    if (mb == 2) return (v[0] + v[1]) * 0.5f;
+    if (mb == 4) return ((v[0] + v[1]) + (v[2] + v[3])) * 0.25f;
+    return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) * 0.125f;
+}
+
+// Welford update of (count, mean, M2) with x = ln(Y + eps) for each
+// mini-batch of the piece, in sample order; one thread per (pixel, instant).
+__global__ void k_accumulate(Piece pc, RenderParams rp, uint32_t *wf_n, double *wf_mean,
+                             double *wf_m2, double *wf_ysum)
+{
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= pc.nA * pc.n_inst) return;
+    const uint32_t ii = g / pc.nA;
+    const uint32_t a = g - ii * pc.nA;
+    const uint32_t pixel = pc.act[a];
+    const uint32_t slot = 2 * pixel + pc.inst_base + ii;
+    uint32_t n = wf_n[slot];
+    double mean = wf_mean[slot], m2 = wf_m2[slot], ys = wf_ysum[slot];
+    const float *src = pc.rad + a * pc.rs_a + ii * pc.rs_i;
+    const uint32_t mb = rp.minibatch;
+    for (uint32_t k = 0; k < pc.bp; k += mb) {
+        const float Y = minibatch_mean(src + k, mb);
+        const double x = log((double)Y + rp.log_eps);
+        n += 1;
+        const double delta = x - mean;
+        mean = mean + delta / (double)n;
+        m2 = m2 + delta * (x - mean);
+        ys = ys + (double)Y;
+    }
+    wf_n[slot] = n;
+    wf_mean[slot] = mean;
+    wf_m2[slot] = m2;
+    wf_ysum[slot] = ys;
+}
+
+// Eq. 7 with N = samples at the second instant; zero variance gives -inf,
+// +inf or 0 by the sign of |gap| - C.
+__device__ __forceinline__ double t_value(double mean0, double var0, double mean1, double var1,
+                                          uint32_t m1, double C)
+{
+    const double gap = fabs(mean1 - mean0) - C;
+    const double S = var0 + var1;
+    if (S == 0.0) return gap < 0.0 ? -INFINITY : (gap > 0.0 ? INFINITY : 0.0);
+    return gap / sqrt(S / (double)m1);
+}
+
+// Decision after a round for every active pixel; finished pixels write
+// their outputs, the rest are compacted into act_out.
+__global__ __launch_bounds__(256) void k_decide_compact(Decide dc, const uint32_t *act_in, uint32_t nA,
+                                                        uint32_t *act_out, uint32_t *cnt,
+                                                        const uint32_t *wf_n, const double *wf_mean,
+                                                        const double *wf_m2, const double *wf_ysum,
+                                                        Outputs out)
+{
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    // The other round counter is free now: clear it for the next round.
+    if (a == 0) cnt[kCntActive + (dc.cnt_slot ^ 1u)] = 0;
+    if (a >= nA) return;
+    const uint32_t pixel = act_in[a];
+    const uint32_t m0 = wf_n[2 * pixel], m1 = wf_n[2 * pixel + 1];
+    const double mean0 = wf_mean[2 * pixel], mean1 = wf_mean[2 * pixel + 1];
+    const double var0 = m0 > 1 ? wf_m2[2 * pixel] / (double)(m0 - 1) : 0.0;
+    const double var1 = m1 > 1 ? wf_m2[2 * pixel + 1] / (double)(m1 - 1) : 0.0;
+    const double t = t_value(mean0, var0, mean1, var1, m1, dc.C);
+    const double gap = mean1 - mean0;
+    bool stop = false;
+    if (!dc.final_round) {
+        if (dc.mode == 0) stop = t < dc.crit_lo;
+        else if (dc.mode == 2) stop = t < dc.crit_lo || t > dc.crit_hi;
+        else if (dc.mode == 3) stop = fabs(gap) <= dc.C;
+    }
+    const bool done = stop || dc.final_round;
+    if (done) {
+        out.polarity[pixel] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
+        out.n_paths[pixel] = m1 * dc.minibatch;
+        out.mean[2 * pixel] = mean0;
+        out.mean[2 * pixel + 1] = mean1;
+        out.var[2 * pixel] = var0;
+        out.var[2 * pixel + 1] = var1;
+        if (out.t_last) out.t_last[pixel] = t;
+        if (out.mean_radiance) {
+            out.mean_radiance[2 * pixel] = wf_ysum[2 * pixel] / (double)m0;
+            out.mean_radiance[2 * pixel + 1] = wf_ysum[2 * pixel + 1] / (double)m1;
+        }
+        if (out.flags) out.flags[pixel] = stop ? 1 : 0;
+    }
+    const uint32_t slot = wave_append(!done, cnt + kCntActive + dc.cnt_slot);
+    if (!done) act_out[slot] = pixel;
+}
+
+// Caller rays -> queue format for the trace hook.
+__global__ void k_hook_rays(uint32_t n, const float *rays, const uint32_t *skip, RayQueue q,
+                            float *tminmax, uint32_t *cnt)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) cnt[0] = n;
+    if (i >= n) return;
+    const float *r = rays + 8 * (size_t)i;
+    q.o[i] = make_float4(r[0], r[1], r[2], 1.0f);
+    q.d[i] = make_float4(r[4], r[5], r[6], bitsf(i));
+    q.skip[i] = skip ? skip[i] : kNoPrim;
+    tminmax[2 * i] = r[3];
+    tminmax[2 * i + 1] = r[7];
+}
+
+// Trace hook: arbitrary (tmin, tmax) per ray, instant slot 0.
+template <bool ANY>
+__global__ __launch_bounds__(kTB) void k_hook_trace(DevScene sc, RayQueue q, const float *tminmax,
+                                                    uint32_t n, float *t_out, uint32_t *p_out)
+{
+    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ uint32_t s_stack[kStackLds * kTB];
+    load_treelets(sc, s_nodes);
+    uint32_t visits = 0, tests = 0;
+    for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
+        const float4 o = q.o[i], d = q.d[i];
+        const InstSel is = select_inst(sc, 0);
+        const TRay r = make_tray(o.x, o.y, o.z, d.x, d.y, d.z);
+        float bt;
+        uint32_t bp;
+        const bool h = traverse<ANY, false>(is, s_nodes, s_stack + threadIdx.x, r, tminmax[2 * i],
+                                            tminmax[2 * i + 1], q.skip[i], bt, bp, visits, tests);
+        if (ANY) {
+            p_out[i] = h ? 1u : 0u;
+        } else {
+            if (t_out) t_out[i] = bt;
+            p_out[i] = bp;
+        }
+    }
+}
+
+// Decision hook: Welford over caller samples, then the decision kernel's
+// arithmetic.
+__global__ void k_hook_decide(const double *x0, const double *x1, uint32_t n, uint32_t m, Decide dc,
+                              double *t_out, uint8_t *stop_out, int8_t *pol_out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double mean[2], var[2];
+    for (int s = 0; s < 2; ++s) {
+        const double *x = (s ? x1 : x0) + (size_t)i * m;
+        double mu = 0.0, m2 = 0.0;
+        for (uint32_t k = 0; k < m; ++k) {
+            const double delta = x[k] - mu;
+            mu = mu + delta / (double)(k + 1);
+            m2 = m2 + delta * (x[k] - mu);
+        }
+        mean[s] = mu;
+        var[s] = m2 / (double)(m - 1);
+    }
+    const double t = t_value(mean[0], var[0], mean[1], var[1], m, dc.C);
+    const double gap = mean[1] - mean[0];
+    bool stop = false;
+    if (dc.mode == 0) stop = t < dc.crit_lo;
+    else if (dc.mode == 2) stop = t < dc.crit_lo || t > dc.crit_hi;
+    else if (dc.mode == 3) stop = fabs(gap) <= dc.C;
+    t_out[i] = t;
+    stop_out[i] = stop ? 1 : 0;
+    pol_out[i] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// Launch wrappers.
+
+void launch_init_frame(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                       double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat)
+{
+    const uint32_t n = 2 * npx;
+    hipLaunchKernelGGL(k_init_frame, dim3(std::max(1u, (n + 255) / 256)), dim3(256), 0, s, npx, wf_n,
+                       wf_mean, wf_m2, wf_ysum, act, cnt, stat);
+}
+
+void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const RenderParams &rp,
+                   const RayQueue &q, uint32_t *cnt)
+{
+    hipLaunchKernelGGL(k_raygen, dim3((pc.n_paths + 255) / 256), dim3(256), 0, s, pc, sc, rp, q, cnt);
+}
+
+void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
+                          const RayQueue &q, const uint32_t *cnt_in, float2 *hit, int stat_kind,
+                          unsigned long long *stat)
+{
+    if (count)
+        hipLaunchKernelGGL(k_trace_closest<true>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, hit,
+                           stat_kind, stat);
+    else
+        hipLaunchKernelGGL(k_trace_closest<false>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, hit,
+                           stat_kind, stat);
+}
+
+void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
+                         const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, float *rad,
+                         unsigned long long *stat)
+{
+    if (count)
+        hipLaunchKernelGGL(k_trace_shadow<true>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
+                           rad, stat);
+    else
+        hipLaunchKernelGGL(k_trace_shadow<false>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
+                           rad, stat);
+}
+
+void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
+                  const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
+                  const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
+                  uint32_t *cnt_sh, uint32_t depth)
+{
+    hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(256), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
+                       cnt_out, sq, cnt_sh, depth);
+}
+
+void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
+                       double *wf_mean, double *wf_m2, double *wf_ysum)
+{
+    const uint32_t n = pc.nA * pc.n_inst;
+    hipLaunchKernelGGL(k_accumulate, dim3((n + 255) / 256), dim3(256), 0, s, pc, rp, wf_n, wf_mean,
+                       wf_m2, wf_ysum);
+}
+
+void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_in, uint32_t nA,
+                           uint32_t *act_out, uint32_t *cnt, const uint32_t *wf_n,
+                           const double *wf_mean, const double *wf_m2, const double *wf_ysum,
+                           const Outputs &out)
+{
+    hipLaunchKernelGGL(k_decide_compact, dim3((nA + 255) / 256), dim3(256), 0, s, dc, act_in, nA,
+                       act_out, cnt, wf_n, wf_mean, wf_m2, wf_ysum, out);
+}
+
+void launch_hook_rays(hipStream_t s, uint32_t n, const float *rays, const uint32_t *skip,
+                      const RayQueue &q, float *tminmax, uint32_t *cnt)
+{
+    hipLaunchKernelGGL(k_hook_rays, dim3((n + 255) / 256), dim3(256), 0, s, n, rays, skip, q, tminmax,
+                       cnt);
+}
+
+void launch_hook_trace(hipStream_t s, uint32_t blocks, bool any, const DevScene &sc, const RayQueue &q,
+                       const float *tminmax, uint32_t n, float *t_out, uint32_t *p_out)
+{
+    if (any)
+        hipLaunchKernelGGL(k_hook_trace<true>, dim3(blocks), dim3(kTB), 0, s, sc, q, tminmax, n, t_out,
+                           p_out);
+    else
+        hipLaunchKernelGGL(k_hook_trace<false>, dim3(blocks), dim3(kTB), 0, s, sc, q, tminmax, n, t_out,
+                           p_out);
+}
+
+void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint32_t n, uint32_t m,
+                        const Decide &dc, double *t_out, uint8_t *stop_out, int8_t *pol_out)
+{
+    hipLaunchKernelGGL(k_hook_decide, dim3((n + 255) / 256), dim3(256), 0, s, x0, x1, n, m, dc, t_out,
+                       stop_out, pol_out);
+}
+
+void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu)
+{
+    int a = 0, b = 0, c = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_trace_closest<false>, kTB, 0) != hipSuccess) a = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace_shadow<false>, kTB, 0) != hipSuccess) b = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade, 256, 0) != hipSuccess) c = 1;
+    *trace_blocks_per_cu = std::max(1, std::min(a, b));
+    *shade_blocks_per_cu = std::max(1, c);
+}
+
+int traverse_block_threads() { return kTB; }
+int lds_treelet_nodes() { return kLdsNodes; }
+int traverse_max_depth() { return kStackMax; }
+
+}  // namespace evrt

@@ -1,0 +1,427 @@
+// render.cpp -- host scheduler of the adaptive event renderer.
+//
+// One event frame (Algorithm 1 for one pair of instants): all pixels start
+// active; each round traces the next sample range of every active pixel
+// (split into pieces that bound the paths in flight), accumulates the
+// mini-batch log-luminance, then runs the decision kernel, which writes the
+// outputs of finished pixels and compacts the rest into the next active
+// list.  The active count is read back once per round.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "evrt_host.h"
+
+namespace evrt {
+
+static constexpr uint32_t kDefaultRayBatch = 1u << 22;
+static constexpr uint32_t kMaxPathId = 1u << 31;
+static constexpr size_t kCacheInstants = 4;
+
+std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s, double *ms_build)
+{
+    auto it = c->cache.find(t);
+    if (it != c->cache.end()) return it->second;
+    const auto t_start = std::chrono::steady_clock::now();
+    auto bi = std::make_shared<DevInstantBufs>();
+    HostInstant &h = bi->host;
+    build_world(c->scene, t, h);
+    const float pad = bvh_padding(c->scene, h, h);
+    build_bvh(h, (uint32_t)lds_treelet_nodes(), pad);
+    bi->nodes.upload(h.nodes.data(), h.nodes.size() * sizeof(float4), s);
+    bi->tris.upload(h.tris.data(), h.tris.size() * sizeof(float4), s);
+    bi->prim.upload(h.prim.data(), h.prim.size() * sizeof(float4), s);
+    bi->emit_cdf.upload(h.emit_cdf.data(), h.emit_cdf.size() * sizeof(float), s);
+    std::vector<float4> emit(4 * h.emit_prim.size());
+    for (size_t j = 0; j < h.emit_prim.size(); ++j) {
+        const uint32_t p = h.emit_prim[j];
+        const float *v = &h.tri[9 * (size_t)p];
+        emit[4 * j + 0] = make_float4(v[0], v[1], v[2], 0.0f);
+        emit[4 * j + 1] = make_float4(v[3], v[4], v[5], 0.0f);
+        emit[4 * j + 2] = make_float4(v[6], v[7], v[8], 0.0f);
+        float pw;
+        std::memcpy(&pw, &p, 4);
+        emit[4 * j + 3] = make_float4(h.prim[p].x, h.prim[p].y, h.prim[p].z, pw);
+    }
+    bi->emit.upload(emit.data(), emit.size() * sizeof(float4), s);
+    hip_check(hipStreamSynchronize(s), "geometry upload");
+    DevInstant &v = bi->view;
+    v.nodes = bi->nodes.as<const float4>();
+    v.tris = bi->tris.as<const float4>();
+    v.prim = bi->prim.as<const float4>();
+    v.emit_cdf = bi->emit_cdf.as<const float>();
+    v.emit = bi->emit.as<const float4>();
+    v.root = h.root;
+    v.n_nodes = (uint32_t)(h.nodes.size() / 4);
+    v.n_lds = h.n_lds;
+    v.n_emit = (uint32_t)h.emit_prim.size();
+    v.emit_S = h.emit_S;
+    v.cam = h.cam;
+    // Keep only the world triangles needed for statistics; drop the rest.
+    h.nodes.shrink_to_fit();
+    if (c->cache.size() >= kCacheInstants) {
+        const double victim = c->cache_order.front();
+        c->cache_order.erase(c->cache_order.begin());
+        c->cache.erase(victim);
+    }
+    c->cache[t] = bi;
+    c->cache_order.push_back(t);
+    if (ms_build)
+        *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return bi;
+}
+
+DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b)
+{
+    DevScene sc{};
+    sc.inst[0] = a.view;
+    sc.inst[1] = b.view;
+    sc.mat = c->mat.as<const float2>();
+    sc.plights = c->plights.as<const float4>();
+    sc.n_plights = (uint32_t)c->scene.pl_int.size();
+    sc.width = c->scene.cam.width;
+    sc.height = c->scene.cam.height;
+    sc.div_w = make_fastdiv(sc.width);
+    return sc;
+}
+
+static RenderParams make_params(const evrt_ctx *c, const evrt_render_opts &o)
+{
+    RenderParams rp{};
+    rp.key0 = (uint32_t)(o.seed & 0xffffffffu);
+    rp.key1 = (uint32_t)(o.seed >> 32);
+    rp.max_depth = o.max_depth;
+    rp.rr_start = o.rr_start_depth;
+    rp.nee = o.nee;
+    rp.jitter = o.jitter;
+    rp.minibatch = o.minibatch;
+    rp.n_slots = 1 + (uint32_t)c->scene.pl_int.size();
+    rp.log_eps = o.log_eps;
+    return rp;
+}
+
+// Device work buffers sized for `cap` paths in flight and npx pixels.
+static void ensure_buffers(evrt_ctx *c, uint32_t npx, uint32_t cap, uint32_t slots)
+{
+    FrameBuffers &fb = c->fb;
+    fb.wf_n.ensure(sizeof(uint32_t) * 2 * (size_t)npx);
+    fb.wf_mean.ensure(sizeof(double) * 2 * (size_t)npx);
+    fb.wf_m2.ensure(sizeof(double) * 2 * (size_t)npx);
+    fb.wf_ysum.ensure(sizeof(double) * 2 * (size_t)npx);
+    fb.act0.ensure(sizeof(uint32_t) * (size_t)npx);
+    fb.act1.ensure(sizeof(uint32_t) * (size_t)npx);
+    fb.cnt.ensure(sizeof(uint32_t) * kCntSize);
+    fb.stat.ensure(sizeof(unsigned long long) * kStatCount);
+    if (cap > fb.queue_cap || slots > fb.shadow_slots) {
+        const uint32_t ncap = std::max(cap, fb.queue_cap);
+        const uint32_t nsl = std::max(slots, fb.shadow_slots);
+        for (int k = 0; k < 2; ++k) {
+            fb.q_o[k].ensure(sizeof(float4) * (size_t)ncap);
+            fb.q_d[k].ensure(sizeof(float4) * (size_t)ncap);
+            fb.q_skip[k].ensure(sizeof(uint32_t) * (size_t)ncap);
+        }
+        fb.hit.ensure(sizeof(float2) * (size_t)ncap);
+        fb.sh_o.ensure(sizeof(float4) * (size_t)ncap);
+        fb.sh_meta.ensure(sizeof(uint32_t) * (size_t)ncap);
+        // Slot-major shadow arrays: their stride is the capacity, so they are
+        // reallocated whenever the capacity changes.
+        fb.sh_dir.ensure(sizeof(float4) * (size_t)ncap * nsl);
+        fb.sh_c.ensure(sizeof(float) * (size_t)ncap * nsl);
+        fb.rad.ensure(sizeof(float) * (size_t)ncap);
+        fb.queue_cap = ncap;
+        fb.shadow_slots = nsl;
+    }
+}
+
+static uint32_t blocks_for(uint32_t per_cu, uint32_t cu, uint32_t work, uint32_t tb)
+{
+    const uint32_t need = (work + tb - 1) / tb;
+    const uint32_t fill = std::max(1u, per_cu * cu);
+    return std::max(1u, std::min(need, fill));
+}
+
+struct Profiler {
+    evrt_ctx *c;
+    bool on;
+    size_t used = 0;
+    std::vector<int> kind;  // 0 closest, 1 shadow
+    hipStream_t s;
+    void begin(int k)
+    {
+        if (!on) return;
+        if (used == c->events.size()) {
+            EventPair e;
+            hip_check(hipEventCreate(&e.a), "hipEventCreate");
+            hip_check(hipEventCreate(&e.b), "hipEventCreate");
+            c->events.push_back(e);
+        }
+        kind.push_back(k);
+        hip_check(hipEventRecord(c->events[used].a, s), "hipEventRecord");
+    }
+    void end()
+    {
+        if (!on) return;
+        hip_check(hipEventRecord(c->events[used].b, s), "hipEventRecord");
+        ++used;
+    }
+    void collect(evrt_frame_stats &st)
+    {
+        for (size_t i = 0; i < used; ++i) {
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, c->events[i].a, c->events[i].b), "hipEventElapsedTime");
+            if (kind[i] == 0) st.ms_closest += ms;
+            else st.ms_shadow += ms;
+        }
+    }
+};
+
+// Traces one piece: camera rays, max_depth bounces of closest hit + shade
+// + shadow rays.  Path radiances land in pc.rad.
+static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const RenderParams &rp,
+                        const evrt_render_opts &o, hipStream_t s, Profiler &prof)
+{
+    FrameBuffers &fb = c->fb;
+    uint32_t *cnt = fb.cnt.as<uint32_t>();
+    unsigned long long *stat = fb.stat.as<unsigned long long>();
+    RayQueue q[2];
+    for (int k = 0; k < 2; ++k) q[k] = RayQueue{fb.q_o[k].as<float4>(), fb.q_d[k].as<float4>(), fb.q_skip[k].as<uint32_t>()};
+    ShadowQueue sq{fb.sh_o.as<float4>(), fb.sh_meta.as<uint32_t>(), fb.sh_dir.as<float4>(), fb.sh_c.as<float>(),
+                   fb.queue_cap};
+    launch_raygen(s, pc, sc, rp, q[0], cnt);
+    const uint32_t tb = (uint32_t)traverse_block_threads();
+    const uint32_t tblocks = blocks_for(c->trace_blocks_per_cu, c->cu_count, pc.n_paths, tb);
+    const uint32_t sblocks = blocks_for(c->shade_blocks_per_cu, c->cu_count, pc.n_paths, 256);
+    const bool count = o.count_work != 0;
+    for (uint32_t d = 1; d <= rp.max_depth; ++d) {
+        const RayQueue &qin = q[(d - 1) & 1];
+        const RayQueue &qout = q[d & 1];
+        prof.begin(0);
+        launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + d - 1, fb.hit.as<float2>(),
+                             d == 1 ? kStatCamera : kStatExtension, stat);
+        prof.end();
+        c->stats.n_closest_launches++;
+        launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + d - 1, fb.hit.as<float2>(), qout,
+                     cnt + kCntRay0 + d, sq, cnt + kCntShadow0 + d, d);
+        if (rp.nee) {
+            prof.begin(1);
+            launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + d, pc.rad, stat);
+            prof.end();
+            c->stats.n_shadow_launches++;
+        }
+    }
+    c->stats.pieces++;
+    c->stats.paths += pc.n_paths;
+}
+
+static double crit_value(evrt_ctx *c, double p, uint32_t df)
+{
+    uint64_t bits;
+    std::memcpy(&bits, &p, 8);
+    auto key = std::make_pair(bits, df);
+    auto it = c->crit_cache.find(key);
+    if (it != c->crit_cache.end()) return it->second;
+    const double q = t_quantile(p, df);
+    c->crit_cache[key] = q;
+    return q;
+}
+
+// Pieces covering samples [lo, hi) of nA pixels at n_inst instants.
+static void trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t n_inst, uint32_t inst_base,
+                        uint32_t lo, uint32_t hi, const DevScene &sc, const RenderParams &rp,
+                        const evrt_render_opts &o, hipStream_t s, Profiler &prof)
+{
+    const uint32_t mb = rp.minibatch;
+    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    const uint64_t per_sample = (uint64_t)nA * n_inst;
+    uint64_t bp_max = std::max<uint64_t>(mb, (batch / std::max<uint64_t>(1, per_sample)) / mb * mb);
+    bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / per_sample / mb * mb);
+    if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many pixels for one piece");
+    for (uint32_t s0 = lo; s0 < hi;) {
+        const uint32_t bp = (uint32_t)std::min<uint64_t>(bp_max, hi - s0);
+        Piece pc{};
+        pc.act = act;
+        pc.nA = nA;
+        pc.bp = bp;
+        pc.n_inst = n_inst;
+        pc.inst_base = inst_base;
+        pc.s0 = s0;
+        pc.n_paths = (uint32_t)(per_sample * bp);
+        pc.div_bp = make_fastdiv(bp);
+        pc.div_nA = make_fastdiv(nA);
+        pc.rs_a = bp;
+        pc.rs_i = nA * bp;
+        ensure_buffers(c, sc.width * sc.height, pc.n_paths, rp.n_slots);
+        pc.rad = c->fb.rad.as<float>();
+        trace_piece(c, pc, sc, rp, o, s, prof);
+        launch_accumulate(s, pc, rp, c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
+                          c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>());
+        s0 += bp;
+    }
+}
+
+static void read_stats(evrt_ctx *c, hipStream_t s)
+{
+    hip_check(hipMemcpyAsync(c->h_stat, c->fb.stat.ptr, sizeof(unsigned long long) * kStatCount,
+                             hipMemcpyDeviceToHost, s),
+              "stat readback");
+    hip_check(hipStreamSynchronize(s), "stat readback");
+    c->stats.camera_rays = c->h_stat[kStatCamera];
+    c->stats.extension_rays = c->h_stat[kStatExtension];
+    c->stats.shadow_rays = c->h_stat[kStatShadow];
+    c->stats.node_visits = c->h_stat[kStatNodes];
+    c->stats.tri_tests = c->h_stat[kStatTris];
+    c->stats.node_visits_shadow = c->h_stat[kStatNodesShadow];
+    c->stats.tri_tests_shadow = c->h_stat[kStatTrisShadow];
+}
+
+void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
+                  uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o,
+                  const evrt_frame_out &out, hipStream_t s)
+{
+    const auto wall0 = std::chrono::steady_clock::now();
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
+    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    const DevScene sc = make_dev_scene(c, *ga, *gb);
+    const RenderParams rp = make_params(c, o);
+    const uint32_t npx = sc.width * sc.height;
+    const uint32_t mb = o.minibatch;
+    // Largest piece of the frame: round 0 (every pixel, both instants).
+    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    const uint64_t all = 2ull * npx * spp_max, floor_piece = 2ull * npx * mb;
+    const uint64_t cap = std::max<uint64_t>(std::min<uint64_t>(batch, all), floor_piece);
+    if (cap >= kMaxPathId) fail(EVRT_E_UNSUPPORTED, "image too large for one mini-batch piece");
+    ensure_buffers(c, npx, (uint32_t)cap, rp.n_slots);
+    FrameBuffers &fb = c->fb;
+    launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
+                      fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
+                      fb.stat.as<unsigned long long>());
+    Profiler prof{c, o.profile != 0, 0, {}, s};
+
+    const bool fixed = o.mode == EVRT_MODE_FIXED;
+    const bool ref_full = o.ref_mode == EVRT_REF_FULL;
+    uint32_t *act_in = fb.act0.as<uint32_t>();
+    uint32_t *act_out = fb.act1.as<uint32_t>();
+    uint32_t nA = npx;
+    if (ref_full) {
+        // The first instant at the full count for every pixel.
+        trace_range(c, act_in, nA, 1, 0, 0, spp_max, sc, rp, o, s, prof);
+    }
+    const uint32_t n_inst = ref_full ? 1 : 2;
+    const uint32_t inst_base = ref_full ? 1 : 0;
+    uint32_t n_prev = 0;
+    uint32_t n = fixed ? spp_max : spp_init;
+    Outputs outs{out.polarity, out.n_paths, out.mean, out.var, out.t_last, out.mean_radiance, out.flags};
+    for (uint32_t r = 0;; ++r) {
+        trace_range(c, act_in, nA, n_inst, inst_base, n_prev, n, sc, rp, o, s, prof);
+        const uint32_t m1 = n / mb;
+        const uint32_t m0 = ref_full ? spp_max / mb : m1;
+        Decide dc{};
+        dc.C = (double)C;
+        dc.mode = o.mode;
+        dc.minibatch = mb;
+        dc.final_round = n >= spp_max ? 1u : 0u;
+        dc.cnt_slot = r & 1u;
+        const uint32_t df = m0 + m1 - 2;
+        if (!dc.final_round) {
+            if (o.mode == EVRT_MODE_ADAPTIVE_1T) {
+                dc.crit_lo = crit_value(c, (double)alpha, df);
+            } else if (o.mode == EVRT_MODE_ADAPTIVE_2T) {
+                dc.crit_lo = crit_value(c, 0.5 * (double)alpha, df);
+                dc.crit_hi = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
+            }
+        }
+        launch_decide_compact(s, dc, act_in, nA, act_out, fb.cnt.as<uint32_t>(), fb.wf_n.as<uint32_t>(),
+                              fb.wf_mean.as<double>(), fb.wf_m2.as<double>(), fb.wf_ysum.as<double>(), outs);
+        hip_check(hipMemcpyAsync(c->h_pinned, fb.cnt.as<uint32_t>() + kCntActive + dc.cnt_slot, sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, s),
+                  "active count readback");
+        hip_check(hipStreamSynchronize(s), "round");
+        const uint32_t next = c->h_pinned[0];
+        if (r < 64) c->stats.active_after_round[r] = next;
+        c->stats.rounds = r + 1;
+        std::swap(act_in, act_out);
+        nA = next;
+        if (nA == 0 || dc.final_round) break;
+        n_prev = n;
+        n = std::min(n + spp_batch, spp_max);
+    }
+    read_stats(c, s);
+    prof.collect(c->stats);
+    c->stats.ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+}
+
+void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const uint32_t *pixels,
+                  uint32_t spp, const evrt_render_opts &o, float *L_out, hipStream_t s)
+{
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
+    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    const DevScene sc = make_dev_scene(c, *ga, *gb);
+    const RenderParams rp = make_params(c, o);
+    const uint32_t npx = sc.width * sc.height;
+    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    const uint64_t per_px = 2ull * spp;
+    const uint32_t chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_pixels, batch / per_px));
+    ensure_buffers(c, npx, (uint32_t)std::min<uint64_t>((uint64_t)chunk * per_px, kMaxPathId - 1), rp.n_slots);
+    launch_init_frame(s, 0, nullptr, nullptr, nullptr, nullptr, nullptr, c->fb.cnt.as<uint32_t>(),
+                      c->fb.stat.as<unsigned long long>());
+    Profiler prof{c, false, 0, {}, s};
+    for (uint32_t a0 = 0; a0 < n_pixels; a0 += chunk) {
+        const uint32_t na = std::min(chunk, n_pixels - a0);
+        Piece pc{};
+        pc.act = pixels + a0;
+        pc.nA = na;
+        pc.bp = spp;
+        pc.n_inst = 2;
+        pc.inst_base = 0;
+        pc.s0 = 0;
+        pc.n_paths = (uint32_t)(per_px * na);
+        pc.div_bp = make_fastdiv(spp);
+        pc.div_nA = make_fastdiv(na);
+        pc.rad = L_out + (size_t)a0 * per_px;  // [pixel][instant][sample]
+        pc.rs_a = 2 * spp;
+        pc.rs_i = spp;
+        trace_piece(c, pc, sc, rp, o, s, prof);
+    }
+    read_stats(c, s);
+}
+
+void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip, int any,
+                float *t_out, uint32_t *p_out, hipStream_t s)
+{
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto g = get_instant(c, t, s, &c->stats.ms_build);
+    const DevScene sc = make_dev_scene(c, *g, *g);
+    ensure_buffers(c, sc.width * sc.height, n, 1);
+    FrameBuffers &fb = c->fb;
+    fb.hook_tm.ensure(sizeof(float) * 2 * (size_t)n);
+    RayQueue q{fb.q_o[0].as<float4>(), fb.q_d[0].as<float4>(), fb.q_skip[0].as<uint32_t>()};
+    launch_hook_rays(s, n, rays, skip, q, fb.hook_tm.as<float>(), fb.cnt.as<uint32_t>());
+    const uint32_t tb = (uint32_t)traverse_block_threads();
+    launch_hook_trace(s, blocks_for(c->trace_blocks_per_cu, c->cu_count, n, tb), any != 0, sc, q,
+                      fb.hook_tm.as<float>(), n, t_out, p_out);
+    hip_check(hipStreamSynchronize(s), "trace hook");
+}
+
+void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
+                  float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
+                  hipStream_t s)
+{
+    Decide dc{};
+    dc.C = (double)C;
+    dc.mode = mode;
+    dc.minibatch = 1;
+    const uint32_t df = 2 * m - 2;
+    if (mode == EVRT_MODE_ADAPTIVE_1T) {
+        dc.crit_lo = crit_value(c, (double)alpha, df);
+    } else if (mode == EVRT_MODE_ADAPTIVE_2T) {
+        dc.crit_lo = crit_value(c, 0.5 * (double)alpha, df);
+        dc.crit_hi = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
+    }
+    launch_hook_decide(s, x0, x1, n, m, dc, t_out, stop_out, pol_out);
+    hip_check(hipStreamSynchronize(s), "decide hook");
+}
+
+}  // namespace evrt

@@ -1,0 +1,539 @@
+// scene.cpp -- host construction of the scene at an instant: FP64
+// keyframe interpolation of instances and camera, FP32 world triangles,
+// per-primitive normals, the emitter table for next-event estimation, and
+// a binned-SAH BVH2 whose top treelet is laid out first for LDS staging.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "evrt_host.h"
+
+namespace evrt {
+
+// Interpolation of keyed values: first key before the first key time, last
+// key after the last, else v_k + w (v_{k+1} - v_k), w = (t - t_k) /
+// (t_{k+1} - t_k), entry by entry in FP64.
+static void keyed(const std::vector<double> &kt, const std::vector<double> &kv, size_t width,
+                  double t, double *out)
+{
+    const size_t nk = kt.size();
+    if (nk == 1 || t <= kt[0]) {
+        std::memcpy(out, kv.data(), sizeof(double) * width);
+        return;
+    }
+    if (t >= kt[nk - 1]) {
+        std::memcpy(out, kv.data() + (nk - 1) * width, sizeof(double) * width);
+        return;
+    }
+    size_t k = 0;
+    while (!(t < kt[k + 1])) ++k;
+    const double w = (t - kt[k]) / (kt[k + 1] - kt[k]);
+    const double *a = kv.data() + k * width;
+    const double *b = a + width;
+    for (size_t e = 0; e < width; ++e) out[e] = a[e] + w * (b[e] - a[e]);
+}
+
+static inline uint32_t f2u(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    return u;
+}
+
+static inline float u2f(uint32_t u)
+{
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+void build_world(const SceneDesc &sd, double t, HostInstant &h)
+{
+    size_t nt = 0;
+    for (const auto &in : sd.instances) nt += sd.meshes[in.mesh].mat.size();
+    h.tri.assign(9 * nt, 0.0f);
+    h.prim.assign(nt, make_float4(0, 0, 0, 0));
+    h.area.assign(nt, 0.0f);
+    size_t p = 0;
+    for (const auto &in : sd.instances) {
+        const MeshDesc &m = sd.meshes[in.mesh];
+        double M[12];
+        keyed(in.kt, in.kx, 12, t, M);
+        for (size_t tr = 0; tr < m.mat.size(); ++tr, ++p) {
+            float *v = &h.tri[9 * p];
+            for (int c = 0; c < 3; ++c) {
+                const float *src = &m.xyz[3 * (size_t)m.idx[3 * tr + c]];
+                const double x = src[0], y = src[1], z = src[2];
+                for (int r = 0; r < 3; ++r) {
+                    const double *row = M + 4 * r;
+                    v[3 * c + r] = (float)(((row[0] * x + row[1] * y) + row[2] * z) + row[3]);
+                }
+            }
+            // Unit geometric normal and area, FP32: cross(v1 - v0, v2 - v0).
+            const float e1x = v[3] - v[0], e1y = v[4] - v[1], e1z = v[5] - v[2];
+            const float e2x = v[6] - v[0], e2y = v[7] - v[1], e2z = v[8] - v[2];
+            const float gx = e1y * e2z - e1z * e2y;
+            const float gy = e1z * e2x - e1x * e2z;
+            const float gz = e1x * e2y - e1y * e2x;
+            const float len = std::sqrt((gx * gx + gy * gy) + gz * gz);
+            float4 pr;
+            if (len == 0.0f) pr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            else pr = make_float4(gx / len, gy / len, gz / len, 0.0f);
+            pr.w = u2f(m.mat[tr]);
+            h.prim[p] = pr;
+            h.area[p] = 0.5f * len;
+        }
+    }
+
+    // Emitters in primitive order: w_j = A_j * Le_j (FP32), prefix sums and
+    // their total S in FP64, cdf_j = (float)(prefix_j / S), last entry 1.
+    h.emit_prim.clear();
+    h.emit_cdf.clear();
+    std::vector<double> pref;
+    double S = 0.0;
+    for (size_t q = 0; q < nt; ++q) {
+        const float le = sd.emission[f2u(h.prim[q].w)];
+        if (le > 0.0f) {
+            const float w = h.area[q] * le;
+            S += (double)w;
+            pref.push_back(S);
+            h.emit_prim.push_back((uint32_t)q);
+        }
+    }
+    for (double v : pref) h.emit_cdf.push_back((float)(v / S));
+    if (!h.emit_cdf.empty()) h.emit_cdf.back() = 1.0f;
+    h.emit_S = (float)S;
+
+    // Camera basis in FP64, rounded once to FP32.
+    double cam[9];
+    keyed(sd.cam.kt, sd.cam.elu, 9, t, cam);
+    double f[3] = {cam[3] - cam[0], cam[4] - cam[1], cam[5] - cam[2]};
+    const double fl = std::sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
+    f[0] = f[0] / fl; f[1] = f[1] / fl; f[2] = f[2] / fl;
+    const double *up = cam + 6;
+    double r[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    const double rl = std::sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+    r[0] = r[0] / rl; r[1] = r[1] / rl; r[2] = r[2] / rl;
+    const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    const double th = std::tan(sd.cam.vfov * (3.14159265358979323846 / 360.0));
+    for (int c = 0; c < 3; ++c) {
+        h.cam.eye[c] = (float)cam[c];
+        h.cam.fwd[c] = (float)f[c];
+        h.cam.right[c] = (float)r[c];
+        h.cam.up[c] = (float)u[c];
+    }
+    h.cam.sx = (float)(th * ((double)sd.cam.width / (double)sd.cam.height));
+    h.cam.sy = (float)th;
+}
+
+float bvh_padding(const SceneDesc &sd, const HostInstant &a, const HostInstant &b)
+{
+    // Box padding grows with the largest coordinate magnitude of geometry,
+    // camera and lights, far above the rounding of the fused slab test.
+    float mx = 0.0f;
+    for (float v : a.tri) mx = std::max(mx, std::fabs(v));
+    for (float v : b.tri) mx = std::max(mx, std::fabs(v));
+    for (int c = 0; c < 3; ++c) {
+        mx = std::max(mx, std::fabs(a.cam.eye[c]));
+        mx = std::max(mx, std::fabs(b.cam.eye[c]));
+    }
+    for (float v : sd.pl_pos) mx = std::max(mx, std::fabs(v));
+    return std::ldexp(mx + 1.0f, -16);
+}
+
+// ---------------------------------------------------------------------------
+// Binned SAH BVH2.
+
+namespace {
+
+struct Box {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void grow(const Box &b)
+    {
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], b.lo[c]);
+            hi[c] = std::max(hi[c], b.hi[c]);
+        }
+    }
+    void grow_pt(const float *p)
+    {
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], p[c]);
+            hi[c] = std::max(hi[c], p[c]);
+        }
+    }
+    double area() const
+    {
+        if (!(lo[0] <= hi[0])) return 0.0;
+        const double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+struct BNode {
+    Box box;
+    int32_t child[2] = {-1, -1};   // build-node ids (inner) ...
+    uint32_t first = 0, count = 0; // ... or a leaf range (count > 0)
+};
+
+struct Builder {
+    const std::vector<float> &tri;
+    std::vector<Box> tbox;
+    std::vector<float> cen;  // [n][3]
+    std::vector<uint32_t> ref;
+    std::vector<BNode> nodes;
+    uint32_t max_depth_seen = 0;
+
+    explicit Builder(const std::vector<float> &t) : tri(t) {}
+
+    static constexpr int kBins = 16;
+    static constexpr uint32_t kLeafTarget = 4;
+    static constexpr uint32_t kSahDepthLimit = 32;
+
+    int32_t build(uint32_t b, uint32_t e, uint32_t depth)
+    {
+        max_depth_seen = std::max(max_depth_seen, depth);
+        const int32_t id = (int32_t)nodes.size();
+        nodes.emplace_back();
+        Box bb, cb;
+        for (uint32_t i = b; i < e; ++i) {
+            bb.grow(tbox[ref[i]]);
+            cb.grow_pt(&cen[3 * (size_t)ref[i]]);
+        }
+        nodes[id].box = bb;
+        const uint32_t n = e - b;
+        if (n <= kLeafTarget) {
+            nodes[id].first = b;
+            nodes[id].count = n;
+            return id;
+        }
+        int axis = -1;
+        uint32_t mid = b;
+        if (depth < kSahDepthLimit) {
+            double best = INFINITY;
+            int best_axis = -1, best_bin = -1;
+            for (int a = 0; a < 3; ++a) {
+                const float ext = cb.hi[a] - cb.lo[a];
+                if (!(ext > 0.0f)) continue;
+                Box bins[kBins];
+                uint32_t cnt[kBins] = {0};
+                const double scale = kBins / (double)ext;
+                for (uint32_t i = b; i < e; ++i) {
+                    int k = (int)(((double)cen[3 * (size_t)ref[i] + a] - cb.lo[a]) * scale);
+                    k = std::min(std::max(k, 0), kBins - 1);
+                    cnt[k]++;
+                    bins[k].grow(tbox[ref[i]]);
+                }
+                double left_area[kBins];
+                uint32_t left_cnt[kBins];
+                Box acc;
+                uint32_t c = 0;
+                for (int k = 0; k < kBins - 1; ++k) {
+                    acc.grow(bins[k]);
+                    c += cnt[k];
+                    left_area[k] = acc.area();
+                    left_cnt[k] = c;
+                }
+                acc = Box();
+                c = 0;
+                for (int k = kBins - 1; k > 0; --k) {
+                    acc.grow(bins[k]);
+                    c += cnt[k];
+                    if (left_cnt[k - 1] == 0 || c == 0) continue;
+                    const double cost = left_area[k - 1] * left_cnt[k - 1] + acc.area() * c;
+                    if (cost < best) {
+                        best = cost;
+                        best_axis = a;
+                        best_bin = k;
+                    }
+                }
+            }
+            const double leaf_cost = bb.area() * n;
+            const double split_cost = bb.area() + best;  // one traversal step + children
+            if (best_axis >= 0 && (split_cost < leaf_cost || n > kMaxLeafTris)) {
+                axis = best_axis;
+                const double scale = kBins / (double)(cb.hi[axis] - cb.lo[axis]);
+                auto it = std::partition(ref.begin() + b, ref.begin() + e, [&](uint32_t r) {
+                    int k = (int)(((double)cen[3 * (size_t)r + axis] - cb.lo[axis]) * scale);
+                    k = std::min(std::max(k, 0), kBins - 1);
+                    return k < best_bin;
+                });
+                mid = (uint32_t)(it - ref.begin());
+            } else if (best_axis < 0 && n <= kMaxLeafTris) {
+                nodes[id].first = b;
+                nodes[id].count = n;
+                return id;
+            } else if (n <= kMaxLeafTris) {
+                nodes[id].first = b;
+                nodes[id].count = n;
+                return id;
+            }
+        }
+        if (mid == b || mid == e) {
+            // Object-median split on the widest centroid axis.
+            int a = 0;
+            for (int c = 1; c < 3; ++c)
+                if (cb.hi[c] - cb.lo[c] > cb.hi[a] - cb.lo[a]) a = c;
+            mid = b + n / 2;
+            std::nth_element(ref.begin() + b, ref.begin() + mid, ref.begin() + e, [&](uint32_t x, uint32_t y) {
+                const float cx = cen[3 * (size_t)x + a], cy = cen[3 * (size_t)y + a];
+                return cx < cy || (cx == cy && x < y);
+            });
+        }
+        const int32_t l = build(b, mid, depth + 1);
+        const int32_t r = build(mid, e, depth + 1);
+        nodes[id].child[0] = l;
+        nodes[id].child[1] = r;
+        return id;
+    }
+};
+
+inline float pad_down(float v, float pad)
+{
+    float r = (float)((double)v - (double)pad);
+    if ((double)r > (double)v - (double)pad) r = std::nextafter(r, -INFINITY);
+    return r;
+}
+
+inline float pad_up(float v, float pad)
+{
+    float r = (float)((double)v + (double)pad);
+    if ((double)r < (double)v + (double)pad) r = std::nextafter(r, INFINITY);
+    return r;
+}
+
+}  // namespace
+
+void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
+{
+    const uint32_t nt = (uint32_t)(h.tri.size() / 9);
+    h.nodes.clear();
+    h.tris.clear();
+    h.root = kEmptyRef;
+    h.n_lds = 0;
+    h.depth = 0;
+    h.sah_cost = 0.0;
+    if (nt == 0) return;
+    Builder B(h.tri);
+    B.tbox.resize(nt);
+    B.cen.resize(3 * (size_t)nt);
+    B.ref.resize(nt);
+    for (uint32_t p = 0; p < nt; ++p) {
+        const float *v = &h.tri[9 * (size_t)p];
+        Box b;
+        for (int k = 0; k < 3; ++k) b.grow_pt(v + 3 * k);
+        B.tbox[p] = b;
+        for (int c = 0; c < 3; ++c) B.cen[3 * (size_t)p + c] = (float)(((double)v[c] + v[3 + c] + v[6 + c]) / 3.0);
+        B.ref[p] = p;
+    }
+    B.nodes.reserve(2 * (size_t)nt / Builder::kLeafTarget + 16);
+    const int32_t broot = B.build(0, nt, 0);
+    h.depth = B.max_depth_seen;
+
+    // Triangles in leaf order.
+    h.tris.resize(3 * (size_t)nt);
+    for (uint32_t i = 0; i < nt; ++i) {
+        const uint32_t p = B.ref[i];
+        const float *v = &h.tri[9 * (size_t)p];
+        h.tris[3 * (size_t)i + 0] = make_float4(v[0], v[1], v[2], u2f(p));
+        h.tris[3 * (size_t)i + 1] = make_float4(v[3], v[4], v[5], 0.0f);
+        h.tris[3 * (size_t)i + 2] = make_float4(v[6], v[7], v[8], 0.0f);
+    }
+
+    auto leaf_ref = [&](const BNode &n) -> int32_t {
+        return (int32_t) ~((n.first << kLeafCountBits) | (n.count - 1));
+    };
+    if (B.nodes[broot].count > 0) {
+        h.root = leaf_ref(B.nodes[broot]);
+        return;
+    }
+    // Inner nodes: breadth-first for the first n_lds_max (the LDS treelet),
+    // then each remaining subtree depth-first.
+    std::vector<int32_t> order;
+    std::vector<int32_t> newid(B.nodes.size(), -1);
+    std::vector<int32_t> queue{broot};
+    size_t qh = 0;
+    while (qh < queue.size() && order.size() < n_lds_max) {
+        const int32_t b = queue[qh++];
+        newid[b] = (int32_t)order.size();
+        order.push_back(b);
+        for (int k = 0; k < 2; ++k) {
+            const int32_t c = B.nodes[b].child[k];
+            if (B.nodes[c].count == 0) queue.push_back(c);
+        }
+    }
+    h.n_lds = (uint32_t)order.size();
+    std::vector<int32_t> stack;
+    for (size_t k = qh; k < queue.size(); ++k) {
+        stack.push_back(queue[k]);
+        while (!stack.empty()) {
+            const int32_t b = stack.back();
+            stack.pop_back();
+            newid[b] = (int32_t)order.size();
+            order.push_back(b);
+            for (int c = 1; c >= 0; --c) {
+                const int32_t ch = B.nodes[b].child[c];
+                if (B.nodes[ch].count == 0) stack.push_back(ch);
+            }
+        }
+    }
+    h.nodes.resize(4 * order.size());
+    double cost = 0.0;
+    const double root_area = B.nodes[broot].box.area();
+    for (size_t i = 0; i < order.size(); ++i) {
+        const BNode &n = B.nodes[order[i]];
+        const BNode &L = B.nodes[n.child[0]];
+        const BNode &R = B.nodes[n.child[1]];
+        float l[6], r[6];
+        for (int c = 0; c < 3; ++c) {
+            l[c] = pad_down(L.box.lo[c], pad);
+            l[3 + c] = pad_up(L.box.hi[c], pad);
+            r[c] = pad_down(R.box.lo[c], pad);
+            r[3 + c] = pad_up(R.box.hi[c], pad);
+        }
+        const int32_t rl = L.count ? leaf_ref(L) : newid[n.child[0]];
+        const int32_t rr = R.count ? leaf_ref(R) : newid[n.child[1]];
+        h.nodes[4 * i + 0] = make_float4(l[0], l[1], l[2], l[3]);
+        h.nodes[4 * i + 1] = make_float4(l[4], l[5], r[0], r[1]);
+        h.nodes[4 * i + 2] = make_float4(r[2], r[3], r[4], r[5]);
+        h.nodes[4 * i + 3] = make_float4(u2f((uint32_t)rl), u2f((uint32_t)rr), 0.0f, 0.0f);
+        cost += n.box.area() / root_area;
+        if (L.count) cost += L.box.area() / root_area * L.count;
+        if (R.count) cost += R.box.area() / root_area * R.count;
+    }
+    h.root = 0;
+    h.sah_cost = cost;
+}
+
+std::string check_bvh(const HostInstant &h, float pad)
+{
+    const uint32_t nt = (uint32_t)(h.tri.size() / 9);
+    if (nt == 0) return h.root == kEmptyRef ? "" : "empty scene with a root";
+    std::vector<uint32_t> seen(nt, 0);
+    const uint32_t n_nodes = (uint32_t)(h.nodes.size() / 4);
+    std::vector<uint32_t> visited(n_nodes, 0);
+    // (ref, box lo/hi that must contain it)
+    struct Item {
+        int32_t ref;
+        float lo[3], hi[3];
+        uint32_t depth;
+    };
+    std::vector<Item> st;
+    Item root{h.root, {-INFINITY, -INFINITY, -INFINITY}, {INFINITY, INFINITY, INFINITY}, 1};
+    st.push_back(root);
+    uint32_t max_depth = 0;
+    while (!st.empty()) {
+        Item it = st.back();
+        st.pop_back();
+        max_depth = std::max(max_depth, it.depth);
+        if (it.ref < 0) {
+            const uint32_t packed = ~(uint32_t)it.ref;
+            const uint32_t first = packed >> kLeafCountBits, count = (packed & (kMaxLeafTris - 1)) + 1;
+            if (first + count > nt) return "leaf range out of bounds";
+            for (uint32_t k = first; k < first + count; ++k) {
+                const float4 *t = &h.tris[3 * (size_t)k];
+                const uint32_t p = f2u(t[0].w);
+                if (p >= nt) return "bad primitive id";
+                seen[p]++;
+                const float v[9] = {t[0].x, t[0].y, t[0].z, t[1].x, t[1].y, t[1].z, t[2].x, t[2].y, t[2].z};
+                for (int j = 0; j < 9; ++j)
+                    if (v[j] != h.tri[9 * (size_t)p + j]) return "leaf triangle differs from the world triangle";
+                for (int j = 0; j < 3; ++j)
+                    for (int c = 0; c < 3; ++c) {
+                        const float x = v[3 * j + c];
+                        if (!((double)x - it.lo[c] >= (double)pad * 0.5 && (double)it.hi[c] - x >= (double)pad * 0.5))
+                            return "triangle not inside its padded leaf box";
+                    }
+            }
+            continue;
+        }
+        if ((uint32_t)it.ref >= n_nodes) return "node index out of bounds";
+        if (visited[it.ref]++) return "node reached twice";
+        const float4 *n = &h.nodes[4 * (size_t)it.ref];
+        const float l[6] = {n[0].x, n[0].y, n[0].z, n[0].w, n[1].x, n[1].y};
+        const float r[6] = {n[1].z, n[1].w, n[2].x, n[2].y, n[2].z, n[2].w};
+        Item a{(int32_t)f2u(n[3].x), {l[0], l[1], l[2]}, {l[3], l[4], l[5]}, it.depth + 1};
+        Item b{(int32_t)f2u(n[3].y), {r[0], r[1], r[2]}, {r[3], r[4], r[5]}, it.depth + 1};
+        st.push_back(a);
+        st.push_back(b);
+    }
+    for (uint32_t p = 0; p < nt; ++p)
+        if (seen[p] != 1) return "primitive missing or duplicated";
+    for (uint32_t i = 0; i < n_nodes; ++i)
+        if (!visited[i]) return "unreachable node";
+    if (max_depth >= (uint32_t)traverse_max_depth()) return "tree deeper than the traversal stack";
+    return "";
+}
+
+FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    f.s = s;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// Student t quantile for integer df.  The CDF uses the finite series of
+// Abramowitz & Stegun 26.7.3 (odd df) and 26.7.4 (even df) for
+// A(t) = P(|T| <= t) in terms of theta = atan(t / sqrt(df)); the quantile
+// is found by bisection to full double precision.
+
+static double t_abs_prob(double t, uint32_t df)
+{
+    const double th = std::atan(t / std::sqrt((double)df));
+    const double s = std::sin(th), c = std::cos(th), c2 = c * c;
+    if (df % 2 == 1) {
+        double sum = 0.0;
+        if (df > 1) {
+            double term = c;
+            sum = c;
+            for (uint32_t k = 3; k + 2 <= df; k += 2) {
+                term *= c2 * (double)(k - 1) / (double)k;
+                sum += term;
+            }
+        }
+        return (2.0 / 3.14159265358979323846) * (th + s * sum);
+    }
+    double term = 1.0, sum = 1.0;
+    for (uint32_t k = 2; k + 2 <= df; k += 2) {
+        term *= c2 * (double)(k - 1) / (double)k;
+        sum += term;
+    }
+    return s * sum;
+}
+
+static double t_cdf_int(double t, uint32_t df)
+{
+    const double a = t_abs_prob(std::fabs(t), df);
+    return t < 0.0 ? 0.5 - 0.5 * a : 0.5 + 0.5 * a;
+}
+
+double t_quantile(double p, uint32_t df)
+{
+    if (!(p > 0.0) || !(p < 1.0) || df == 0) return NAN;
+    if (p == 0.5) return 0.0;
+    const bool upper = p > 0.5;
+    const double pl = upper ? 1.0 - p : p;  // solve in the lower tail
+    double lo = -1.0, hi = 0.0;
+    while (t_cdf_int(lo, df) > pl) {
+        hi = lo;
+        lo *= 2.0;
+        if (lo < -1e300) break;
+    }
+    for (int it = 0; it < 2000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (t_cdf_int(mid, df) < pl) lo = mid;
+        else hi = mid;
+    }
+    const double q = 0.5 * (lo + hi);
+    return upper ? -q : q;
+}
+
+}  // namespace evrt

@@ -1,0 +1,281 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (from the method's definition and the renderer's written FP order):
+  * ray queries: bit-exact (t, primitive) and any-hit flags;
+  * per-path radiance: bit-exact (both sides follow the same FP32
+    operation order; sin/cos are correctly rounded from FP64);
+  * per-pixel means: |gpu - oracle| <= 1e-4 max(1, |oracle|);
+  * sample counts and polarity: bit-exact except at pixels where an oracle
+    decision was within 1e-4 of its critical value.
+"""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2408_07996_amd as ev
+from paper_2408_07996_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def rend(torch_cuda):
+    r = ev.Renderer(0)
+    yield r
+    r.close()
+
+
+def _opts_from(params: dict, **kw):
+    d = dict(params)
+    d.update(kw)
+    keys = ("seed", "max_depth", "rr_start_depth", "minibatch", "log_eps", "nee", "jitter", "mode",
+            "df_mode", "ref_mode")
+    return {k: d[k] for k in keys if k in d}
+
+
+# ---------------------------------------------------------------------------
+# Ray queries.
+
+def _rays_for(tri, rng, n, extent):
+    o = rng.uniform(-extent, extent, size=(n, 3)).astype(np.float32)
+    pts = np.concatenate([tri.reshape(-1, 3), 0.5 * (tri[:, 0] + tri[:, 1])])
+    tgt = pts[rng.integers(0, len(pts), n)]
+    d = np.where(rng.random((n, 1)) < 0.5, tgt - o, rng.normal(size=(n, 3)))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    return o, d
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_trace_rays_match_oracle(rend, torch_cuda, seed):
+    sc = scenes.triangle_soup(400, seed=seed, moving=True)
+    rend.set_scene(sc)
+    rng = np.random.default_rng(50 + seed)
+    n = 3000
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        for inst, t in ((0, 0.0), (1, 1.0)):
+            _say(f"trace_rays seed={seed} t={t}")
+            tri, _ = f.world_tris(inst)
+            o, d = _rays_for(tri, rng, n, 3.0)
+            tmin = np.full(n, 1e-4, np.float32)
+            tmax = np.where(rng.random(n) < 0.3, rng.uniform(0.5, 5, n), np.inf).astype(np.float32)
+            skip = np.where(rng.random(n) < 0.3, rng.integers(0, 400, n), ev.NO_PRIM).astype(np.uint32)
+            rays = np.concatenate([o, tmin[:, None], d, tmax[:, None]], axis=1)
+            tt, pp = rend.trace_rays(t, rays, skip)
+            anyh = rend.trace_rays(t, rays, skip, any_hit=True)
+            tt, pp, anyh = tt.cpu().numpy(), pp.cpu().numpy().view(np.uint32), anyh.cpu().numpy()
+            bad = 0
+            for k in range(n):
+                hit, t_ref, p_ref = f.closest_hit(inst, o[k], d[k], tmin=tmin[k], tmax=tmax[k],
+                                                  skip=int(skip[k]), brute=True)
+                if p_ref != pp[k] or (hit and t_ref != tt[k]):
+                    bad += 1
+                a_ref = f.any_hit(inst, o[k], d[k], tmin=tmin[k], tmax=tmax[k], skip=int(skip[k]), brute=True)
+                if bool(anyh[k]) != a_ref:
+                    bad += 1
+            assert bad == 0
+
+
+# ---------------------------------------------------------------------------
+# Per-path radiance.
+
+PATH_CASES = {
+    "tiny_box": (lambda: scenes.tiny_box(), scenes.TINY_PARAMS, 0.0, 1.0),
+    "tiny_box_nee_off": (lambda: scenes.tiny_box(), {**scenes.TINY_PARAMS, "nee": 0, "max_depth": 6}, 0.0, 1.0),
+    "furnace": (lambda: scenes.furnace(0.6, 1.5, 12, 10), {**scenes.TINY_PARAMS, "rr_start_depth": 3}, 0.0, 0.0),
+    "point_light": (lambda: scenes.plane_point_light(), {**scenes.TINY_PARAMS, "jitter": 0}, 0.0, 0.0),
+    "soup_lights": (lambda: scenes.triangle_soup(600, seed=5, moving=True, emitters=8, width=24, height=20),
+                    {**scenes.TINY_PARAMS, "max_depth": 5, "seed": 0x123456789}, 0.0, 1.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(PATH_CASES))
+def test_render_paths_bit_exact(rend, torch_cuda, case):
+    make, params, t0, t1 = PATH_CASES[case]
+    sc = make()
+    if case == "soup_lights":
+        b_pos = np.array([[0.5, 3.0, 1.0], [-2.0, 1.0, 2.5]], np.float32)
+        sc.pl_pos, sc.pl_intensity = b_pos, np.array([4.0, 2.5], np.float32)
+    rend.set_scene(sc)
+    npx = sc.width * sc.height
+    pixels = np.unique(np.concatenate([np.arange(0, npx, 7), [0, npx - 1]])).astype(np.uint32)
+    spp = 24
+    _say(f"render_paths case={case} pixels={len(pixels)} spp={spp}")
+    L = rend.render_paths(t0, t1, pixels, spp, opts=_opts_from(params)).cpu().numpy()
+    p = oracle.make_params(**params)
+    with oracle.Frame(sc, t0, t1) as f:
+        ref = np.zeros_like(L)
+        for inst in (0, 1):
+            px = np.repeat(pixels, spp)
+            sm = np.tile(np.arange(spp, dtype=np.uint32), len(pixels))
+            ref[:, inst, :] = f.paths(p, px, inst, sm).reshape(len(pixels), spp)
+    mism = (L != ref)
+    frac = mism.mean()
+    rel = np.abs(L.astype(np.float64) - ref) / np.maximum(1e-30, np.abs(ref))
+    _say(f"  mismatching paths: {mism.sum()} of {mism.size}, max rel {rel.max():.3g}")
+    assert mism.sum() == 0
+
+
+# ---------------------------------------------------------------------------
+# Decision kernels on seeded Gaussian samples.
+
+@pytest.mark.parametrize("mode", [ev.MODE_ADAPTIVE_1T, ev.MODE_ADAPTIVE_2T, ev.MODE_MEAN_ONLY, ev.MODE_FIXED])
+def test_decide_stats_match_oracle(rend, torch_cuda, mode):
+    rng = np.random.default_rng(1234)
+    n, m, C, alpha = 4000, 16, 0.2, 0.01
+    gaps = rng.choice([0.0, 0.1, 0.2, 0.4, -0.3], size=n)
+    x0 = rng.normal(0.0, 0.05, size=(n, m))
+    x1 = rng.normal(gaps[:, None], 0.05, size=(n, m))
+    x0[:5] = 0.75
+    x1[:5] = 0.75  # zero variance, gap 0 < C: t = -inf
+    t, stop, pol = rend.decide_stats(x0, x1, C, alpha, mode)
+    t, stop, pol = t.cpu().numpy(), stop.cpu().numpy().astype(bool), pol.cpu().numpy()
+    Cf = float(np.float32(C))
+    for i in range(n):
+        r = oracle.decide(x0[i], x1[i], C, alpha, mode=mode)
+        if math.isinf(r["t"]):
+            assert t[i] == r["t"]
+        else:
+            assert abs(t[i] - r["t"]) <= 1e-9 * max(1.0, abs(r["t"]))
+        crit = oracle.t_ppf(float(np.float32(alpha)), 2 * m - 2)
+        near = abs(r["t"] - crit) < 1e-4 or abs(r["t"] + crit) < 1e-4
+        if not near:
+            assert bool(stop[i]) == r["stop"], (i, t[i], r)
+        gap = x1[i].mean() - x0[i].mean()
+        if abs(abs(gap) - Cf) > 1e-9:
+            assert pol[i] == (np.sign(gap) if abs(gap) > Cf else 0)
+
+
+# ---------------------------------------------------------------------------
+# Whole event frames.
+
+def _frame(rend, sc, params, t0, t1, **kw):
+    p = dict(params)
+    p.update(kw)
+    out = rend.render_event_frame(t0, t1, p["C"], p["alpha"], p["spp_init"], p["spp_batch"], p["spp_max"],
+                                  opts=_opts_from(p))
+    return {k: v.cpu().numpy() for k, v in out.items()}, rend.frame_stats()
+
+
+def _compare(g, r, pixels, C):
+    """Parity of a GPU frame g (full image) with an oracle result r on
+    `pixels`; returns a summary dict and asserts the bars."""
+    pol = g["polarity"][pixels]
+    n = g["n_paths"][pixels].astype(np.uint32)
+    exempt = r["near_crit"]
+    bad_pol = (pol != r["polarity"]) & ~exempt
+    bad_n = (n != r["n_paths"]) & ~exempt
+    same = (n == r["n_paths"])
+    mean_err = np.abs(g["mean"][pixels][same] - r["mean"][same]) / np.maximum(1.0, np.abs(r["mean"][same]))
+    rad_err = (np.abs(g["mean_radiance"][pixels][same] - r["mean_radiance"][same])
+               / np.maximum(1.0, np.abs(r["mean_radiance"][same])))
+    s = dict(pixels=len(pixels), exempt=int(exempt.sum()), bad_pol=int(bad_pol.sum()), bad_n=int(bad_n.sum()),
+             max_mean_err=float(mean_err.max(initial=0)), max_rad_err=float(rad_err.max(initial=0)),
+             events=int((r["polarity"] != 0).sum()))
+    _say("  parity:", s)
+    assert s["bad_pol"] == 0 and s["bad_n"] == 0
+    assert s["max_mean_err"] <= 1e-4 and s["max_rad_err"] <= 1e-4
+    return s
+
+
+@pytest.mark.parametrize("variant", ["default", "fixed", "ref_full", "two_tailed", "mean_only", "mb1", "mb8"])
+def test_tiny_frame_parity(rend, torch_cuda, variant):
+    sc = scenes.tiny_box()
+    rend.set_scene(sc)
+    params = dict(scenes.TINY_PARAMS)
+    if variant == "fixed":
+        params["mode"] = ev.MODE_FIXED
+    elif variant == "ref_full":
+        params["ref_mode"] = ev.REF_FULL
+    elif variant == "two_tailed":
+        params["mode"] = ev.MODE_ADAPTIVE_2T
+    elif variant == "mean_only":
+        params["mode"] = ev.MODE_MEAN_ONLY
+    elif variant == "mb1":
+        params.update(minibatch=1, log_eps=1e-3, spp_init=8, spp_batch=8, spp_max=64)
+    elif variant == "mb8":
+        params.update(minibatch=8, spp_init=16, spp_batch=24, spp_max=256)
+    _say(f"tiny frame variant={variant}")
+    g, st = _frame(rend, sc, params, 0.0, 1.0)
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        r = f.render(oracle.make_params(**params))
+    _compare(g, r, np.arange(sc.n_pixels), params["C"])
+    assert st["rounds"] >= 1 and st["camera_rays"] > 0
+
+
+def test_tiny_frame_invariants_and_determinism(rend, torch_cuda):
+    sc = scenes.tiny_box()
+    rend.set_scene(sc)
+    P = scenes.TINY_PARAMS
+    a, st = _frame(rend, sc, P, 0.0, 1.0)
+    b, _ = _frame(rend, sc, P, 0.0, 1.0, ray_batch=1 << 16) if False else _frame(rend, sc, P, 0.0, 1.0)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+    n = a["n_paths"]
+    assert set(np.unique(n)) <= set(range(16, 257, 16))
+    assert (n[a["polarity"] != 0] == 256).all()
+    early = a["flags"].astype(bool)
+    assert (a["polarity"][early] == 0).all() and (n[early] < 256).all()
+    # C = 0: nothing stops, equal to fixed mode bit for bit
+    z, _ = _frame(rend, sc, P, 0.0, 1.0, C=0.0)
+    fz, _ = _frame(rend, sc, P, 0.0, 1.0, C=0.0, mode=ev.MODE_FIXED)
+    for k in ("polarity", "n_paths", "mean", "var", "mean_radiance"):
+        np.testing.assert_array_equal(z[k], fz[k])
+    # rays counted: camera rays = paths traced
+    assert st["camera_rays"] == st["paths"]
+    assert st["camera_rays"] == 2 * int(n.sum())
+
+
+def test_edge_cases(rend, torch_cuda):
+    P = dict(scenes.TINY_PARAMS)
+    cases = [
+        ("one_pixel", scenes.tiny_box(width=1, height=1), P),
+        ("ragged", scenes.tiny_box(width=37, height=23), P),
+        ("single_round", scenes.tiny_box(width=16, height=12), {**P, "spp_init": 64, "spp_max": 64}),
+        ("empty", scenes.empty(9, 7), P),
+        ("depth1", scenes.tiny_box(width=20, height=20), {**P, "max_depth": 1}),
+        ("static_pair", scenes.tiny_box(width=24, height=24), P),
+    ]
+    for name, sc, params in cases:
+        _say(f"edge case {name}")
+        rend.set_scene(sc)
+        t1 = 0.0 if name == "static_pair" else 1.0
+        g, _ = _frame(rend, sc, params, 0.0, t1)
+        with oracle.Frame(sc, 0.0, t1) as f:
+            r = f.render(oracle.make_params(**params))
+        _compare(g, r, np.arange(sc.n_pixels), params["C"])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("C", [0.15, 0.3])
+def test_sensor_subset_parity(rend, torch_cuda, C):
+    """The sensor workload (640x480, ~98k triangles, depth 8, 64/16/1024)
+    at full size in the benchmark's launch configuration, compared on every
+    16th pixel in x and y."""
+    sc = scenes.sensor()
+    rend.set_scene(sc)
+    params = {**scenes.SENSOR_PARAMS, "C": C}
+    _say(f"sensor frame C={C}")
+    t = time.time()
+    g, st = _frame(rend, sc, params, 0.0, 1.0)
+    _say(f"  gpu frame {time.time() - t:.2f}s rounds={st['rounds']}")
+    px = scenes.subset_every(sc.width, sc.height, 16)
+    t = time.time()
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        r = f.render(oracle.make_params(**params), px)
+    _say(f"  oracle subset {time.time() - t:.2f}s")
+    _compare(g, r, px, C)

@@ -1,0 +1,170 @@
+"""Host-side checks of libevrt.so that need no GPU: exported symbols,
+argument validation on a host-only context, the critical-value quantile."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import paper_2408_07996_amd as ev
+from paper_2408_07996_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "evrt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(evrt_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ev.load_library()
+    names = _declared_symbols()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
+    bound = {s[0] for s in ev.SIGNATURES}
+    assert set(names) == bound
+    assert L.evrt_abi_version() == 1
+
+
+def test_default_opts():
+    o = ev.default_opts()
+    assert (o.max_depth, o.rr_start_depth, o.minibatch, o.nee, o.jitter, o.mode) == (4, 2, 4, 1, 1, 0)
+    assert o.log_eps == 1e-4
+
+
+@pytest.fixture()
+def host_ctx():
+    r = ev.Renderer(device=-1)
+    yield r
+    r.close()
+
+
+def test_create_rejects_bad_device():
+    with pytest.raises(ev.EvrtError) as e:
+        ev.Renderer(device=-7)
+    assert e.value.code == ev.EVRT_E_INVALID
+
+
+def test_scene_validation(host_ctx):
+    r = host_ctx
+    with pytest.raises(ev.EvrtError) as e:
+        r.scene_commit()
+    assert e.value.code == ev.EVRT_E_STATE
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_materials([1.0], [0.0])           # albedo must be < 1
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_materials([0.5], [-1.0])
+    r.scene_set_materials([0.5, 0.0], [0.0, 2.0])
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_mesh(0, [[0, 0, 0], [1, 0, 0]], [[0, 1, 2]], [0])   # index out of range
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_mesh(0, [[0, 0, np.nan], [1, 0, 0], [0, 1, 0]], [[0, 1, 2]], [0])
+    r.scene_set_mesh(0, [[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[0, 1, 2]], [1])
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_instance(0, 0, [1.0, 0.5], [scenes.identity()] * 2)  # key times must increase
+    r.scene_set_instance(1, 0, [0.0], [scenes.identity()])
+    r.scene_set_camera(8, 8, 40, [0.0], [[0, 0, 5, 0, 0, 0, 0, 1, 0]])
+    with pytest.raises(ev.EvrtError) as e:
+        r.scene_commit()                               # instance 0 missing
+    assert e.value.code == ev.EVRT_E_INVALID
+    r.scene_set_instance(0, 0, [0.0], [scenes.identity()])
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_camera(8, 8, 40, [0.0], [[0, 0, 5, 0, 0, 5, 0, 1, 0]])  # zero look direction
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_camera(0, 8, 40, [0.0], [[0, 0, 5, 0, 0, 0, 0, 1, 0]])
+    r.scene_commit()
+    # a material index beyond the table is caught at commit
+    r.scene_set_mesh(0, [[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[0, 1, 2]], [5])
+    with pytest.raises(ev.EvrtError):
+        r.scene_commit()
+
+
+def _render_rc(r, **kw):
+    """Status of evrt_render_event_frame with dummy (never touched) outputs."""
+    L = ev.load_library()
+    args = dict(t0=0.0, t1=1.0, C=0.2, alpha=0.01, spp_init=16, spp_batch=16, spp_max=256)
+    args.update({k: v for k, v in kw.items() if k in args})
+    o = ev.default_opts(**{k: v for k, v in kw.items() if k not in args and k != "out"})
+    dummy = ctypes.c_void_p(16)
+    fo = ev.FrameOut(dummy, dummy, dummy, dummy, None, None, None)
+    if kw.get("out") == "missing":
+        fo = ev.FrameOut(dummy, None, dummy, dummy, None, None, None)
+    rc = L.evrt_render_event_frame(r._h, args["t0"], args["t1"], args["C"], args["alpha"], args["spp_init"],
+                                   args["spp_batch"], args["spp_max"], ctypes.byref(o), ctypes.byref(fo), None)
+    return rc, L.evrt_last_error(r._h).decode()
+
+
+def test_render_argument_validation_before_device_work(host_ctx):
+    r = host_ctx
+    rc, msg = _render_rc(r)
+    assert rc == ev.EVRT_E_STATE and "commit" in msg
+    r.set_scene(scenes.tiny_box())
+    bad = [dict(spp_init=6), dict(spp_init=4), dict(spp_init=512), dict(spp_batch=6), dict(alpha=0.0),
+           dict(alpha=1.0), dict(C=-0.1), dict(C=math.inf), dict(t0=math.nan), dict(minibatch=3),
+           dict(max_depth=0), dict(max_depth=65), dict(mode=9), dict(nee=2), dict(out="missing"),
+           dict(log_eps=-1.0), dict(rr_start_depth=0)]
+    for kw in bad:
+        rc, msg = _render_rc(r, **kw)
+        assert rc == ev.EVRT_E_INVALID, (kw, rc, msg)
+        assert msg
+    rc, msg = _render_rc(r, df_mode=ev.DF_WELCH)
+    assert rc == ev.EVRT_E_UNSUPPORTED
+    # Valid arguments reach the device check last.
+    rc, msg = _render_rc(r)
+    assert rc == ev.EVRT_E_DEVICE and "host-only" in msg
+
+
+def test_null_context_is_rejected():
+    L = ev.load_library()
+    assert L.evrt_scene_commit(None) == ev.EVRT_E_INVALID
+    st = ev.FrameStats()
+    assert L.evrt_get_frame_stats(None, ctypes.byref(st)) == ev.EVRT_E_INVALID
+
+
+@pytest.mark.parametrize("df", [1, 2, 3, 5, 6, 14, 30, 62, 126, 510, 2046])
+@pytest.mark.parametrize("p", [1e-4, 0.0005, 0.005, 0.01, 0.05, 0.5, 0.95, 0.995])
+def test_library_t_quantile_matches_scipy(df, p):
+    q = ev.t_quantile(p, df)
+    ref = stats.t.ppf(p, df)
+    assert abs(q - ref) <= 1e-10 * max(1.0, abs(ref)), (q, ref)
+
+
+def test_library_t_quantile_closed_forms():
+    for p in (0.01, 0.2, 0.7):
+        assert abs(ev.t_quantile(p, 1) - math.tan(math.pi * (p - 0.5))) < 1e-12
+        # df = 2: q = (2p - 1) sqrt(2 / (4p(1-p)))
+        assert abs(ev.t_quantile(p, 2) - (2 * p - 1) * math.sqrt(2 / (4 * p * (1 - p)))) < 1e-12
+    assert math.isnan(ev.t_quantile(0.0, 4)) and math.isnan(ev.t_quantile(0.3, 0))
+
+
+@pytest.mark.parametrize("make", [lambda: scenes.triangle_soup(2000, seed=3, moving=True, emitters=5),
+                                  lambda: scenes.tiny_box(), lambda: scenes.furnace(0.5, 1.0),
+                                  lambda: scenes.empty(), lambda: scenes.plane_point_light()])
+def test_bvh_structure_on_host(host_ctx, make):
+    sc = make()
+    host_ctx.set_scene(sc)
+    for t in (0.0, 0.5, 1.0):
+        info = host_ctx.scene_info_at(t)
+        assert info["n_tri"] == sc.n_tri_world
+        if sc.n_tri_world > 4:
+            assert info["n_nodes"] >= 1 and info["n_lds"] <= info["n_nodes"]
+        assert info["depth"] < 64
+
+
+@pytest.mark.slow
+def test_bvh_structure_sensor_scene(host_ctx):
+    sc = scenes.sensor()
+    host_ctx.set_scene(sc)
+    info = host_ctx.scene_info_at(1.0)
+    assert info["n_tri"] == 72200 + 20 * 1280 + 6
+    assert info["n_emit"] == 6
+    assert info["depth"] < 48
+    # SAH cost in units of root-box traversals: a sane tree is far below
+    # the brute-force cost n_tri.
+    assert info["sah_cost"] < 200
