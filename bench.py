@@ -60,6 +60,8 @@ def main() -> int:
     ap.add_argument("--cpu-step", type=int, default=16, help="oracle sample: every n-th pixel in x and y")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the timed adaptive frames (for profiler runs)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB on the device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every pixel and sample is "
@@ -74,6 +76,12 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sc = scenes.sensor()
     P = dict(scenes.SENSOR_PARAMS, C=args.C)
     base_opts = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],

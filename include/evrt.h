@@ -141,7 +141,7 @@ typedef struct {
     uint8_t ref_mode;        /* EVRT_REF_*                                         */
     uint8_t profile;         /* 1: time traversal launches with HIP events         */
     uint8_t count_work;      /* 1: count BVH node visits and triangle tests        */
-    uint8_t reserved0;
+    uint8_t lds_nodes;       /* top BVH nodes staged in LDS per block, 0..64 (0)   */
     uint32_t ray_batch;      /* max paths in flight per wavefront piece (0: auto)  */
     uint32_t reserved1;
 } evrt_render_opts;

@@ -24,7 +24,8 @@ __all__ = ["Renderer", "EvrtError", "default_opts", "load_library", "MODE_ADAPTI
            "MODE_ADAPTIVE_2T", "MODE_MEAN_ONLY", "REF_LOCKSTEP", "REF_FULL"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libevrt.so")
+# EVRT_LIBRARY may point at another build of the same library (tuning runs).
+LIB_PATH = os.environ.get("EVRT_LIBRARY") or os.path.join(_HERE, "libevrt.so")
 
 EVRT_OK, EVRT_E_INVALID, EVRT_E_NOMEM, EVRT_E_DEVICE, EVRT_E_STATE, EVRT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 MODE_ADAPTIVE_1T, MODE_FIXED, MODE_ADAPTIVE_2T, MODE_MEAN_ONLY = 0, 1, 2, 3
@@ -41,7 +42,7 @@ class RenderOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("max_depth", _u32), ("rr_start_depth", _u32), ("minibatch", _u32),
         ("log_eps", ctypes.c_double), ("nee", ctypes.c_uint8), ("jitter", ctypes.c_uint8),
         ("mode", ctypes.c_uint8), ("df_mode", ctypes.c_uint8), ("ref_mode", ctypes.c_uint8),
-        ("profile", ctypes.c_uint8), ("count_work", ctypes.c_uint8), ("reserved0", ctypes.c_uint8),
+        ("profile", ctypes.c_uint8), ("count_work", ctypes.c_uint8), ("lds_nodes", ctypes.c_uint8),
         ("ray_batch", _u32), ("reserved1", _u32),
     ]
 

@@ -59,6 +59,7 @@ void validate_opts(const evrt_render_opts &o)
     if (o.mode > EVRT_MODE_MEAN_ONLY) fail(EVRT_E_INVALID, "unknown mode");
     if (o.df_mode > EVRT_DF_WELCH) fail(EVRT_E_INVALID, "unknown df_mode");
     if (o.ref_mode > EVRT_REF_FULL) fail(EVRT_E_INVALID, "unknown ref_mode");
+    if (o.lds_nodes > (uint32_t)lds_treelet_nodes()) fail(EVRT_E_INVALID, "lds_nodes above the treelet capacity");
 }
 
 }  // namespace evrt

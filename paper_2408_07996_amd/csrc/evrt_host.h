@@ -141,7 +141,7 @@ struct evrt_ctx {
 namespace evrt {
 // Geometry of instant t on the device (built and cached on first use).
 std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s, double *ms_build);
-DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b);
+DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b, uint32_t lds_nodes);
 void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
                   uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o,
                   const evrt_frame_out &out, hipStream_t s);

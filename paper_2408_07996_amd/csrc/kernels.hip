@@ -93,12 +93,11 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // Ray preparation shared by both traversal kinds.
 
 struct TRay {
-    float ox, oy, oz;       // origin
     float ix, iy, iz;       // reciprocal direction (tiny components clamped)
     float nox, noy, noz;    // -origin * reciprocal, for the fused slab test
     float okx, oky, okz;    // origin permuted into the watertight frame
     float Sx, Sy, Sz;       // shear constants
-    int kx, ky, kz;
+    uint32_t kperm;         // kx | ky << 2 | kz << 4
 };
 
 __device__ __forceinline__ float safe_dir(float d)
@@ -112,10 +111,10 @@ __device__ __forceinline__ float safe_dir(float d)
 __device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx, float dy, float dz)
 {
     TRay r;
-    r.ox = ox; r.oy = oy; r.oz = oz;
-    r.ix = 1.0f / safe_dir(dx);
-    r.iy = 1.0f / safe_dir(dy);
-    r.iz = 1.0f / safe_dir(dz);
+    // Reciprocals for the box test only (culling, covered by the padding).
+    r.ix = __builtin_amdgcn_rcpf(safe_dir(dx));
+    r.iy = __builtin_amdgcn_rcpf(safe_dir(dy));
+    r.iz = __builtin_amdgcn_rcpf(safe_dir(dz));
     r.nox = -(ox * r.ix);
     r.noy = -(oy * r.iy);
     r.noz = -(oz * r.iz);
@@ -129,7 +128,7 @@ __device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx
     const float4 d4 = make_float4(dx, dy, dz, 0.0f);
     const float dkz = sel3(d4, kz);
     if (dkz < 0.0f) { const int tmp = kx; kx = ky; ky = tmp; }
-    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.kperm = (uint32_t)kx | ((uint32_t)ky << 2) | ((uint32_t)kz << 4);
     r.Sx = sel3(d4, kx) / dkz;
     r.Sy = sel3(d4, ky) / dkz;
     r.Sz = 1.0f / dkz;
@@ -143,9 +142,10 @@ __device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx
 // Watertight test against (v0, v1, v2); on a hit stores t = T / det.
 __device__ __forceinline__ bool tri_test(const TRay &r, float4 v0, float4 v1, float4 v2, float &t)
 {
-    const float ax = sel3(v0, r.kx) - r.okx, ay = sel3(v0, r.ky) - r.oky, az = sel3(v0, r.kz) - r.okz;
-    const float bx = sel3(v1, r.kx) - r.okx, by = sel3(v1, r.ky) - r.oky, bz = sel3(v1, r.kz) - r.okz;
-    const float cx = sel3(v2, r.kx) - r.okx, cy = sel3(v2, r.ky) - r.oky, cz = sel3(v2, r.kz) - r.okz;
+    const int kx = r.kperm & 3, ky = (r.kperm >> 2) & 3, kz = r.kperm >> 4;
+    const float ax = sel3(v0, kx) - r.okx, ay = sel3(v0, ky) - r.oky, az = sel3(v0, kz) - r.okz;
+    const float bx = sel3(v1, kx) - r.okx, by = sel3(v1, ky) - r.oky, bz = sel3(v1, kz) - r.okz;
+    const float cx = sel3(v2, kx) - r.okx, cy = sel3(v2, ky) - r.oky, cz = sel3(v2, kz) - r.okz;
     const float Ax = ax - r.Sx * az, Ay = ay - r.Sy * az;
     const float Bx = bx - r.Sx * bz, By = by - r.Sy * bz;
     const float Cx = cx - r.Sx * cz, Cy = cy - r.Sy * cz;
@@ -206,81 +206,155 @@ __device__ __forceinline__ InstSel select_inst(const DevScene &sc, uint32_t inst
 // Traversal block shape: kTB threads, a top treelet of kLdsNodes nodes per
 // instant staged in LDS, and a per-lane stack whose first kStackLds entries
 // live in LDS (deeper entries spill to private memory).
+#ifndef EVRT_STACK_LDS
+#define EVRT_STACK_LDS 12
+#endif
+#ifndef EVRT_LDS_NODES
+#define EVRT_LDS_NODES 64
+#endif
+#ifndef EVRT_TRACE_WAVES
+#define EVRT_TRACE_WAVES 8
+#endif
 constexpr int kTB = 256;
-constexpr int kLdsNodes = 64;
-constexpr int kStackLds = 16;
+constexpr int kLdsNodes = EVRT_LDS_NODES;
+constexpr int kStackLds = EVRT_STACK_LDS;
 constexpr int kStackMax = 64;
 
-template <bool ANY, bool COUNT>
-__device__ __forceinline__ bool traverse(const InstSel &is, const float4 *lds_nodes,
-                                         uint32_t *lds_stack, const TRay &r, float tmin, float tmax,
-                                         uint32_t skip, float &best_t, uint32_t &best_p,
-                                         uint32_t &visits, uint32_t &tests)
+
+// Per-lane traversal state: the ray, the open segment (tmin, tmax), the
+// current far bound (closest hit so far, or tmax for any-hit), the next
+// reference to process and the stack depth.
+struct Trav {
+    TRay r;
+    float tmin, tmax, tfar;
+    uint32_t skip, best_p;
+    int32_t ref;
+    int sp;
+    uint32_t inst;
+};
+
+__device__ __forceinline__ void trav_begin(Trav &T, const DevScene &sc, uint32_t inst, float ox, float oy,
+                                           float oz, float dx, float dy, float dz, float tmin, float tmax,
+                                           uint32_t skip)
 {
-    best_t = tmax;
-    best_p = kNoPrim;
-    if (is.root == kEmptyRef) return false;
+    T.r = make_tray(ox, oy, oz, dx, dy, dz);
+    T.tmin = tmin;
+    T.tmax = tmax;
+    T.tfar = tmax;
+    T.skip = skip;
+    T.best_p = kNoPrim;
+    T.inst = inst;
+    T.ref = inst ? sc.inst[1].root : sc.inst[0].root;
+    T.sp = 0;
+}
+
+// LDS-typed pointers keep LDS accesses as ds_read/ds_write (a generic
+// pointer that may also point elsewhere compiles to flat accesses).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) float lds_f32;
+
+__device__ __forceinline__ float4 lds_load4(const lds_f32 *p)
+{
+    return make_float4(p[0], p[1], p[2], p[3]);
+}
+
+// Stack entry sp: LDS for the first kStackLds entries, private memory
+// beyond (the LDS read is always issued in bounds so that it stays a plain
+// LDS access).
+__device__ __forceinline__ int32_t stack_pop(int sp, const lds_u32 *lds_stack, const int32_t *spill)
+{
+    int32_t v = (int32_t)lds_stack[min(sp, kStackLds - 1) * kTB];
+    if (sp >= kStackLds) v = spill[sp - kStackLds];
+    return v;
+}
+
+// Ordered descent through one inner node: test both child boxes, go to the
+// nearer hit child and push the farther one, or pop when neither is hit.
+// Returns false when the stack is empty (traversal complete).
+__device__ __forceinline__ bool visit_node(Trav &T, float4 n0, float4 n1, float4 n2, float4 n3,
+                                           lds_u32 *lds_stack, int32_t *spill)
+{
+    float tl, tr;
+    box2(T.r, n0, n1, n2, T.tmin, T.tfar, tl, tr);
+    const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+    const bool hl = tl != INFINITY, hr = tr != INFINITY;
+    if (hl && hr) {
+        const bool lfirst = tl <= tr;
+        const int32_t far = lfirst ? cr : cl;
+        T.ref = lfirst ? cl : cr;
+        if (T.sp < kStackLds) lds_stack[T.sp * kTB] = (uint32_t)far;
+        else spill[T.sp - kStackLds] = far;
+        ++T.sp;
+        return true;
+    }
+    if (hl || hr) {
+        T.ref = hl ? cl : cr;
+        return true;
+    }
+    if (T.sp == 0) return false;
+    --T.sp;
+    T.ref = stack_pop(T.sp, lds_stack, spill);
+    return true;
+}
+
+// Full traversal of one ray (while-while): inner nodes of the LDS treelet,
+// inner nodes in global memory, then one leaf, until the stack empties.
+// ANY stops at the first accepted hit.  Result: T.tfar / T.best_p.
+template <bool ANY, bool COUNT>
+__device__ __forceinline__ void traverse(Trav &T, const DevScene &sc, const lds_f32 *s_nodes,
+                                         lds_u32 *lds_stack, uint32_t &visits, uint32_t &tests)
+{
+    if (T.ref == kEmptyRef) return;
     int32_t spill[kStackMax - kStackLds];
-    int sp = 0;
-    int32_t ref = is.root;
-    for (;;) {
-        if (ref >= 0) {
-            float4 n0, n1, n2, n3;
-            if ((uint32_t)ref < is.n_lds) {
-                const float4 *p = lds_nodes + 4 * ref;
-                n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
-            } else {
-                const float4 *p = is.nodes + 4 * (size_t)ref;
-                n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
-            }
+    const uint32_t n_lds = T.inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
+    const lds_f32 *lds = s_nodes + T.inst * 16 * kLdsNodes;
+    const float4 *nodes = T.inst ? sc.inst[1].nodes : sc.inst[0].nodes;
+    const float4 *tris = T.inst ? sc.inst[1].tris : sc.inst[0].tris;
+    bool live = true;
+    while (live) {
+        while (live && T.ref >= 0 && (uint32_t)T.ref < n_lds) {
+            const lds_f32 *p = lds + 16 * T.ref;
             if (COUNT) ++visits;
-            float tl, tr;
-            box2(r, n0, n1, n2, tmin, best_t, tl, tr);
-            const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-            const bool hl = tl != INFINITY, hr = tr != INFINITY;
-            if (hl && hr) {
-                const bool lfirst = tl <= tr;
-                const int32_t far = lfirst ? cr : cl;
-                ref = lfirst ? cl : cr;
-                if (sp < kStackLds) lds_stack[sp * kTB] = (uint32_t)far;
-                else spill[sp - kStackLds] = far;
-                ++sp;
-                continue;
-            }
-            if (hl || hr) {
-                ref = hl ? cl : cr;
-                continue;
-            }
-        } else {
-            const uint32_t packed = ~(uint32_t)ref;
+            live = visit_node(T, lds_load4(p), lds_load4(p + 4), lds_load4(p + 8), lds_load4(p + 12), lds_stack,
+                              spill);
+        }
+        while (live && T.ref >= 0 && (uint32_t)T.ref >= n_lds) {
+            const float4 *p = nodes + 4 * (size_t)T.ref;
+            if (COUNT) ++visits;
+            live = visit_node(T, p[0], p[1], p[2], p[3], lds_stack, spill);
+        }
+        if (live && T.ref < 0) {
+            const uint32_t packed = ~(uint32_t)T.ref;
             const uint32_t first = packed >> kLeafCountBits;
             const uint32_t count = (packed & (kMaxLeafTris - 1)) + 1;
             for (uint32_t k = 0; k < count; ++k) {
-                const float4 *tp = is.tris + 3 * (size_t)(first + k);
+                const float4 *tp = tris + 3 * (size_t)(first + k);
                 const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
                 const uint32_t prim = fbits(v0.w);
-                if (prim == skip) continue;
-                if (COUNT) ++tests;
+                if (COUNT) tests += prim != T.skip;
                 float t;
-                if (!tri_test(r, v0, v1, v2, t)) continue;
-                if (!(t > tmin) || !(t < tmax)) continue;
+                // The test runs before the origin-primitive check so that the
+                // three vertex loads issue together.
+                const bool h = tri_test(T.r, v0, v1, v2, t);
+                if (!h || prim == T.skip) continue;
+                if (!(t > T.tmin) || !(t < T.tmax)) continue;
                 if (ANY) {
-                    best_t = t;
-                    best_p = prim;
-                    return true;
+                    T.best_p = prim;
+                    return;
                 }
-                if (t < best_t || (t == best_t && prim < best_p)) {
-                    best_t = t;
-                    best_p = prim;
+                if (t < T.tfar || (t == T.tfar && prim < T.best_p)) {
+                    T.tfar = t;
+                    T.best_p = prim;
                 }
             }
+            if (T.sp == 0) {
+                live = false;
+            } else {
+                --T.sp;
+                T.ref = stack_pop(T.sp, lds_stack, spill);
+            }
         }
-        // pop
-        if (sp == 0) break;
-        --sp;
-        ref = sp < kStackLds ? (int32_t)lds_stack[sp * kTB] : spill[sp - kStackLds];
     }
-    return best_p != kNoPrim;
 }
 
 __device__ __forceinline__ void load_treelets(const DevScene &sc, float4 *s_nodes)
@@ -359,9 +433,9 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
 }
 
 // Closest hit of the queued rays; hit[i] = (t, prim bits), prim = kNoPrim on
-// a miss.  Persistent grid-stride over the device-side queue count.
+// a miss.  Grid-stride over the device-side queue count, one ray per lane.
 template <bool COUNT>
-__global__ __launch_bounds__(kTB) void k_trace_closest(DevScene sc, RayQueue q, const uint32_t *cnt_in,
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_closest(DevScene sc, RayQueue q, const uint32_t *cnt_in,
                                                        float2 *hit, int stat_kind,
                                                        unsigned long long *stat)
 {
@@ -373,15 +447,11 @@ __global__ __launch_bounds__(kTB) void k_trace_closest(DevScene sc, RayQueue q, 
     uint32_t visits = 0, tests = 0;
     for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
         const float4 o = q.o[i], d = q.d[i];
-        const uint32_t skip = q.skip[i];
         const uint32_t inst = fbits(d.w) >> 31;
-        const InstSel is = select_inst(sc, inst);
-        const TRay r = make_tray(o.x, o.y, o.z, d.x, d.y, d.z);
-        float bt;
-        uint32_t bp;
-        traverse<false, COUNT>(is, s_nodes + inst * 4 * kLdsNodes, s_stack + threadIdx.x, r, kRayTmin,
-                               INFINITY, skip, bt, bp, visits, tests);
-        hit[i] = make_float2(bt, bitsf(bp));
+        Trav T;
+        trav_begin(T, sc, inst, o.x, o.y, o.z, d.x, d.y, d.z, kRayTmin, INFINITY, q.skip[i]);
+        traverse<false, COUNT>(T, sc, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
+        hit[i] = make_float2(T.tfar, bitsf(T.best_p));
     }
     if (COUNT) {
         const unsigned long long v = wave_sum_u64(visits), t = wave_sum_u64(tests);
@@ -392,10 +462,11 @@ __global__ __launch_bounds__(kTB) void k_trace_closest(DevScene sc, RayQueue q, 
     }
 }
 
-// Shadow rays: every unoccluded slot adds its contribution; the sum over
-// the entry's slots (in slot order) is added to the path radiance.
+// Shadow entries: the n_slots rays of an entry share its origin; the
+// contributions of the unoccluded slots are summed in slot order and added
+// to the path radiance once.
 template <bool COUNT>
-__global__ __launch_bounds__(kTB) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
                                                       const uint32_t *cnt_in, float *rad,
                                                       unsigned long long *stat)
 {
@@ -408,20 +479,16 @@ __global__ __launch_bounds__(kTB) void k_trace_shadow(DevScene sc, ShadowQueue s
         const float4 o = sq.o[e];
         const uint32_t meta = sq.meta[e];
         const uint32_t inst = meta >> 31;
-        const uint32_t skip = meta & ~kInstBit;
-        const InstSel is = select_inst(sc, inst);
         float sum = 0.0f;
         for (uint32_t k = 0; k < n_slots; ++k) {
             const float c = sq.c[k * sq.cap + e];
             if (!(c > 0.0f)) continue;
             const float4 w = sq.dir[k * sq.cap + e];
-            const TRay r = make_tray(o.x, o.y, o.z, w.x, w.y, w.z);
-            float bt;
-            uint32_t bp;
+            Trav T;
+            trav_begin(T, sc, inst, o.x, o.y, o.z, w.x, w.y, w.z, kRayTmin, w.w, meta & ~kInstBit);
             ++rays;
-            if (!traverse<true, COUNT>(is, s_nodes + inst * 4 * kLdsNodes, s_stack + threadIdx.x, r,
-                                       kRayTmin, w.w, skip, bt, bp, visits, tests))
-                sum = sum + c;
+            traverse<true, COUNT>(T, sc, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
+            if (T.best_p == kNoPrim) sum = sum + c;
         }
         const uint32_t ri = fbits(o.w);
         rad[ri] = rad[ri] + sum;
@@ -553,7 +620,9 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                     const float e0 = u01(r1.x), e1 = u01(r1.y);
                     const float rr = sqrtf(e0);
                     const double ph = kTwoPi * (double)e1;
-                    const float cph = (float)cos(ph), sph = (float)sin(ph);
+                    double sd, cd;
+                    sincos(ph, &sd, &cd);
+                    const float cph = (float)cd, sph = (float)sd;
                     const float lx = rr * cph, ly = rr * sph, lz = sqrtf(fmaxf(0.0f, 1.0f - e0));
                     // Orthonormal basis around ns (Duff et al. 2017).
                     const float sg = copysignf(1.0f, nsz);
@@ -702,7 +771,7 @@ __global__ void k_hook_rays(uint32_t n, const float *rays, const uint32_t *skip,
 
 // Trace hook: arbitrary (tmin, tmax) per ray, instant slot 0.
 template <bool ANY>
-__global__ __launch_bounds__(kTB) void k_hook_trace(DevScene sc, RayQueue q, const float *tminmax,
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_hook_trace(DevScene sc, RayQueue q, const float *tminmax,
                                                     uint32_t n, float *t_out, uint32_t *p_out)
 {
     __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
@@ -711,17 +780,14 @@ __global__ __launch_bounds__(kTB) void k_hook_trace(DevScene sc, RayQueue q, con
     uint32_t visits = 0, tests = 0;
     for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
         const float4 o = q.o[i], d = q.d[i];
-        const InstSel is = select_inst(sc, 0);
-        const TRay r = make_tray(o.x, o.y, o.z, d.x, d.y, d.z);
-        float bt;
-        uint32_t bp;
-        const bool h = traverse<ANY, false>(is, s_nodes, s_stack + threadIdx.x, r, tminmax[2 * i],
-                                            tminmax[2 * i + 1], q.skip[i], bt, bp, visits, tests);
+        Trav T;
+        trav_begin(T, sc, 0, o.x, o.y, o.z, d.x, d.y, d.z, tminmax[2 * i], tminmax[2 * i + 1], q.skip[i]);
+        traverse<ANY, false>(T, sc, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
         if (ANY) {
-            p_out[i] = h ? 1u : 0u;
+            p_out[i] = T.best_p != kNoPrim ? 1u : 0u;
         } else {
-            if (t_out) t_out[i] = bt;
-            p_out[i] = bp;
+            if (t_out) t_out[i] = T.tfar;
+            p_out[i] = T.best_p;
         }
     }
 }
@@ -792,11 +858,11 @@ void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevSc
                          unsigned long long *stat)
 {
     if (count)
-        hipLaunchKernelGGL(k_trace_shadow<true>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
-                           rad, stat);
+        hipLaunchKernelGGL(k_trace_shadow<true>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, rad,
+                           stat);
     else
-        hipLaunchKernelGGL(k_trace_shadow<false>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
-                           rad, stat);
+        hipLaunchKernelGGL(k_trace_shadow<false>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, rad,
+                           stat);
 }
 
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
@@ -836,11 +902,9 @@ void launch_hook_trace(hipStream_t s, uint32_t blocks, bool any, const DevScene 
                        const float *tminmax, uint32_t n, float *t_out, uint32_t *p_out)
 {
     if (any)
-        hipLaunchKernelGGL(k_hook_trace<true>, dim3(blocks), dim3(kTB), 0, s, sc, q, tminmax, n, t_out,
-                           p_out);
+        hipLaunchKernelGGL(k_hook_trace<true>, dim3(blocks), dim3(kTB), 0, s, sc, q, tminmax, n, t_out, p_out);
     else
-        hipLaunchKernelGGL(k_hook_trace<false>, dim3(blocks), dim3(kTB), 0, s, sc, q, tminmax, n, t_out,
-                           p_out);
+        hipLaunchKernelGGL(k_hook_trace<false>, dim3(blocks), dim3(kTB), 0, s, sc, q, tminmax, n, t_out, p_out);
 }
 
 void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint32_t n, uint32_t m,

@@ -72,11 +72,14 @@ std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s
     return bi;
 }
 
-DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b)
+DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b, uint32_t lds_nodes)
 {
     DevScene sc{};
     sc.inst[0] = a.view;
     sc.inst[1] = b.view;
+    // The builder lays the top nodes out first; stage only as many as asked.
+    sc.inst[0].n_lds = std::min(sc.inst[0].n_lds, lds_nodes);
+    sc.inst[1].n_lds = std::min(sc.inst[1].n_lds, lds_nodes);
     sc.mat = c->mat.as<const float2>();
     sc.plights = c->plights.as<const float4>();
     sc.n_plights = (uint32_t)c->scene.pl_int.size();
@@ -283,7 +286,7 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
     std::memset(&c->stats, 0, sizeof(c->stats));
     auto ga = get_instant(c, t0, s, &c->stats.ms_build);
     auto gb = get_instant(c, t1, s, &c->stats.ms_build);
-    const DevScene sc = make_dev_scene(c, *ga, *gb);
+    const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
     const uint32_t npx = sc.width * sc.height;
     const uint32_t mb = o.minibatch;
@@ -358,7 +361,7 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
     std::memset(&c->stats, 0, sizeof(c->stats));
     auto ga = get_instant(c, t0, s, &c->stats.ms_build);
     auto gb = get_instant(c, t1, s, &c->stats.ms_build);
-    const DevScene sc = make_dev_scene(c, *ga, *gb);
+    const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
     const uint32_t npx = sc.width * sc.height;
     const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
@@ -393,7 +396,7 @@ void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint
 {
     std::memset(&c->stats, 0, sizeof(c->stats));
     auto g = get_instant(c, t, s, &c->stats.ms_build);
-    const DevScene sc = make_dev_scene(c, *g, *g);
+    const DevScene sc = make_dev_scene(c, *g, *g, (uint32_t)lds_treelet_nodes());
     ensure_buffers(c, sc.width * sc.height, n, 1);
     FrameBuffers &fb = c->fb;
     fb.hook_tm.ensure(sizeof(float) * 2 * (size_t)n);

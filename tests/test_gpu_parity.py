@@ -44,7 +44,7 @@ def _opts_from(params: dict, **kw):
     d = dict(params)
     d.update(kw)
     keys = ("seed", "max_depth", "rr_start_depth", "minibatch", "log_eps", "nee", "jitter", "mode",
-            "df_mode", "ref_mode")
+            "df_mode", "ref_mode", "lds_nodes", "ray_batch")
     return {k: d[k] for k in keys if k in d}
 
 
@@ -192,7 +192,8 @@ def _compare(g, r, pixels, C):
     return s
 
 
-@pytest.mark.parametrize("variant", ["default", "fixed", "ref_full", "two_tailed", "mean_only", "mb1", "mb8"])
+@pytest.mark.parametrize("variant", ["default", "fixed", "ref_full", "two_tailed", "mean_only", "mb1", "mb8",
+                                     "lds_treelet", "small_pieces"])
 def test_tiny_frame_parity(rend, torch_cuda, variant):
     sc = scenes.tiny_box()
     rend.set_scene(sc)
@@ -209,10 +210,14 @@ def test_tiny_frame_parity(rend, torch_cuda, variant):
         params.update(minibatch=1, log_eps=1e-3, spp_init=8, spp_batch=8, spp_max=64)
     elif variant == "mb8":
         params.update(minibatch=8, spp_init=16, spp_batch=24, spp_max=256)
+    elif variant == "lds_treelet":
+        params["lds_nodes"] = 64
+    elif variant == "small_pieces":
+        params["ray_batch"] = 40000   # many pieces per round
     _say(f"tiny frame variant={variant}")
     g, st = _frame(rend, sc, params, 0.0, 1.0)
     with oracle.Frame(sc, 0.0, 1.0) as f:
-        r = f.render(oracle.make_params(**params))
+        r = f.render(oracle.make_params(**{k: v for k, v in params.items() if k not in ("lds_nodes", "ray_batch")}))
     _compare(g, r, np.arange(sc.n_pixels), params["C"])
     assert st["rounds"] >= 1 and st["camera_rays"] > 0
 
@@ -222,7 +227,7 @@ def test_tiny_frame_invariants_and_determinism(rend, torch_cuda):
     rend.set_scene(sc)
     P = scenes.TINY_PARAMS
     a, st = _frame(rend, sc, P, 0.0, 1.0)
-    b, _ = _frame(rend, sc, P, 0.0, 1.0, ray_batch=1 << 16) if False else _frame(rend, sc, P, 0.0, 1.0)
+    b, _ = _frame(rend, sc, P, 0.0, 1.0, ray_batch=1 << 15, lds_nodes=64)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
     n = a["n_paths"]
