@@ -60,6 +60,8 @@ def main() -> int:
     ap.add_argument("--cpu-step", type=int, default=16, help="oracle sample: every n-th pixel in x and y")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the timed adaptive frames (for profiler runs)")
+    ap.add_argument("--ray-batch", type=int, default=0, help="paths in flight per piece (0: library default)")
+    ap.add_argument("--lds-nodes", type=int, default=0, help="top BVH nodes staged in LDS")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
     args = ap.parse_args()
@@ -85,7 +87,8 @@ def main() -> int:
     sc = scenes.sensor()
     P = dict(scenes.SENSOR_PARAMS, C=args.C)
     base_opts = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
-                     minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+                     minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"],
+                     ray_batch=args.ray_batch, lds_nodes=args.lds_nodes)
     r = ev.Renderer(0)
     t_build = time.perf_counter()
     r.set_scene(sc)

@@ -15,7 +15,7 @@
 
 namespace evrt {
 
-static constexpr uint32_t kDefaultRayBatch = 1u << 22;
+static constexpr uint32_t kDefaultRayBatch = 1u << 24;
 static constexpr uint32_t kMaxPathId = 1u << 31;
 static constexpr size_t kCacheInstants = 4;
 
@@ -229,37 +229,52 @@ static double crit_value(evrt_ctx *c, double p, uint32_t df)
     return q;
 }
 
-// Pieces covering samples [lo, hi) of nA pixels at n_inst instants.
+// Pieces covering samples [lo, hi) of nA pixels at n_inst instants.  A
+// piece holds at most `ray_batch` paths: blocks of consecutive active pixels
+// with the whole sample range when that fits, otherwise every pixel with a
+// sub-range of whole mini-batches.  Each pixel's samples are accumulated in
+// increasing order either way.
 static void trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t n_inst, uint32_t inst_base,
                         uint32_t lo, uint32_t hi, const DevScene &sc, const RenderParams &rp,
                         const evrt_render_opts &o, hipStream_t s, Profiler &prof)
 {
     const uint32_t mb = rp.minibatch;
-    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
-    const uint64_t per_sample = (uint64_t)nA * n_inst;
-    uint64_t bp_max = std::max<uint64_t>(mb, (batch / std::max<uint64_t>(1, per_sample)) / mb * mb);
-    bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / per_sample / mb * mb);
+    const uint64_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    const uint64_t range = hi - lo;
+    const uint64_t per_px = (uint64_t)n_inst * range;
+    uint64_t px_block = std::max<uint64_t>(1, batch / per_px);
+    uint64_t bp_max = range;
+    if (px_block < 64 && px_block < nA) {
+        // Too few pixels per block: split the samples instead.
+        px_block = nA;
+        bp_max = std::max<uint64_t>(mb, batch / ((uint64_t)nA * n_inst) / mb * mb);
+    }
+    px_block = std::min<uint64_t>(px_block, nA);
+    bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / (px_block * n_inst) / mb * mb);
     if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many pixels for one piece");
-    for (uint32_t s0 = lo; s0 < hi;) {
-        const uint32_t bp = (uint32_t)std::min<uint64_t>(bp_max, hi - s0);
-        Piece pc{};
-        pc.act = act;
-        pc.nA = nA;
-        pc.bp = bp;
-        pc.n_inst = n_inst;
-        pc.inst_base = inst_base;
-        pc.s0 = s0;
-        pc.n_paths = (uint32_t)(per_sample * bp);
-        pc.div_bp = make_fastdiv(bp);
-        pc.div_nA = make_fastdiv(nA);
-        pc.rs_a = bp;
-        pc.rs_i = nA * bp;
-        ensure_buffers(c, sc.width * sc.height, pc.n_paths, rp.n_slots);
-        pc.rad = c->fb.rad.as<float>();
-        trace_piece(c, pc, sc, rp, o, s, prof);
-        launch_accumulate(s, pc, rp, c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
-                          c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>());
-        s0 += bp;
+    for (uint32_t a0 = 0; a0 < nA; a0 += (uint32_t)px_block) {
+        const uint32_t na = (uint32_t)std::min<uint64_t>(px_block, nA - a0);
+        for (uint32_t s0 = lo; s0 < hi;) {
+            const uint32_t bp = (uint32_t)std::min<uint64_t>(bp_max, hi - s0);
+            Piece pc{};
+            pc.act = act + a0;
+            pc.nA = na;
+            pc.bp = bp;
+            pc.n_inst = n_inst;
+            pc.inst_base = inst_base;
+            pc.s0 = s0;
+            pc.n_paths = na * n_inst * bp;
+            pc.div_bp = make_fastdiv(bp);
+            pc.div_nA = make_fastdiv(na);
+            pc.rs_a = bp;
+            pc.rs_i = na * bp;
+            ensure_buffers(c, sc.width * sc.height, pc.n_paths, rp.n_slots);
+            pc.rad = c->fb.rad.as<float>();
+            trace_piece(c, pc, sc, rp, o, s, prof);
+            launch_accumulate(s, pc, rp, c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
+                              c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>());
+            s0 += bp;
+        }
     }
 }
 
@@ -290,9 +305,11 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
     const RenderParams rp = make_params(c, o);
     const uint32_t npx = sc.width * sc.height;
     const uint32_t mb = o.minibatch;
-    // Largest piece of the frame: round 0 (every pixel, both instants).
+    // Largest piece of the frame: at most ray_batch paths, or one
+    // mini-batch of every pixel when that is larger, or 64 pixels' ranges.
     const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
-    const uint64_t all = 2ull * npx * spp_max, floor_piece = 2ull * npx * mb;
+    const uint64_t all = 2ull * npx * spp_max;
+    const uint64_t floor_piece = std::min<uint64_t>(2ull * npx * mb, 2ull * 64 * spp_max);
     const uint64_t cap = std::max<uint64_t>(std::min<uint64_t>(batch, all), floor_piece);
     if (cap >= kMaxPathId) fail(EVRT_E_UNSUPPORTED, "image too large for one mini-batch piece");
     ensure_buffers(c, npx, (uint32_t)cap, rp.n_slots);
