@@ -6,12 +6,13 @@
 
 namespace evrt {
 
-// Layout of the uint32 device counter array.
-constexpr int kCntMaxDepth = 64;                   // max_depth limit
-constexpr int kCntRay0 = 0;                        // [0, 64]: rays to trace per bounce
-constexpr int kCntShadow0 = kCntRay0 + kCntMaxDepth + 1;  // [65, 129]: shadow entries
-constexpr int kCntActive = 200;                    // [200, 201]: compaction counts (alternating rounds)
-constexpr int kCntSize = 256;
+// Layout of the uint32 device counter array: two counts (one per instant
+// region) per bounce.
+constexpr int kCntMaxDepth = 64;                           // max_depth limit
+constexpr int kCntRay0 = 0;                                // [0, 130): rays to trace per bounce
+constexpr int kCntShadow0 = kCntRay0 + 2 * (kCntMaxDepth + 1);  // [130, 260): shadow entries
+constexpr int kCntActive = kCntShadow0 + 2 * (kCntMaxDepth + 1); // [260, 262): compaction counts
+constexpr int kCntSize = 320;
 
 // Decision constants of one round.
 struct Decide {
@@ -35,12 +36,14 @@ void launch_init_frame(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_m
                        double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat);
 void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const RenderParams &rp,
                    const RayQueue &q, uint32_t *cnt);
+// Traversal and shading kernels take the per-region counts cnt_in[0..1],
+// the region size and the number of regions; grids must be multiples of 8.
 void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
-                          const RayQueue &q, const uint32_t *cnt_in, float2 *hit, int stat_kind,
-                          unsigned long long *stat);
+                          const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
+                          float2 *hit, int stat_kind, unsigned long long *stat);
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
-                         const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, float *rad,
-                         unsigned long long *stat);
+                         const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
+                         uint32_t n_split, float *rad, unsigned long long *stat);
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,

@@ -70,10 +70,12 @@ struct RenderParams {
 // A piece of a round: samples [s0, s0 + bp) of nA pixels (the active list)
 // at n_inst instants starting at inst_base.  Piece-local path id
 // p = (ii * nA + a) * bp + s; its radiance goes to rad[a*rs_a + ii*rs_i + s].
+// Queues are split into n_inst regions of `region` slots, one per instant
+// (the camera ray of path p sits at slot p).
 struct Piece {
     const uint32_t *act;
     uint32_t nA, bp, n_inst, inst_base, s0;
-    uint32_t n_paths;
+    uint32_t n_paths, region;
     FastDiv div_bp, div_nA;
     float *rad;
     uint32_t rs_a, rs_i;

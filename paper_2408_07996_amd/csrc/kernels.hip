@@ -91,6 +91,32 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// XCD-aware split of a queue with one region per instant.  Workgroups are
+// dispatched round-robin over the 8 XCDs, so with n_split = 2 the blocks of
+// XCDs 0-3 take the first instant's region and those of XCDs 4-7 the
+// second's: each XCD's L2 then caches one instant's geometry.
+struct Part {
+    uint32_t base, n, lb, lgrid;
+};
+
+__device__ __forceinline__ Part partition(const uint32_t *cnt2, uint32_t region, uint32_t n_split)
+{
+    Part p;
+    uint32_t r = 0;
+    if (n_split == 2) {
+        const uint32_t xcd = blockIdx.x & 7u;
+        r = xcd >> 2;
+        p.lb = (blockIdx.x >> 3) * 4u + (xcd & 3u);
+        p.lgrid = (gridDim.x >> 3) * 4u;
+    } else {
+        p.lb = blockIdx.x;
+        p.lgrid = gridDim.x;
+    }
+    p.base = r * region;
+    p.n = cnt2[r];
+    return p;
+}
+
 // ------------------------------------------------------------------------
 // Ray preparation shared by both traversal kinds.
 
@@ -398,9 +424,10 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
 {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0) {
-        cnt[kCntRay0] = pc.n_paths;
-        for (int k = 1; k < kCntMaxDepth + 1; ++k) cnt[kCntRay0 + k] = 0;
-        for (int k = 0; k < kCntMaxDepth + 1; ++k) cnt[kCntShadow0 + k] = 0;
+        cnt[kCntRay0] = pc.region;
+        cnt[kCntRay0 + 1] = pc.n_inst == 2 ? pc.region : 0u;
+        for (int k = 2; k < 2 * (kCntMaxDepth + 1); ++k) cnt[kCntRay0 + k] = 0;
+        for (int k = 0; k < 2 * (kCntMaxDepth + 1); ++k) cnt[kCntShadow0 + k] = 0;
     }
     if (p >= pc.n_paths) return;
     const uint32_t qq = fdiv(pc.div_bp, p);
@@ -438,16 +465,17 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
 // a miss.  Grid-stride over the device-side queue count, one ray per lane.
 template <bool COUNT>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_closest(DevScene sc, RayQueue q, const uint32_t *cnt_in,
-                                                       float2 *hit, int stat_kind,
-                                                       unsigned long long *stat)
+                                                       uint32_t region, uint32_t n_split, float2 *hit,
+                                                       int stat_kind, unsigned long long *stat)
 {
     __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
     load_treelets(sc, s_nodes);
-    const uint32_t n = *cnt_in;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(stat + stat_kind, (unsigned long long)n);
+    const Part pt = partition(cnt_in, region, n_split);
+    if (pt.lb == 0 && threadIdx.x == 0 && pt.n) atomicAdd(stat + stat_kind, (unsigned long long)pt.n);
     uint32_t visits = 0, tests = 0;
-    for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
+    for (uint32_t j = pt.lb * kTB + threadIdx.x; j < pt.n; j += pt.lgrid * kTB) {
+        const uint32_t i = pt.base + j;
         const float4 o = q.o[i], d = q.d[i];
         const uint32_t inst = fbits(d.w) >> 31;
         Trav T;
@@ -469,15 +497,17 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
 // to the path radiance once.
 template <bool COUNT>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
-                                                      const uint32_t *cnt_in, float *rad,
+                                                      const uint32_t *cnt_in, uint32_t region,
+                                                      uint32_t n_split, float *rad,
                                                       unsigned long long *stat)
 {
     __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
     load_treelets(sc, s_nodes);
-    const uint32_t n = *cnt_in;
+    const Part pt = partition(cnt_in, region, n_split);
     uint32_t visits = 0, tests = 0, rays = 0;
-    for (uint32_t e = blockIdx.x * kTB + threadIdx.x; e < n; e += gridDim.x * kTB) {
+    for (uint32_t j = pt.lb * kTB + threadIdx.x; j < pt.n; j += pt.lgrid * kTB) {
+        const uint32_t e = pt.base + j;
         const float4 o = sq.o[e];
         const uint32_t meta = sq.meta[e];
         const uint32_t inst = meta >> 31;
@@ -533,8 +563,9 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                                                RayQueue qout, uint32_t *cnt_out, ShadowQueue sq,
                                                uint32_t *cnt_sh, uint32_t depth)
 {
-    const uint32_t n = *cnt_in;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const Part pt = partition(cnt_in, pc.region, pc.n_inst);
+    for (uint32_t j = pt.lb * blockDim.x + threadIdx.x; j < pt.n; j += pt.lgrid * blockDim.x) {
+        const uint32_t i = pt.base + j;
         const float2 h = hit[i];
         const uint32_t prim = fbits(h.y);
         bool want_shadow = false, want_ext = false;
@@ -640,7 +671,8 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                 }
             }
         }
-        const uint32_t se = wave_append(want_shadow, cnt_sh);
+        const uint32_t r = pt.base / max(pc.region, 1u);
+        const uint32_t se = pt.base + wave_append(want_shadow, cnt_sh + r);
         if (want_shadow) {
             sq.o[se] = make_float4(Px, Py, Pz, bitsf(ri));
             sq.meta[se] = prim | (inst << 31);
@@ -653,7 +685,7 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                 if (ck > 0.0f) sq.dir[(k + 1) * sq.cap + se] = dk;
             }
         }
-        const uint32_t xe = wave_append(want_ext, cnt_out);
+        const uint32_t xe = pt.base + wave_append(want_ext, cnt_out + r);
         if (want_ext) {
             qout.o[xe] = make_float4(Px, Py, Pz, beta);
             qout.d[xe] = make_float4(ndx, ndy, ndz, bitsf(pword));
@@ -844,27 +876,27 @@ void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const Ren
 }
 
 void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
-                          const RayQueue &q, const uint32_t *cnt_in, float2 *hit, int stat_kind,
-                          unsigned long long *stat)
+                          const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
+                          float2 *hit, int stat_kind, unsigned long long *stat)
 {
     if (count)
-        hipLaunchKernelGGL(k_trace_closest<true>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, hit,
-                           stat_kind, stat);
+        hipLaunchKernelGGL(k_trace_closest<true>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region, n_split,
+                           hit, stat_kind, stat);
     else
-        hipLaunchKernelGGL(k_trace_closest<false>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, hit,
-                           stat_kind, stat);
+        hipLaunchKernelGGL(k_trace_closest<false>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region, n_split,
+                           hit, stat_kind, stat);
 }
 
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
-                         const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, float *rad,
-                         unsigned long long *stat)
+                         const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
+                         uint32_t n_split, float *rad, unsigned long long *stat)
 {
     if (count)
-        hipLaunchKernelGGL(k_trace_shadow<true>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, rad,
-                           stat);
+        hipLaunchKernelGGL(k_trace_shadow<true>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, region,
+                           n_split, rad, stat);
     else
-        hipLaunchKernelGGL(k_trace_shadow<false>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, rad,
-                           stat);
+        hipLaunchKernelGGL(k_trace_shadow<false>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, region,
+                           n_split, rad, stat);
 }
 
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,

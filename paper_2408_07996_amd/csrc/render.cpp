@@ -137,11 +137,15 @@ static void ensure_buffers(evrt_ctx *c, uint32_t npx, uint32_t cap, uint32_t slo
     }
 }
 
+// Grid for a queue of up to `work` items: enough blocks to fill the chip or
+// cover the work, rounded up to a multiple of the 8 XCDs (the per-instant
+// queue split maps XCDs to instants).
 static uint32_t blocks_for(uint32_t per_cu, uint32_t cu, uint32_t work, uint32_t tb)
 {
     const uint32_t need = (work + tb - 1) / tb;
     const uint32_t fill = std::max(1u, per_cu * cu);
-    return std::max(1u, std::min(need, fill));
+    const uint32_t b = std::max(1u, std::min(need, fill));
+    return (b + 7u) & ~7u;
 }
 
 struct Profiler {
@@ -200,15 +204,16 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
         const RayQueue &qin = q[(d - 1) & 1];
         const RayQueue &qout = q[d & 1];
         prof.begin(0);
-        launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + d - 1, fb.hit.as<float2>(),
-                             d == 1 ? kStatCamera : kStatExtension, stat);
+        launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + 2 * (d - 1), pc.region, pc.n_inst,
+                             fb.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat);
         prof.end();
         c->stats.n_closest_launches++;
-        launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + d - 1, fb.hit.as<float2>(), qout,
-                     cnt + kCntRay0 + d, sq, cnt + kCntShadow0 + d, d);
+        launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), fb.hit.as<float2>(), qout,
+                     cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d);
         if (rp.nee) {
             prof.begin(1);
-            launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + d, pc.rad, stat);
+            launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
+                                pc.n_inst, pc.rad, stat);
             prof.end();
             c->stats.n_shadow_launches++;
         }
@@ -264,6 +269,7 @@ static void trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
             pc.inst_base = inst_base;
             pc.s0 = s0;
             pc.n_paths = na * n_inst * bp;
+            pc.region = na * bp;
             pc.div_bp = make_fastdiv(bp);
             pc.div_nA = make_fastdiv(na);
             pc.rs_a = bp;
@@ -398,6 +404,7 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
         pc.inst_base = 0;
         pc.s0 = 0;
         pc.n_paths = (uint32_t)(per_px * na);
+        pc.region = na * spp;
         pc.div_bp = make_fastdiv(spp);
         pc.div_nA = make_fastdiv(na);
         pc.rad = L_out + (size_t)a0 * per_px;  // [pixel][instant][sample]

@@ -189,7 +189,10 @@ struct Builder {
     explicit Builder(const std::vector<float> &t) : tri(t) {}
 
     static constexpr int kBins = 16;
-    static constexpr uint32_t kLeafTarget = 4;
+#ifndef EVRT_LEAF_TARGET
+#define EVRT_LEAF_TARGET 4
+#endif
+    static constexpr uint32_t kLeafTarget = EVRT_LEAF_TARGET;
     static constexpr uint32_t kSahDepthLimit = 32;
 
     int32_t build(uint32_t b, uint32_t e, uint32_t depth)
