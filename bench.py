@@ -57,7 +57,7 @@ def main() -> int:
     ap.add_argument("--C", type=float, default=0.15)
     ap.add_argument("--no-quality", action="store_true", help="skip the equal-quality fixed-spp ladder")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-step", type=int, default=16, help="oracle sample: every n-th pixel in x and y")
+    ap.add_argument("--cpu-step", type=int, default=2, help="oracle sample: every n-th pixel in x and y")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the timed adaptive frames (for profiler runs)")
     ap.add_argument("--ray-batch", type=int, default=0, help="paths in flight per piece (0: library default)")

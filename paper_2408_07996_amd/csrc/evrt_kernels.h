@@ -14,12 +14,17 @@ constexpr int kCntShadow0 = kCntRay0 + 2 * (kCntMaxDepth + 1);  // [130, 260): s
 constexpr int kCntActive = kCntShadow0 + 2 * (kCntMaxDepth + 1); // [260, 262): compaction counts
 constexpr int kCntSize = 320;
 
-// Decision constants of one round.
+// Decision constants of one round.  A round covers one or more checkpoints
+// of the mini-batch schedule: checkpoint j ends at sample count ck_end[j]
+// at the second instant and is tested with crit_lo[j] / crit_hi[j].
+constexpr uint32_t kMaxChecks = 32;
 struct Decide {
     double C;
-    double crit_lo, crit_hi;   // t critical values (lower tail, upper tail)
+    double crit_lo[kMaxChecks], crit_hi[kMaxChecks];  // t critical values (lower, upper tail)
+    uint32_t ck_end[kMaxChecks];
+    uint32_t n_checks;
     uint32_t mode;             // EVRT_MODE_*
-    uint32_t final_round;      // 1 at spp_max: event rule only
+    uint32_t final_round;      // 1 when the last checkpoint is spp_max: event rule only
     uint32_t minibatch;
     uint32_t cnt_slot;         // which of the two compaction counters this round uses
 };
@@ -50,6 +55,11 @@ void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScen
                   uint32_t *cnt_sh, uint32_t depth);
 void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
                        double *wf_mean, double *wf_m2, double *wf_ysum);
+// Welford updates and the decision at every checkpoint of the round, for
+// pieces that hold the round's whole sample range of their pixels.
+void launch_accumulate_decide(hipStream_t s, const Piece &pc, const RenderParams &rp, const Decide &dc,
+                              uint32_t *act_out, uint32_t *cnt, uint32_t *wf_n, double *wf_mean,
+                              double *wf_m2, double *wf_ysum, const Outputs &out);
 void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_in, uint32_t nA,
                            uint32_t *act_out, uint32_t *cnt, const uint32_t *wf_n,
                            const double *wf_mean, const double *wf_m2, const double *wf_ysum,

@@ -703,8 +703,46 @@ __device__ __forceinline__ float minibatch_mean(const float *v, uint32_t mb)
     return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) * 0.125f;
 }
 
-// Welford update of (count, mean, M2) with x = ln(Y + eps) for each
-// mini-batch of the piece, in sample order; one thread per (pixel, instant).
+// Running (count, mean, M2) of x = ln(Y + eps) over mini-batch means Y of
+// one pixel at one instant, and the sum of Y.
+struct Welford {
+    uint32_t n;
+    double mean, m2, ys;
+};
+
+__device__ __forceinline__ Welford welford_load(uint32_t slot, const uint32_t *wf_n, const double *wf_mean,
+                                                const double *wf_m2, const double *wf_ysum)
+{
+    return Welford{wf_n[slot], wf_mean[slot], wf_m2[slot], wf_ysum[slot]};
+}
+
+__device__ __forceinline__ void welford_store(const Welford &w, uint32_t slot, uint32_t *wf_n, double *wf_mean,
+                                              double *wf_m2, double *wf_ysum)
+{
+    wf_n[slot] = w.n;
+    wf_mean[slot] = w.mean;
+    wf_m2[slot] = w.m2;
+    wf_ysum[slot] = w.ys;
+}
+
+// Welford steps over len consecutive path radiances, mb per mini-batch, in
+// sample order.
+__device__ __forceinline__ void welford_run(Welford &w, const float *src, uint32_t len, uint32_t mb,
+                                            double log_eps)
+{
+    for (uint32_t k = 0; k < len; k += mb) {
+        const float Y = minibatch_mean(src + k, mb);
+        const double x = log((double)Y + log_eps);
+        w.n += 1;
+        const double delta = x - w.mean;
+        w.mean = w.mean + delta / (double)w.n;
+        w.m2 = w.m2 + delta * (x - w.mean);
+        w.ys = w.ys + (double)Y;
+    }
+}
+
+// Welford update for each mini-batch of the piece, in sample order; one
+// thread per (pixel, instant).
 __global__ void k_accumulate(Piece pc, RenderParams rp, uint32_t *wf_n, double *wf_mean,
                              double *wf_m2, double *wf_ysum)
 {
@@ -714,23 +752,9 @@ __global__ void k_accumulate(Piece pc, RenderParams rp, uint32_t *wf_n, double *
     const uint32_t a = g - ii * pc.nA;
     const uint32_t pixel = pc.act[a];
     const uint32_t slot = 2 * pixel + pc.inst_base + ii;
-    uint32_t n = wf_n[slot];
-    double mean = wf_mean[slot], m2 = wf_m2[slot], ys = wf_ysum[slot];
-    const float *src = pc.rad + a * pc.rs_a + ii * pc.rs_i;
-    const uint32_t mb = rp.minibatch;
-    for (uint32_t k = 0; k < pc.bp; k += mb) {
-        const float Y = minibatch_mean(src + k, mb);
-        const double x = log((double)Y + rp.log_eps);
-        n += 1;
-        const double delta = x - mean;
-        mean = mean + delta / (double)n;
-        m2 = m2 + delta * (x - mean);
-        ys = ys + (double)Y;
-    }
-    wf_n[slot] = n;
-    wf_mean[slot] = mean;
-    wf_m2[slot] = m2;
-    wf_ysum[slot] = ys;
+    Welford w = welford_load(slot, wf_n, wf_mean, wf_m2, wf_ysum);
+    welford_run(w, pc.rad + a * pc.rs_a + ii * pc.rs_i, pc.bp, rp.minibatch, rp.log_eps);
+    welford_store(w, slot, wf_n, wf_mean, wf_m2, wf_ysum);
 }
 
 // Eq. 7 with N = samples at the second instant; zero variance gives -inf,
@@ -742,6 +766,41 @@ __device__ __forceinline__ double t_value(double mean0, double var0, double mean
     const double S = var0 + var1;
     if (S == 0.0) return gap < 0.0 ? -INFINITY : (gap > 0.0 ? INFINITY : 0.0);
     return gap / sqrt(S / (double)m1);
+}
+
+// Decision for one pixel at checkpoint j of the round (Eq. 7 against the
+// checkpoint's critical values; at the last checkpoint of the schedule only
+// the event rule of Alg. 1).  A finished pixel writes its outputs.
+__device__ __forceinline__ bool decide_pixel(const Decide &dc, uint32_t j, bool final_ck, uint32_t pixel,
+                                             const Welford &w0, const Welford &w1, const Outputs &out)
+{
+    const uint32_t m0 = w0.n, m1 = w1.n;
+    const double var0 = m0 > 1 ? w0.m2 / (double)(m0 - 1) : 0.0;
+    const double var1 = m1 > 1 ? w1.m2 / (double)(m1 - 1) : 0.0;
+    const double t = t_value(w0.mean, var0, w1.mean, var1, m1, dc.C);
+    const double gap = w1.mean - w0.mean;
+    bool stop = false;
+    if (!final_ck) {
+        if (dc.mode == 0) stop = t < dc.crit_lo[j];
+        else if (dc.mode == 2) stop = t < dc.crit_lo[j] || t > dc.crit_hi[j];
+        else if (dc.mode == 3) stop = fabs(gap) <= dc.C;
+    }
+    const bool done = stop || final_ck;
+    if (done) {
+        out.polarity[pixel] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
+        out.n_paths[pixel] = m1 * dc.minibatch;
+        out.mean[2 * pixel] = w0.mean;
+        out.mean[2 * pixel + 1] = w1.mean;
+        out.var[2 * pixel] = var0;
+        out.var[2 * pixel + 1] = var1;
+        if (out.t_last) out.t_last[pixel] = t;
+        if (out.mean_radiance) {
+            out.mean_radiance[2 * pixel] = w0.ys / (double)m0;
+            out.mean_radiance[2 * pixel + 1] = w1.ys / (double)m1;
+        }
+        if (out.flags) out.flags[pixel] = stop ? 1 : 0;
+    }
+    return done;
 }
 
 // Decision after a round for every active pixel; finished pixels write
@@ -757,32 +816,52 @@ __global__ __launch_bounds__(256) void k_decide_compact(Decide dc, const uint32_
     if (a == 0) cnt[kCntActive + (dc.cnt_slot ^ 1u)] = 0;
     if (a >= nA) return;
     const uint32_t pixel = act_in[a];
-    const uint32_t m0 = wf_n[2 * pixel], m1 = wf_n[2 * pixel + 1];
-    const double mean0 = wf_mean[2 * pixel], mean1 = wf_mean[2 * pixel + 1];
-    const double var0 = m0 > 1 ? wf_m2[2 * pixel] / (double)(m0 - 1) : 0.0;
-    const double var1 = m1 > 1 ? wf_m2[2 * pixel + 1] / (double)(m1 - 1) : 0.0;
-    const double t = t_value(mean0, var0, mean1, var1, m1, dc.C);
-    const double gap = mean1 - mean0;
-    bool stop = false;
-    if (!dc.final_round) {
-        if (dc.mode == 0) stop = t < dc.crit_lo;
-        else if (dc.mode == 2) stop = t < dc.crit_lo || t > dc.crit_hi;
-        else if (dc.mode == 3) stop = fabs(gap) <= dc.C;
-    }
-    const bool done = stop || dc.final_round;
-    if (done) {
-        out.polarity[pixel] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
-        out.n_paths[pixel] = m1 * dc.minibatch;
-        out.mean[2 * pixel] = mean0;
-        out.mean[2 * pixel + 1] = mean1;
-        out.var[2 * pixel] = var0;
-        out.var[2 * pixel + 1] = var1;
-        if (out.t_last) out.t_last[pixel] = t;
-        if (out.mean_radiance) {
-            out.mean_radiance[2 * pixel] = wf_ysum[2 * pixel] / (double)m0;
-            out.mean_radiance[2 * pixel + 1] = wf_ysum[2 * pixel + 1] / (double)m1;
+    const Welford w0 = welford_load(2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
+    const Welford w1 = welford_load(2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
+    const bool done = decide_pixel(dc, dc.n_checks - 1, dc.final_round != 0, pixel, w0, w1, out);
+    const uint32_t slot = wave_append(!done, cnt + kCntActive + dc.cnt_slot);
+    if (!done) act_out[slot] = pixel;
+}
+
+// Statistics and decisions of a round whose piece holds the whole sample
+// range of its pixels: checkpoint by checkpoint, the mini-batches up to the
+// checkpoint enter the Welford state and the pixel is tested as if the round
+// had ended there.  A pixel that stops ignores the samples traced past its
+// checkpoint; the others keep their state and are compacted into act_out.
+__global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParams rp, Decide dc,
+                                                           uint32_t *act_out, uint32_t *cnt, uint32_t *wf_n,
+                                                           double *wf_mean, double *wf_m2, double *wf_ysum,
+                                                           Outputs out)
+{
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a == 0) cnt[kCntActive + (dc.cnt_slot ^ 1u)] = 0;
+    if (a >= pc.nA) return;
+    const uint32_t pixel = pc.act[a];
+    Welford w0 = welford_load(2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
+    Welford w1 = welford_load(2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
+    const uint32_t mb = rp.minibatch;
+    const float *src = pc.rad + a * pc.rs_a;
+    const bool both = pc.n_inst == 2;
+    uint32_t k = pc.s0;
+    bool done = false;
+    for (uint32_t j = 0; j < dc.n_checks; ++j) {
+        const uint32_t end = dc.ck_end[j];
+        if (both) {
+            welford_run(w0, src + (k - pc.s0), end - k, mb, rp.log_eps);
+            welford_run(w1, src + pc.rs_i + (k - pc.s0), end - k, mb, rp.log_eps);
+        } else {
+            welford_run(w1, src + (k - pc.s0), end - k, mb, rp.log_eps);
         }
-        if (out.flags) out.flags[pixel] = stop ? 1 : 0;
+        k = end;
+        const bool final_ck = dc.final_round != 0 && j + 1 == dc.n_checks;
+        if (decide_pixel(dc, j, final_ck, pixel, w0, w1, out)) {
+            done = true;
+            break;
+        }
+    }
+    if (!done) {
+        if (both) welford_store(w0, 2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
+        welford_store(w1, 2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
     }
     const uint32_t slot = wave_append(!done, cnt + kCntActive + dc.cnt_slot);
     if (!done) act_out[slot] = pixel;
@@ -848,8 +927,8 @@ __global__ void k_hook_decide(const double *x0, const double *x1, uint32_t n, ui
     const double t = t_value(mean[0], var[0], mean[1], var[1], m, dc.C);
     const double gap = mean[1] - mean[0];
     bool stop = false;
-    if (dc.mode == 0) stop = t < dc.crit_lo;
-    else if (dc.mode == 2) stop = t < dc.crit_lo || t > dc.crit_hi;
+    if (dc.mode == 0) stop = t < dc.crit_lo[0];
+    else if (dc.mode == 2) stop = t < dc.crit_lo[0] || t > dc.crit_hi[0];
     else if (dc.mode == 3) stop = fabs(gap) <= dc.C;
     t_out[i] = t;
     stop_out[i] = stop ? 1 : 0;
@@ -914,6 +993,14 @@ void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, u
     const uint32_t n = pc.nA * pc.n_inst;
     hipLaunchKernelGGL(k_accumulate, dim3((n + 255) / 256), dim3(256), 0, s, pc, rp, wf_n, wf_mean,
                        wf_m2, wf_ysum);
+}
+
+void launch_accumulate_decide(hipStream_t s, const Piece &pc, const RenderParams &rp, const Decide &dc,
+                              uint32_t *act_out, uint32_t *cnt, uint32_t *wf_n, double *wf_mean,
+                              double *wf_m2, double *wf_ysum, const Outputs &out)
+{
+    hipLaunchKernelGGL(k_accumulate_decide, dim3((pc.nA + 255) / 256), dim3(256), 0, s, pc, rp, dc, act_out, cnt,
+                       wf_n, wf_mean, wf_m2, wf_ysum, out);
 }
 
 void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_in, uint32_t nA,

@@ -239,9 +239,10 @@ static double crit_value(evrt_ctx *c, double p, uint32_t df)
 // with the whole sample range when that fits, otherwise every pixel with a
 // sub-range of whole mini-batches.  Each pixel's samples are accumulated in
 // increasing order either way.
-static void trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t n_inst, uint32_t inst_base,
+static bool trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t n_inst, uint32_t inst_base,
                         uint32_t lo, uint32_t hi, const DevScene &sc, const RenderParams &rp,
-                        const evrt_render_opts &o, hipStream_t s, Profiler &prof)
+                        const evrt_render_opts &o, hipStream_t s, Profiler &prof, const Decide *dc = nullptr,
+                        uint32_t *act_out = nullptr, const Outputs *outs = nullptr)
 {
     const uint32_t mb = rp.minibatch;
     const uint64_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
@@ -257,6 +258,10 @@ static void trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
     px_block = std::min<uint64_t>(px_block, nA);
     bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / (px_block * n_inst) / mb * mb);
     if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many pixels for one piece");
+    // Pieces that hold the whole range of their pixels also take the
+    // decisions; split sample ranges leave them to a separate kernel.
+    const bool fused = dc != nullptr && bp_max >= range;
+    if (dc != nullptr && !fused && dc->n_checks != 1) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
     for (uint32_t a0 = 0; a0 < nA; a0 += (uint32_t)px_block) {
         const uint32_t na = (uint32_t)std::min<uint64_t>(px_block, nA - a0);
         for (uint32_t s0 = lo; s0 < hi;) {
@@ -277,11 +282,17 @@ static void trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
             ensure_buffers(c, sc.width * sc.height, pc.n_paths, rp.n_slots);
             pc.rad = c->fb.rad.as<float>();
             trace_piece(c, pc, sc, rp, o, s, prof);
-            launch_accumulate(s, pc, rp, c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
-                              c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>());
+            if (fused)
+                launch_accumulate_decide(s, pc, rp, *dc, act_out, c->fb.cnt.as<uint32_t>(),
+                                         c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
+                                         c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>(), *outs);
+            else
+                launch_accumulate(s, pc, rp, c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
+                                  c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>());
             s0 += bp;
         }
     }
+    return fused;
 }
 
 static void read_stats(evrt_ctx *c, hipStream_t s)
@@ -337,29 +348,47 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
     const uint32_t n_inst = ref_full ? 1 : 2;
     const uint32_t inst_base = ref_full ? 1 : 0;
     uint32_t n_prev = 0;
-    uint32_t n = fixed ? spp_max : spp_init;
+    uint32_t n_next = fixed ? spp_max : spp_init;  // first checkpoint of the next round
     Outputs outs{out.polarity, out.n_paths, out.mean, out.var, out.t_last, out.mean_radiance, out.flags};
     for (uint32_t r = 0;; ++r) {
-        trace_range(c, act_in, nA, n_inst, inst_base, n_prev, n, sc, rp, o, s, prof);
-        const uint32_t m1 = n / mb;
-        const uint32_t m0 = ref_full ? spp_max / mb : m1;
+        // Checkpoints of this round: the schedule's next sample counts, as
+        // many as keep the round's paths within one batch (at least one).
+        // Every checkpoint is tested in order, so a pixel stops exactly
+        // where one checkpoint per round would stop it; samples traced past
+        // its stop are the price of fuller launches.
         Decide dc{};
         dc.C = (double)C;
         dc.mode = o.mode;
         dc.minibatch = mb;
-        dc.final_round = n >= spp_max ? 1u : 0u;
         dc.cnt_slot = r & 1u;
-        const uint32_t df = m0 + m1 - 2;
-        if (!dc.final_round) {
+        uint32_t hi = n_next;
+        dc.ck_end[0] = hi;
+        dc.n_checks = 1;
+        while (hi < spp_max && dc.n_checks < kMaxChecks) {
+            const uint32_t nx = std::min(hi + spp_batch, spp_max);
+            if ((uint64_t)nA * n_inst * (nx - n_prev) > batch) break;
+            hi = nx;
+            dc.ck_end[dc.n_checks++] = hi;
+        }
+        dc.final_round = hi >= spp_max ? 1u : 0u;
+        for (uint32_t j = 0; j < dc.n_checks; ++j) {
+            if (dc.ck_end[j] >= spp_max) break;
+            const uint32_t m1 = dc.ck_end[j] / mb;
+            const uint32_t m0 = ref_full ? spp_max / mb : m1;
+            const uint32_t df = m0 + m1 - 2;
             if (o.mode == EVRT_MODE_ADAPTIVE_1T) {
-                dc.crit_lo = crit_value(c, (double)alpha, df);
+                dc.crit_lo[j] = crit_value(c, (double)alpha, df);
             } else if (o.mode == EVRT_MODE_ADAPTIVE_2T) {
-                dc.crit_lo = crit_value(c, 0.5 * (double)alpha, df);
-                dc.crit_hi = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
+                dc.crit_lo[j] = crit_value(c, 0.5 * (double)alpha, df);
+                dc.crit_hi[j] = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
             }
         }
-        launch_decide_compact(s, dc, act_in, nA, act_out, fb.cnt.as<uint32_t>(), fb.wf_n.as<uint32_t>(),
-                              fb.wf_mean.as<double>(), fb.wf_m2.as<double>(), fb.wf_ysum.as<double>(), outs);
+        const bool fused = trace_range(c, act_in, nA, n_inst, inst_base, n_prev, hi, sc, rp, o, s, prof, &dc,
+                                       act_out, &outs);
+        if (!fused)
+            launch_decide_compact(s, dc, act_in, nA, act_out, fb.cnt.as<uint32_t>(), fb.wf_n.as<uint32_t>(),
+                                  fb.wf_mean.as<double>(), fb.wf_m2.as<double>(), fb.wf_ysum.as<double>(),
+                                  outs);
         hip_check(hipMemcpyAsync(c->h_pinned, fb.cnt.as<uint32_t>() + kCntActive + dc.cnt_slot, sizeof(uint32_t),
                                  hipMemcpyDeviceToHost, s),
                   "active count readback");
@@ -370,8 +399,8 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
         std::swap(act_in, act_out);
         nA = next;
         if (nA == 0 || dc.final_round) break;
-        n_prev = n;
-        n = std::min(n + spp_batch, spp_max);
+        n_prev = hi;
+        n_next = std::min(hi + spp_batch, spp_max);
     }
     read_stats(c, s);
     prof.collect(c->stats);
@@ -440,12 +469,13 @@ void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, u
     dc.C = (double)C;
     dc.mode = mode;
     dc.minibatch = 1;
+    dc.n_checks = 1;
     const uint32_t df = 2 * m - 2;
     if (mode == EVRT_MODE_ADAPTIVE_1T) {
-        dc.crit_lo = crit_value(c, (double)alpha, df);
+        dc.crit_lo[0] = crit_value(c, (double)alpha, df);
     } else if (mode == EVRT_MODE_ADAPTIVE_2T) {
-        dc.crit_lo = crit_value(c, 0.5 * (double)alpha, df);
-        dc.crit_hi = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
+        dc.crit_lo[0] = crit_value(c, 0.5 * (double)alpha, df);
+        dc.crit_hi[0] = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
     }
     launch_hook_decide(s, x0, x1, n, m, dc, t_out, stop_out, pol_out);
     hip_check(hipStreamSynchronize(s), "decide hook");

@@ -237,12 +237,17 @@ def test_tiny_frame_invariants_and_determinism(rend, torch_cuda):
     assert (a["polarity"][early] == 0).all() and (n[early] < 256).all()
     # C = 0: nothing stops, equal to fixed mode bit for bit
     z, _ = _frame(rend, sc, P, 0.0, 1.0, C=0.0)
-    fz, _ = _frame(rend, sc, P, 0.0, 1.0, C=0.0, mode=ev.MODE_FIXED)
+    fz, fst = _frame(rend, sc, P, 0.0, 1.0, C=0.0, mode=ev.MODE_FIXED)
     for k in ("polarity", "n_paths", "mean", "var", "mean_radiance"):
         np.testing.assert_array_equal(z[k], fz[k])
-    # rays counted: camera rays = paths traced
+    # rays counted: camera rays = paths traced; rounds that test several
+    # checkpoints trace paths past a pixel's stop, fixed mode traces exactly
+    # the paths it uses
     assert st["camera_rays"] == st["paths"]
-    assert st["camera_rays"] == 2 * int(n.sum())
+    assert st["camera_rays"] >= 2 * int(n.sum())
+    assert fst["camera_rays"] == 2 * int(fz["n_paths"].sum())
+    # every round after the first tests at least one checkpoint per pixel
+    assert 1 <= st["rounds"] <= (P["spp_max"] - P["spp_init"]) // P["spp_batch"] + 1
 
 
 def test_edge_cases(rend, torch_cuda):
