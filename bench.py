@@ -21,6 +21,8 @@ Reported next to the headline (event frames/s):
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +41,23 @@ OPS_PER_TRI = 52.0    # watertight test: translate, permute, shear, 3 edge funct
 # Peak FP32 VALU issue of MI355X without packed math: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz.
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+# HBM bytes per closest-hit launch of this workload: FETCH_SIZE and
+# WRITE_SIZE (one rocprofv3 --pmc pass each, summed over the frame's
+# launches) scaled by what the same counters read for a 256 MiB device copy
+# (x1.9997 and x1.0000), divided by the launches.  It holds for the kernel
+# sources it was taken with and is reported as null for any others.
+TRAFFIC = {"sources_sha256": "346ce64e0357800d8820237e2a8c55ebf8e0cdfa5dc2a298cede39b3a986a092",
+           "bytes_per_launch": 216973428.6}
+
+
+def kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2408_07996_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def polarity_f1(pred: np.ndarray, ref: np.ndarray) -> float:
@@ -138,6 +157,8 @@ def main() -> int:
     ops_per_launch = ops_closest / max(1.0, launches_per_frame)
     achieved = ops_per_launch / (ms_per_closest * 1e-3) if ms_per_closest > 0 else 0.0
 
+    traffic = TRAFFIC["bytes_per_launch"] if kernel_sources_digest() == TRAFFIC["sources_sha256"] else None
+
     adaptive_map = out["polarity"].cpu().numpy()
     adaptive_paths = out["n_paths"].cpu().numpy().astype(np.int64)
 
@@ -191,7 +212,7 @@ def main() -> int:
             t_cpu = time.perf_counter() - tc
         s_per_frame = t_cpu * sc.n_pixels / len(px)
         cpu = dict(value=1.0 / s_per_frame, unit="event frames/s", cores=threads, kind="oracle",
-                   sample=f"every {args.cpu_step}th pixel in x and y ({len(px)} of {sc.n_pixels} pixels, "
+                   sample=f"every pixel whose x and y are multiples of {args.cpu_step} ({len(px)} of {sc.n_pixels} pixels, "
                           f"adaptive, both instants), {t_cpu:.1f} s, scaled by {sc.n_pixels / len(px):.0f}")
 
     res = {
@@ -228,7 +249,8 @@ def main() -> int:
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch",
             "ms_per_launch": ms_per_closest,
             "launches_per_frame": launches_per_frame,
             "node_visits_per_frame": cst["node_visits"],

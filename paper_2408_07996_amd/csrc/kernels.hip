@@ -84,6 +84,42 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter)
     return base + rank;
 }
 
+// Slots in two append-only queues for a 256-thread block: one device-scope
+// atomic per queue and block (not per wave), so that thousands of resident
+// waves do not serialize on the two counters.  Every thread of the block
+// must call it the same number of times; par alternates between calls so
+// that a wave running ahead cannot overwrite counts still being read.
+struct BlockAppend {
+    uint32_t wc[2][2][4];
+    uint32_t base[2][2];
+};
+
+__device__ __forceinline__ void block_append2(BlockAppend &sm, uint32_t par, bool pa, bool pb, uint32_t *ca,
+                                              uint32_t *cb, uint32_t &sa, uint32_t &sb)
+{
+    const unsigned long long ma = __ballot(pa), mb = __ballot(pb);
+    const uint32_t w = threadIdx.x >> 6;
+    if (__lane_id() == 0) {
+        sm.wc[par][0][w] = (uint32_t)__popcll(ma);
+        sm.wc[par][1][w] = (uint32_t)__popcll(mb);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t ta = (sm.wc[par][0][0] + sm.wc[par][0][1]) + (sm.wc[par][0][2] + sm.wc[par][0][3]);
+        const uint32_t tb = (sm.wc[par][1][0] + sm.wc[par][1][1]) + (sm.wc[par][1][2] + sm.wc[par][1][3]);
+        sm.base[par][0] = ta ? atomicAdd(ca, ta) : 0u;
+        sm.base[par][1] = tb ? atomicAdd(cb, tb) : 0u;
+    }
+    __syncthreads();
+    uint32_t oa = sm.base[par][0], ob = sm.base[par][1];
+    for (uint32_t v = 0; v < w; ++v) {
+        oa += sm.wc[par][0][v];
+        ob += sm.wc[par][1][v];
+    }
+    sa = oa + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+    sb = ob + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
 #pragma unroll
@@ -564,10 +600,16 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                                                uint32_t *cnt_sh, uint32_t depth)
 {
     const Part pt = partition(cnt_in, pc.region, pc.n_inst);
-    for (uint32_t j = pt.lb * blockDim.x + threadIdx.x; j < pt.n; j += pt.lgrid * blockDim.x) {
-        const uint32_t i = pt.base + j;
+    __shared__ BlockAppend s_app;
+    uint32_t par = 0;
+    // Block-uniform trip count: the appends synchronize the block.
+    for (uint32_t j0 = pt.lb * blockDim.x; j0 < pt.n; j0 += pt.lgrid * blockDim.x, par ^= 1u) {
+        const uint32_t j = j0 + threadIdx.x;
+        const bool valid = j < pt.n;
+        const uint32_t i = pt.base + (valid ? j : 0u);
         const float2 h = hit[i];
-        const uint32_t prim = fbits(h.y);
+        const float4 o = qin.o[i], d = qin.d[i];
+        const uint32_t prim = valid ? fbits(h.y) : kNoPrim;
         bool want_shadow = false, want_ext = false;
         float Px = 0.0f, Py = 0.0f, Pz = 0.0f;
         float nsx = 0.0f, nsy = 0.0f, nsz = 0.0f, beta = 0.0f, fr = 0.0f, beta_v = 0.0f;
@@ -576,7 +618,6 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
         float4 d0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         uint32_t pword = 0, ri = 0, inst = 0;
         if (prim != kNoPrim) {
-            const float4 o = qin.o[i], d = qin.d[i];
             pword = fbits(d.w);
             inst = pword >> 31;
             const uint32_t p = pword & ~kInstBit;
@@ -672,7 +713,10 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
             }
         }
         const uint32_t r = pt.base / max(pc.region, 1u);
-        const uint32_t se = pt.base + wave_append(want_shadow, cnt_sh + r);
+        uint32_t se, xe;
+        block_append2(s_app, par, want_shadow, want_ext, cnt_sh + r, cnt_out + r, se, xe);
+        se += pt.base;
+        xe += pt.base;
         if (want_shadow) {
             sq.o[se] = make_float4(Px, Py, Pz, bitsf(ri));
             sq.meta[se] = prim | (inst << 31);
@@ -685,7 +729,6 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                 if (ck > 0.0f) sq.dir[(k + 1) * sq.cap + se] = dk;
             }
         }
-        const uint32_t xe = pt.base + wave_append(want_ext, cnt_out + r);
         if (want_ext) {
             qout.o[xe] = make_float4(Px, Py, Pz, beta);
             qout.d[xe] = make_float4(ndx, ndy, ndz, bitsf(pword));
