@@ -361,64 +361,115 @@ __device__ __forceinline__ bool visit_node(Trav &T, float4 n0, float4 n1, float4
     return true;
 }
 
-// Full traversal of one ray (while-while): inner nodes of the LDS treelet,
-// inner nodes in global memory, then one leaf, until the stack empties.
-// ANY stops at the first accepted hit.  Result: T.tfar / T.best_p.
+// One outer iteration of the while-while traversal: inner nodes of the LDS
+// treelet, inner nodes in global memory, then one leaf.  ANY stops at the
+// first accepted hit.  Returns false when the ray is finished; the result is
+// T.tfar / T.best_p.
+template <bool ANY, bool COUNT>
+__device__ __forceinline__ bool traverse_step(Trav &T, const DevScene &sc, const lds_f32 *s_nodes,
+                                              lds_u32 *lds_stack, int32_t *spill, uint32_t &visits,
+                                              uint32_t &tests)
+{
+    const uint32_t n_lds = T.inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
+    const lds_f32 *lds = s_nodes + T.inst * 16 * kLdsNodes;
+    const float4 *nodes = T.inst ? sc.inst[1].nodes : sc.inst[0].nodes;
+    const float4 *tris = T.inst ? sc.inst[1].tris : sc.inst[0].tris;
+    bool live = true;
+    while (live && T.ref >= 0 && (uint32_t)T.ref < n_lds) {
+        const lds_f32 *p = lds + 16 * T.ref;
+        if (COUNT) ++visits;
+        live = visit_node(T, lds_load4(p), lds_load4(p + 4), lds_load4(p + 8), lds_load4(p + 12), lds_stack, spill);
+    }
+    while (live && T.ref >= 0 && (uint32_t)T.ref >= n_lds) {
+        const float4 *p = nodes + 4 * (size_t)T.ref;
+        if (COUNT) ++visits;
+        live = visit_node(T, p[0], p[1], p[2], p[3], lds_stack, spill);
+    }
+    if (!live) return false;
+    // A pop in the global loop can return a treelet node: not a leaf yet.
+    if (T.ref >= 0) return true;
+    const uint32_t packed = ~(uint32_t)T.ref;
+    const uint32_t first = packed >> kLeafCountBits;
+    const uint32_t count = (packed & (kMaxLeafTris - 1)) + 1;
+    for (uint32_t k = 0; k < count; ++k) {
+        const float4 *tp = tris + 3 * (size_t)(first + k);
+        const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
+        const uint32_t prim = fbits(v0.w);
+        if (COUNT) tests += prim != T.skip;
+        float t;
+        // The test runs before the origin-primitive check so that the
+        // three vertex loads issue together.
+        const bool h = tri_test(T.r, v0, v1, v2, t);
+        if (!h || prim == T.skip) continue;
+        if (!(t > T.tmin) || !(t < T.tmax)) continue;
+        if (ANY) {
+            T.best_p = prim;
+            return false;
+        }
+        if (t < T.tfar || (t == T.tfar && prim < T.best_p)) {
+            T.tfar = t;
+            T.best_p = prim;
+        }
+    }
+    if (T.sp == 0) return false;
+    --T.sp;
+    T.ref = stack_pop(T.sp, lds_stack, spill);
+    return true;
+}
+
+// Full traversal of one ray.
 template <bool ANY, bool COUNT>
 __device__ __forceinline__ void traverse(Trav &T, const DevScene &sc, const lds_f32 *s_nodes,
                                          lds_u32 *lds_stack, uint32_t &visits, uint32_t &tests)
 {
     if (T.ref == kEmptyRef) return;
     int32_t spill[kStackMax - kStackLds];
-    const uint32_t n_lds = T.inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
-    const lds_f32 *lds = s_nodes + T.inst * 16 * kLdsNodes;
-    const float4 *nodes = T.inst ? sc.inst[1].nodes : sc.inst[0].nodes;
-    const float4 *tris = T.inst ? sc.inst[1].tris : sc.inst[0].tris;
-    bool live = true;
-    while (live) {
-        while (live && T.ref >= 0 && (uint32_t)T.ref < n_lds) {
-            const lds_f32 *p = lds + 16 * T.ref;
-            if (COUNT) ++visits;
-            live = visit_node(T, lds_load4(p), lds_load4(p + 4), lds_load4(p + 8), lds_load4(p + 12), lds_stack,
-                              spill);
-        }
-        while (live && T.ref >= 0 && (uint32_t)T.ref >= n_lds) {
-            const float4 *p = nodes + 4 * (size_t)T.ref;
-            if (COUNT) ++visits;
-            live = visit_node(T, p[0], p[1], p[2], p[3], lds_stack, spill);
-        }
-        if (live && T.ref < 0) {
-            const uint32_t packed = ~(uint32_t)T.ref;
-            const uint32_t first = packed >> kLeafCountBits;
-            const uint32_t count = (packed & (kMaxLeafTris - 1)) + 1;
-            for (uint32_t k = 0; k < count; ++k) {
-                const float4 *tp = tris + 3 * (size_t)(first + k);
-                const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
-                const uint32_t prim = fbits(v0.w);
-                if (COUNT) tests += prim != T.skip;
-                float t;
-                // The test runs before the origin-primitive check so that the
-                // three vertex loads issue together.
-                const bool h = tri_test(T.r, v0, v1, v2, t);
-                if (!h || prim == T.skip) continue;
-                if (!(t > T.tmin) || !(t < T.tmax)) continue;
-                if (ANY) {
-                    T.best_p = prim;
-                    return;
-                }
-                if (t < T.tfar || (t == T.tfar && prim < T.best_p)) {
-                    T.tfar = t;
-                    T.best_p = prim;
-                }
-            }
-            if (T.sp == 0) {
-                live = false;
-            } else {
-                --T.sp;
-                T.ref = stack_pop(T.sp, lds_stack, spill);
-            }
-        }
+    while (traverse_step<ANY, COUNT>(T, sc, s_nodes, lds_stack, spill, visits, tests)) {
     }
+}
+
+// Rays of one wave: the wave's share of a grid-stride walk over the queue in
+// chunks of 64 (chunk k of wave w starts at (k W + w) 64 for W waves), so
+// that all waves sweep the queue together and rays traced at the same time
+// share BVH nodes in L2.  Idle lanes take the next rays of the sequence
+// whenever at most kRefillBelow lanes of the wave are still traversing, so
+// that lanes whose rays finish early do not idle until the slowest ray of
+// the wave is done.
+#ifndef EVRT_REFILL_BELOW
+#define EVRT_REFILL_BELOW 32
+#endif
+constexpr uint32_t kRefillBelow = EVRT_REFILL_BELOW;
+
+struct WaveRange {
+    uint32_t next;   // position in the wave's sequence
+    uint32_t w, W;   // wave index and wave count
+    uint32_t n;      // queue length
+    __device__ uint32_t at(uint32_t v) const { return ((v >> 6) * W + w) * 64u + (v & 63u); }
+    __device__ bool done() const { return at(next) >= n; }
+};
+
+__device__ __forceinline__ WaveRange wave_range(const Part &pt)
+{
+    WaveRange r;
+    r.next = 0;
+    r.W = pt.lgrid * (kTB / 64);
+    r.w = pt.lb * (kTB / 64) + (threadIdx.x >> 6);
+    r.n = pt.n;
+    return r;
+}
+
+// Hands the next rays of the range to the idle lanes when few lanes are
+// busy; returns the lane's new item (or ~0u).  Wave-uniform control flow.
+__device__ __forceinline__ uint32_t wave_refill(WaveRange &wr, bool busy)
+{
+    const unsigned long long bm = __ballot(busy);
+    const uint32_t nb = (uint32_t)__popcll(bm);
+    if (nb > kRefillBelow || wr.done()) return ~0u;
+    const unsigned long long im = ~bm;
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(im >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)im, 0u));
+    const uint32_t j = wr.at(wr.next + rank);
+    wr.next += 64u - nb;
+    return (!busy && j < wr.n) ? j : ~0u;
 }
 
 __device__ __forceinline__ void load_treelets(const DevScene &sc, float4 *s_nodes)
@@ -510,14 +561,30 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
     const Part pt = partition(cnt_in, region, n_split);
     if (pt.lb == 0 && threadIdx.x == 0 && pt.n) atomicAdd(stat + stat_kind, (unsigned long long)pt.n);
     uint32_t visits = 0, tests = 0;
-    for (uint32_t j = pt.lb * kTB + threadIdx.x; j < pt.n; j += pt.lgrid * kTB) {
-        const uint32_t i = pt.base + j;
-        const float4 o = q.o[i], d = q.d[i];
-        const uint32_t inst = fbits(d.w) >> 31;
-        Trav T;
-        trav_begin(T, sc, inst, o.x, o.y, o.z, d.x, d.y, d.z, kRayTmin, INFINITY, q.skip[i]);
-        traverse<false, COUNT>(T, sc, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
-        hit[i] = make_float2(T.tfar, bitsf(T.best_p));
+    int32_t spill[kStackMax - kStackLds];
+    lds_u32 *lds_stack = (lds_u32 *)s_stack + threadIdx.x;
+    WaveRange wr = wave_range(pt);
+    Trav T;
+    uint32_t cur = 0;
+    bool busy = false;
+    for (;;) {
+        const uint32_t j = wave_refill(wr, busy);
+        if (j != ~0u) {
+            cur = pt.base + j;
+            const float4 o = q.o[cur], d = q.d[cur];
+            const uint32_t inst = fbits(d.w) >> 31;
+            trav_begin(T, sc, inst, o.x, o.y, o.z, d.x, d.y, d.z, kRayTmin, INFINITY, q.skip[cur]);
+            busy = T.ref != kEmptyRef;
+            if (!busy) hit[cur] = make_float2(T.tfar, bitsf(T.best_p));
+        }
+        if (!__any(busy)) {
+            if (wr.done()) break;
+            continue;
+        }
+        if (busy && !traverse_step<false, COUNT>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
+            busy = false;
+            hit[cur] = make_float2(T.tfar, bitsf(T.best_p));
+        }
     }
     if (COUNT) {
         const unsigned long long v = wave_sum_u64(visits), t = wave_sum_u64(tests);
@@ -542,24 +609,61 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
     load_treelets(sc, s_nodes);
     const Part pt = partition(cnt_in, region, n_split);
     uint32_t visits = 0, tests = 0, rays = 0;
-    for (uint32_t j = pt.lb * kTB + threadIdx.x; j < pt.n; j += pt.lgrid * kTB) {
-        const uint32_t e = pt.base + j;
-        const float4 o = sq.o[e];
-        const uint32_t meta = sq.meta[e];
-        const uint32_t inst = meta >> 31;
-        float sum = 0.0f;
-        for (uint32_t k = 0; k < n_slots; ++k) {
-            const float c = sq.c[k * sq.cap + e];
-            if (!(c > 0.0f)) continue;
-            const float4 w = sq.dir[k * sq.cap + e];
-            Trav T;
-            trav_begin(T, sc, inst, o.x, o.y, o.z, w.x, w.y, w.z, kRayTmin, w.w, meta & ~kInstBit);
-            ++rays;
-            traverse<true, COUNT>(T, sc, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
-            if (T.best_p == kNoPrim) sum = sum + c;
+    int32_t spill[kStackMax - kStackLds];
+    lds_u32 *lds_stack = (lds_u32 *)s_stack + threadIdx.x;
+    WaveRange wr = wave_range(pt);
+    Trav T;
+    uint32_t e = 0, slot = 0;
+    float sum = 0.0f, c = 0.0f;
+    bool busy = false;     // an entry is in progress
+    bool tracing = false;  // its slot `slot` is being traced
+    for (;;) {
+        const uint32_t j = wave_refill(wr, busy);
+        if (j != ~0u) {
+            e = pt.base + j;
+            slot = 0;
+            sum = 0.0f;
+            busy = true;
         }
-        const uint32_t ri = fbits(o.w);
-        rad[ri] = rad[ri] + sum;
+        // Start the next slot with a contribution, or end the entry after
+        // its last slot.
+        while (busy && !tracing) {
+            if (slot >= n_slots) {
+                const uint32_t ri = fbits(sq.o[e].w);
+                rad[ri] = rad[ri] + sum;
+                busy = false;
+                break;
+            }
+            c = sq.c[slot * sq.cap + e];
+            if (c > 0.0f) {
+                const float4 o = sq.o[e];
+                const float4 w = sq.dir[slot * sq.cap + e];
+                const uint32_t meta = sq.meta[e];
+                trav_begin(T, sc, meta >> 31, o.x, o.y, o.z, w.x, w.y, w.z, kRayTmin, w.w, meta & ~kInstBit);
+                ++rays;
+                tracing = T.ref != kEmptyRef;
+                if (!tracing) {
+                    sum = sum + c;
+                    ++slot;
+                }
+            } else {
+                ++slot;
+            }
+        }
+        if (!__any(busy)) {
+            if (wr.done()) break;
+            continue;
+        }
+        if (tracing && !traverse_step<true, COUNT>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
+            tracing = false;
+            if (T.best_p == kNoPrim) sum = sum + c;
+            ++slot;
+            if (slot >= n_slots) {
+                const uint32_t ri = fbits(sq.o[e].w);
+                rad[ri] = rad[ri] + sum;
+                busy = false;
+            }
+        }
     }
     const unsigned long long rs = wave_sum_u64(rays);
     if (__lane_id() == 0 && rs) atomicAdd(stat + kStatShadow, rs);
