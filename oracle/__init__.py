@@ -70,6 +70,17 @@ class _PixelOut(ctypes.Structure):
     ]
 
 
+REC_MAX = 64
+
+
+class _PathRec(ctypes.Structure):
+    _fields_ = [
+        ("n_vert", ctypes.c_uint32), ("n_term", ctypes.c_uint32),
+        ("vmat", ctypes.c_uint32 * REC_MAX), ("vlb", ctypes.c_float * REC_MAX),
+        ("tmat", ctypes.c_uint32 * (2 * REC_MAX)), ("tval", ctypes.c_float * (2 * REC_MAX)),
+    ]
+
+
 def lib():
     """Load liboracle.so (building it with gcc first if it is absent)."""
     global _lib
@@ -103,6 +114,12 @@ def lib():
     L.evo_path_radiance.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32,
                                     ctypes.c_int, ctypes.c_uint32]
     L.evo_path_radiance.restype = ctypes.c_float
+    L.evo_path_radiance_rec.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32,
+                                        ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_PathRec)]
+    L.evo_path_radiance_rec.restype = ctypes.c_float
+    L.evo_event_loss.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_uint32, _u32p, ctypes.c_uint32, ctypes.c_int,
+                                 _f64p, _f64p, _f64p, _f64p, _f64p]
     L.evo_paths_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32,
                                   _u32p, _u8p, _u32p, _f32p, ctypes.c_int]
     L.evo_decide.argtypes = [_f64p, ctypes.c_uint32, _f64p, ctypes.c_uint32, ctypes.c_float,
@@ -287,6 +304,53 @@ class Frame:
     def path_radiance(self, params: Params, pixel: int, instant: int, sample: int) -> np.float32:
         return np.float32(lib().evo_path_radiance(self._frame, ctypes.byref(params), int(pixel),
                                                   int(instant), int(sample)))
+
+    def path_record(self, params: Params, pixel: int, instant: int, sample: int):
+        """Radiance of one path and its derivative record: (L, [(material,
+        radiance before the vertex's light samples)], [(emitter material,
+        term value)])."""
+        rec = _PathRec()
+        L = lib().evo_path_radiance_rec(self._frame, ctypes.byref(params), int(pixel), int(instant),
+                                        int(sample), ctypes.byref(rec))
+        verts = [(int(rec.vmat[k]), np.float32(rec.vlb[k])) for k in range(rec.n_vert)]
+        terms = [(int(rec.tmat[k]), np.float32(rec.tval[k])) for k in range(rec.n_term)]
+        return np.float32(L), verts, terms
+
+    def path_gradient(self, params: Params, pixel: int, instant: int, sample: int):
+        """dL/d albedo and dL/d emission (per material, FP64) of one path with
+        its sampling decisions held fixed."""
+        L, verts, terms = self.path_record(params, pixel, instant, sample)
+        alb = np.asarray(self.scene.albedo, np.float32)
+        emi = np.asarray(self.scene.emission, np.float32)
+        ga = np.zeros(len(alb))
+        ge = np.zeros(len(emi))
+        for m, lb in verts:
+            ga[m] += (float(L) - float(lb)) / float(alb[m])
+        for m, v in terms:
+            ge[m] += float(v) / float(emi[m])
+        return L, ga, ge
+
+    def event_loss(self, params: Params, C: float, tau: float, spp: int,
+                   pixels: Optional[np.ndarray] = None, threads: int = 0) -> Dict[str, np.ndarray]:
+        """Smoothed event loss sum softplus((|Delta| - C) / tau) at a fixed
+        count of spp paths per pixel and instant, and its gradient with
+        respect to every material's albedo and emission (FP64)."""
+        nm = len(self.scene.albedo)
+        n = self.scene.width * self.scene.height if pixels is None else len(pixels)
+        px = None if pixels is None else np.ascontiguousarray(pixels, np.uint32)
+        loss = np.zeros(1)
+        ga = np.zeros(nm)
+        ge = np.zeros(nm)
+        lpx = np.zeros(n)
+        dpx = np.zeros(n)
+        rc = lib().evo_event_loss(self._frame, ctypes.byref(params), float(C), float(tau), int(spp),
+                                  None if px is None else _ptr(px, ctypes.c_uint32), n, int(threads),
+                                  _ptr(loss, ctypes.c_double), _ptr(ga, ctypes.c_double),
+                                  _ptr(ge, ctypes.c_double), _ptr(lpx, ctypes.c_double),
+                                  _ptr(dpx, ctypes.c_double))
+        if rc != 0:
+            raise ValueError("invalid event-loss parameters")
+        return dict(loss=float(loss[0]), grad_albedo=ga, grad_emission=ge, loss_px=lpx, delta=dpx)
 
     def paths(self, params: Params, pixel, instant, sample, threads: int = 0) -> np.ndarray:
         """Per-path radiance for arrays of (pixel, instant, sample)."""

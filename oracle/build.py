@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["evo_stats.c", "evo_scene.c", "evo_bvh.c", "evo_render.c", "evo_batch.c"]
+SRC = ["evo_stats.c", "evo_scene.c", "evo_bvh.c", "evo_render.c", "evo_batch.c", "evo_diff.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -124,6 +124,37 @@ float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
 
 /* Decision on given logL sample sets (m0 samples at the reference instant,
  * m1 at the second); writes t, the p-value and the stop flag. */
+/* Record of one path for the derivatives of its radiance L with respect to
+ * material albedos and emitted radiances, with every sampling decision
+ * (light pick, Russian roulette, directions) held fixed: vertex k with
+ * material vmat[k] and albedo a > 0 multiplies every term added after
+ * vlb[k] (the radiance accumulated before its light samples), so
+ * dL/da_j = sum over k with vmat[k] = j of (L - vlb[k]) / a_j; term k of
+ * value tval[k] is proportional to the emitted radiance of material
+ * tmat[k], so dL/dLe_e = sum over k with tmat[k] = e of tval[k] / Le_e. */
+#define EVO_REC_MAX 64
+typedef struct {
+    uint32_t n_vert, n_term;
+    uint32_t vmat[EVO_REC_MAX];
+    float vlb[EVO_REC_MAX];
+    uint32_t tmat[2 * EVO_REC_MAX];
+    float tval[2 * EVO_REC_MAX];
+} evo_path_rec;
+
+float evo_path_radiance_rec(const evo_frame *f, const evo_params *p, uint32_t pixel,
+                            int instant, uint32_t sample, evo_path_rec *rec);
+
+/* Smoothed event loss of one pair at a fixed count of spp paths per pixel
+ * and instant: Delta = mean_k ln(Y_k(t1) + eps) - mean_k ln(Y_k(t0) + eps)
+ * over mini-batch means Y_k, loss = sum over the pixels of
+ * softplus((|Delta| - C) / tau).  Its gradient with respect to every
+ * material's albedo and emitted radiance by path replay (the derivative of
+ * each path's radiance with its sampling decisions held fixed), all in
+ * FP64.  pixels = NULL means every pixel.  Outputs may be NULL. */
+int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau, uint32_t spp,
+                   const uint32_t *pixels, uint32_t n_pixels, int n_threads, double *loss,
+                   double *grad_albedo, double *grad_emission, double *loss_px, double *delta_px);
+
 int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
                float C, float alpha, int df_mode, int mode,
                double *t_out, double *p_out, double *df_out, int *stop_out);

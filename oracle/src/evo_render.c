@@ -52,8 +52,8 @@ static float dot3(const float *a, const float *b)
  * sample, instant, vertex, block): vertex 0 block 0 gives the pixel jitter;
  * vertex d block 0 gives (light pick, two light-point numbers, roulette);
  * vertex d block 1 gives the two direction numbers. */
-float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
-                        int instant, uint32_t sample)
+static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel, int instant,
+                           uint32_t sample, evo_path_rec *rec)
 {
     const evo_scene_desc *sd = &f->scene->d;
     const evo_instant *I = &f->inst[instant];
@@ -82,6 +82,10 @@ float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
 
     float L = 0.0f, beta = 1.0f;
     uint32_t skip = EVO_NO_PRIM;
+    if (rec) {
+        rec->n_vert = 0;
+        rec->n_term = 0;
+    }
     for (uint32_t depth = 1; depth <= p->max_depth; ++depth) {
         evo_ray ray;
         evo__ray_setup(&ray, o, d);
@@ -99,8 +103,22 @@ float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
 
         /* Emission of a front-facing emitter: at the first vertex only
          * when next-event estimation accounts for direct light. */
-        if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !p->nee)) L = L + beta * Le;
+        if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !p->nee)) {
+            const float term = beta * Le;
+            L = L + term;
+            if (rec) {
+                rec->tmat[rec->n_term] = m;
+                rec->tval[rec->n_term++] = term;
+            }
+        }
         if (!(alb > 0.0f)) break;
+        /* Every term added from here on carries the factor a of this
+         * vertex (the BRDF of its light samples, the throughput of its
+         * continuation). */
+        if (rec) {
+            rec->vmat[rec->n_vert] = m;
+            rec->vlb[rec->n_vert++] = L;
+        }
 
         uint32_t r0[4];
         rng4(p, pixel, sample, instant, depth, 0, r0);
@@ -139,6 +157,10 @@ float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
                              * collapse to S. */
                             float cval = ((((beta * fr) * cx) * cy) * I->emit_S) / r2;
                             Dd = Dd + cval;
+                            if (rec) {
+                                rec->tmat[rec->n_term] = f->inst[instant].mat[q];
+                                rec->tval[rec->n_term++] = cval;
+                            }
                         }
                     }
                 }
@@ -190,6 +212,19 @@ float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
         skip = prim;
     }
     return L;
+}
+
+float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
+                        int instant, uint32_t sample)
+{
+    return path_radiance(f, p, pixel, instant, sample, NULL);
+}
+
+float evo_path_radiance_rec(const evo_frame *f, const evo_params *p, uint32_t pixel,
+                            int instant, uint32_t sample, evo_path_rec *rec)
+{
+    if (p->max_depth > EVO_REC_MAX) return NAN;
+    return path_radiance(f, p, pixel, instant, sample, rec);
 }
 
 /* Mean of a power-of-two mini-batch by a pairwise sum tree, FP32. */

@@ -318,6 +318,67 @@ def sensor(seed: int = 0, width: int = 640, height: int = 480, n_spheres: int = 
     return b.build()
 
 
+def diff_scene(seed: int = 0, width: int = 256, height: int = 256, floor_n: int = 50,
+               n_spheres: int = 12, subdiv: int = 2) -> Scene:
+    """Workload of the event-loss gradient (256x256, 9,648 triangles, 32
+    Lambertian materials of albedo U[0.2, 0.8] and 4 emitters of radiance
+    U[1, 20]): a floor_n x floor_n-quad floor on [-3, 3]^2 in 4x4 tiles of 16
+    materials, a 20x20-quad back wall at z = -3 in 2x2 tiles of 4 materials,
+    12 icospheres (subdivision 2, 320 triangles) of radius U[0.2, 0.5] and
+    one material each resting on the floor at centres U[-2.2, 2.2]^2, and
+    four 0.8 x 0.8 lights at y = 3 facing down, one material each.  Every
+    sphere translates by U[-0.05, 0.05]^3 between t = 0 and t = 1.  Static
+    camera at (0, 2.2, 5.5) looking at (0, 0.4, 0), 45 degrees."""
+    rng = np.random.default_rng(seed)
+    b = SceneBuilder()
+    floor_m = [b.material(rng.uniform(0.2, 0.8)) for _ in range(16)]
+    wall_m = [b.material(rng.uniform(0.2, 0.8)) for _ in range(4)]
+    sphere_m = [b.material(rng.uniform(0.2, 0.8)) for _ in range(n_spheres)]
+    light_m = [b.material(0.0, rng.uniform(1.0, 20.0)) for _ in range(4)]
+
+    def grid(n, corner, du, dv, tile_mats, tiles):
+        u = np.arange(n + 1)
+        U, V = np.meshgrid(u, u, indexing="ij")
+        P = (np.asarray(corner)[None, None, :] + U[..., None] * np.asarray(du)[None, None, :] / n
+             + V[..., None] * np.asarray(dv)[None, None, :] / n).reshape(-1, 3)
+        i = np.arange(n)[:, None]
+        j = np.arange(n)[None, :]
+        v00 = (i * (n + 1) + j).reshape(-1)
+        v10 = ((i + 1) * (n + 1) + j).reshape(-1)
+        v01 = (i * (n + 1) + j + 1).reshape(-1)
+        v11 = ((i + 1) * (n + 1) + j + 1).reshape(-1)
+        tr = np.stack([np.stack([v00, v01, v11], 1), np.stack([v00, v11, v10], 1)], 1).reshape(-1, 3)
+        ti = (i * tiles // n) * tiles + (j * tiles // n)
+        mats = np.repeat(np.asarray(tile_mats)[ti.reshape(-1)], 2)
+        return P, tr, mats
+
+    # Floor facing +y (corner, du along +z, dv along +x), wall facing +z.
+    fv, ft, fm = grid(floor_n, (-3.0, 0.0, -3.0), (0.0, 0.0, 6.0), (6.0, 0.0, 0.0), floor_m, 4)
+    b.static(b.mesh(fv, ft, fm))
+    wv, wt, wm = grid(20, (-3.0, 0.0, -3.0), (6.0, 0.0, 0.0), (0.0, 3.5, 0.0), wall_m, 2)
+    b.static(b.mesh(wv, wt, wm))
+    sv, st = icosphere(subdiv)
+    for k in range(n_spheres):
+        mesh = b.mesh(sv, st, sphere_m[k])
+        r = rng.uniform(0.2, 0.5)
+        cx, cz = rng.uniform(-2.2, 2.2, size=2)
+        c = np.array([cx, r, cz])
+        dt = rng.uniform(-0.05, 0.05, size=3)
+        b.instance(mesh, [0.0, 1.0], [compose(np.eye(3), c, r), compose(np.eye(3), c + dt, r)])
+    for k, (lx, lz) in enumerate(((-1.2, -1.0), (1.2, -1.0), (-1.2, 1.0), (1.2, 1.0))):
+        lv, lt = oriented_quad([(lx - 0.4, 3.0, lz - 0.4), (lx + 0.4, 3.0, lz - 0.4),
+                                (lx + 0.4, 3.0, lz + 0.4), (lx - 0.4, 3.0, lz + 0.4)], (0, -1, 0))
+        b.static(b.mesh(lv, lt, light_m[k]))
+    b.set_camera(width, height, 45.0, [0.0], [[0, 2.2, 5.5, 0, 0.4, 0, 0, 1, 0]])
+    return b.build()
+
+
+# Event loss of the differentiation workload: 256 paths per pixel and
+# instant, loss sum softplus((|Delta| - C) / tau).
+DIFF_PARAMS = dict(seed=0, max_depth=4, rr_start_depth=2, minibatch=4, log_eps=1e-4, nee=1, jitter=1,
+                   C=0.2, tau=0.05, spp=256)
+
+
 # ---------------------------------------------------------------------------
 # Closed-form and structural test scenes.
 
