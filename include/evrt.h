@@ -220,6 +220,48 @@ int evrt_decide_stats(evrt_ctx *ctx, const double *x0, const double *x1, uint32_
                       uint32_t m, float C, float alpha, uint8_t mode, double *t_out,
                       uint8_t *stop_out, int8_t *polarity_out, void *stream);
 
+/* ---- Differentiation: a smoothed event loss and its gradient ---------
+ *
+ * For the pair (t0, t1) every pixel is sampled with spp paths per instant
+ * (fixed count; spp a multiple of opts->minibatch).  With Y_{i,k} the mean
+ * radiance of mini-batch k at instant i and m = spp / minibatch:
+ *   mu_i  = (1/m) sum_k ln(Y_{i,k} + log_eps)    (the log-luminance of
+ *           Eq. 3, averaged as in Eq. 4),
+ *   Delta = mu_1 - mu_0                          (the change that Eq. 1
+ *           compares with the threshold C),
+ *   loss  = sum over pixels of softplus((|Delta| - C) / tau), tau > 0,
+ * a smooth stand-in for the count of events.  The gradient with respect to
+ * every material's albedo and emitted radiance is computed by replaying
+ * each path from its random-number keys (nothing per path is stored
+ * besides its radiance) and differentiating its radiance with every
+ * sampling decision held fixed: light pick, Russian roulette and scattering
+ * directions.  This estimates the gradient of the expected loss terms
+ * without bias; it is reported for materials with albedo > 0 (albedo) and
+ * emission > 0 (emission), zero elsewhere.
+ *
+ * out (caller-owned device memory, double precision):
+ *   loss            [1]
+ *   grad            [2 * n_mat]: d loss / d albedo[j] at j, then
+ *                   d loss / d emission[j] at n_mat + j
+ *   loss_px, delta  [width * height] per-pixel loss term and Delta, or NULL
+ *   replay_mismatch [1] number of paths whose replayed radiance differs in
+ *                   any bit from the forward pass (0 expected), or NULL
+ * Errors: EVRT_E_INVALID for tau <= 0, C < 0, non-finite arguments, spp not
+ * a positive multiple of the mini-batch, NULL loss or grad;
+ * EVRT_E_UNSUPPORTED for more than 2048 materials or 2^31 paths.  The
+ * library keeps per-path radiances and weights (12 bytes per path) in its
+ * own buffers between calls. */
+typedef struct {
+    double *loss;
+    double *grad;
+    double *loss_px;
+    double *delta;
+    uint32_t *replay_mismatch;
+} evrt_diff_out;
+
+int evrt_event_loss_grad(evrt_ctx *ctx, double t0, double t1, float C, float tau, uint32_t spp,
+                         const evrt_render_opts *opts, const evrt_diff_out *out, void *stream);
+
 /* Host-side build of the scene at time t (world triangles and BVH2, no
  * device work) with a structural check of the BVH: every primitive in
  * exactly one leaf, every vertex inside its padded leaf box, every node

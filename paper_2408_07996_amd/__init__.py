@@ -69,6 +69,11 @@ class SceneInfo(ctypes.Structure):
                 ("box_pad", ctypes.c_float), ("sah_cost", ctypes.c_double)]
 
 
+class DiffOut(ctypes.Structure):
+    _fields_ = [("loss", _c_p), ("grad", _c_p), ("loss_px", _c_p), ("delta", _c_p),
+                ("replay_mismatch", _c_p)]
+
+
 class EvrtError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"evrt error {code}: {msg}")
@@ -100,6 +105,9 @@ SIGNATURES = [
      [_c_p, ctypes.c_double, ctypes.c_double, _u32, _c_p, _u32, ctypes.POINTER(RenderOpts), _c_p, _c_p]),
     ("evrt_decide_stats", ctypes.c_int,
      [_c_p, _c_p, _c_p, _u32, _u32, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, _c_p, _c_p, _c_p, _c_p]),
+    ("evrt_event_loss_grad", ctypes.c_int,
+     [_c_p, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float, _u32, ctypes.POINTER(RenderOpts),
+      ctypes.POINTER(DiffOut), _c_p]),
     ("evrt_scene_info_at", ctypes.c_int, [_c_p, ctypes.c_double, ctypes.POINTER(SceneInfo)]),
     ("evrt_t_quantile", ctypes.c_double, [ctypes.c_double, _u32]),
 ]
@@ -113,6 +121,10 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         from . import build as _build
         _build.build()
+    # torch brings its own HIP and HSA runtimes; loading them before the
+    # library makes the library bind to the same ones (a second copy of the
+    # runtime in the process does not see the device).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     for name, res, args in SIGNATURES:
         fn = getattr(L, name)
@@ -157,6 +169,12 @@ class Renderer:
 
     def __init__(self, device: int = 0):
         L = load_library()
+        if device >= 0:
+            # Outputs are torch tensors: bring up torch's device runtime before
+            # the library's, which it does not detect when it starts second.
+            import torch
+            if not torch.cuda.is_available():
+                raise EvrtError(EVRT_E_DEVICE, "no visible GPU")
         h = _c_p()
         rc = L.evrt_create(int(device), ctypes.byref(h))
         if rc != EVRT_OK:
@@ -244,6 +262,16 @@ class Renderer:
         self.scene_commit()
         self.scene = sc
 
+    def set_materials(self, albedo, emission) -> None:
+        """Replaces the materials of the committed scene and commits again
+        (geometry is kept; instants are rebuilt on next use)."""
+        self.scene_set_materials(albedo, emission)
+        self.scene_commit()
+        if getattr(self, "scene", None) is not None:
+            import dataclasses
+            self.scene = dataclasses.replace(self.scene, albedo=np.asarray(albedo, np.float32).copy(),
+                                             emission=np.asarray(emission, np.float32).copy())
+
     def scene_info_at(self, t: float) -> Dict:
         """Host-side BVH build and structural check at time t."""
         info = SceneInfo()
@@ -320,6 +348,31 @@ class Renderer:
                                                    _dptr(tt), _dptr(prim), _stream_ptr(stream)))
         return prim if any_hit else (tt, prim)
 
+    def event_loss_grad(self, t0: float, t1: float, C: float, tau: float, spp: int, opts=None,
+                        per_pixel: bool = False, stream=None) -> Dict:
+        """Smoothed event loss sum softplus((|Delta| - C) / tau) at spp paths
+        per pixel and instant, and its path-replay gradient (float64 device
+        tensors): loss [1], grad_albedo [n_mat], grad_emission [n_mat],
+        replay_mismatch [1]; with per_pixel also loss_px and delta [H*W]."""
+        import torch
+        o = self._opts(opts)
+        dev = torch.device("cuda", self.device)
+        n_mat = len(self.scene.albedo)
+        npx = self.scene.width * self.scene.height
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        grad = torch.empty(2 * n_mat, dtype=torch.float64, device=dev)
+        mism = torch.empty(1, dtype=torch.int32, device=dev)
+        lpx = torch.empty(npx, dtype=torch.float64, device=dev) if per_pixel else None
+        dpx = torch.empty(npx, dtype=torch.float64, device=dev) if per_pixel else None
+        out = DiffOut(_dptr(loss), _dptr(grad), _dptr(lpx), _dptr(dpx), _dptr(mism))
+        self._check(load_library().evrt_event_loss_grad(self._h, float(t0), float(t1), float(C), float(tau),
+                                                        int(spp), ctypes.byref(o), ctypes.byref(out),
+                                                        _stream_ptr(stream)))
+        res = dict(loss=loss, grad_albedo=grad[:n_mat], grad_emission=grad[n_mat:], replay_mismatch=mism)
+        if per_pixel:
+            res.update(loss_px=lpx, delta=dpx)
+        return res
+
     def decide_stats(self, x0, x1, C: float, alpha: float, mode: int = MODE_ADAPTIVE_1T, stream=None):
         """Decision kernels on caller log-luminance samples [n, m] (float64)."""
         import torch
@@ -334,3 +387,44 @@ class Renderer:
                                                      int(mode), _dptr(t), _dptr(stop), _dptr(pol),
                                                      _stream_ptr(stream)))
         return t, stop, pol
+
+
+# ---------------------------------------------------------------------------
+# Differentiable event loss.
+
+_EVENT_LOSS_FN = None
+
+
+def _event_loss_function():
+    global _EVENT_LOSS_FN
+    if _EVENT_LOSS_FN is not None:
+        return _EVENT_LOSS_FN
+    import torch
+
+    class EventLoss(torch.autograd.Function):
+        """loss(albedo, emission) of Renderer.event_loss_grad; the backward
+        pass returns the path-replay gradient computed with the forward."""
+
+        @staticmethod
+        def forward(ctx, albedo, emission, renderer, t0, t1, C, tau, spp, opts):
+            renderer.set_materials(albedo.detach().cpu().numpy(), emission.detach().cpu().numpy())
+            r = renderer.event_loss_grad(t0, t1, C, tau, spp, opts)
+            ctx.save_for_backward(r["grad_albedo"].to(albedo.device, albedo.dtype),
+                                  r["grad_emission"].to(emission.device, emission.dtype))
+            return r["loss"][0].to(device=albedo.device, dtype=albedo.dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            ga, ge = ctx.saved_tensors
+            return g * ga, g * ge, None, None, None, None, None, None, None
+
+    _EVENT_LOSS_FN = EventLoss
+    return EventLoss
+
+
+def event_loss(renderer: "Renderer", albedo, emission, t0: float, t1: float, C: float, tau: float,
+               spp: int, opts=None):
+    """Differentiable smoothed event loss of the renderer's scene with the
+    given per-material albedo and emission tensors (any device and float
+    dtype); gradients flow to both."""
+    return _event_loss_function().apply(albedo, emission, renderer, t0, t1, C, tau, spp, opts)

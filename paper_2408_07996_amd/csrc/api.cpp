@@ -425,6 +425,29 @@ int evrt_render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, cons
     });
 }
 
+int evrt_event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint32_t spp,
+                         const evrt_render_opts *opts, const evrt_diff_out *out, void *stream)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        evrt_render_opts o;
+        if (opts) o = *opts;
+        else evrt_default_opts(&o);
+        validate_opts(o);
+        if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
+        if (!std::isfinite(t0) || !std::isfinite(t1)) fail(EVRT_E_INVALID, "t0 and t1 must be finite");
+        if (!std::isfinite(C) || C < 0.0f) fail(EVRT_E_INVALID, "C must be finite and >= 0");
+        if (!std::isfinite(tau) || !(tau > 0.0f)) fail(EVRT_E_INVALID, "tau must be finite and > 0");
+        if (spp == 0 || spp % o.minibatch != 0) fail(EVRT_E_INVALID, "spp must be a positive multiple of minibatch");
+        if (!out || !out->loss || !out->grad) fail(EVRT_E_INVALID, "NULL loss or gradient output");
+        if (c->scene.albedo.size() > 2048) fail(EVRT_E_UNSUPPORTED, "more than 2048 materials");
+        const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;
+        if (2ull * npx * spp >= (1ull << 31)) fail(EVRT_E_UNSUPPORTED, "more than 2^31 paths");
+        need_device(c);
+        event_loss_grad(c, t0, t1, C, tau, spp, o, *out, static_cast<hipStream_t>(stream));
+    });
+}
+
 int evrt_decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n_pixels, uint32_t m, float C,
                       float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *polarity_out,
                       void *stream)

@@ -107,6 +107,7 @@ struct FrameBuffers {
     DevBuf sh_o, sh_meta, sh_dir, sh_c;
     DevBuf rad;
     DevBuf hook_tm;
+    DevBuf diff_px, diff_L, diff_W;  // event-loss gradient: pixel list, path radiance, weights
     uint32_t queue_cap = 0, shadow_slots = 0;
 };
 
@@ -152,5 +153,7 @@ void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint
 void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
                   float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
                   hipStream_t s);
+void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint32_t spp,
+                     const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s);
 void validate_opts(const evrt_render_opts &o);
 }  // namespace evrt

@@ -71,6 +71,15 @@ void launch_hook_trace(hipStream_t s, uint32_t blocks, bool any, const DevScene 
 void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint32_t n, uint32_t m,
                         const Decide &dc, double *t_out, uint8_t *stop_out, int8_t *pol_out);
 
+// Event loss and its gradient: zeroing, per-pixel statistics and weights,
+// path-replay adjoint (g = [albedo gradients | emission gradients]).
+void launch_diff_zero(hipStream_t s, double *loss, double *g, uint32_t n_g, uint32_t *mismatch);
+void launch_diff_stats(hipStream_t s, uint32_t npx, uint32_t spp, uint32_t mb, double log_eps, double C,
+                       double tau, const float *L, double *W, double *loss, double *loss_px, double *delta_px);
+void launch_adjoint(hipStream_t s, uint32_t blocks, const DevScene &sc, const RenderParams &rp, uint32_t npx,
+                    uint32_t spp, const float *Lfwd, const double *W, uint32_t n_mat, double *g,
+                    uint32_t *mismatch);
+
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu);
 int traverse_block_threads();
 int lds_treelet_nodes();

@@ -1082,6 +1082,252 @@ __global__ void k_hook_decide(const double *x0, const double *x1, uint32_t n, ui
     pol_out[i] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
 }
 
+// ------------------------------------------------------------------------
+// Smoothed event loss and its gradient by path replay.
+
+__device__ __forceinline__ double softplus_d(double z) { return z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z)); }
+
+__device__ __forceinline__ double sigmoid_d(double z)
+{
+    if (z >= 0.0) return 1.0 / (1.0 + exp(-z));
+    const double e = exp(z);
+    return e / (1.0 + e);
+}
+
+// Zeroes the loss, the gradients and the replay mismatch count.
+__global__ void k_diff_zero(double *loss, double *g, uint32_t n_g, uint32_t *mismatch)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_g) g[i] = 0.0;
+    if (i == 0) {
+        *loss = 0.0;
+        if (mismatch) *mismatch = 0;
+    }
+}
+
+// Per pixel, from its stored path radiances L[pixel][instant][sample]: the
+// mini-batch means Y_k, mu_i = (1/m) sum_k ln(Y_k + eps) (k ascending,
+// FP64), Delta = mu_1 - mu_0, the loss term softplus((|Delta| - C) / tau)
+// and the weight of every mini-batch in the gradient,
+// W = +-sigmoid(z) sign(Delta) / tau / m / mb / (Y_k + eps) (+ at t1).
+__global__ __launch_bounds__(256) void k_diff_stats(uint32_t npx, uint32_t spp, uint32_t mb, double log_eps,
+                                                    double C, double tau, const float *L, double *W,
+                                                    double *loss, double *loss_px, double *delta_px)
+{
+    __shared__ double s_sum[256];
+    const uint32_t px = blockIdx.x * blockDim.x + threadIdx.x;
+    double lp = 0.0;
+    if (px < npx) {
+        const uint32_t m = spp / mb;
+        double mu[2];
+        for (uint32_t i = 0; i < 2; ++i) {
+            const float *src = L + ((size_t)px * 2 + i) * spp;
+            double sum = 0.0;
+            for (uint32_t k = 0; k < m; ++k) sum += log((double)minibatch_mean(src + k * mb, mb) + log_eps);
+            mu[i] = sum / (double)m;
+        }
+        const double delta = mu[1] - mu[0];
+        const double z = (fabs(delta) - C) / tau;
+        lp = softplus_d(z);
+        if (loss_px) loss_px[px] = lp;
+        if (delta_px) delta_px[px] = delta;
+        const double sgn = delta > 0.0 ? 1.0 : (delta < 0.0 ? -1.0 : 0.0);
+        const double g = sigmoid_d(z) / tau * sgn;
+        for (uint32_t i = 0; i < 2; ++i) {
+            const float *src = L + ((size_t)px * 2 + i) * spp;
+            double *dst = W + ((size_t)px * 2 + i) * m;
+            for (uint32_t k = 0; k < m; ++k)
+                dst[k] = (i ? g : -g) / (double)m / (double)mb / ((double)minibatch_mean(src + k * mb, mb) + log_eps);
+        }
+    }
+    s_sum[threadIdx.x] = lp;
+    __syncthreads();
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && s_sum[0] != 0.0) atomicAdd(loss, s_sum[0]);
+}
+
+// One path of (pixel, instant, sample) traced again from its keys with the
+// arithmetic of the wavefront kernels (camera ray of k_raygen, shading of
+// k_shade, light samples of k_trace_shadow summed in slot order), adding w
+// times its derivatives to the block's accumulators: every term added after
+// the light samples of a vertex with albedo a carries a, so that vertex
+// contributes w (L - L_before) / a to its material; every emitter term c
+// contributes w c / Le to the emitter's material.  L is the radiance of the
+// forward pass; the return value is the replayed radiance.
+__device__ float replay_path(const DevScene &sc, const RenderParams &rp, const lds_f32 *s_nodes,
+                             lds_u32 *lds_stack, uint32_t pixel, uint32_t inst, uint32_t sample, double w,
+                             float Lfwd, double *acc_a, double *acc_e)
+{
+    const DevInstant &I = inst ? sc.inst[1] : sc.inst[0];
+    const DevCamera &cam = I.cam;
+    const uint32_t py = fdiv(sc.div_w, pixel);
+    const uint32_t px = pixel - py * sc.width;
+    float j0 = 0.5f, j1 = 0.5f;
+    if (rp.jitter) {
+        const uint4 rb = rng_block(rp, pixel, sample, inst, 0, 0);
+        j0 = u01(rb.x);
+        j1 = u01(rb.y);
+    }
+    const float fx = (float)px + j0, fy = (float)py + j1;
+    const float nx = (2.0f * fx) / (float)sc.width - 1.0f;
+    const float ny = 1.0f - (2.0f * fy) / (float)sc.height;
+    const float ca = nx * cam.sx, cb = ny * cam.sy;
+    float dx = (cam.fwd[0] + ca * cam.right[0]) + cb * cam.up[0];
+    float dy = (cam.fwd[1] + ca * cam.right[1]) + cb * cam.up[1];
+    float dz = (cam.fwd[2] + ca * cam.right[2]) + cb * cam.up[2];
+    const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
+    dx = dx / len;
+    dy = dy / len;
+    dz = dz / len;
+    float ox = cam.eye[0], oy = cam.eye[1], oz = cam.eye[2];
+    float L = 0.0f, beta = 1.0f;
+    uint32_t skip = kNoPrim;
+    uint32_t visits = 0, tests = 0;
+    for (uint32_t depth = 1; depth <= rp.max_depth; ++depth) {
+        Trav T;
+        trav_begin(T, sc, inst, ox, oy, oz, dx, dy, dz, kRayTmin, INFINITY, skip);
+        traverse<false, false>(T, sc, s_nodes, lds_stack, visits, tests);
+        const uint32_t prim = T.best_p;
+        if (prim == kNoPrim) break;
+        const float t = T.tfar;
+        const float Px = ox + t * dx, Py = oy + t * dy, Pz = oz + t * dz;
+        const float4 pr = I.prim[prim];
+        const uint32_t mat = fbits(pr.w);
+        const float2 mt = sc.mat[mat];
+        const float alb = mt.x, Le = mt.y;
+        const float cosi = dot3f(pr.x, pr.y, pr.z, dx, dy, dz);
+        const float nsx = cosi < 0.0f ? pr.x : -pr.x;
+        const float nsy = cosi < 0.0f ? pr.y : -pr.y;
+        const float nsz = cosi < 0.0f ? pr.z : -pr.z;
+        if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee)) {
+            const float term = beta * Le;
+            L = L + term;
+            atomicAdd(&acc_e[mat], w * (double)term / (double)Le);
+        }
+        if (!(alb > 0.0f)) break;
+        const float Lb = L;
+        const uint4 r0 = rng_block(rp, pixel, sample, inst, depth, 0);
+        const float fr = alb * kInvPi;
+        if (rp.nee) {
+            float sum = 0.0f;
+            if (I.n_emit > 0) {
+                const float ul = u01(r0.x);
+                uint32_t lo = 0, hi = I.n_emit - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (ul < I.emit_cdf[mid]) hi = mid; else lo = mid + 1;
+                }
+                const float4 *E = I.emit + 4 * (size_t)lo;
+                const float4 v0 = E[0], v1 = E[1], v2 = E[2], en = E[3];
+                const float su = sqrtf(u01(r0.y));
+                const float u2 = u01(r0.z);
+                const float w0 = 1.0f - su, w1 = su * (1.0f - u2), w2 = su * u2;
+                const float wx = ((w0 * v0.x + w1 * v1.x) + w2 * v2.x) - Px;
+                const float wy = ((w0 * v0.y + w1 * v1.y) + w2 * v2.y) - Py;
+                const float wz = ((w0 * v0.z + w1 * v1.z) + w2 * v2.z) - Pz;
+                const float r2 = dot3f(wx, wy, wz, wx, wy, wz);
+                if (r2 > 0.0f) {
+                    const float rl = sqrtf(r2);
+                    const float wix = wx / rl, wiy = wy / rl, wiz = wz / rl;
+                    const float cx = dot3f(nsx, nsy, nsz, wix, wiy, wiz);
+                    const float cy = -dot3f(en.x, en.y, en.z, wix, wiy, wiz);
+                    if (cx > 0.0f && cy > 0.0f) {
+                        const float c0 = ((((beta * fr) * cx) * cy) * I.emit_S) / r2;
+                        if (c0 > 0.0f) {
+                            Trav S;
+                            trav_begin(S, sc, inst, Px, Py, Pz, wix, wiy, wiz, kRayTmin, rl * kShadowScale, prim);
+                            traverse<true, false>(S, sc, s_nodes, lds_stack, visits, tests);
+                            if (S.best_p == kNoPrim) {
+                                sum = sum + c0;
+                                const uint32_t emat = fbits(I.prim[fbits(en.w)].w);
+                                atomicAdd(&acc_e[emat], w * (double)c0 / (double)sc.mat[emat].y);
+                            }
+                        }
+                    }
+                }
+            }
+            for (uint32_t k = 0; k < sc.n_plights; ++k) {
+                float4 dk = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float ck = point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta, fr, dk);
+                if (!(ck > 0.0f)) continue;
+                Trav S;
+                trav_begin(S, sc, inst, Px, Py, Pz, dk.x, dk.y, dk.z, kRayTmin, dk.w, prim);
+                traverse<true, false>(S, sc, s_nodes, lds_stack, visits, tests);
+                if (S.best_p == kNoPrim) sum = sum + ck;
+            }
+            L = L + sum;
+        }
+        atomicAdd(&acc_a[mat], w * ((double)Lfwd - (double)Lb) / (double)alb);
+        if (depth >= rp.max_depth) break;
+        if (depth >= rp.rr_start) {
+            const float qs = fminf(1.0f, beta);
+            if (u01(r0.w) >= qs) break;
+            beta = beta / qs;
+        }
+        const uint4 r1 = rng_block(rp, pixel, sample, inst, depth, 1);
+        const float e0 = u01(r1.x), e1 = u01(r1.y);
+        const float rr = sqrtf(e0);
+        const double ph = kTwoPi * (double)e1;
+        double sd, cd;
+        sincos(ph, &sd, &cd);
+        const float cph = (float)cd, sph = (float)sd;
+        const float lx = rr * cph, ly = rr * sph, lz = sqrtf(fmaxf(0.0f, 1.0f - e0));
+        const float sg = copysignf(1.0f, nsz);
+        const float aa = -1.0f / (sg + nsz);
+        const float bb = (nsx * nsy) * aa;
+        const float tx = 1.0f + ((sg * nsx) * nsx) * aa, ty = sg * bb, tz = (-sg) * nsx;
+        const float bx = bb, by = sg + (nsy * nsy) * aa, bz = -nsy;
+        dx = (tx * lx + bx * ly) + nsx * lz;
+        dy = (ty * lx + by * ly) + nsy * lz;
+        dz = (tz * lx + bz * ly) + nsz * lz;
+        ox = Px;
+        oy = Py;
+        oz = Pz;
+        beta = beta * alb;
+        skip = prim;
+    }
+    return L;
+}
+
+// Adjoint pass: one thread per path (grid-stride over pixel-major paths
+// [pixel][instant][sample]); gradients accumulate per block in LDS (FP64)
+// and are added to g[0..n_mat) (albedo) and g[n_mat..2 n_mat) (emission)
+// with one atomic per block and entry.
+__global__ __launch_bounds__(kTB) void k_adjoint(DevScene sc, RenderParams rp, uint32_t npx, uint32_t spp,
+                                                 const float *Lfwd, const double *W, uint32_t n_mat, double *g,
+                                                 uint32_t *mismatch)
+{
+    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ uint32_t s_stack[kStackLds * kTB];
+    extern __shared__ double s_acc[];
+    for (uint32_t k = threadIdx.x; k < 2 * n_mat; k += kTB) s_acc[k] = 0.0;
+    load_treelets(sc, s_nodes);
+    const uint32_t mb = rp.minibatch, m = spp / mb;
+    const uint64_t n = (uint64_t)npx * 2u * spp;
+    uint32_t bad = 0;
+    for (uint64_t p = (uint64_t)blockIdx.x * kTB + threadIdx.x; p < n; p += (uint64_t)gridDim.x * kTB) {
+        const uint32_t s = (uint32_t)(p % spp);
+        const uint64_t pi = p / spp;
+        const uint32_t inst = (uint32_t)(pi & 1u), pixel = (uint32_t)(pi >> 1);
+        const double w = W[pi * m + s / mb];
+        if (w == 0.0) continue;
+        const float Lp = Lfwd[p];
+        const float Lr = replay_path(sc, rp, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, pixel, inst,
+                                     s, w, Lp, s_acc, s_acc + n_mat);
+        bad += __float_as_uint(Lr) != __float_as_uint(Lp) ? 1u : 0u;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < 2 * n_mat; k += kTB)
+        if (s_acc[k] != 0.0) atomicAdd(&g[k], s_acc[k]);
+    if (mismatch) {
+        const unsigned long long b = wave_sum_u64(bad);
+        if (__lane_id() == 0 && b) atomicAdd(mismatch, (uint32_t)b);
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------
@@ -1157,6 +1403,26 @@ void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_
 {
     hipLaunchKernelGGL(k_decide_compact, dim3((nA + 255) / 256), dim3(256), 0, s, dc, act_in, nA,
                        act_out, cnt, wf_n, wf_mean, wf_m2, wf_ysum, out);
+}
+
+void launch_diff_zero(hipStream_t s, double *loss, double *g, uint32_t n_g, uint32_t *mismatch)
+{
+    hipLaunchKernelGGL(k_diff_zero, dim3(std::max(1u, (n_g + 255) / 256)), dim3(256), 0, s, loss, g, n_g, mismatch);
+}
+
+void launch_diff_stats(hipStream_t s, uint32_t npx, uint32_t spp, uint32_t mb, double log_eps, double C,
+                       double tau, const float *L, double *W, double *loss, double *loss_px, double *delta_px)
+{
+    hipLaunchKernelGGL(k_diff_stats, dim3((npx + 255) / 256), dim3(256), 0, s, npx, spp, mb, log_eps, C, tau, L,
+                       W, loss, loss_px, delta_px);
+}
+
+void launch_adjoint(hipStream_t s, uint32_t blocks, const DevScene &sc, const RenderParams &rp, uint32_t npx,
+                    uint32_t spp, const float *Lfwd, const double *W, uint32_t n_mat, double *g,
+                    uint32_t *mismatch)
+{
+    hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kTB), 2 * n_mat * sizeof(double), s, sc, rp, npx, spp, Lfwd,
+                       W, n_mat, g, mismatch);
 }
 
 void launch_hook_rays(hipStream_t s, uint32_t n, const float *rays, const uint32_t *skip,

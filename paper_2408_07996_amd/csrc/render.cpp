@@ -444,6 +444,41 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
     read_stats(c, s);
 }
 
+// Smoothed event loss at spp paths per pixel and instant and its gradient:
+// forward path radiances of every pixel (the wavefront renderer), per-pixel
+// statistics and mini-batch weights, then the path-replay adjoint.
+void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint32_t spp,
+                     const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s)
+{
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
+    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    const uint32_t npx = c->scene.cam.width * c->scene.cam.height;
+    const uint32_t n_mat = (uint32_t)c->scene.albedo.size();
+    const uint32_t mb = o.minibatch, m = spp / mb;
+    FrameBuffers &fb = c->fb;
+    fb.diff_px.ensure(sizeof(uint32_t) * npx);
+    {
+        std::vector<uint32_t> iota(npx);
+        for (uint32_t i = 0; i < npx; ++i) iota[i] = i;
+        fb.diff_px.upload(iota.data(), sizeof(uint32_t) * npx, s);
+    }
+    fb.diff_L.ensure(sizeof(float) * 2 * (size_t)npx * spp);
+    fb.diff_W.ensure(sizeof(double) * 2 * (size_t)npx * m);
+    launch_diff_zero(s, out.loss, out.grad, 2 * n_mat, out.replay_mismatch);
+    render_paths(c, t0, t1, npx, fb.diff_px.as<uint32_t>(), spp, o, fb.diff_L.as<float>(), s);
+    launch_diff_stats(s, npx, spp, mb, (double)o.log_eps, (double)C, (double)tau, fb.diff_L.as<float>(),
+                      fb.diff_W.as<double>(), out.loss, out.loss_px, out.delta);
+    const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
+    const RenderParams rp = make_params(c, o);
+    const uint64_t n = 2ull * npx * spp;
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(
+        8, std::min<uint64_t>((n + traverse_block_threads() - 1) / traverse_block_threads(), 8ull * c->cu_count));
+    launch_adjoint(s, blocks, sc, rp, npx, spp, fb.diff_L.as<float>(), fb.diff_W.as<double>(), n_mat, out.grad,
+                   out.replay_mismatch);
+    hip_check(hipGetLastError(), "adjoint launch");
+}
+
 void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip, int any,
                 float *t_out, uint32_t *p_out, hipStream_t s)
 {

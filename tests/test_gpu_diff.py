@@ -1,0 +1,101 @@
+"""GPU parity of the event-loss gradient (path-replay adjoint) with the
+oracle, finite differences through the autograd function, and the full
+differentiation workload."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2408_07996_amd as ev
+from paper_2408_07996_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _opts(P):
+    return dict(seed=P.get("seed", 0), max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+                minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+
+
+def _oracle_params(P):
+    return oracle.make_params(seed=P.get("seed", 0), max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+                              minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+
+
+def _compare(sc, P, t0=0.0, t1=1.0, threads=0):
+    rend = ev.Renderer(0)
+    rend.set_scene(sc)
+    _say(f"gpu event loss {sc.width}x{sc.height} spp {P['spp']}")
+    t = time.time()
+    g = rend.event_loss_grad(t0, t1, P["C"], P["tau"], P["spp"], _opts(P), per_pixel=True)
+    gl = float(g["loss"].cpu()[0])
+    _say(f"  gpu {time.time() - t:.2f}s loss {gl:.6f} mismatch {int(g['replay_mismatch'].cpu()[0])}")
+    t = time.time()
+    # The ABI takes C and tau in FP32: the oracle gets the same values.
+    C32, tau32 = float(np.float32(P["C"])), float(np.float32(P["tau"]))
+    with oracle.Frame(sc, t0, t1) as f:
+        r = f.event_loss(_oracle_params(P), C32, tau32, P["spp"], threads=threads)
+    _say(f"  oracle {time.time() - t:.2f}s loss {r['loss']:.6f}")
+    assert int(g["replay_mismatch"].cpu()[0]) == 0
+    np.testing.assert_allclose(g["delta"].cpu().numpy(), r["delta"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g["loss_px"].cpu().numpy(), r["loss_px"], rtol=1e-12, atol=1e-14)
+    assert gl == pytest.approx(r["loss"], rel=1e-12)
+    for k in ("grad_albedo", "grad_emission"):
+        a = g[k].cpu().numpy()
+        b = r[k]
+        scale = max(np.abs(b).max(), 1e-300)
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * scale, err_msg=k)
+    return g, r
+
+
+def test_event_loss_gradient_matches_oracle_small():
+    P = dict(scenes.DIFF_PARAMS, spp=32)
+    g, r = _compare(scenes.diff_scene(width=32, height=24), P)
+    assert np.abs(r["grad_albedo"]).max() > 0 and np.abs(r["grad_emission"]).max() > 0
+
+
+def test_event_loss_gradient_matches_oracle_point_lights_mb8():
+    sc = scenes.tiny_box(width=20, height=16)
+    import dataclasses
+    sc = dataclasses.replace(sc, pl_pos=np.array([[0.4, 1.6, 0.3], [-0.5, 1.2, 0.6]], np.float32),
+                             pl_intensity=np.array([4.0, 2.0], np.float32))
+    P = dict(scenes.DIFF_PARAMS, spp=64, minibatch=8, max_depth=5)
+    _compare(sc, P)
+
+
+def test_autograd_matches_central_differences():
+    import torch
+    sc = scenes.tiny_box(width=16, height=12)
+    P = dict(scenes.DIFF_PARAMS, spp=32, max_depth=3, rr_start_depth=99)
+    rend = ev.Renderer(0)
+    rend.set_scene(sc)
+    a = torch.tensor(np.asarray(sc.albedo), dtype=torch.float64, requires_grad=True)
+    e = torch.tensor(np.asarray(sc.emission), dtype=torch.float64, requires_grad=True)
+    loss = ev.event_loss(rend, a, e, 0.0, 1.0, P["C"], P["tau"], P["spp"], _opts(P))
+    loss.backward()
+    ga = a.grad.numpy()
+    scale = np.abs(ga).max()
+    assert scale > 0
+    base_a = np.asarray(sc.albedo, np.float32)
+    for m in np.nonzero(base_a > 0)[0][:3]:
+        vals = []
+        for sgn in (1, -1):
+            aa = base_a.copy()
+            aa[m] = np.float32(aa[m] + sgn * 1e-3)
+            vals.append((float(aa[m]), float(ev.event_loss(rend, torch.tensor(aa, dtype=torch.float64),
+                                                            torch.tensor(np.asarray(sc.emission)), 0.0, 1.0,
+                                                            P["C"], P["tau"], P["spp"], _opts(P)))))
+        fd = (vals[0][1] - vals[1][1]) / (vals[0][0] - vals[1][0])
+        assert ga[m] == pytest.approx(fd, rel=1e-2, abs=1e-3 * scale), m
+
+
+@pytest.mark.slow
+def test_event_loss_gradient_full_workload():
+    # 256x256, 9,648 triangles, 32 albedos, 4 emitters, 256 paths per pixel
+    # and instant: the GPU gradient against the oracle's full-image gradient.
+    _compare(scenes.diff_scene(), dict(scenes.DIFF_PARAMS), threads=16)
