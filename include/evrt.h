@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define EVRT_ABI_VERSION 1
+#define EVRT_ABI_VERSION 2
 
 enum {
     EVRT_OK = 0,
@@ -143,7 +143,10 @@ typedef struct {
     uint8_t count_work;      /* 1: count BVH node visits and triangle tests        */
     uint8_t lds_nodes;       /* top BVH nodes staged in LDS per block, 0..64 (0)   */
     uint32_t ray_batch;      /* max paths in flight per wavefront piece (0: auto)  */
-    uint32_t reserved1;
+    uint32_t key_base;       /* frame index of instant t0 in the random-number
+                                keys; t1 is key_base + 1 (default 0)              */
+    uint32_t trace_blocks_per_cu; /* traversal blocks per CU (0: occupancy max)    */
+    uint32_t reserved;       /* must be 0                                          */
 } evrt_render_opts;
 
 /* Fills *opts with the defaults listed above (seed 0). */
@@ -173,6 +176,21 @@ int evrt_render_event_frame(evrt_ctx *ctx, double t0, double t1, float C, float 
                             uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
                             const evrt_render_opts *opts, const evrt_frame_out *out,
                             void *stream);
+
+/* Renders n_pairs consecutive event frames at once: pair k is (times[k],
+ * times[k+1]) (host array of n_pairs + 1 finite times) and is computed as
+ * evrt_render_event_frame(times[k], times[k+1]) with opts->key_base + k
+ * would compute it, bit for bit.  The frame shared by pairs k - 1 and k is
+ * sampled once, up to the larger count the two pairs need (its samples are
+ * the same random-number stream in both), and all pairs advance through the
+ * schedule together.  The geometry must not move across the batch (every
+ * instance has the same transform at every time; the camera may move),
+ * else EVRT_E_UNSUPPORTED; lock-step sampling only (ref_mode LOCKSTEP);
+ * at most 2047 pairs and 2^21 pixels.  Outputs as for one frame, pair-major:
+ * entry k * width * height + pixel (x2 arrays: two per entry). */
+int evrt_render_event_batch(evrt_ctx *ctx, uint32_t n_pairs, const double *times, float C, float alpha,
+                            uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
+                            const evrt_render_opts *opts, const evrt_frame_out *out, void *stream);
 
 /* Counters of the last render call on ctx. */
 typedef struct {

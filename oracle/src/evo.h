@@ -71,6 +71,7 @@ typedef struct {
     double log_eps;
     float C, alpha;
     uint8_t nee, jitter, mode, df_mode, ref_mode;
+    uint32_t key_base;        /* frame index of instant 0 in the keys */
 } evo_params;
 
 typedef struct {

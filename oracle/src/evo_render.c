@@ -34,10 +34,14 @@
 #define INV_PI_F 0.318309886183790671538f
 #define TWO_PI_D 6.283185307179586476925
 
+/* Four random words of (pixel, sample, frame q = key_base + instant, vertex,
+ * block): Philox counter (pixel, sample, (q mod 256) << 24 | vertex << 8 |
+ * block, q >> 8). */
 static void rng4(const evo_params *p, uint32_t pixel, uint32_t sample, int instant,
                  uint32_t vertex, uint32_t block, uint32_t out[4])
 {
-    uint32_t ctr[4] = {pixel, sample, ((uint32_t)instant << 24) | (vertex << 8) | block, 0u};
+    const uint32_t q = p->key_base + (uint32_t)instant;
+    uint32_t ctr[4] = {pixel, sample, ((q & 0xffu) << 24) | (vertex << 8) | block, q >> 8};
     uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
     evo_philox4x32_10(ctr, key, out);
 }

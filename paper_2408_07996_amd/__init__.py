@@ -43,7 +43,7 @@ class RenderOpts(ctypes.Structure):
         ("log_eps", ctypes.c_double), ("nee", ctypes.c_uint8), ("jitter", ctypes.c_uint8),
         ("mode", ctypes.c_uint8), ("df_mode", ctypes.c_uint8), ("ref_mode", ctypes.c_uint8),
         ("profile", ctypes.c_uint8), ("count_work", ctypes.c_uint8), ("lds_nodes", ctypes.c_uint8),
-        ("ray_batch", _u32), ("reserved1", _u32),
+        ("ray_batch", _u32), ("key_base", _u32), ("trace_blocks_per_cu", _u32), ("reserved", _u32),
     ]
 
 
@@ -99,6 +99,9 @@ SIGNATURES = [
     ("evrt_render_event_frame", ctypes.c_int,
      [_c_p, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float, _u32, _u32, _u32,
       ctypes.POINTER(RenderOpts), ctypes.POINTER(FrameOut), _c_p]),
+    ("evrt_render_event_batch", ctypes.c_int,
+     [_c_p, _u32, _c_p, ctypes.c_float, ctypes.c_float, _u32, _u32, _u32, ctypes.POINTER(RenderOpts),
+      ctypes.POINTER(FrameOut), _c_p]),
     ("evrt_get_frame_stats", ctypes.c_int, [_c_p, ctypes.POINTER(FrameStats)]),
     ("evrt_trace_rays", ctypes.c_int, [_c_p, ctypes.c_double, _u32, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, _c_p]),
     ("evrt_render_paths", ctypes.c_int,
@@ -312,6 +315,37 @@ class Renderer:
         self._check(load_library().evrt_render_event_frame(
             self._h, float(t0), float(t1), float(C), float(alpha), int(spp_init), int(spp_batch),
             int(spp_max), ctypes.byref(o), ctypes.byref(fo), _stream_ptr(stream)))
+        return out
+
+    def render_event_batch(self, times, C: float, alpha: float, spp_init: int, spp_batch: int, spp_max: int,
+                           opts=None, stream=None, extras: bool = True) -> Dict:
+        """Renders the consecutive pairs (times[k], times[k+1]) at once;
+        returns device tensors with a leading pair axis (see evrt.h)."""
+        import torch
+        o = self._opts(opts)
+        if self.scene is None:
+            raise EvrtError(EVRT_E_STATE, "no scene")
+        t = np.ascontiguousarray(times, np.float64).reshape(-1)
+        n_pairs = len(t) - 1
+        if n_pairs < 1:
+            raise EvrtError(EVRT_E_INVALID, "need at least two times")
+        npx = self.scene.width * self.scene.height
+        dev = torch.device("cuda", self.device)
+        out = dict(
+            polarity=torch.empty(n_pairs, npx, dtype=torch.int8, device=dev),
+            n_paths=torch.empty(n_pairs, npx, dtype=torch.int32, device=dev),
+            mean=torch.empty(n_pairs, npx, 2, dtype=torch.float64, device=dev),
+            var=torch.empty(n_pairs, npx, 2, dtype=torch.float64, device=dev),
+        )
+        if extras:
+            out["t_last"] = torch.empty(n_pairs, npx, dtype=torch.float64, device=dev)
+            out["mean_radiance"] = torch.empty(n_pairs, npx, 2, dtype=torch.float64, device=dev)
+            out["flags"] = torch.empty(n_pairs, npx, dtype=torch.uint8, device=dev)
+        fo = FrameOut(_dptr(out["polarity"]), _dptr(out["n_paths"]), _dptr(out["mean"]), _dptr(out["var"]),
+                      _dptr(out.get("t_last")), _dptr(out.get("mean_radiance")), _dptr(out.get("flags")))
+        self._check(load_library().evrt_render_event_batch(
+            self._h, n_pairs, _np_ptr(t), float(C), float(alpha), int(spp_init), int(spp_batch), int(spp_max),
+            ctypes.byref(o), ctypes.byref(fo), _stream_ptr(stream)))
         return out
 
     def frame_stats(self) -> Dict:

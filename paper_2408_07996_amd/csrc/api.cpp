@@ -60,6 +60,8 @@ void validate_opts(const evrt_render_opts &o)
     if (o.df_mode > EVRT_DF_WELCH) fail(EVRT_E_INVALID, "unknown df_mode");
     if (o.ref_mode > EVRT_REF_FULL) fail(EVRT_E_INVALID, "unknown ref_mode");
     if (o.lds_nodes > (uint32_t)lds_treelet_nodes()) fail(EVRT_E_INVALID, "lds_nodes above the treelet capacity");
+    if (o.key_base > (1u << 24)) fail(EVRT_E_INVALID, "key_base above 2^24");
+    if (o.reserved != 0) fail(EVRT_E_INVALID, "reserved option field must be 0");
 }
 
 }  // namespace evrt
@@ -353,6 +355,24 @@ void evrt_default_opts(evrt_render_opts *o)
     o->ref_mode = EVRT_REF_LOCKSTEP;
 }
 
+static void validate_frame_args(const evrt_render_opts &o, float C, float alpha, uint32_t spp_init,
+                                uint32_t spp_batch, uint32_t spp_max, const evrt_frame_out *out)
+{
+    if (!out || !out->polarity || !out->n_paths || !out->mean || !out->var)
+        fail(EVRT_E_INVALID, "polarity, n_paths, mean and var outputs are required");
+    if (!std::isfinite(C) || C < 0.0f) fail(EVRT_E_INVALID, "C must be finite and >= 0");
+    if (!(alpha > 0.0f && alpha < 1.0f)) fail(EVRT_E_INVALID, "alpha must be in (0, 1)");
+    const uint32_t mb = o.minibatch;
+    if (spp_init % mb || spp_batch % mb || spp_max % mb)
+        fail(EVRT_E_INVALID, "spp_init, spp_batch and spp_max must be multiples of minibatch");
+    if (spp_init < 2 * mb) fail(EVRT_E_INVALID, "spp_init must hold at least two mini-batches");
+    if (spp_init > spp_max) fail(EVRT_E_INVALID, "spp_init must not exceed spp_max");
+    if (spp_batch == 0 && spp_init < spp_max && o.mode != EVRT_MODE_FIXED)
+        fail(EVRT_E_INVALID, "spp_batch must be positive");
+    if (spp_max > (1u << 24)) fail(EVRT_E_UNSUPPORTED, "spp_max above 2^24");
+    if (o.df_mode == EVRT_DF_WELCH) fail(EVRT_E_UNSUPPORTED, "Welch degrees of freedom are not implemented");
+}
+
 int evrt_render_event_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
                             uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts *opts,
                             const evrt_frame_out *out, void *stream)
@@ -364,22 +384,40 @@ int evrt_render_event_frame(evrt_ctx *c, double t0, double t1, float C, float al
         else evrt_default_opts(&o);
         validate_opts(o);
         if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
-        if (!out || !out->polarity || !out->n_paths || !out->mean || !out->var)
-            fail(EVRT_E_INVALID, "polarity, n_paths, mean and var outputs are required");
         if (!std::isfinite(t0) || !std::isfinite(t1)) fail(EVRT_E_INVALID, "t0 and t1 must be finite");
-        if (!std::isfinite(C) || C < 0.0f) fail(EVRT_E_INVALID, "C must be finite and >= 0");
-        if (!(alpha > 0.0f && alpha < 1.0f)) fail(EVRT_E_INVALID, "alpha must be in (0, 1)");
-        const uint32_t mb = o.minibatch;
-        if (spp_init % mb || spp_batch % mb || spp_max % mb)
-            fail(EVRT_E_INVALID, "spp_init, spp_batch and spp_max must be multiples of minibatch");
-        if (spp_init < 2 * mb) fail(EVRT_E_INVALID, "spp_init must hold at least two mini-batches");
-        if (spp_init > spp_max) fail(EVRT_E_INVALID, "spp_init must not exceed spp_max");
-        if (spp_batch == 0 && spp_init < spp_max && o.mode != EVRT_MODE_FIXED)
-            fail(EVRT_E_INVALID, "spp_batch must be positive");
-        if (spp_max > (1u << 24)) fail(EVRT_E_UNSUPPORTED, "spp_max above 2^24");
-        if (o.df_mode == EVRT_DF_WELCH) fail(EVRT_E_UNSUPPORTED, "Welch degrees of freedom are not implemented");
+        validate_frame_args(o, C, alpha, spp_init, spp_batch, spp_max, out);
         need_device(c);
         render_frame(c, t0, t1, C, alpha, spp_init, spp_batch, spp_max, o, *out,
+                     static_cast<hipStream_t>(stream));
+    });
+}
+
+int evrt_render_event_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, float alpha,
+                            uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts *opts,
+                            const evrt_frame_out *out, void *stream)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        evrt_render_opts o;
+        if (opts) o = *opts;
+        else evrt_default_opts(&o);
+        validate_opts(o);
+        if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
+        if (n_pairs == 0) fail(EVRT_E_INVALID, "n_pairs must be positive");
+        if (!times) fail(EVRT_E_INVALID, "NULL times");
+        for (uint32_t k = 0; k <= n_pairs; ++k)
+            if (!std::isfinite(times[k])) fail(EVRT_E_INVALID, "times must be finite");
+        validate_frame_args(o, C, alpha, spp_init, spp_batch, spp_max, out);
+        if (o.ref_mode != EVRT_REF_LOCKSTEP) fail(EVRT_E_UNSUPPORTED, "frame batches sample in lock step only");
+        if (n_pairs + 1 > kMaxBatchFrames) fail(EVRT_E_UNSUPPORTED, "more than 2047 pairs in one batch");
+        if ((uint64_t)o.key_base + n_pairs > (1u << 24)) fail(EVRT_E_INVALID, "key_base + n_pairs above 2^24");
+        const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;
+        if (npx > kPixMask + 1ull) fail(EVRT_E_UNSUPPORTED, "more than 2^21 pixels per frame in a batch");
+        if ((n_pairs + 1ull) * npx >= (1ull << 31)) fail(EVRT_E_UNSUPPORTED, "more than 2^31 (frame, pixel) items");
+        if (!instances_static(c->scene, times, n_pairs + 1))
+            fail(EVRT_E_UNSUPPORTED, "frame batches need geometry that does not move across the batch");
+        need_device(c);
+        render_batch(c, n_pairs, times, C, alpha, spp_init, spp_batch, spp_max, o, *out,
                      static_cast<hipStream_t>(stream));
     });
 }

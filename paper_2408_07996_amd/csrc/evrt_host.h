@@ -87,6 +87,10 @@ struct DevInstantBufs {
 
 // World geometry at time t (primitive order, FP64 transform, FP32 round).
 void build_world(const SceneDesc &sd, double t, HostInstant &out);
+// Camera basis at time t (FP64 interpolation, FP32 round).
+void camera_at(const SceneDesc &sd, double t, DevCamera &out);
+// True when every instance has the same transform at all n times.
+bool instances_static(const SceneDesc &sd, const double *times, uint32_t n);
 // BVH2 over out.tri (binned SAH), LDS treelet of up to n_lds_max nodes first.
 void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad);
 // Validates structural invariants of a built BVH; returns an empty string
@@ -108,6 +112,11 @@ struct FrameBuffers {
     DevBuf rad;
     DevBuf hook_tm;
     DevBuf diff_px, diff_L, diff_W;  // event-loss gradient: pixel list, path radiance, weights
+    // Frame batches: per-(frame, pixel) state and item index, item list,
+    // active pairs (two lists) with their items, checkpoint snapshots,
+    // per-frame cameras.
+    DevBuf b_wf_n, b_wf_mean, b_wf_m2, b_wf_ysum, b_item_idx, b_items, b_act0, b_act1, b_pair_items, b_snap,
+        b_cams;
     uint32_t queue_cap = 0, shadow_slots = 0;
 };
 
@@ -152,6 +161,9 @@ void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint
                 float *t_out, uint32_t *p_out, hipStream_t s);
 void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
                   float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
+                  hipStream_t s);
+void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, float alpha, uint32_t spp_init,
+                  uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o, const evrt_frame_out &out,
                   hipStream_t s);
 void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint32_t spp,
                      const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s);

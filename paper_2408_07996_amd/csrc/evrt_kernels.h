@@ -12,6 +12,7 @@ constexpr int kCntMaxDepth = 64;                           // max_depth limit
 constexpr int kCntRay0 = 0;                                // [0, 130): rays to trace per bounce
 constexpr int kCntShadow0 = kCntRay0 + 2 * (kCntMaxDepth + 1);  // [130, 260): shadow entries
 constexpr int kCntActive = kCntShadow0 + 2 * (kCntMaxDepth + 1); // [260, 262): compaction counts
+constexpr int kCntItems = kCntActive + 2;                  // 262: items of a frame-batch round
 constexpr int kCntSize = 320;
 
 // Decision constants of one round.  A round covers one or more checkpoints
@@ -79,6 +80,24 @@ void launch_diff_stats(hipStream_t s, uint32_t npx, uint32_t spp, uint32_t mb, d
 void launch_adjoint(hipStream_t s, uint32_t blocks, const DevScene &sc, const RenderParams &rp, uint32_t npx,
                     uint32_t spp, const float *Lfwd, const double *W, uint32_t n_mat, double *g,
                     uint32_t *mismatch);
+
+// Frame batches (see k_batch_* in the kernels).
+void launch_batch_init(hipStream_t s, uint32_t n_frames, uint32_t npx, uint32_t *wf_n, double *wf_mean,
+                       double *wf_m2, double *wf_ysum, uint32_t *item_idx, uint32_t *items, uint32_t *act,
+                       uint2 *pair_items, uint32_t *cnt);
+void launch_batch_items(hipStream_t s, const uint32_t *act, uint32_t nA, uint32_t npx, uint32_t *item_idx,
+                        uint32_t *items, uint32_t *cnt);
+void launch_batch_pair_items(hipStream_t s, const uint32_t *act, uint32_t nA, uint32_t npx,
+                             const uint32_t *item_idx, uint2 *pair_items);
+void launch_batch_clear(hipStream_t s, const uint32_t *items, uint32_t n_items, uint32_t npx, uint32_t *item_idx,
+                        uint32_t *cnt);
+void launch_batch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, const Decide &dc,
+                             uint32_t npx, uint32_t item_base, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                             double *wf_ysum, double *snap);
+void launch_batch_decide(hipStream_t s, const Decide &dc, const uint32_t *act, uint32_t nA, uint32_t npx,
+                         const uint2 *pair_items, const uint32_t *items, const uint32_t *wf_n,
+                         const double *wf_mean, const double *wf_m2, const double *wf_ysum, const double *snap,
+                         uint32_t *act_out, uint32_t *cnt, const Outputs &out);
 
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu);
 int traverse_block_threads();

@@ -64,6 +64,7 @@ struct RenderParams {
     uint32_t nee, jitter;
     uint32_t minibatch;
     uint32_t n_slots;        // shadow rays per shade vertex: 1 + point lights
+    uint32_t key_base;       // frame index of instant slot 0 in the keys
     double log_eps;
 };
 
@@ -79,7 +80,15 @@ struct Piece {
     FastDiv div_bp, div_nA;
     float *rad;
     uint32_t rs_a, rs_i;
+    // Frame batches: act entries are (frame << kPixBits) | pixel, the camera
+    // of frame f is cams[f], geometry is slot 0 and the random-number frame
+    // is key_base + f.  Null for single pairs.
+    const DevCamera *cams;
 };
+
+constexpr uint32_t kPixBits = 21;                      // pixels per frame < 2^21
+constexpr uint32_t kPixMask = (1u << kPixBits) - 1u;
+constexpr uint32_t kMaxBatchFrames = 1u << (32 - kPixBits);
 
 // Ray queue (SoA of float4): o = (origin xyz, throughput beta),
 // d = (direction xyz, path word = p | instant << 31), skip = origin primitive.

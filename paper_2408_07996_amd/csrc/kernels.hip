@@ -49,11 +49,12 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
-// Random block for (pixel, sample, instant, vertex, block).
+// Random block of (pixel, sample, frame q, vertex, block): Philox counter
+// (pixel, sample, (q mod 256) << 24 | vertex << 8 | block, q >> 8).
 __device__ __forceinline__ uint4 rng_block(const RenderParams &rp, uint32_t pixel, uint32_t sample,
-                                           uint32_t inst, uint32_t vertex, uint32_t block)
+                                           uint32_t q, uint32_t vertex, uint32_t block)
 {
-    return philox10(make_uint4(pixel, sample, (inst << 24) | (vertex << 8) | block, 0u), rp.key0,
+    return philox10(make_uint4(pixel, sample, ((q & 0xffu) << 24) | (vertex << 8) | block, q >> 8), rp.key0,
                     rp.key1);
 }
 
@@ -521,15 +522,17 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
     const uint32_t s = p - qq * pc.bp;
     const uint32_t ii = fdiv(pc.div_nA, qq);
     const uint32_t a = qq - ii * pc.nA;
-    const uint32_t pixel = pc.act[a];
-    const uint32_t inst = pc.inst_base + ii;
+    const uint32_t e = pc.act[a];
+    const uint32_t inst = pc.cams ? 0u : pc.inst_base + ii;
+    const uint32_t pixel = pc.cams ? (e & kPixMask) : e;
+    const uint32_t frame = rp.key_base + (pc.cams ? (e >> kPixBits) : inst);
     const uint32_t sample = pc.s0 + s;
-    const DevCamera &cam = inst ? sc.inst[1].cam : sc.inst[0].cam;
+    const DevCamera &cam = pc.cams ? pc.cams[e >> kPixBits] : (inst ? sc.inst[1].cam : sc.inst[0].cam);
     const uint32_t py = fdiv(sc.div_w, pixel);
     const uint32_t px = pixel - py * sc.width;
     float j0 = 0.5f, j1 = 0.5f;
     if (rp.jitter) {
-        const uint4 rb = rng_block(rp, pixel, sample, inst, 0, 0);
+        const uint4 rb = rng_block(rp, pixel, sample, frame, 0, 0);
         j0 = u01(rb.x);
         j1 = u01(rb.y);
     }
@@ -729,7 +732,9 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
             const uint32_t s = p - qq * pc.bp;
             const uint32_t ii = fdiv(pc.div_nA, qq);
             const uint32_t a = qq - ii * pc.nA;
-            const uint32_t pixel = pc.act[a];
+            const uint32_t e = pc.act[a];
+            const uint32_t pixel = pc.cams ? (e & kPixMask) : e;
+            const uint32_t q = rp.key_base + (pc.cams ? (e >> kPixBits) : inst);
             const uint32_t sample = pc.s0 + s;
             ri = a * pc.rs_a + ii * pc.rs_i + s;
             beta = o.w;
@@ -746,7 +751,7 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
             nsz = cosi < 0.0f ? pr.z : -pr.z;
             if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee)) pc.rad[ri] = pc.rad[ri] + beta * Le;
             if (alb > 0.0f) {
-                const uint4 r0 = rng_block(rp, pixel, sample, inst, depth, 0);
+                const uint4 r0 = rng_block(rp, pixel, sample, q, depth, 0);
                 fr = alb * kInvPi;
                 beta_v = beta;
                 if (rp.nee) {
@@ -794,7 +799,7 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                     else beta = beta / qs;
                 }
                 if (cont) {
-                    const uint4 r1 = rng_block(rp, pixel, sample, inst, depth, 1);
+                    const uint4 r1 = rng_block(rp, pixel, sample, q, depth, 1);
                     const float e0 = u01(r1.x), e1 = u01(r1.y);
                     const float rr = sqrtf(e0);
                     const double ph = kTwoPi * (double)e1;
@@ -1014,6 +1019,166 @@ __global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParam
     if (!done) act_out[slot] = pixel;
 }
 
+// ------------------------------------------------------------------------
+// Frame batches: pairs (f, f + 1) of consecutive frames share the samples of
+// their common frame.  Items are (frame, pixel) sample streams, traced
+// whenever a pair that contains them is still undecided; decisions are per
+// (pair, pixel).  State arrays are frame-major: index f * npx + pixel.
+
+constexpr uint32_t kItemUnset = 0xffffffffu;
+constexpr uint32_t kItemClaimed = 0xfffffffeu;
+
+// Every frame's state cleared, every (frame, pixel) an item (round 0), every
+// (pair, pixel) active with its two items.
+__global__ void k_batch_init(uint32_t n_frames, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                             double *wf_ysum, uint32_t *item_idx, uint32_t *items, uint32_t *act, uint2 *pair_items,
+                             uint32_t *cnt)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = n_frames * npx;
+    if (i < n) {
+        const uint32_t f = i / npx, px = i - f * npx;
+        wf_n[i] = 0;
+        wf_mean[i] = 0.0;
+        wf_m2[i] = 0.0;
+        wf_ysum[i] = 0.0;
+        item_idx[i] = i;
+        items[i] = (f << kPixBits) | px;
+        if (f + 1 < n_frames) {
+            act[i] = (f << kPixBits) | px;
+            pair_items[i] = make_uint2(i, i + npx);
+        }
+    }
+    if (i == 0) {
+        cnt[kCntActive] = 0;
+        cnt[kCntActive + 1] = 0;
+        cnt[kCntItems] = 0;
+    }
+}
+
+// Items of the round: both frames of every active pair, each once (the
+// first pair to claim a (frame, pixel) appends it).  One thread per active
+// pair; appends aggregated per block.
+__global__ __launch_bounds__(256) void k_batch_items(const uint32_t *act, uint32_t nA, uint32_t npx,
+                                                     uint32_t *item_idx, uint32_t *items, uint32_t *cnt)
+{
+    __shared__ BlockAppend s_app;
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    bool c0 = false, c1 = false;
+    uint32_t e = 0, px = 0, f = 0;
+    if (a < nA) {
+        e = act[a];
+        f = e >> kPixBits;
+        px = e & kPixMask;
+        c0 = atomicCAS(&item_idx[f * npx + px], kItemUnset, kItemClaimed) == kItemUnset;
+        c1 = atomicCAS(&item_idx[(f + 1) * npx + px], kItemUnset, kItemClaimed) == kItemUnset;
+    }
+    uint32_t s0, s1;
+    block_append2(s_app, 0, c0, c1, cnt + kCntItems, cnt + kCntItems, s0, s1);
+    if (c0) {
+        items[s0] = (f << kPixBits) | px;
+        item_idx[f * npx + px] = s0;
+    }
+    if (c1) {
+        items[s1] = ((f + 1) << kPixBits) | px;
+        item_idx[(f + 1) * npx + px] = s1;
+    }
+}
+
+// Item indices of both frames of every active pair.
+__global__ void k_batch_pair_items(const uint32_t *act, uint32_t nA, uint32_t npx, const uint32_t *item_idx,
+                                   uint2 *pair_items)
+{
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nA) return;
+    const uint32_t e = act[a];
+    const uint32_t f = e >> kPixBits, px = e & kPixMask;
+    pair_items[a] = make_uint2(item_idx[f * npx + px], item_idx[(f + 1) * npx + px]);
+}
+
+// Releases the round's items for the next round.
+__global__ void k_batch_clear(const uint32_t *items, uint32_t n_items, uint32_t npx, uint32_t *item_idx,
+                              uint32_t *cnt)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) cnt[kCntItems] = 0;
+    if (i >= n_items) return;
+    const uint32_t e = items[i];
+    item_idx[(e >> kPixBits) * npx + (e & kPixMask)] = kItemUnset;
+}
+
+// Welford updates of the piece's items over the round's samples, with the
+// state at every checkpoint of the round kept in snap (item-major, three
+// doubles per checkpoint) when the round has more than one.
+__global__ void k_batch_accumulate(Piece pc, RenderParams rp, Decide dc, uint32_t npx, uint32_t item_base,
+                                   uint32_t *wf_n, double *wf_mean, double *wf_m2, double *wf_ysum, double *snap)
+{
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= pc.nA) return;
+    const uint32_t e = pc.act[a];
+    const uint32_t slot = (e >> kPixBits) * npx + (e & kPixMask);
+    Welford w = welford_load(slot, wf_n, wf_mean, wf_m2, wf_ysum);
+    const float *src = pc.rad + a * pc.rs_a;
+    if (dc.n_checks == 1) {
+        welford_run(w, src, pc.bp, rp.minibatch, rp.log_eps);
+    } else {
+        uint32_t k = pc.s0;
+        double *sn = snap + (size_t)(item_base + a) * dc.n_checks * 3;
+        for (uint32_t j = 0; j < dc.n_checks; ++j) {
+            const uint32_t end = dc.ck_end[j];
+            welford_run(w, src + (k - pc.s0), end - k, rp.minibatch, rp.log_eps);
+            k = end;
+            sn[3 * j] = w.mean;
+            sn[3 * j + 1] = w.m2;
+            sn[3 * j + 2] = w.ys;
+        }
+    }
+    welford_store(w, slot, wf_n, wf_mean, wf_m2, wf_ysum);
+}
+
+// Decisions of the active pairs at every checkpoint of the round, from the
+// states (one checkpoint) or snapshots of their two frames; outputs at index
+// pair * npx + pixel; undecided pairs compacted into act_out.
+__global__ __launch_bounds__(256) void k_batch_decide(Decide dc, const uint32_t *act, uint32_t nA, uint32_t npx,
+                                                      const uint2 *pair_items, const uint32_t *items,
+                                                      const uint32_t *wf_n, const double *wf_mean,
+                                                      const double *wf_m2, const double *wf_ysum,
+                                                      const double *snap, uint32_t *act_out, uint32_t *cnt,
+                                                      Outputs out)
+{
+    __shared__ BlockAppend s_app;
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a == 0) cnt[kCntActive + (dc.cnt_slot ^ 1u)] = 0;
+    bool keep = false;
+    uint32_t e = 0;
+    if (a < nA) {
+        e = act[a];
+        const uint32_t f = e >> kPixBits, px = e & kPixMask;
+        const uint32_t oi = f * npx + px;
+        const uint2 it = pair_items[a];
+        bool done = false;
+        if (dc.n_checks == 1) {
+            const Welford w0 = welford_load(f * npx + px, wf_n, wf_mean, wf_m2, wf_ysum);
+            const Welford w1 = welford_load((f + 1) * npx + px, wf_n, wf_mean, wf_m2, wf_ysum);
+            done = decide_pixel(dc, 0, dc.final_round != 0, oi, w0, w1, out);
+        } else {
+            const double *s0 = snap + (size_t)it.x * dc.n_checks * 3;
+            const double *s1 = snap + (size_t)it.y * dc.n_checks * 3;
+            for (uint32_t j = 0; j < dc.n_checks && !done; ++j) {
+                const uint32_t m = dc.ck_end[j] / dc.minibatch;
+                const Welford w0{m, s0[3 * j], s0[3 * j + 1], s0[3 * j + 2]};
+                const Welford w1{m, s1[3 * j], s1[3 * j + 1], s1[3 * j + 2]};
+                done = decide_pixel(dc, j, dc.final_round != 0 && j + 1 == dc.n_checks, oi, w0, w1, out);
+            }
+        }
+        keep = !done;
+    }
+    uint32_t slot, unused;
+    block_append2(s_app, 0, keep, false, cnt + kCntActive + dc.cnt_slot, cnt + kCntActive + dc.cnt_slot, slot,
+                  unused);
+    if (keep) act_out[slot] = e;
+}
+
 // Caller rays -> queue format for the trace hook.
 __global__ void k_hook_rays(uint32_t n, const float *rays, const uint32_t *skip, RayQueue q,
                             float *tminmax, uint32_t *cnt)
@@ -1167,7 +1332,7 @@ __device__ float replay_path(const DevScene &sc, const RenderParams &rp, const l
     const uint32_t px = pixel - py * sc.width;
     float j0 = 0.5f, j1 = 0.5f;
     if (rp.jitter) {
-        const uint4 rb = rng_block(rp, pixel, sample, inst, 0, 0);
+        const uint4 rb = rng_block(rp, pixel, sample, rp.key_base + inst, 0, 0);
         j0 = u01(rb.x);
         j1 = u01(rb.y);
     }
@@ -1209,7 +1374,7 @@ __device__ float replay_path(const DevScene &sc, const RenderParams &rp, const l
         }
         if (!(alb > 0.0f)) break;
         const float Lb = L;
-        const uint4 r0 = rng_block(rp, pixel, sample, inst, depth, 0);
+        const uint4 r0 = rng_block(rp, pixel, sample, rp.key_base + inst, depth, 0);
         const float fr = alb * kInvPi;
         if (rp.nee) {
             float sum = 0.0f;
@@ -1267,7 +1432,7 @@ __device__ float replay_path(const DevScene &sc, const RenderParams &rp, const l
             if (u01(r0.w) >= qs) break;
             beta = beta / qs;
         }
-        const uint4 r1 = rng_block(rp, pixel, sample, inst, depth, 1);
+        const uint4 r1 = rng_block(rp, pixel, sample, rp.key_base + inst, depth, 1);
         const float e0 = u01(r1.x), e1 = u01(r1.y);
         const float rr = sqrtf(e0);
         const double ph = kTwoPi * (double)e1;
@@ -1403,6 +1568,53 @@ void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_
 {
     hipLaunchKernelGGL(k_decide_compact, dim3((nA + 255) / 256), dim3(256), 0, s, dc, act_in, nA,
                        act_out, cnt, wf_n, wf_mean, wf_m2, wf_ysum, out);
+}
+
+void launch_batch_init(hipStream_t s, uint32_t n_frames, uint32_t npx, uint32_t *wf_n, double *wf_mean,
+                       double *wf_m2, double *wf_ysum, uint32_t *item_idx, uint32_t *items, uint32_t *act,
+                       uint2 *pair_items, uint32_t *cnt)
+{
+    const uint32_t n = n_frames * npx;
+    hipLaunchKernelGGL(k_batch_init, dim3(std::max(1u, (n + 255) / 256)), dim3(256), 0, s, n_frames, npx, wf_n,
+                       wf_mean, wf_m2, wf_ysum, item_idx, items, act, pair_items, cnt);
+}
+
+void launch_batch_items(hipStream_t s, const uint32_t *act, uint32_t nA, uint32_t npx, uint32_t *item_idx,
+                        uint32_t *items, uint32_t *cnt)
+{
+    hipLaunchKernelGGL(k_batch_items, dim3(std::max(1u, (nA + 255) / 256)), dim3(256), 0, s, act, nA, npx,
+                       item_idx, items, cnt);
+}
+
+void launch_batch_pair_items(hipStream_t s, const uint32_t *act, uint32_t nA, uint32_t npx,
+                             const uint32_t *item_idx, uint2 *pair_items)
+{
+    hipLaunchKernelGGL(k_batch_pair_items, dim3(std::max(1u, (nA + 255) / 256)), dim3(256), 0, s, act, nA, npx,
+                       item_idx, pair_items);
+}
+
+void launch_batch_clear(hipStream_t s, const uint32_t *items, uint32_t n_items, uint32_t npx, uint32_t *item_idx,
+                        uint32_t *cnt)
+{
+    hipLaunchKernelGGL(k_batch_clear, dim3(std::max(1u, (n_items + 255) / 256)), dim3(256), 0, s, items, n_items,
+                       npx, item_idx, cnt);
+}
+
+void launch_batch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, const Decide &dc,
+                             uint32_t npx, uint32_t item_base, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                             double *wf_ysum, double *snap)
+{
+    hipLaunchKernelGGL(k_batch_accumulate, dim3((pc.nA + 255) / 256), dim3(256), 0, s, pc, rp, dc, npx, item_base,
+                       wf_n, wf_mean, wf_m2, wf_ysum, snap);
+}
+
+void launch_batch_decide(hipStream_t s, const Decide &dc, const uint32_t *act, uint32_t nA, uint32_t npx,
+                         const uint2 *pair_items, const uint32_t *items, const uint32_t *wf_n,
+                         const double *wf_mean, const double *wf_m2, const double *wf_ysum, const double *snap,
+                         uint32_t *act_out, uint32_t *cnt, const Outputs &out)
+{
+    hipLaunchKernelGGL(k_batch_decide, dim3(std::max(1u, (nA + 255) / 256)), dim3(256), 0, s, dc, act, nA, npx,
+                       pair_items, items, wf_n, wf_mean, wf_m2, wf_ysum, snap, act_out, cnt, out);
 }
 
 void launch_diff_zero(hipStream_t s, double *loss, double *g, uint32_t n_g, uint32_t *mismatch)

@@ -100,6 +100,7 @@ static RenderParams make_params(const evrt_ctx *c, const evrt_render_opts &o)
     rp.jitter = o.jitter;
     rp.minibatch = o.minibatch;
     rp.n_slots = 1 + (uint32_t)c->scene.pl_int.size();
+    rp.key_base = o.key_base;
     rp.log_eps = o.log_eps;
     return rp;
 }
@@ -197,7 +198,9 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
                    fb.queue_cap};
     launch_raygen(s, pc, sc, rp, q[0], cnt);
     const uint32_t tb = (uint32_t)traverse_block_threads();
-    const uint32_t tblocks = blocks_for(c->trace_blocks_per_cu, c->cu_count, pc.n_paths, tb);
+    const uint32_t tper = o.trace_blocks_per_cu ? std::min(o.trace_blocks_per_cu, c->trace_blocks_per_cu)
+                                                : c->trace_blocks_per_cu;
+    const uint32_t tblocks = blocks_for(tper, c->cu_count, pc.n_paths, tb);
     const uint32_t sblocks = blocks_for(c->shade_blocks_per_cu, c->cu_count, pc.n_paths, 256);
     const bool count = o.count_work != 0;
     for (uint32_t d = 1; d <= rp.max_depth; ++d) {
@@ -393,6 +396,158 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
                                  hipMemcpyDeviceToHost, s),
                   "active count readback");
         hip_check(hipStreamSynchronize(s), "round");
+        const uint32_t next = c->h_pinned[0];
+        if (r < 64) c->stats.active_after_round[r] = next;
+        c->stats.rounds = r + 1;
+        std::swap(act_in, act_out);
+        nA = next;
+        if (nA == 0 || dc.final_round) break;
+        n_prev = hi;
+        n_next = std::min(hi + spp_batch, spp_max);
+    }
+    read_stats(c, s);
+    prof.collect(c->stats);
+    c->stats.ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+}
+
+// A batch of consecutive pairs (times[k], times[k+1]), k < n_pairs, of a
+// scene whose geometry is the same at every time (the camera may move).
+// Frame f is keyed as key_base + f, so pair k equals render_frame of
+// (times[k], times[k+1]) with key_base + k bit for bit; the frames a pair
+// shares with its neighbours are traced once.  Each round: the items
+// (frame, pixel) of the active pairs, pieces of items over the round's
+// samples (the checkpoints that fit one batch of paths), Welford updates
+// per item, decisions per (pair, pixel).
+void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, float alpha, uint32_t spp_init,
+                  uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o, const evrt_frame_out &out,
+                  hipStream_t s)
+{
+    const auto wall0 = std::chrono::steady_clock::now();
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto g = get_instant(c, times[0], s, &c->stats.ms_build);
+    const DevScene sc = make_dev_scene(c, *g, *g, o.lds_nodes);
+    const RenderParams rp = make_params(c, o);
+    const uint32_t npx = sc.width * sc.height;
+    const uint32_t nf = n_pairs + 1;
+    const uint32_t mb = o.minibatch;
+    const uint64_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    FrameBuffers &fb = c->fb;
+    std::vector<DevCamera> cams(nf);
+    for (uint32_t k = 0; k < nf; ++k) camera_at(c->scene, times[k], cams[k]);
+    fb.b_cams.upload(cams.data(), sizeof(DevCamera) * nf, s);
+    const size_t nfp = (size_t)nf * npx, npp = (size_t)n_pairs * npx;
+    fb.b_wf_n.ensure(sizeof(uint32_t) * nfp);
+    fb.b_wf_mean.ensure(sizeof(double) * nfp);
+    fb.b_wf_m2.ensure(sizeof(double) * nfp);
+    fb.b_wf_ysum.ensure(sizeof(double) * nfp);
+    fb.b_item_idx.ensure(sizeof(uint32_t) * nfp);
+    fb.b_items.ensure(sizeof(uint32_t) * nfp);
+    fb.b_act0.ensure(sizeof(uint32_t) * npp);
+    fb.b_act1.ensure(sizeof(uint32_t) * npp);
+    fb.b_pair_items.ensure(sizeof(uint2) * npp);
+    ensure_buffers(c, npx, 1, rp.n_slots);
+    uint32_t *cnt = fb.cnt.as<uint32_t>();
+    uint32_t *wf_n = fb.b_wf_n.as<uint32_t>();
+    double *wf_mean = fb.b_wf_mean.as<double>(), *wf_m2 = fb.b_wf_m2.as<double>();
+    double *wf_ysum = fb.b_wf_ysum.as<double>();
+    uint32_t *item_idx = fb.b_item_idx.as<uint32_t>(), *items = fb.b_items.as<uint32_t>();
+    uint2 *pair_items = fb.b_pair_items.as<uint2>();
+    launch_init_frame(s, 0, nullptr, nullptr, nullptr, nullptr, nullptr, cnt, fb.stat.as<unsigned long long>());
+    uint32_t *act_in = fb.b_act0.as<uint32_t>();
+    uint32_t *act_out = fb.b_act1.as<uint32_t>();
+    launch_batch_init(s, nf, npx, wf_n, wf_mean, wf_m2, wf_ysum, item_idx, items, act_in, pair_items, cnt);
+    Profiler prof{c, o.profile != 0, 0, {}, s};
+    const bool fixed = o.mode == EVRT_MODE_FIXED;
+    uint32_t nA = n_pairs * npx;
+    uint32_t n_items = nf * npx;
+    uint32_t n_prev = 0;
+    uint32_t n_next = fixed ? spp_max : spp_init;
+    Outputs outs{out.polarity, out.n_paths, out.mean, out.var, out.t_last, out.mean_radiance, out.flags};
+    for (uint32_t r = 0;; ++r) {
+        if (r > 0) {
+            launch_batch_items(s, act_in, nA, npx, item_idx, items, cnt);
+            hip_check(hipMemcpyAsync(c->h_pinned, cnt + kCntItems, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                      "item count readback");
+            hip_check(hipStreamSynchronize(s), "batch items");
+            n_items = c->h_pinned[0];
+            launch_batch_pair_items(s, act_in, nA, npx, item_idx, pair_items);
+        }
+        Decide dc{};
+        dc.C = (double)C;
+        dc.mode = o.mode;
+        dc.minibatch = mb;
+        dc.cnt_slot = r & 1u;
+        uint32_t hi = n_next;
+        dc.ck_end[0] = hi;
+        dc.n_checks = 1;
+        while (hi < spp_max && dc.n_checks < kMaxChecks) {
+            const uint32_t nx = std::min(hi + spp_batch, spp_max);
+            if ((uint64_t)n_items * (nx - n_prev) > batch) break;
+            hi = nx;
+            dc.ck_end[dc.n_checks++] = hi;
+        }
+        dc.final_round = hi >= spp_max ? 1u : 0u;
+        for (uint32_t j = 0; j < dc.n_checks; ++j) {
+            if (dc.ck_end[j] >= spp_max) break;
+            const uint32_t df = 2 * (dc.ck_end[j] / mb) - 2;
+            if (o.mode == EVRT_MODE_ADAPTIVE_1T) {
+                dc.crit_lo[j] = crit_value(c, (double)alpha, df);
+            } else if (o.mode == EVRT_MODE_ADAPTIVE_2T) {
+                dc.crit_lo[j] = crit_value(c, 0.5 * (double)alpha, df);
+                dc.crit_hi[j] = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
+            }
+        }
+        double *snap = nullptr;
+        if (dc.n_checks > 1) {
+            fb.b_snap.ensure(sizeof(double) * 3 * (size_t)n_items * dc.n_checks);
+            snap = fb.b_snap.as<double>();
+        }
+        // Pieces over the items: blocks of items with the whole sample range,
+        // or every item over sub-ranges when the blocks would be too small
+        // (then the round has one checkpoint).
+        const uint64_t range = hi - n_prev;
+        uint64_t it_block = std::max<uint64_t>(1, batch / range);
+        uint64_t bp_max = range;
+        if (it_block < 64 && it_block < n_items) {
+            it_block = n_items;
+            bp_max = std::max<uint64_t>(mb, batch / n_items / mb * mb);
+        }
+        it_block = std::min<uint64_t>(it_block, n_items);
+        bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / it_block / mb * mb);
+        if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many items for one piece");
+        if (dc.n_checks > 1 && bp_max < range) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
+        for (uint32_t a0 = 0; a0 < n_items; a0 += (uint32_t)it_block) {
+            const uint32_t na = (uint32_t)std::min<uint64_t>(it_block, n_items - a0);
+            for (uint32_t s0 = n_prev; s0 < hi;) {
+                const uint32_t bp = (uint32_t)std::min<uint64_t>(bp_max, hi - s0);
+                Piece pc{};
+                pc.act = items + a0;
+                pc.nA = na;
+                pc.bp = bp;
+                pc.n_inst = 1;
+                pc.inst_base = 0;
+                pc.s0 = s0;
+                pc.n_paths = na * bp;
+                pc.region = na * bp;
+                pc.div_bp = make_fastdiv(bp);
+                pc.div_nA = make_fastdiv(na);
+                pc.rs_a = bp;
+                pc.rs_i = na * bp;
+                pc.cams = fb.b_cams.as<DevCamera>();
+                ensure_buffers(c, npx, pc.n_paths, rp.n_slots);
+                pc.rad = fb.rad.as<float>();
+                trace_piece(c, pc, sc, rp, o, s, prof);
+                launch_batch_accumulate(s, pc, rp, dc, npx, a0, wf_n, wf_mean, wf_m2, wf_ysum, snap);
+                s0 += bp;
+            }
+        }
+        launch_batch_decide(s, dc, act_in, nA, npx, pair_items, items, wf_n, wf_mean, wf_m2, wf_ysum, snap,
+                            act_out, cnt, outs);
+        launch_batch_clear(s, items, n_items, npx, item_idx, cnt);
+        hip_check(hipMemcpyAsync(c->h_pinned, cnt + kCntActive + dc.cnt_slot, sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, s),
+                  "active count readback");
+        hip_check(hipStreamSynchronize(s), "batch round");
         const uint32_t next = c->h_pinned[0];
         if (r < 64) c->stats.active_after_round[r] = next;
         c->stats.rounds = r + 1;

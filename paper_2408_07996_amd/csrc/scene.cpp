@@ -105,6 +105,24 @@ void build_world(const SceneDesc &sd, double t, HostInstant &h)
     if (!h.emit_cdf.empty()) h.emit_cdf.back() = 1.0f;
     h.emit_S = (float)S;
 
+    camera_at(sd, t, h.cam);
+}
+
+bool instances_static(const SceneDesc &sd, const double *times, uint32_t n)
+{
+    for (const auto &in : sd.instances) {
+        double M0[12], M[12];
+        keyed(in.kt, in.kx, 12, times[0], M0);
+        for (uint32_t k = 1; k < n; ++k) {
+            keyed(in.kt, in.kx, 12, times[k], M);
+            if (std::memcmp(M0, M, sizeof(M)) != 0) return false;
+        }
+    }
+    return true;
+}
+
+void camera_at(const SceneDesc &sd, double t, DevCamera &out)
+{
     // Camera basis in FP64, rounded once to FP32.
     double cam[9];
     keyed(sd.cam.kt, sd.cam.elu, 9, t, cam);
@@ -118,13 +136,13 @@ void build_world(const SceneDesc &sd, double t, HostInstant &h)
     const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
     const double th = std::tan(sd.cam.vfov * (3.14159265358979323846 / 360.0));
     for (int c = 0; c < 3; ++c) {
-        h.cam.eye[c] = (float)cam[c];
-        h.cam.fwd[c] = (float)f[c];
-        h.cam.right[c] = (float)r[c];
-        h.cam.up[c] = (float)u[c];
+        out.eye[c] = (float)cam[c];
+        out.fwd[c] = (float)f[c];
+        out.right[c] = (float)r[c];
+        out.up[c] = (float)u[c];
     }
-    h.cam.sx = (float)(th * ((double)sd.cam.width / (double)sd.cam.height));
-    h.cam.sy = (float)th;
+    out.sx = (float)(th * ((double)sd.cam.width / (double)sd.cam.height));
+    out.sy = (float)th;
 }
 
 float bvh_padding(const SceneDesc &sd, const HostInstant &a, const HostInstant &b)

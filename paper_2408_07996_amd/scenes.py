@@ -373,6 +373,80 @@ def diff_scene(seed: int = 0, width: int = 256, height: int = 256, floor_n: int 
     return b.build()
 
 
+def _pan_keys(eye, look, up, n_frames: int, deg_per_frame: float):
+    """Camera keys at t = 0, 1, ..., n_frames - 1: the view direction turns
+    about the vertical axis through the eye by deg_per_frame per frame."""
+    eye = np.asarray(eye, np.float64)
+    d0 = np.asarray(look, np.float64) - eye
+    keys = []
+    for k in range(n_frames):
+        a = math.radians(deg_per_frame * k)
+        c, s_ = math.cos(a), math.sin(a)
+        d = np.array([c * d0[0] + s_ * d0[2], d0[1], -s_ * d0[0] + c * d0[2]])
+        keys.append(list(eye) + list(eye + d) + list(up))
+    return np.arange(n_frames, dtype=np.float64), np.asarray(keys, np.float64)
+
+
+def panning(sc: Scene, n_frames: int, deg_per_frame: float) -> Scene:
+    """The scene with every instance frozen at its first key and the camera
+    turning by deg_per_frame per frame at t = 0, 1, ..., n_frames - 1."""
+    import dataclasses
+    koff = sc.inst_key_off.astype(np.int64)
+    key_t = np.zeros(len(sc.inst_mesh), np.float64)
+    key_x = np.stack([sc.key_xform[koff[i]] for i in range(len(sc.inst_mesh))]) if len(sc.inst_mesh) else \
+        np.zeros((0, 3, 4))
+    e = sc.cam_elu[0]
+    ct, ce = _pan_keys(e[0:3], e[3:6], e[6:9], n_frames, deg_per_frame)
+    return dataclasses.replace(sc, key_t=key_t, key_xform=key_x,
+                               inst_key_off=np.arange(len(sc.inst_mesh) + 1, dtype=np.uint32),
+                               cam_t=ct, cam_elu=ce)
+
+
+def batch_scene(seed: int = 0, width: int = 1280, height: int = 720, grid: int = 24, n_cubes: int = 20000,
+                subdiv: int = 3, n_frames: int = 65, deg_per_frame: float = 0.5) -> Scene:
+    """Frame-batch workload (1280x720, 977,290 triangles): a 40 x 40 ground
+    quad, a grid x grid lattice of icospheres (subdivision 3, 1,280
+    triangles, radius U[0.25, 0.45]) on a 1.2-unit pitch, n_cubes small
+    cubes (12 triangles, edge U[0.1, 0.3], random yaw) scattered over
+    [-16, 16]^2, 16 Lambertian materials of albedo U[0.1, 0.9], four 2 x 2
+    lights at y = 8 (Le = 15).  All geometry static; the camera at
+    (0, 4, 18) looking at (0, 0.5, 0) turns by deg_per_frame per frame about
+    the vertical axis, keyed at t = 0 ... n_frames - 1; 45 degrees."""
+    rng = np.random.default_rng(seed)
+    b = SceneBuilder()
+    mats = [b.material(rng.uniform(0.1, 0.9)) for _ in range(16)]
+    gv, gt = oriented_quad([(-20, 0, -20), (20, 0, -20), (20, 0, 20), (-20, 0, 20)], (0, 1, 0))
+    b.static(b.mesh(gv, gt, mats[0]))
+    sv, st = icosphere(subdiv)
+    sphere_meshes = [b.mesh(sv, st, m) for m in mats[1:9]]
+    off = (grid - 1) * 1.2 / 2.0
+    for i in range(grid):
+        for j in range(grid):
+            r = rng.uniform(0.25, 0.45)
+            c = np.array([i * 1.2 - off, r, j * 1.2 - off])
+            b.instance(sphere_meshes[int(rng.integers(0, 8))], [0.0], [compose(np.eye(3), c, r)])
+    cv, ct = box_mesh((-0.5, 0.0, -0.5), (0.5, 1.0, 0.5))
+    cube_meshes = [b.mesh(cv, ct, m) for m in mats[9:16]]
+    for _ in range(n_cubes):
+        e = rng.uniform(0.1, 0.3)
+        x, z = rng.uniform(-16.0, 16.0, size=2)
+        rot = rotation_axis_angle((0, 1, 0), rng.uniform(0.0, 2 * math.pi))
+        b.instance(cube_meshes[int(rng.integers(0, 7))], [0.0], [compose(rot, (x, 0.0, z), e)])
+    light_m = b.material(0.0, 15.0)
+    for (lx, lz) in ((-6.0, -4.0), (6.0, -4.0), (-6.0, 6.0), (6.0, 6.0)):
+        lv, lt = oriented_quad([(lx - 1, 8.0, lz - 1), (lx + 1, 8.0, lz - 1), (lx + 1, 8.0, lz + 1),
+                                (lx - 1, 8.0, lz + 1)], (0, -1, 0))
+        b.static(b.mesh(lv, lt, light_m))
+    ct_, ce = _pan_keys((0.0, 4.0, 18.0), (0.0, 0.5, 0.0), (0, 1, 0), n_frames, deg_per_frame)
+    b.set_camera(width, height, 45.0, list(ct_), [list(r) for r in ce])
+    return b.build()
+
+
+# Frame-batch workload: 64 pairs, schedule 16/16/2048, depth 8.
+BATCH_PARAMS = dict(seed=0, max_depth=8, rr_start_depth=2, minibatch=4, log_eps=1e-4, nee=1, jitter=1,
+                    spp_init=16, spp_batch=16, spp_max=2048, C=0.2, alpha=0.01)
+
+
 # Event loss of the differentiation workload: 256 paths per pixel and
 # instant, loss sum softplus((|Delta| - C) / tau).
 DIFF_PARAMS = dict(seed=0, max_depth=4, rr_start_depth=2, minibatch=4, log_eps=1e-4, nee=1, jitter=1,

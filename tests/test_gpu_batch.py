@@ -1,0 +1,116 @@
+"""Frame batches: many consecutive pairs in one call, the frame shared by
+two pairs sampled once.  Each pair must equal the single-pair renderer with
+the batch's frame keys bit for bit, and the oracle within the parity bars."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2408_07996_amd as ev
+from paper_2408_07996_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("polarity", "n_paths", "mean", "var", "t_last", "mean_radiance", "flags")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _opts(P, **kw):
+    d = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    d.update(kw)
+    return d
+
+
+@pytest.fixture(scope="module")
+def rend():
+    import torch
+    assert torch.cuda.is_available()
+    r = ev.Renderer(0)
+    yield r
+    r.close()
+
+
+def _batch_vs_pairs(rend, sc, P, times, **kw):
+    rend.set_scene(sc)
+    o = _opts(P, **kw)
+    b = rend.render_event_batch(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], o)
+    bst = rend.frame_stats()
+    paths_batch = bst["camera_rays"]
+    paths_pairs = 0
+    for k in range(len(times) - 1):
+        f = rend.render_event_frame(times[k], times[k + 1], P["C"], P["alpha"], P["spp_init"], P["spp_batch"],
+                                    P["spp_max"], dict(o, key_base=o.get("key_base", 0) + k))
+        paths_pairs += rend.frame_stats()["camera_rays"]
+        for key in KEYS:
+            np.testing.assert_array_equal(b[key][k].cpu().numpy(), f[key].cpu().numpy(), err_msg=f"pair {k} {key}")
+    return b, paths_batch, paths_pairs
+
+
+@pytest.mark.parametrize("variant", ["default", "small_pieces", "fixed", "two_tailed", "mb8", "key_base"])
+def test_batch_equals_single_pairs(rend, variant):
+    P = dict(scenes.TINY_PARAMS)
+    kw = {}
+    if variant == "small_pieces":
+        kw = dict(ray_batch=1 << 14)
+    elif variant == "fixed":
+        kw = dict(mode=ev.MODE_FIXED)
+    elif variant == "two_tailed":
+        kw = dict(mode=ev.MODE_ADAPTIVE_2T)
+    elif variant == "mb8":
+        P.update(minibatch=8, spp_init=32, spp_batch=32)
+    elif variant == "key_base":
+        kw = dict(key_base=300)
+    sc = scenes.panning(scenes.tiny_box(width=32, height=24), 5, 2.0)
+    _say(f"batch variant {variant}")
+    b, pb, pp = _batch_vs_pairs(rend, sc, P, [0.0, 1.0, 2.0, 3.0, 4.0], **kw)
+    # shared frames are traced once: fewer camera rays than the pairs
+    assert pb < pp
+
+
+def test_batch_matches_oracle(rend):
+    P = dict(scenes.TINY_PARAMS)
+    sc = scenes.panning(scenes.tiny_box(width=24, height=20), 4, 3.0)
+    rend.set_scene(sc)
+    times = [0.0, 1.0, 2.0, 3.0]
+    b = rend.render_event_batch(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], _opts(P))
+    for k in range(3):
+        with oracle.Frame(sc, times[k], times[k + 1]) as f:
+            r = f.render(oracle.make_params(**P, key_base=k))
+        ok = ~r["near_crit"]
+        assert ok.mean() > 0.9
+        np.testing.assert_array_equal(b["polarity"][k].cpu().numpy()[ok], r["polarity"][ok])
+        np.testing.assert_array_equal(b["n_paths"][k].cpu().numpy()[ok], r["n_paths"][ok])
+        m = b["mean"][k].cpu().numpy()
+        assert (np.abs(m - r["mean"]) <= 1e-4 * np.maximum(1.0, np.abs(r["mean"]))).all()
+
+
+def test_single_frame_key_base_matches_oracle(rend):
+    P = dict(scenes.TINY_PARAMS)
+    sc = scenes.tiny_box(width=24, height=20)
+    rend.set_scene(sc)
+    g = rend.render_event_frame(0.0, 1.0, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"],
+                                _opts(P, key_base=257))
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        r = f.render(oracle.make_params(**P, key_base=257))
+        r0 = f.render(oracle.make_params(**P))
+    ok = ~r["near_crit"]
+    np.testing.assert_array_equal(g["n_paths"].cpu().numpy()[ok], r["n_paths"][ok])
+    m = g["mean"].cpu().numpy()
+    assert (np.abs(m - r["mean"]) <= 1e-4 * np.maximum(1.0, np.abs(r["mean"]))).all()
+    assert not np.array_equal(r["mean"], r0["mean"])
+
+
+def test_batch_rejects_moving_geometry_and_ref_full(rend):
+    P = dict(scenes.TINY_PARAMS)
+    rend.set_scene(scenes.tiny_box(width=8, height=8))
+    with pytest.raises(ev.EvrtError) as e:
+        rend.render_event_batch([0.0, 1.0], P["C"], P["alpha"], 16, 16, 64, _opts(P))
+    assert e.value.code == ev.EVRT_E_UNSUPPORTED
+    rend.set_scene(scenes.panning(scenes.tiny_box(width=8, height=8), 3, 1.0))
+    with pytest.raises(ev.EvrtError) as e:
+        rend.render_event_batch([0.0, 1.0, 2.0], P["C"], P["alpha"], 16, 16, 64,
+                                _opts(P, ref_mode=ev.REF_FULL))
+    assert e.value.code == ev.EVRT_E_UNSUPPORTED

@@ -105,3 +105,19 @@ def test_u01_uniformity_chi_square():
     a = np.array(vals, dtype=np.float64).reshape(-1, 4) / 2.0**32
     c = np.corrcoef(a.T)
     assert np.abs(c - np.eye(4)).max() < 0.03
+
+
+def test_frame_keys_shift_with_key_base():
+    # Frame q = key_base + instant: instant 1 of key_base 5 is instant 0 of
+    # key_base 6 (same geometry at t0 = t1); q >= 256 carries into the
+    # fourth counter word instead of wrapping.
+    import oracle as _o
+    from paper_2408_07996_amd import scenes as _s
+    sc = _s.tiny_box(width=8, height=8)
+    with _o.Frame(sc, 0.5, 0.5) as f:
+        for px, smp in ((3, 0), (17, 5), (60, 11)):
+            a = f.path_radiance(_o.make_params(key_base=5), px, 1, smp)
+            b = f.path_radiance(_o.make_params(key_base=6), px, 0, smp)
+            assert a == b
+        vals = [f.path_radiance(_o.make_params(key_base=k), 20, 0, s) for k in (0, 256) for s in range(16)]
+        assert vals[:16] != vals[16:]
