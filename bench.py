@@ -68,6 +68,92 @@ def polarity_f1(pred: np.ndarray, ref: np.ndarray) -> float:
     return 1.0 if tp + fp + fn == 0 else 2.0 * tp / (2.0 * tp + fp + fn)
 
 
+def bench_diff(ev, scenes, steps: int = 3) -> dict:
+    """Event-loss gradient of the differentiation workload (256x256, 9,648
+    triangles, 36 materials, 256 paths per pixel and instant): forward
+    paths, per-pixel statistics and the path-replay adjoint per call."""
+    import torch
+    P = scenes.DIFF_PARAMS
+    sc = scenes.diff_scene()
+    r = ev.Renderer(0)
+    r.set_scene(sc)
+    o = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    print("[bench] differentiation workload", file=sys.stderr, flush=True)
+    g = r.event_loss_grad(0.0, 1.0, P["C"], P["tau"], P["spp"], o)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        g = r.event_loss_grad(0.0, 1.0, P["C"], P["tau"], P["spp"], o)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    paths = 2 * 2 * sc.width * sc.height * P["spp"]
+    out = dict(workload=f"{sc.width}x{sc.height}, {sc.n_tri_world} triangles, {len(sc.albedo)} materials, "
+                        f"{P['spp']} paths per pixel and instant, depth {P['max_depth']}",
+               grad_evals_per_s=1.0 / dt, ms_per_grad=1000.0 * dt, path_evals_per_s=paths / dt,
+               loss=float(g["loss"].cpu()[0]), replay_mismatch=int(g["replay_mismatch"].cpu()[0]))
+    r.close()
+    return out
+
+
+def bench_batch(ev, scenes, args) -> dict:
+    """Frame-batch workload (1280x720, 977,290 triangles, camera panning
+    0.5 degrees per frame, schedule 16/16/2048, depth 8): K consecutive pairs
+    in one batch call against the loop of K single-pair calls with the same
+    frame keys, whose outputs it must equal."""
+    import numpy as np
+    import torch
+    from paper_2408_07996_amd import autotune
+    P = scenes.BATCH_PARAMS
+    K = args.batch_pairs
+    sc = scenes.batch_scene(n_frames=max(65, K + 1))
+    r = ev.Renderer(0)
+    r.set_scene(sc)
+    o = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    tuned = None
+    if not args.no_autotune:
+        print("[bench] autotuning the launch shape", file=sys.stderr, flush=True)
+        at = autotune.autotune(r, 0.0, 1.0, o)
+        o = at["opts"]
+        tuned = dict(ray_batch=o["ray_batch"], trace_blocks_per_cu=o["trace_blocks_per_cu"],
+                     table=[list(x) for x in at["table"]])
+    times = [float(k) for k in range(K + 1)]
+    print(f"[bench] batch of {K} pairs", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b = r.render_event_batch(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], o,
+                             extras=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    st = r.frame_stats()
+    rays_b = st["camera_rays"] + st["extension_rays"] + st["shadow_rays"]
+    print(f"[bench] {K} single-pair calls", file=sys.stderr, flush=True)
+    same = True
+    rays_p = 0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(K):
+        f = r.render_event_frame(times[k], times[k + 1], P["C"], P["alpha"], P["spp_init"], P["spp_batch"],
+                                 P["spp_max"], dict(o, key_base=k), extras=False)
+        s2 = r.frame_stats()
+        rays_p += s2["camera_rays"] + s2["extension_rays"] + s2["shadow_rays"]
+        same = same and bool(torch.equal(f["polarity"], b["polarity"][k])) and \
+            bool(torch.equal(f["n_paths"], b["n_paths"][k]))
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    npth = b["n_paths"].cpu().numpy()
+    out = dict(workload=f"{sc.width}x{sc.height}, {sc.n_tri_world} triangles, {K} consecutive pairs, camera "
+                        f"panning 0.5 deg/frame, spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}, "
+                        f"depth {P['max_depth']}, C {P['C']}",
+               pairs=K, batch_s=tb, pair_loop_s=tp, speedup=tp / tb, identical_to_pair_loop=same,
+               batch_pairs_per_s=K / tb, batch_rays_per_s=rays_b / tb, pair_loop_rays_per_s=rays_p / tp,
+               sample_share_bound=2.0 * K / (K + 1), mean_paths_per_pixel=float(npth.mean()),
+               events_per_pair=float((b["polarity"].cpu().numpy() != 0).sum(axis=1).mean()), autotune=tuned)
+    r.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +169,10 @@ def main() -> int:
     ap.add_argument("--lds-nodes", type=int, default=0, help="top BVH nodes staged in LDS")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
+    ap.add_argument("--only", choices=("all", "frame", "diff", "batch"), default="all",
+                    help="which workloads to run (the headline is the frame workload)")
+    ap.add_argument("--batch-pairs", type=int, default=4, help="pairs of the frame-batch workload")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every pixel and sample is "
@@ -103,6 +193,14 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only in ("diff", "batch"):
+        res = {"metric": "next-row workloads", "next_rows": {}}
+        if args.only == "diff":
+            res["next_rows"]["differentiation"] = bench_diff(ev, scenes)
+        else:
+            res["next_rows"]["batching"] = bench_batch(ev, scenes, args)
+        print(json.dumps(res), flush=True)
+        return 0
     sc = scenes.sensor()
     P = dict(scenes.SENSOR_PARAMS, C=args.C)
     base_opts = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
@@ -113,9 +211,9 @@ def main() -> int:
     r.set_scene(sc)
     info = r.scene_info_at(0.0)
 
-    def frame(mode=ev.MODE_ADAPTIVE_1T, spp_max=P["spp_max"], spp_init=P["spp_init"], **kw):
+    def frame(mode=ev.MODE_ADAPTIVE_1T, spp_max=P["spp_max"], spp_init=P["spp_init"], C=P["C"], **kw):
         o = dict(base_opts, mode=mode, **kw)
-        out = r.render_event_frame(0.0, 1.0, P["C"], P["alpha"], min(spp_init, spp_max), P["spp_batch"],
+        out = r.render_event_frame(0.0, 1.0, C, P["alpha"], min(spp_init, spp_max), P["spp_batch"],
                                    spp_max, opts=o, extras=False)
         return out, r.frame_stats()
 
@@ -172,33 +270,56 @@ def main() -> int:
         fout, fst = frame(mode=ev.MODE_FIXED)
     torch.cuda.synchronize()
     t_fixed = (time.perf_counter() - tf) / nf
-    fixed_map = fout["polarity"].cpu().numpy()
     t_adapt = elapsed / args.steps
-    quality = {}
-    s_eq = None
-    if not args.no_quality:
-        print("[bench] equal-quality ladder", file=sys.stderr, flush=True)
-        ref, _ = frame(mode=ev.MODE_FIXED, spp_max=4 * P["spp_max"])
+
+    def quality(C, adapt_map, t_ad):
+        """Polarity F1 of the adaptive map and of fixed counts against a
+        4 x spp_max reference at threshold C; N_eq and S_eq."""
+        ref, _ = frame(mode=ev.MODE_FIXED, spp_max=4 * P["spp_max"], C=C)
         ref_map = ref["polarity"].cpu().numpy()
-        f1_adapt = polarity_f1(adaptive_map, ref_map)
-        quality = dict(reference_spp=4 * P["spp_max"], f1_adaptive=f1_adapt,
-                       f1_fixed={}, ref_events=int((ref_map != 0).sum()))
+        f1_adapt = polarity_f1(adapt_map, ref_map)
+        q = dict(reference_spp=4 * P["spp_max"], f1_adaptive=f1_adapt, f1_fixed={},
+                 ref_events=int((ref_map != 0).sum()))
         n_eq = None
         for n in (64, 128, 256, 512, 1024, 2048):
-            fo, _ = frame(mode=ev.MODE_FIXED, spp_max=n)
+            fo, _ = frame(mode=ev.MODE_FIXED, spp_max=n, C=C)
             f1 = polarity_f1(fo["polarity"].cpu().numpy(), ref_map)
-            quality["f1_fixed"][str(n)] = f1
+            q["f1_fixed"][str(n)] = f1
             if f1 >= f1_adapt:
                 n_eq = n
                 break
+        s = None
         if n_eq is not None:
-            frame(mode=ev.MODE_FIXED, spp_max=n_eq)
+            frame(mode=ev.MODE_FIXED, spp_max=n_eq, C=C)
             torch.cuda.synchronize()
             te = time.perf_counter()
-            frame(mode=ev.MODE_FIXED, spp_max=n_eq)
+            frame(mode=ev.MODE_FIXED, spp_max=n_eq, C=C)
             torch.cuda.synchronize()
-            s_eq = (time.perf_counter() - te) / t_adapt
-            quality["n_eq"] = n_eq
+            s = (time.perf_counter() - te) / t_ad
+            q["n_eq"] = n_eq
+        return q, s
+
+    quality_main, s_eq = ({}, None)
+    second = None
+    if not args.no_quality:
+        print("[bench] equal-quality ladder", file=sys.stderr, flush=True)
+        quality_main, s_eq = quality(P["C"], adaptive_map, t_adapt)
+        # The second threshold of the workload: its own timing and ladder.
+        C2 = 0.3 if abs(P["C"] - 0.3) > 1e-6 else 0.15
+        print(f"[bench] threshold C = {C2}", file=sys.stderr, flush=True)
+        frame(C=C2)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(3):
+            o2, s2 = frame(C=C2)
+        torch.cuda.synchronize()
+        t_ad2 = (time.perf_counter() - t2) / 3
+        map2 = o2["polarity"].cpu().numpy()
+        q2, s_eq2 = quality(C2, map2, t_ad2)
+        second = dict(C=C2, frames_per_s=1.0 / t_ad2, ms_per_step=1000.0 * t_ad2,
+                      mean_paths_per_pixel=float(o2["n_paths"].cpu().numpy().mean()),
+                      events=int((map2 != 0).sum()), speedup_vs_fixed_spp_max=t_fixed / t_ad2,
+                      speedup_equal_quality=s_eq2, quality=q2)
 
     cpu = None
     if not args.no_cpu:
@@ -240,8 +361,9 @@ def main() -> int:
         "fixed_frames_per_s": 1.0 / t_fixed,
         "speedup_vs_fixed_spp_max": t_fixed / t_adapt,
         "speedup_equal_quality": s_eq,
-        "f1_vs_fixed_spp_max": polarity_f1(adaptive_map, fixed_map),
-        "quality": quality,
+        "f1_vs_fixed_spp_max": polarity_f1(adaptive_map, fout["polarity"].cpu().numpy()),
+        "quality": quality_main,
+        "second_threshold": second,
         "roofline": {
             "kernel": "k_trace_closest",
             "bound": "alu",
@@ -262,6 +384,10 @@ def main() -> int:
         "cpu_baseline": cpu,
         "scene_build_and_warmup_s": build_ms,
     }
+    if args.only == "all":
+        r.close()
+        res["next_rows"] = {"differentiation": bench_diff(ev, scenes),
+                            "batching": bench_batch(ev, scenes, args)}
     print(json.dumps(res), flush=True)
     return 0
 

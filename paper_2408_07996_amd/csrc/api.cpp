@@ -321,6 +321,7 @@ int evrt_scene_commit(evrt_ctx *c)
             for (uint32_t mt : m.mat)
                 if (mt >= p.albedo.size()) fail(EVRT_E_INVALID, "triangle material out of range");
         c->scene = p;
+        c->static_geom = scene_static(p);
         c->cache.clear();
         c->cache_order.clear();
         ++c->scene_version;

@@ -83,6 +83,9 @@ struct DevInstantBufs {
     DevBuf nodes, tris, prim, emit_cdf, emit;
     DevInstant view{};
     HostInstant host;  // kept for statistics and validation
+    // Owner of the buffers that view points to, when they are shared with
+    // another time of a scene whose geometry does not move.
+    std::shared_ptr<DevInstantBufs> geom;
 };
 
 // World geometry at time t (primitive order, FP64 transform, FP32 round).
@@ -91,6 +94,8 @@ void build_world(const SceneDesc &sd, double t, HostInstant &out);
 void camera_at(const SceneDesc &sd, double t, DevCamera &out);
 // True when every instance has the same transform at all n times.
 bool instances_static(const SceneDesc &sd, const double *times, uint32_t n);
+// True when every instance's keys hold one transform (no motion at all).
+bool scene_static(const SceneDesc &sd);
 // BVH2 over out.tri (binned SAH), LDS treelet of up to n_lds_max nodes first.
 void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad);
 // Validates structural invariants of a built BVH; returns an empty string
@@ -133,6 +138,7 @@ struct evrt_ctx {
     evrt::SceneDesc pending;
     evrt::SceneDesc scene;
     bool committed = false;
+    bool static_geom = false;  // no instance moves: one geometry for all times
     uint64_t scene_version = 0;
     std::map<double, std::shared_ptr<evrt::DevInstantBufs>> cache;
     std::vector<double> cache_order;

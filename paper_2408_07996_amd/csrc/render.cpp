@@ -19,12 +19,35 @@ static constexpr uint32_t kDefaultRayBatch = 1u << 24;
 static constexpr uint32_t kMaxPathId = 1u << 31;
 static constexpr size_t kCacheInstants = 4;
 
+static void cache_insert(evrt_ctx *c, double t, const std::shared_ptr<DevInstantBufs> &bi)
+{
+    if (c->cache.size() >= kCacheInstants) {
+        const double victim = c->cache_order.front();
+        c->cache_order.erase(c->cache_order.begin());
+        c->cache.erase(victim);
+    }
+    c->cache[t] = bi;
+    c->cache_order.push_back(t);
+}
+
 std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s, double *ms_build)
 {
     auto it = c->cache.find(t);
     if (it != c->cache.end()) return it->second;
     const auto t_start = std::chrono::steady_clock::now();
     auto bi = std::make_shared<DevInstantBufs>();
+    if (c->static_geom && !c->cache.empty()) {
+        // Geometry that no instance moves is the same at every time: share
+        // the device buffers of a cached instant, only the camera differs.
+        const auto base = c->cache.begin()->second;
+        bi->view = base->view;
+        camera_at(c->scene, t, bi->view.cam);
+        bi->geom = base->geom ? base->geom : base;
+        cache_insert(c, t, bi);
+        if (ms_build)
+            *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        return bi;
+    }
     HostInstant &h = bi->host;
     build_world(c->scene, t, h);
     const float pad = bvh_padding(c->scene, h, h);
@@ -60,13 +83,7 @@ std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s
     v.cam = h.cam;
     // Keep only the world triangles needed for statistics; drop the rest.
     h.nodes.shrink_to_fit();
-    if (c->cache.size() >= kCacheInstants) {
-        const double victim = c->cache_order.front();
-        c->cache_order.erase(c->cache_order.begin());
-        c->cache.erase(victim);
-    }
-    c->cache[t] = bi;
-    c->cache_order.push_back(t);
+    cache_insert(c, t, bi);
     if (ms_build)
         *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return bi;

@@ -121,6 +121,14 @@ bool instances_static(const SceneDesc &sd, const double *times, uint32_t n)
     return true;
 }
 
+bool scene_static(const SceneDesc &sd)
+{
+    for (const auto &in : sd.instances)
+        for (size_t k = 1; k < in.kt.size(); ++k)
+            if (std::memcmp(in.kx.data(), in.kx.data() + 12 * k, 12 * sizeof(double)) != 0) return false;
+    return true;
+}
+
 void camera_at(const SceneDesc &sd, double t, DevCamera &out)
 {
     // Camera basis in FP64, rounded once to FP32.
