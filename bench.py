@@ -140,6 +140,8 @@ def bench_batch(ev, scenes, args) -> dict:
         rays_p += s2["camera_rays"] + s2["extension_rays"] + s2["shadow_rays"]
         same = same and bool(torch.equal(f["polarity"], b["polarity"][k])) and \
             bool(torch.equal(f["n_paths"], b["n_paths"][k]))
+        if (k + 1) % 8 == 0:
+            print(f"[bench]   {k + 1} of {K} pairs", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t
     npth = b["n_paths"].cpu().numpy()
