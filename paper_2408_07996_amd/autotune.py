@@ -13,7 +13,7 @@ import itertools
 import time
 from typing import Dict, Iterable, Optional, Sequence
 
-DEFAULT_RAY_BATCH = (1 << 23, 1 << 24, 1 << 25)
+DEFAULT_RAY_BATCH = (1 << 24, 1 << 25, 1 << 26)
 DEFAULT_BLOCKS_PER_CU = (4, 6, 8)
 
 

@@ -15,7 +15,7 @@
 
 namespace evrt {
 
-static constexpr uint32_t kDefaultRayBatch = 1u << 24;
+static constexpr uint32_t kDefaultRayBatch = 1u << 26;
 static constexpr uint32_t kMaxPathId = 1u << 31;
 static constexpr size_t kCacheInstants = 4;
 
