@@ -128,6 +128,8 @@ def lib():
                              ctypes.POINTER(ctypes.c_int)]
     L.evo_render.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _u32p, ctypes.c_uint32,
                              ctypes.c_int, ctypes.POINTER(_PixelOut)]
+    L.evo_render_video.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.POINTER(Params),
+                                   _u32p, ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(_PixelOut)]
     _lib = L
     return L
 
@@ -376,18 +378,49 @@ class Frame:
                               len(px), int(threads), out)
         if rc != 0:
             raise ValueError("invalid render parameters")
-        raw = np.ctypeslib.as_array(out)[: len(px)]
-        return dict(
-            pixels=px.copy(),
-            polarity=raw["polarity"].astype(np.int8),
-            decided_early=raw["decided_early"].astype(bool),
-            near_crit=raw["near_crit"].astype(bool),
-            n_paths=raw["n_paths"].astype(np.uint32),
-            n_paths_ref=raw["n_paths_ref"].astype(np.uint32),
-            rounds=raw["rounds"].astype(np.uint32),
-            mean=raw["mean"].astype(np.float64).copy(),
-            var=raw["var"].astype(np.float64).copy(),
-            mean_radiance=raw["mean_radiance"].astype(np.float64).copy(),
-            t_last=raw["t_last"].astype(np.float64),
-            crit_margin=raw["crit_margin"].astype(np.float64),
-        )
+        return _pixel_dict(px, np.ctypeslib.as_array(out)[: len(px)])
+
+
+def _pixel_dict(px, raw):
+    """Per-pixel oracle outputs (structured array) as a dict of arrays."""
+    return dict(
+        pixels=px.copy(),
+        polarity=raw["polarity"].astype(np.int8),
+        decided_early=raw["decided_early"].astype(bool),
+        near_crit=raw["near_crit"].astype(bool),
+        n_paths=raw["n_paths"].astype(np.uint32),
+        n_paths_ref=raw["n_paths_ref"].astype(np.uint32),
+        rounds=raw["rounds"].astype(np.uint32),
+        mean=raw["mean"].astype(np.float64).copy(),
+        var=raw["var"].astype(np.float64).copy(),
+        mean_radiance=raw["mean_radiance"].astype(np.float64).copy(),
+        t_last=raw["t_last"].astype(np.float64),
+        crit_margin=raw["crit_margin"].astype(np.float64),
+    )
+
+
+def render_video(scene, times, params: Params, pixels: Optional[np.ndarray] = None,
+                 threads: int = 0) -> Dict[str, np.ndarray]:
+    """Sequential event video over frames at `times` (Algorithm 1 with the
+    reference carried per pixel and replaced at events; frame 0 at the full
+    count).  Arrays have a leading axis of len(times) - 1 frames."""
+    times = [float(t) for t in times]
+    if len(times) < 2:
+        raise ValueError("need at least two frames")
+    frames = [Frame(scene, times[k - 1], times[k]) for k in range(1, len(times))]
+    try:
+        if pixels is None:
+            pixels = np.arange(scene.width * scene.height, dtype=np.uint32)
+        px = np.ascontiguousarray(pixels, np.uint32)
+        nf = len(times) - 1
+        out = (_PixelOut * max(1, nf * len(px)))()
+        ptrs = (ctypes.c_void_p * nf)(*[f._frame for f in frames])
+        rc = lib().evo_render_video(ptrs, len(times), ctypes.byref(params), _ptr(px, ctypes.c_uint32), len(px),
+                                    int(threads), out)
+        if rc != 0:
+            raise ValueError("invalid video parameters")
+        raw = np.ctypeslib.as_array(out)[: nf * len(px)].reshape(nf, len(px))
+        return _pixel_dict(px, raw)
+    finally:
+        for f in frames:
+            f.close()

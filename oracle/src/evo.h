@@ -156,6 +156,14 @@ int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau
                    const uint32_t *pixels, uint32_t n_pixels, int n_threads, double *loss,
                    double *grad_albedo, double *grad_emission, double *loss_px, double *delta_px);
 
+/* Sequential event video (Algorithm 1 over n_frames frames): pairs[k - 1]
+ * is the frame of instants (t_{k-1}, t_k); frame 0 at spp_max is the first
+ * reference of every pixel, frame k is sampled adaptively against the
+ * pixel's reference and replaces it where it produces an event; frame k is
+ * keyed key_base + k.  out: [(n_frames - 1) * n_pixels], frame-major. */
+int evo_render_video(const evo_frame *const *pairs, uint32_t n_frames, const evo_params *p,
+                     const uint32_t *pixels, uint32_t n_pixels, int n_threads, evo_pixel_out *out);
+
 int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
                float C, float alpha, int df_mode, int mode,
                double *t_out, double *p_out, double *df_out, int *stop_out);

@@ -255,13 +255,15 @@ static void update_margin(double *margin, double value)
 }
 
 /* Algorithm 1 for one pixel and one pair of instants. */
+/* One pixel of one pair.  ref_given: the first instant's samples are
+ * already in ws->x[0] / ws->y[0] at the full count (a carried reference). */
 static void render_pixel(const evo_frame *f, const evo_params *p, uint32_t pixel,
-                         pixel_scratch *ws, evo_pixel_out *o)
+                         pixel_scratch *ws, evo_pixel_out *o, int ref_given)
 {
     const uint32_t mb = p->minibatch;
-    const int full_ref = p->ref_mode == EVO_REF_FULL;
+    const int full_ref = ref_given || p->ref_mode == EVO_REF_FULL;
     const int fixed = p->mode == EVO_MODE_FIXED;
-    uint32_t n_prev[2] = {0, 0};
+    uint32_t n_prev[2] = {ref_given ? p->spp_max : 0u, 0};
     uint32_t n1 = fixed ? p->spp_max : p->spp_init;
     double margin = INFINITY;
     double mean[2] = {0, 0}, var[2] = {0, 0}, t = 0.0, df = 0.0, pl = 0.0;
@@ -344,7 +346,7 @@ static void *render_worker(void *arg)
     for (;;) {
         uint32_t k = __atomic_fetch_add(&job->next, 1u, __ATOMIC_RELAXED);
         if (k >= job->n_pixels) break;
-        render_pixel(job->f, p, job->pixels[k], &ws, &job->out[k]);
+        render_pixel(job->f, p, job->pixels[k], &ws, &job->out[k], 0);
     }
     for (int i = 0; i < 2; ++i) { free(ws.L[i]); free(ws.x[i]); free(ws.y[i]); }
     return NULL;
@@ -365,6 +367,74 @@ int evo_render(const evo_frame *f, const evo_params *p, const uint32_t *pixels,
     render_job job = {f, p, pixels, n_pixels, out, 0u};
     pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
     for (int i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, render_worker, &job);
+    for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+    free(th);
+    return 0;
+}
+
+/* Sequential event video (Algorithm 1 over frames t_0 ... t_{n-1}): frame 0
+ * at the full count is every pixel's first reference; frame k >= 1 is
+ * sampled adaptively against the pixel's reference (the first instant held
+ * at the full count, as in REF_FULL) and, where it produces an event,
+ * becomes the pixel's reference.  Frame k is keyed key_base + k.
+ * pairs[k - 1] holds the instants (t_{k-1}, t_k).  out is frame-major:
+ * out[(k - 1) * n_pixels + i]. */
+typedef struct {
+    const evo_frame *const *pairs;
+    uint32_t n_frames;
+    const evo_params *p;
+    const uint32_t *pixels;
+    uint32_t n_pixels;
+    evo_pixel_out *out;
+    uint32_t next;
+} video_job;
+
+static void *video_worker(void *arg)
+{
+    video_job *job = (video_job *)arg;
+    const evo_params *p = job->p;
+    pixel_scratch ws;
+    const uint32_t mmax = p->spp_max / p->minibatch;
+    for (int i = 0; i < 2; ++i) {
+        ws.L[i] = (float *)malloc(sizeof(float) * p->spp_max);
+        ws.x[i] = (double *)malloc(sizeof(double) * mmax);
+        ws.y[i] = (double *)malloc(sizeof(double) * mmax);
+    }
+    for (;;) {
+        uint32_t i = __atomic_fetch_add(&job->next, 1u, __ATOMIC_RELAXED);
+        if (i >= job->n_pixels) break;
+        for (uint32_t k = 1; k < job->n_frames; ++k) {
+            evo_params pk = *p;
+            pk.ref_mode = EVO_REF_FULL;
+            pk.key_base = p->key_base + k - 1;
+            evo_pixel_out *o = &job->out[(size_t)(k - 1) * job->n_pixels + i];
+            render_pixel(job->pairs[k - 1], &pk, job->pixels[i], &ws, o, k > 1);
+            if (o->polarity != 0) {
+                memcpy(ws.x[0], ws.x[1], sizeof(double) * mmax);
+                memcpy(ws.y[0], ws.y[1], sizeof(double) * mmax);
+            }
+        }
+    }
+    for (int i = 0; i < 2; ++i) { free(ws.L[i]); free(ws.x[i]); free(ws.y[i]); }
+    return NULL;
+}
+
+int evo_render_video(const evo_frame *const *pairs, uint32_t n_frames, const evo_params *p,
+                     const uint32_t *pixels, uint32_t n_pixels, int n_threads, evo_pixel_out *out)
+{
+    const uint32_t mb = p->minibatch;
+    if (n_frames < 2) return -1;
+    if (mb == 0 || (mb & (mb - 1)) != 0) return -1;
+    if (p->spp_init % mb || p->spp_batch % mb || p->spp_max % mb) return -1;
+    if (p->spp_init < 2 * mb || p->spp_init > p->spp_max || p->spp_batch == 0) return -1;
+    const uint32_t npx = pairs[0]->scene->d.width * pairs[0]->scene->d.height;
+    for (uint32_t k = 0; k < n_pixels; ++k)
+        if (pixels[k] >= npx) return -1;
+    if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (n_threads < 1) n_threads = 1;
+    video_job job = {pairs, n_frames, p, pixels, n_pixels, out, 0u};
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+    for (int i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, video_worker, &job);
     for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
     free(th);
     return 0;
