@@ -177,6 +177,21 @@ int evrt_render_event_frame(evrt_ctx *ctx, double t0, double t1, float C, float 
                             const evrt_render_opts *opts, const evrt_frame_out *out,
                             void *stream);
 
+/* Sequential event video (Algorithm 1 over a sequence of frames): frame 0
+ * at times[0] is rendered at spp_max and becomes every pixel's reference;
+ * each frame k = 1 .. n_frames - 1 is sampled adaptively against the
+ * pixel's reference, held at the full count (the test of REF_FULL mode:
+ * Eq. 7 with N = the current frame's count, df = m_ref + m - 2), and where
+ * it fires an event (which happens only at spp_max) it replaces the
+ * reference.  Frame k is keyed opts->key_base + k; opts->ref_mode is not
+ * used.  Any scene motion is allowed.  Outputs as for one frame,
+ * frame-major with n_frames - 1 entries per pixel: entry (k - 1) * width *
+ * height + pixel holds frame k against its reference (x2 arrays: reference
+ * first, then frame k). */
+int evrt_render_event_video(evrt_ctx *ctx, uint32_t n_frames, const double *times, float C, float alpha,
+                            uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
+                            const evrt_render_opts *opts, const evrt_frame_out *out, void *stream);
+
 /* Renders n_pairs consecutive event frames at once: pair k is (times[k],
  * times[k+1]) (host array of n_pairs + 1 finite times) and is computed as
  * evrt_render_event_frame(times[k], times[k+1]) with opts->key_base + k

@@ -99,6 +99,9 @@ SIGNATURES = [
     ("evrt_render_event_frame", ctypes.c_int,
      [_c_p, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float, _u32, _u32, _u32,
       ctypes.POINTER(RenderOpts), ctypes.POINTER(FrameOut), _c_p]),
+    ("evrt_render_event_video", ctypes.c_int,
+     [_c_p, _u32, _c_p, ctypes.c_float, ctypes.c_float, _u32, _u32, _u32, ctypes.POINTER(RenderOpts),
+      ctypes.POINTER(FrameOut), _c_p]),
     ("evrt_render_event_batch", ctypes.c_int,
      [_c_p, _u32, _c_p, ctypes.c_float, ctypes.c_float, _u32, _u32, _u32, ctypes.POINTER(RenderOpts),
       ctypes.POINTER(FrameOut), _c_p]),
@@ -317,36 +320,48 @@ class Renderer:
             int(spp_max), ctypes.byref(o), ctypes.byref(fo), _stream_ptr(stream)))
         return out
 
-    def render_event_batch(self, times, C: float, alpha: float, spp_init: int, spp_batch: int, spp_max: int,
+    def render_event_video(self, times, C: float, alpha: float, spp_init: int, spp_batch: int, spp_max: int,
                            opts=None, stream=None, extras: bool = True) -> Dict:
-        """Renders the consecutive pairs (times[k], times[k+1]) at once;
-        returns device tensors with a leading pair axis (see evrt.h)."""
+        """Sequential event video over frames at `times` (reference carried
+        per pixel, replaced at events); device tensors with a leading axis
+        of len(times) - 1 frames (see evrt.h)."""
+        return self._multi("evrt_render_event_video", times, len(times), C, alpha, spp_init, spp_batch, spp_max,
+                           opts, stream, extras)
+
+    def _multi(self, fn, times, n_arg, C, alpha, spp_init, spp_batch, spp_max, opts, stream, extras) -> Dict:
         import torch
         o = self._opts(opts)
         if self.scene is None:
             raise EvrtError(EVRT_E_STATE, "no scene")
         t = np.ascontiguousarray(times, np.float64).reshape(-1)
-        n_pairs = len(t) - 1
-        if n_pairs < 1:
+        n = len(t) - 1
+        if n < 1:
             raise EvrtError(EVRT_E_INVALID, "need at least two times")
         npx = self.scene.width * self.scene.height
         dev = torch.device("cuda", self.device)
         out = dict(
-            polarity=torch.empty(n_pairs, npx, dtype=torch.int8, device=dev),
-            n_paths=torch.empty(n_pairs, npx, dtype=torch.int32, device=dev),
-            mean=torch.empty(n_pairs, npx, 2, dtype=torch.float64, device=dev),
-            var=torch.empty(n_pairs, npx, 2, dtype=torch.float64, device=dev),
+            polarity=torch.empty(n, npx, dtype=torch.int8, device=dev),
+            n_paths=torch.empty(n, npx, dtype=torch.int32, device=dev),
+            mean=torch.empty(n, npx, 2, dtype=torch.float64, device=dev),
+            var=torch.empty(n, npx, 2, dtype=torch.float64, device=dev),
         )
         if extras:
-            out["t_last"] = torch.empty(n_pairs, npx, dtype=torch.float64, device=dev)
-            out["mean_radiance"] = torch.empty(n_pairs, npx, 2, dtype=torch.float64, device=dev)
-            out["flags"] = torch.empty(n_pairs, npx, dtype=torch.uint8, device=dev)
+            out["t_last"] = torch.empty(n, npx, dtype=torch.float64, device=dev)
+            out["mean_radiance"] = torch.empty(n, npx, 2, dtype=torch.float64, device=dev)
+            out["flags"] = torch.empty(n, npx, dtype=torch.uint8, device=dev)
         fo = FrameOut(_dptr(out["polarity"]), _dptr(out["n_paths"]), _dptr(out["mean"]), _dptr(out["var"]),
                       _dptr(out.get("t_last")), _dptr(out.get("mean_radiance")), _dptr(out.get("flags")))
-        self._check(load_library().evrt_render_event_batch(
-            self._h, n_pairs, _np_ptr(t), float(C), float(alpha), int(spp_init), int(spp_batch), int(spp_max),
+        self._check(getattr(load_library(), fn)(
+            self._h, int(n_arg), _np_ptr(t), float(C), float(alpha), int(spp_init), int(spp_batch), int(spp_max),
             ctypes.byref(o), ctypes.byref(fo), _stream_ptr(stream)))
         return out
+
+    def render_event_batch(self, times, C: float, alpha: float, spp_init: int, spp_batch: int, spp_max: int,
+                           opts=None, stream=None, extras: bool = True) -> Dict:
+        """Renders the consecutive pairs (times[k], times[k+1]) at once;
+        returns device tensors with a leading pair axis (see evrt.h)."""
+        return self._multi("evrt_render_event_batch", times, len(times) - 1, C, alpha, spp_init, spp_batch,
+                           spp_max, opts, stream, extras)
 
     def frame_stats(self) -> Dict:
         s = FrameStats()

@@ -393,6 +393,29 @@ int evrt_render_event_frame(evrt_ctx *c, double t0, double t1, float C, float al
     });
 }
 
+int evrt_render_event_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, float alpha,
+                            uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts *opts,
+                            const evrt_frame_out *out, void *stream)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        evrt_render_opts o;
+        if (opts) o = *opts;
+        else evrt_default_opts(&o);
+        validate_opts(o);
+        if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
+        if (n_frames < 2) fail(EVRT_E_INVALID, "n_frames must be at least 2");
+        if (!times) fail(EVRT_E_INVALID, "NULL times");
+        for (uint32_t k = 0; k < n_frames; ++k)
+            if (!std::isfinite(times[k])) fail(EVRT_E_INVALID, "times must be finite");
+        validate_frame_args(o, C, alpha, spp_init, spp_batch, spp_max, out);
+        if ((uint64_t)o.key_base + n_frames > (1u << 24)) fail(EVRT_E_INVALID, "key_base + n_frames above 2^24");
+        need_device(c);
+        render_video(c, n_frames, times, C, alpha, spp_init, spp_batch, spp_max, o, *out,
+                     static_cast<hipStream_t>(stream));
+    });
+}
+
 int evrt_render_event_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, float alpha,
                             uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts *opts,
                             const evrt_frame_out *out, void *stream)

@@ -81,6 +81,13 @@ void launch_adjoint(hipStream_t s, uint32_t blocks, const DevScene &sc, const Re
                     uint32_t spp, const float *Lfwd, const double *W, uint32_t n_mat, double *g,
                     uint32_t *mismatch);
 
+// Sequential video: current-frame slots cleared / references replaced at
+// events.
+void launch_video_frame_init(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                             double *wf_ysum, uint32_t *act, uint32_t *cnt);
+void launch_video_update(hipStream_t s, uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,
+                         double *wf_m2, double *wf_ysum);
+
 // Frame batches (see k_batch_* in the kernels).
 void launch_batch_init(hipStream_t s, uint32_t n_frames, uint32_t npx, uint32_t *wf_n, double *wf_mean,
                        double *wf_m2, double *wf_ysum, uint32_t *item_idx, uint32_t *items, uint32_t *act,

@@ -979,7 +979,8 @@ __global__ __launch_bounds__(256) void k_decide_compact(Decide dc, const uint32_
 // range of its pixels: checkpoint by checkpoint, the mini-batches up to the
 // checkpoint enter the Welford state and the pixel is tested as if the round
 // had ended there.  A pixel that stops ignores the samples traced past its
-// checkpoint; the others keep their state and are compacted into act_out.
+// checkpoint and keeps its state at the stop; the others are compacted into
+// act_out.
 __global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParams rp, Decide dc,
                                                            uint32_t *act_out, uint32_t *cnt, uint32_t *wf_n,
                                                            double *wf_mean, double *wf_m2, double *wf_ysum,
@@ -1011,12 +1012,45 @@ __global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParam
             break;
         }
     }
-    if (!done) {
-        if (both) welford_store(w0, 2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
-        welford_store(w1, 2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
-    }
+    // The state at the stop (or at the round's end) stays in memory: a
+    // sequential video takes it as the pixel's next reference at an event.
+    if (both) welford_store(w0, 2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
+    welford_store(w1, 2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
     const uint32_t slot = wave_append(!done, cnt + kCntActive + dc.cnt_slot);
     if (!done) act_out[slot] = pixel;
+}
+
+// Start of a video frame: the current frame's statistics (second slot of
+// every pixel) cleared and every pixel active; the reference slot is kept.
+__global__ void k_video_frame_init(uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                                   double *wf_ysum, uint32_t *act, uint32_t *cnt)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npx) {
+        wf_n[2 * i + 1] = 0;
+        wf_mean[2 * i + 1] = 0.0;
+        wf_m2[2 * i + 1] = 0.0;
+        wf_ysum[2 * i + 1] = 0.0;
+        act[i] = i;
+    }
+    if (i == 0) {
+        cnt[kCntActive] = 0;
+        cnt[kCntActive + 1] = 0;
+    }
+}
+
+// End of a video frame: a pixel that fired an event takes the frame's
+// statistics as its reference (Algorithm 1 replaces the reference
+// log-luminance at events only).
+__global__ void k_video_update(uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,
+                               double *wf_m2, double *wf_ysum)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npx || polarity[i] == 0) return;
+    wf_n[2 * i] = wf_n[2 * i + 1];
+    wf_mean[2 * i] = wf_mean[2 * i + 1];
+    wf_m2[2 * i] = wf_m2[2 * i + 1];
+    wf_ysum[2 * i] = wf_ysum[2 * i + 1];
 }
 
 // ------------------------------------------------------------------------
@@ -1568,6 +1602,20 @@ void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_
 {
     hipLaunchKernelGGL(k_decide_compact, dim3((nA + 255) / 256), dim3(256), 0, s, dc, act_in, nA,
                        act_out, cnt, wf_n, wf_mean, wf_m2, wf_ysum, out);
+}
+
+void launch_video_frame_init(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
+                             double *wf_ysum, uint32_t *act, uint32_t *cnt)
+{
+    hipLaunchKernelGGL(k_video_frame_init, dim3(std::max(1u, (npx + 255) / 256)), dim3(256), 0, s, npx, wf_n,
+                       wf_mean, wf_m2, wf_ysum, act, cnt);
+}
+
+void launch_video_update(hipStream_t s, uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,
+                         double *wf_m2, double *wf_ysum)
+{
+    hipLaunchKernelGGL(k_video_update, dim3(std::max(1u, (npx + 255) / 256)), dim3(256), 0, s, npx, polarity, wf_n,
+                       wf_mean, wf_m2, wf_ysum);
 }
 
 void launch_batch_init(hipStream_t s, uint32_t n_frames, uint32_t npx, uint32_t *wf_n, double *wf_mean,

@@ -330,46 +330,23 @@ static void read_stats(evrt_ctx *c, hipStream_t s)
     c->stats.tri_tests_shadow = c->h_stat[kStatTrisShadow];
 }
 
-void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
-                  uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o,
-                  const evrt_frame_out &out, hipStream_t s)
+// The adaptive rounds of one pair over the active list (every pixel of
+// fb.act0 at entry): both instants in lock step, or only the second one
+// against a first instant already held at the full count (ref_full).
+static void run_rounds(evrt_ctx *c, const DevScene &sc, const RenderParams &rp, const evrt_render_opts &o,
+                       float C, float alpha, uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
+                       bool ref_full, uint32_t nA, const Outputs &outs, hipStream_t s, Profiler &prof)
 {
-    const auto wall0 = std::chrono::steady_clock::now();
-    std::memset(&c->stats, 0, sizeof(c->stats));
-    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
-    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
-    const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
-    const RenderParams rp = make_params(c, o);
-    const uint32_t npx = sc.width * sc.height;
-    const uint32_t mb = o.minibatch;
-    // Largest piece of the frame: at most ray_batch paths, or one
-    // mini-batch of every pixel when that is larger, or 64 pixels' ranges.
-    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
-    const uint64_t all = 2ull * npx * spp_max;
-    const uint64_t floor_piece = std::min<uint64_t>(2ull * npx * mb, 2ull * 64 * spp_max);
-    const uint64_t cap = std::max<uint64_t>(std::min<uint64_t>(batch, all), floor_piece);
-    if (cap >= kMaxPathId) fail(EVRT_E_UNSUPPORTED, "image too large for one mini-batch piece");
-    ensure_buffers(c, npx, (uint32_t)cap, rp.n_slots);
     FrameBuffers &fb = c->fb;
-    launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
-                      fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
-                      fb.stat.as<unsigned long long>());
-    Profiler prof{c, o.profile != 0, 0, {}, s};
-
+    const uint32_t mb = o.minibatch;
+    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
     const bool fixed = o.mode == EVRT_MODE_FIXED;
-    const bool ref_full = o.ref_mode == EVRT_REF_FULL;
     uint32_t *act_in = fb.act0.as<uint32_t>();
     uint32_t *act_out = fb.act1.as<uint32_t>();
-    uint32_t nA = npx;
-    if (ref_full) {
-        // The first instant at the full count for every pixel.
-        trace_range(c, act_in, nA, 1, 0, 0, spp_max, sc, rp, o, s, prof);
-    }
     const uint32_t n_inst = ref_full ? 1 : 2;
     const uint32_t inst_base = ref_full ? 1 : 0;
     uint32_t n_prev = 0;
     uint32_t n_next = fixed ? spp_max : spp_init;  // first checkpoint of the next round
-    Outputs outs{out.polarity, out.n_paths, out.mean, out.var, out.t_last, out.mean_radiance, out.flags};
     for (uint32_t r = 0;; ++r) {
         // Checkpoints of this round: the schedule's next sample counts, as
         // many as keep the round's paths within one batch (at least one).
@@ -414,13 +391,96 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
                   "active count readback");
         hip_check(hipStreamSynchronize(s), "round");
         const uint32_t next = c->h_pinned[0];
-        if (r < 64) c->stats.active_after_round[r] = next;
-        c->stats.rounds = r + 1;
+        if (c->stats.rounds < 64) c->stats.active_after_round[c->stats.rounds] = next;
+        c->stats.rounds += 1;
         std::swap(act_in, act_out);
         nA = next;
         if (nA == 0 || dc.final_round) break;
         n_prev = hi;
         n_next = std::min(hi + spp_batch, spp_max);
+    }
+}
+
+// Work buffers of a frame of npx pixels with paths in flight per piece.
+static void frame_buffers(evrt_ctx *c, uint32_t npx, uint32_t spp_max, const evrt_render_opts &o,
+                          uint32_t n_slots)
+{
+    const uint32_t mb = o.minibatch;
+    // Largest piece of the frame: at most ray_batch paths, or one
+    // mini-batch of every pixel when that is larger, or 64 pixels' ranges.
+    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    const uint64_t all = 2ull * npx * spp_max;
+    const uint64_t floor_piece = std::min<uint64_t>(2ull * npx * mb, 2ull * 64 * spp_max);
+    const uint64_t cap = std::max<uint64_t>(std::min<uint64_t>(batch, all), floor_piece);
+    if (cap >= kMaxPathId) fail(EVRT_E_UNSUPPORTED, "image too large for one mini-batch piece");
+    ensure_buffers(c, npx, (uint32_t)cap, n_slots);
+}
+
+void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
+                  uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o,
+                  const evrt_frame_out &out, hipStream_t s)
+{
+    const auto wall0 = std::chrono::steady_clock::now();
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
+    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
+    const RenderParams rp = make_params(c, o);
+    const uint32_t npx = sc.width * sc.height;
+    frame_buffers(c, npx, spp_max, o, rp.n_slots);
+    FrameBuffers &fb = c->fb;
+    launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
+                      fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
+                      fb.stat.as<unsigned long long>());
+    Profiler prof{c, o.profile != 0, 0, {}, s};
+    const bool ref_full = o.ref_mode == EVRT_REF_FULL;
+    if (ref_full) {
+        // The first instant at the full count for every pixel.
+        trace_range(c, fb.act0.as<uint32_t>(), npx, 1, 0, 0, spp_max, sc, rp, o, s, prof);
+    }
+    Outputs outs{out.polarity, out.n_paths, out.mean, out.var, out.t_last, out.mean_radiance, out.flags};
+    run_rounds(c, sc, rp, o, C, alpha, spp_init, spp_batch, spp_max, ref_full, npx, outs, s, prof);
+    read_stats(c, s);
+    prof.collect(c->stats);
+    c->stats.ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+}
+
+// Sequential event video over frames times[0 .. n_frames): frame 0 at the
+// full count fills the reference slot of every pixel; each later frame k is
+// sampled adaptively against the pixel's reference (frame keys key_base + k)
+// and replaces it where the frame fires an event.  Outputs frame-major.
+void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, float alpha, uint32_t spp_init,
+                  uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o, const evrt_frame_out &out,
+                  hipStream_t s)
+{
+    const auto wall0 = std::chrono::steady_clock::now();
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto g0 = get_instant(c, times[0], s, &c->stats.ms_build);
+    const DevScene sc0 = make_dev_scene(c, *g0, *g0, o.lds_nodes);
+    const RenderParams rp0 = make_params(c, o);
+    const uint32_t npx = sc0.width * sc0.height;
+    frame_buffers(c, npx, spp_max, o, rp0.n_slots);
+    FrameBuffers &fb = c->fb;
+    launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
+                      fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
+                      fb.stat.as<unsigned long long>());
+    Profiler prof{c, o.profile != 0, 0, {}, s};
+    trace_range(c, fb.act0.as<uint32_t>(), npx, 1, 0, 0, spp_max, sc0, rp0, o, s, prof);
+    for (uint32_t k = 1; k < n_frames; ++k) {
+        auto gk = get_instant(c, times[k], s, &c->stats.ms_build);
+        const DevScene sc = make_dev_scene(c, *gk, *gk, o.lds_nodes);
+        evrt_render_opts ok = o;
+        ok.key_base = o.key_base + k - 1;  // the second instant is frame key_base + k
+        const RenderParams rp = make_params(c, ok);
+        launch_video_frame_init(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
+                                fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>());
+        const size_t f = (size_t)(k - 1) * npx;
+        Outputs outs{out.polarity + f, out.n_paths + f, out.mean + 2 * f, out.var + 2 * f,
+                     out.t_last ? out.t_last + f : nullptr, out.mean_radiance ? out.mean_radiance + 2 * f : nullptr,
+                     out.flags ? out.flags + f : nullptr};
+        run_rounds(c, sc, rp, ok, C, alpha, spp_init, spp_batch, spp_max, true, npx, outs, s, prof);
+        launch_video_update(s, npx, outs.polarity, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(),
+                            fb.wf_m2.as<double>(), fb.wf_ysum.as<double>());
     }
     read_stats(c, s);
     prof.collect(c->stats);
