@@ -60,12 +60,7 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def polarity_f1(pred: np.ndarray, ref: np.ndarray) -> float:
-    """Polarity-aware per-pixel F1 of one event map against a reference."""
-    tp = int(((pred != 0) & (pred == ref)).sum())
-    fp = int(((pred != 0) & (pred != ref)).sum())
-    fn = int(((ref != 0) & (pred != ref)).sum())
-    return 1.0 if tp + fp + fn == 0 else 2.0 * tp / (2.0 * tp + fp + fn)
+from paper_2408_07996_amd.metrics import polarity_f1, video_scores  # noqa: E402
 
 
 def bench_diff(ev, scenes, steps: int = 3) -> dict:
@@ -92,6 +87,40 @@ def bench_diff(ev, scenes, steps: int = 3) -> dict:
                         f"{P['spp']} paths per pixel and instant, depth {P['max_depth']}",
                grad_evals_per_s=1.0 / dt, ms_per_grad=1000.0 * dt, path_evals_per_s=paths / dt,
                loss=float(g["loss"].cpu()[0]), replay_mismatch=int(g["replay_mismatch"].cpu()[0]))
+    r.close()
+    return out
+
+
+def bench_video(ev, scenes) -> dict:
+    """Sequential event video of the sensor scene over 5 frames (t = 0, 0.25,
+    ..., 1; reference carried per pixel, replaced at events), scored by F1,
+    RMSE and PSNR against the same video at a fixed 4096 paths."""
+    import torch
+    P = scenes.SENSOR_PARAMS
+    sc = scenes.sensor()
+    r = ev.Renderer(0)
+    r.set_scene(sc)
+    o = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    times = [0.0, 0.25, 0.5, 0.75, 1.0]
+    print("[bench] sequential video", file=sys.stderr, flush=True)
+    r.render_event_video(times[:2], P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], o,
+                         extras=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    v = r.render_event_video(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], o,
+                             extras=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ref = r.render_event_video(times, P["C"], P["alpha"], 4 * P["spp_max"], 16, 4 * P["spp_max"],
+                               dict(o, mode=ev.MODE_FIXED), extras=False)
+    pol = v["polarity"].cpu().numpy()
+    out = dict(workload=f"sensor scene, {len(times)} frames t = 0 ... 1, spp {P['spp_init']}/{P['spp_batch']}/"
+                        f"{P['spp_max']}, C {P['C']}, reference video at a fixed {4 * P['spp_max']} paths",
+               seconds=dt, frames_per_s=(len(times) - 1) / dt,
+               mean_paths_per_pixel=float(v["n_paths"].cpu().numpy().mean()),
+               events_per_frame=[int(x) for x in (pol != 0).sum(axis=1)],
+               quality=video_scores(pol, ref["polarity"].cpu().numpy()))
     r.close()
     return out
 
@@ -171,7 +200,7 @@ def main() -> int:
     ap.add_argument("--lds-nodes", type=int, default=0, help="top BVH nodes staged in LDS")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
-    ap.add_argument("--only", choices=("all", "frame", "diff", "batch"), default="all",
+    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video"), default="all",
                     help="which workloads to run (the headline is the frame workload)")
     ap.add_argument("--batch-pairs", type=int, default=4, help="pairs of the frame-batch workload")
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
@@ -195,10 +224,12 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.only in ("diff", "batch"):
+    if args.only in ("diff", "batch", "video"):
         res = {"metric": "next-row workloads", "next_rows": {}}
         if args.only == "diff":
             res["next_rows"]["differentiation"] = bench_diff(ev, scenes)
+        elif args.only == "video":
+            res["next_rows"]["sequential_video"] = bench_video(ev, scenes)
         else:
             res["next_rows"]["batching"] = bench_batch(ev, scenes, args)
         print(json.dumps(res), flush=True)
@@ -389,7 +420,8 @@ def main() -> int:
     if args.only == "all":
         r.close()
         res["next_rows"] = {"differentiation": bench_diff(ev, scenes),
-                            "batching": bench_batch(ev, scenes, args)}
+                            "batching": bench_batch(ev, scenes, args),
+                            "sequential_video": bench_video(ev, scenes)}
     print(json.dumps(res), flush=True)
     return 0
 
