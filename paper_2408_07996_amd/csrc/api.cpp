@@ -151,6 +151,11 @@ int evrt_create(int hip_device, evrt_ctx **out)
             kernel_occupancy(&tb, &sb);
             c->trace_blocks_per_cu = (uint32_t)tb;
             c->shade_blocks_per_cu = (uint32_t)sb;
+#ifndef EVRT_ONE_LANE
+            hip_check(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking), "hipStreamCreate");
+            hip_check(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
+            hip_check(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "hipEventCreate");
+#endif
             void *p = nullptr;
             hip_check(hipHostMalloc(&p, 64, hipHostMallocDefault), "hipHostMalloc");
             c->h_pinned = static_cast<uint32_t *>(p);
@@ -179,6 +184,9 @@ void evrt_destroy(evrt_ctx *c)
         }
         if (c->h_pinned) (void)hipHostFree(c->h_pinned);
         if (c->h_stat) (void)hipHostFree(c->h_stat);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (c->s2) (void)hipStreamDestroy(c->s2);
     }
     delete c;
 }

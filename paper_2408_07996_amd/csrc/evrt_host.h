@@ -109,12 +109,20 @@ FastDiv make_fastdiv(uint32_t d);
 // Student t quantile (integer df) and its memoized critical values.
 double t_quantile(double p, uint32_t df);
 
-struct FrameBuffers {
-    DevBuf wf_n, wf_mean, wf_m2, wf_ysum, act0, act1;
-    DevBuf cnt, stat;
+// Wavefront queues of one piece in flight.  Two lanes let consecutive pieces
+// run on two streams so that one piece's kernels fill the other's tails.
+struct LaneBufs {
     DevBuf q_o[2], q_d[2], q_skip[2], hit;
     DevBuf sh_o, sh_meta, sh_dir, sh_c;
     DevBuf rad;
+    uint32_t queue_cap = 0, shadow_slots = 0;
+};
+
+struct FrameBuffers {
+    DevBuf wf_n, wf_mean, wf_m2, wf_ysum, act0, act1;
+    DevBuf cnt, stat;
+    DevBuf cnt1;  // per-bounce queue counts of lane 1 (lane 0 uses cnt)
+    LaneBufs lane[2];
     DevBuf hook_tm;
     DevBuf diff_px, diff_L, diff_W;  // event-loss gradient: pixel list, path radiance, weights
     // Frame batches: per-(frame, pixel) state and item index, item list,
@@ -122,7 +130,6 @@ struct FrameBuffers {
     // per-frame cameras.
     DevBuf b_wf_n, b_wf_mean, b_wf_m2, b_wf_ysum, b_item_idx, b_items, b_act0, b_act1, b_pair_items, b_snap,
         b_cams;
-    uint32_t queue_cap = 0, shadow_slots = 0;
 };
 
 struct EventPair {
@@ -144,6 +151,8 @@ struct evrt_ctx {
     std::vector<double> cache_order;
     evrt::DevBuf mat, plights;
     evrt::FrameBuffers fb;
+    hipStream_t s2 = nullptr;                // second lane's stream (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint32_t *h_pinned = nullptr;            // pinned readback words
     unsigned long long *h_stat = nullptr;    // pinned stat readback
     std::vector<evrt::EventPair> events;

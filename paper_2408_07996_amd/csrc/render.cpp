@@ -122,8 +122,9 @@ static RenderParams make_params(const evrt_ctx *c, const evrt_render_opts &o)
     return rp;
 }
 
-// Device work buffers sized for `cap` paths in flight and npx pixels.
-static void ensure_buffers(evrt_ctx *c, uint32_t npx, uint32_t cap, uint32_t slots)
+// Device work buffers for npx pixels and a piece of `cap` paths in flight
+// on lane `ln`.
+static void ensure_buffers(evrt_ctx *c, uint32_t npx, uint32_t cap, uint32_t slots, int ln = 0)
 {
     FrameBuffers &fb = c->fb;
     fb.wf_n.ensure(sizeof(uint32_t) * 2 * (size_t)npx);
@@ -133,25 +134,27 @@ static void ensure_buffers(evrt_ctx *c, uint32_t npx, uint32_t cap, uint32_t slo
     fb.act0.ensure(sizeof(uint32_t) * (size_t)npx);
     fb.act1.ensure(sizeof(uint32_t) * (size_t)npx);
     fb.cnt.ensure(sizeof(uint32_t) * kCntSize);
+    fb.cnt1.ensure(sizeof(uint32_t) * kCntSize);
     fb.stat.ensure(sizeof(unsigned long long) * kStatCount);
-    if (cap > fb.queue_cap || slots > fb.shadow_slots) {
-        const uint32_t ncap = std::max(cap, fb.queue_cap);
-        const uint32_t nsl = std::max(slots, fb.shadow_slots);
+    LaneBufs &L = fb.lane[ln];
+    if (cap > L.queue_cap || slots > L.shadow_slots) {
+        const uint32_t ncap = std::max(cap, L.queue_cap);
+        const uint32_t nsl = std::max(slots, L.shadow_slots);
         for (int k = 0; k < 2; ++k) {
-            fb.q_o[k].ensure(sizeof(float4) * (size_t)ncap);
-            fb.q_d[k].ensure(sizeof(float4) * (size_t)ncap);
-            fb.q_skip[k].ensure(sizeof(uint32_t) * (size_t)ncap);
+            L.q_o[k].ensure(sizeof(float4) * (size_t)ncap);
+            L.q_d[k].ensure(sizeof(float4) * (size_t)ncap);
+            L.q_skip[k].ensure(sizeof(uint32_t) * (size_t)ncap);
         }
-        fb.hit.ensure(sizeof(float2) * (size_t)ncap);
-        fb.sh_o.ensure(sizeof(float4) * (size_t)ncap);
-        fb.sh_meta.ensure(sizeof(uint32_t) * (size_t)ncap);
+        L.hit.ensure(sizeof(float2) * (size_t)ncap);
+        L.sh_o.ensure(sizeof(float4) * (size_t)ncap);
+        L.sh_meta.ensure(sizeof(uint32_t) * (size_t)ncap);
         // Slot-major shadow arrays: their stride is the capacity, so they are
         // reallocated whenever the capacity changes.
-        fb.sh_dir.ensure(sizeof(float4) * (size_t)ncap * nsl);
-        fb.sh_c.ensure(sizeof(float) * (size_t)ncap * nsl);
-        fb.rad.ensure(sizeof(float) * (size_t)ncap);
-        fb.queue_cap = ncap;
-        fb.shadow_slots = nsl;
+        L.sh_dir.ensure(sizeof(float4) * (size_t)ncap * nsl);
+        L.sh_c.ensure(sizeof(float) * (size_t)ncap * nsl);
+        L.rad.ensure(sizeof(float) * (size_t)ncap);
+        L.queue_cap = ncap;
+        L.shadow_slots = nsl;
     }
 }
 
@@ -171,8 +174,7 @@ struct Profiler {
     bool on;
     size_t used = 0;
     std::vector<int> kind;  // 0 closest, 1 shadow
-    hipStream_t s;
-    void begin(int k)
+    void begin(int k, hipStream_t s)
     {
         if (!on) return;
         if (used == c->events.size()) {
@@ -184,7 +186,7 @@ struct Profiler {
         kind.push_back(k);
         hip_check(hipEventRecord(c->events[used].a, s), "hipEventRecord");
     }
-    void end()
+    void end(hipStream_t s)
     {
         if (!on) return;
         hip_check(hipEventRecord(c->events[used].b, s), "hipEventRecord");
@@ -204,15 +206,16 @@ struct Profiler {
 // Traces one piece: camera rays, max_depth bounces of closest hit + shade
 // + shadow rays.  Path radiances land in pc.rad.
 static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const RenderParams &rp,
-                        const evrt_render_opts &o, hipStream_t s, Profiler &prof)
+                        const evrt_render_opts &o, hipStream_t s, Profiler &prof, int ln = 0)
 {
     FrameBuffers &fb = c->fb;
-    uint32_t *cnt = fb.cnt.as<uint32_t>();
+    LaneBufs &L = fb.lane[ln];
+    uint32_t *cnt = ln ? fb.cnt1.as<uint32_t>() : fb.cnt.as<uint32_t>();
     unsigned long long *stat = fb.stat.as<unsigned long long>();
     RayQueue q[2];
-    for (int k = 0; k < 2; ++k) q[k] = RayQueue{fb.q_o[k].as<float4>(), fb.q_d[k].as<float4>(), fb.q_skip[k].as<uint32_t>()};
-    ShadowQueue sq{fb.sh_o.as<float4>(), fb.sh_meta.as<uint32_t>(), fb.sh_dir.as<float4>(), fb.sh_c.as<float>(),
-                   fb.queue_cap};
+    for (int k = 0; k < 2; ++k) q[k] = RayQueue{L.q_o[k].as<float4>(), L.q_d[k].as<float4>(), L.q_skip[k].as<uint32_t>()};
+    ShadowQueue sq{L.sh_o.as<float4>(), L.sh_meta.as<uint32_t>(), L.sh_dir.as<float4>(), L.sh_c.as<float>(),
+                   L.queue_cap};
     launch_raygen(s, pc, sc, rp, q[0], cnt);
     const uint32_t tb = (uint32_t)traverse_block_threads();
     const uint32_t tper = o.trace_blocks_per_cu ? std::min(o.trace_blocks_per_cu, c->trace_blocks_per_cu)
@@ -223,18 +226,18 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
     for (uint32_t d = 1; d <= rp.max_depth; ++d) {
         const RayQueue &qin = q[(d - 1) & 1];
         const RayQueue &qout = q[d & 1];
-        prof.begin(0);
+        prof.begin(0, s);
         launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + 2 * (d - 1), pc.region, pc.n_inst,
-                             fb.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat);
-        prof.end();
+                             L.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat);
+        prof.end(s);
         c->stats.n_closest_launches++;
-        launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), fb.hit.as<float2>(), qout,
+        launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), L.hit.as<float2>(), qout,
                      cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d);
         if (rp.nee) {
-            prof.begin(1);
+            prof.begin(1, s);
             launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
                                 pc.n_inst, pc.rad, stat);
-            prof.end();
+            prof.end(s);
             c->stats.n_shadow_launches++;
         }
     }
@@ -265,7 +268,9 @@ static bool trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
                         uint32_t *act_out = nullptr, const Outputs *outs = nullptr)
 {
     const uint32_t mb = rp.minibatch;
-    const uint64_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    // With two lanes a piece holds half of the paths in flight.
+    const uint64_t full = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    const uint64_t batch = c->s2 ? (full + 1) / 2 : full;
     const uint64_t range = hi - lo;
     const uint64_t per_px = (uint64_t)n_inst * range;
     uint64_t px_block = std::max<uint64_t>(1, batch / per_px);
@@ -282,6 +287,16 @@ static bool trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
     // decisions; split sample ranges leave them to a separate kernel.
     const bool fused = dc != nullptr && bp_max >= range;
     if (dc != nullptr && !fused && dc->n_checks != 1) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
+    // Consecutive pieces alternate between the caller's stream and the
+    // second lane's, ordered after the work already on the caller's stream
+    // and joined back before the decisions that follow.
+    const uint64_t n_pieces = ((nA + px_block - 1) / px_block) * ((range + bp_max - 1) / bp_max);
+    const bool two = c->s2 != nullptr && n_pieces > 1;
+    if (two) {
+        hip_check(hipEventRecord(c->ev_fork, s), "fork");
+        hip_check(hipStreamWaitEvent(c->s2, c->ev_fork, 0), "fork wait");
+    }
+    uint32_t piece = 0;
     for (uint32_t a0 = 0; a0 < nA; a0 += (uint32_t)px_block) {
         const uint32_t na = (uint32_t)std::min<uint64_t>(px_block, nA - a0);
         for (uint32_t s0 = lo; s0 < hi;) {
@@ -299,18 +314,25 @@ static bool trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
             pc.div_nA = make_fastdiv(na);
             pc.rs_a = bp;
             pc.rs_i = na * bp;
-            ensure_buffers(c, sc.width * sc.height, pc.n_paths, rp.n_slots);
-            pc.rad = c->fb.rad.as<float>();
-            trace_piece(c, pc, sc, rp, o, s, prof);
+            const int ln = two ? (int)(piece & 1u) : 0;
+            hipStream_t ps = ln ? c->s2 : s;
+            ++piece;
+            ensure_buffers(c, sc.width * sc.height, pc.n_paths, rp.n_slots, ln);
+            pc.rad = c->fb.lane[ln].rad.as<float>();
+            trace_piece(c, pc, sc, rp, o, ps, prof, ln);
             if (fused)
-                launch_accumulate_decide(s, pc, rp, *dc, act_out, c->fb.cnt.as<uint32_t>(),
+                launch_accumulate_decide(ps, pc, rp, *dc, act_out, c->fb.cnt.as<uint32_t>(),
                                          c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
                                          c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>(), *outs);
             else
-                launch_accumulate(s, pc, rp, c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
+                launch_accumulate(ps, pc, rp, c->fb.wf_n.as<uint32_t>(), c->fb.wf_mean.as<double>(),
                                   c->fb.wf_m2.as<double>(), c->fb.wf_ysum.as<double>());
             s0 += bp;
         }
+    }
+    if (two) {
+        hip_check(hipEventRecord(c->ev_join, c->s2), "join");
+        hip_check(hipStreamWaitEvent(s, c->ev_join, 0), "join wait");
     }
     return fused;
 }
@@ -406,9 +428,11 @@ static void frame_buffers(evrt_ctx *c, uint32_t npx, uint32_t spp_max, const evr
                           uint32_t n_slots)
 {
     const uint32_t mb = o.minibatch;
-    // Largest piece of the frame: at most ray_batch paths, or one
-    // mini-batch of every pixel when that is larger, or 64 pixels' ranges.
-    const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    // Largest piece of the frame: at most ray_batch paths (half with two
+    // lanes), or one mini-batch of every pixel when that is larger, or 64
+    // pixels' ranges.
+    const uint32_t full = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
+    const uint32_t batch = c->s2 ? (full + 1) / 2 : full;
     const uint64_t all = 2ull * npx * spp_max;
     const uint64_t floor_piece = std::min<uint64_t>(2ull * npx * mb, 2ull * 64 * spp_max);
     const uint64_t cap = std::max<uint64_t>(std::min<uint64_t>(batch, all), floor_piece);
@@ -432,7 +456,7 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
     launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
                       fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
                       fb.stat.as<unsigned long long>());
-    Profiler prof{c, o.profile != 0, 0, {}, s};
+    Profiler prof{c, o.profile != 0, 0, {}};
     const bool ref_full = o.ref_mode == EVRT_REF_FULL;
     if (ref_full) {
         // The first instant at the full count for every pixel.
@@ -464,7 +488,7 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
     launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
                       fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
                       fb.stat.as<unsigned long long>());
-    Profiler prof{c, o.profile != 0, 0, {}, s};
+    Profiler prof{c, o.profile != 0, 0, {}};
     trace_range(c, fb.act0.as<uint32_t>(), npx, 1, 0, 0, spp_max, sc0, rp0, o, s, prof);
     for (uint32_t k = 1; k < n_frames; ++k) {
         auto gk = get_instant(c, times[k], s, &c->stats.ms_build);
@@ -533,7 +557,7 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
     uint32_t *act_in = fb.b_act0.as<uint32_t>();
     uint32_t *act_out = fb.b_act1.as<uint32_t>();
     launch_batch_init(s, nf, npx, wf_n, wf_mean, wf_m2, wf_ysum, item_idx, items, act_in, pair_items, cnt);
-    Profiler prof{c, o.profile != 0, 0, {}, s};
+    Profiler prof{c, o.profile != 0, 0, {}};
     const bool fixed = o.mode == EVRT_MODE_FIXED;
     uint32_t nA = n_pairs * npx;
     uint32_t n_items = nf * npx;
@@ -612,7 +636,7 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
                 pc.rs_i = na * bp;
                 pc.cams = fb.b_cams.as<DevCamera>();
                 ensure_buffers(c, npx, pc.n_paths, rp.n_slots);
-                pc.rad = fb.rad.as<float>();
+                pc.rad = fb.lane[0].rad.as<float>();
                 trace_piece(c, pc, sc, rp, o, s, prof);
                 launch_batch_accumulate(s, pc, rp, dc, npx, a0, wf_n, wf_mean, wf_m2, wf_ysum, snap);
                 s0 += bp;
@@ -654,7 +678,7 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
     ensure_buffers(c, npx, (uint32_t)std::min<uint64_t>((uint64_t)chunk * per_px, kMaxPathId - 1), rp.n_slots);
     launch_init_frame(s, 0, nullptr, nullptr, nullptr, nullptr, nullptr, c->fb.cnt.as<uint32_t>(),
                       c->fb.stat.as<unsigned long long>());
-    Profiler prof{c, false, 0, {}, s};
+    Profiler prof{c, false, 0, {}};
     for (uint32_t a0 = 0; a0 < n_pixels; a0 += chunk) {
         const uint32_t na = std::min(chunk, n_pixels - a0);
         Piece pc{};
@@ -720,7 +744,7 @@ void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint
     ensure_buffers(c, sc.width * sc.height, n, 1);
     FrameBuffers &fb = c->fb;
     fb.hook_tm.ensure(sizeof(float) * 2 * (size_t)n);
-    RayQueue q{fb.q_o[0].as<float4>(), fb.q_d[0].as<float4>(), fb.q_skip[0].as<uint32_t>()};
+    RayQueue q{fb.lane[0].q_o[0].as<float4>(), fb.lane[0].q_d[0].as<float4>(), fb.lane[0].q_skip[0].as<uint32_t>()};
     launch_hook_rays(s, n, rays, skip, q, fb.hook_tm.as<float>(), fb.cnt.as<uint32_t>());
     const uint32_t tb = (uint32_t)traverse_block_threads();
     launch_hook_trace(s, blocks_for(c->trace_blocks_per_cu, c->cu_count, n, tb), any != 0, sc, q,
