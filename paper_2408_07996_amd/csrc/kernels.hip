@@ -366,29 +366,34 @@ __device__ __forceinline__ bool visit_node(Trav &T, float4 n0, float4 n1, float4
 // treelet, inner nodes in global memory, then one leaf.  ANY stops at the
 // first accepted hit.  Returns false when the ray is finished; the result is
 // T.tfar / T.best_p.
-template <bool ANY, bool COUNT>
+// LDS: the instants' top treelets are staged in LDS (else every node is
+// read from global memory and the treelet loop is compiled out).
+template <bool ANY, bool COUNT, bool LDS = true>
 __device__ __forceinline__ bool traverse_step(Trav &T, const DevScene &sc, const lds_f32 *s_nodes,
                                               lds_u32 *lds_stack, int32_t *spill, uint32_t &visits,
                                               uint32_t &tests)
 {
-    const uint32_t n_lds = T.inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
-    const lds_f32 *lds = s_nodes + T.inst * 16 * kLdsNodes;
+    const uint32_t n_lds = LDS ? (T.inst ? sc.inst[1].n_lds : sc.inst[0].n_lds) : 0u;
     const float4 *nodes = T.inst ? sc.inst[1].nodes : sc.inst[0].nodes;
     const float4 *tris = T.inst ? sc.inst[1].tris : sc.inst[0].tris;
     bool live = true;
-    while (live && T.ref >= 0 && (uint32_t)T.ref < n_lds) {
-        const lds_f32 *p = lds + 16 * T.ref;
-        if (COUNT) ++visits;
-        live = visit_node(T, lds_load4(p), lds_load4(p + 4), lds_load4(p + 8), lds_load4(p + 12), lds_stack, spill);
+    if (LDS) {
+        const lds_f32 *lds = s_nodes + T.inst * 16 * kLdsNodes;
+        while (live && T.ref >= 0 && (uint32_t)T.ref < n_lds) {
+            const lds_f32 *p = lds + 16 * T.ref;
+            if (COUNT) ++visits;
+            live = visit_node(T, lds_load4(p), lds_load4(p + 4), lds_load4(p + 8), lds_load4(p + 12), lds_stack,
+                              spill);
+        }
     }
-    while (live && T.ref >= 0 && (uint32_t)T.ref >= n_lds) {
+    while (live && T.ref >= 0 && (!LDS || (uint32_t)T.ref >= n_lds)) {
         const float4 *p = nodes + 4 * (size_t)T.ref;
         if (COUNT) ++visits;
         live = visit_node(T, p[0], p[1], p[2], p[3], lds_stack, spill);
     }
     if (!live) return false;
     // A pop in the global loop can return a treelet node: not a leaf yet.
-    if (T.ref >= 0) return true;
+    if (LDS && T.ref >= 0) return true;
     const uint32_t packed = ~(uint32_t)T.ref;
     const uint32_t first = packed >> kLeafCountBits;
     const uint32_t count = (packed & (kMaxLeafTris - 1)) + 1;
@@ -553,14 +558,14 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
 
 // Closest hit of the queued rays; hit[i] = (t, prim bits), prim = kNoPrim on
 // a miss.  Grid-stride over the device-side queue count, one ray per lane.
-template <bool COUNT>
+template <bool COUNT, bool LDS>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_closest(DevScene sc, RayQueue q, const uint32_t *cnt_in,
                                                        uint32_t region, uint32_t n_split, float2 *hit,
                                                        int stat_kind, unsigned long long *stat)
 {
     __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
-    load_treelets(sc, s_nodes);
+    if (LDS) load_treelets(sc, s_nodes);
     const Part pt = partition(cnt_in, region, n_split);
     if (pt.lb == 0 && threadIdx.x == 0 && pt.n) atomicAdd(stat + stat_kind, (unsigned long long)pt.n);
     uint32_t visits = 0, tests = 0;
@@ -584,7 +589,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             if (wr.done()) break;
             continue;
         }
-        if (busy && !traverse_step<false, COUNT>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
+        if (busy && !traverse_step<false, COUNT, LDS>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
             busy = false;
             hit[cur] = make_float2(T.tfar, bitsf(T.best_p));
         }
@@ -601,7 +606,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
 // Shadow entries: the n_slots rays of an entry share its origin; the
 // contributions of the unoccluded slots are summed in slot order and added
 // to the path radiance once.
-template <bool COUNT>
+template <bool COUNT, bool LDS>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
                                                       const uint32_t *cnt_in, uint32_t region,
                                                       uint32_t n_split, float *rad,
@@ -609,7 +614,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
 {
     __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
-    load_treelets(sc, s_nodes);
+    if (LDS) load_treelets(sc, s_nodes);
     const Part pt = partition(cnt_in, region, n_split);
     uint32_t visits = 0, tests = 0, rays = 0;
     int32_t spill[kStackMax - kStackLds];
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             if (wr.done()) break;
             continue;
         }
-        if (tracing && !traverse_step<true, COUNT>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
+        if (tracing && !traverse_step<true, COUNT, LDS>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
             tracing = false;
             if (T.best_p == kNoPrim) sum = sum + c;
             ++slot;
@@ -1550,24 +1555,38 @@ void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevS
                           const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
                           float2 *hit, int stat_kind, unsigned long long *stat)
 {
-    if (count)
-        hipLaunchKernelGGL(k_trace_closest<true>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region, n_split,
-                           hit, stat_kind, stat);
+    const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
+    if (count && lds)
+        hipLaunchKernelGGL((k_trace_closest<true, true>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
+                           n_split, hit, stat_kind, stat);
+    else if (count)
+        hipLaunchKernelGGL((k_trace_closest<true, false>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
+                           n_split, hit, stat_kind, stat);
+    else if (lds)
+        hipLaunchKernelGGL((k_trace_closest<false, true>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
+                           n_split, hit, stat_kind, stat);
     else
-        hipLaunchKernelGGL(k_trace_closest<false>, dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region, n_split,
-                           hit, stat_kind, stat);
+        hipLaunchKernelGGL((k_trace_closest<false, false>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
+                           n_split, hit, stat_kind, stat);
 }
 
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
                          uint32_t n_split, float *rad, unsigned long long *stat)
 {
-    if (count)
-        hipLaunchKernelGGL(k_trace_shadow<true>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, region,
-                           n_split, rad, stat);
+    const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
+    if (count && lds)
+        hipLaunchKernelGGL((k_trace_shadow<true, true>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
+                           region, n_split, rad, stat);
+    else if (count)
+        hipLaunchKernelGGL((k_trace_shadow<true, false>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
+                           region, n_split, rad, stat);
+    else if (lds)
+        hipLaunchKernelGGL((k_trace_shadow<false, true>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
+                           region, n_split, rad, stat);
     else
-        hipLaunchKernelGGL(k_trace_shadow<false>, dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in, region,
-                           n_split, rad, stat);
+        hipLaunchKernelGGL((k_trace_shadow<false, false>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
+                           region, n_split, rad, stat);
 }
 
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
@@ -1711,8 +1730,8 @@ void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint3
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu)
 {
     int a = 0, b = 0, c = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_trace_closest<false>, kTB, 0) != hipSuccess) a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace_shadow<false>, kTB, 0) != hipSuccess) b = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_trace_closest<false, false>, kTB, 0) != hipSuccess) a = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace_shadow<false, false>, kTB, 0) != hipSuccess) b = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade, 256, 0) != hipSuccess) c = 1;
     *trace_blocks_per_cu = std::max(1, std::min(a, b));
     *shade_blocks_per_cu = std::max(1, c);
