@@ -290,8 +290,10 @@ static bool trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
     // Consecutive pieces alternate between the caller's stream and the
     // second lane's, ordered after the work already on the caller's stream
     // and joined back before the decisions that follow.
+    // Split sample ranges of one pixel block must be accumulated in order:
+    // they stay on one stream.
     const uint64_t n_pieces = ((nA + px_block - 1) / px_block) * ((range + bp_max - 1) / bp_max);
-    const bool two = c->s2 != nullptr && n_pieces > 1;
+    const bool two = c->s2 != nullptr && n_pieces > 1 && bp_max >= range;
     if (two) {
         hip_check(hipEventRecord(c->ev_fork, s), "fork");
         hip_check(hipStreamWaitEvent(c->s2, c->ev_fork, 0), "fork wait");
@@ -605,18 +607,31 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
         }
         // Pieces over the items: blocks of items with the whole sample range,
         // or every item over sub-ranges when the blocks would be too small
-        // (then the round has one checkpoint).
+        // (then the round has one checkpoint).  With two lanes a piece holds
+        // half of the paths in flight and consecutive pieces alternate
+        // streams, as in the single-pair rounds.
         const uint64_t range = hi - n_prev;
-        uint64_t it_block = std::max<uint64_t>(1, batch / range);
+        const uint64_t pbatch = c->s2 ? (batch + 1) / 2 : batch;
+        uint64_t it_block = std::max<uint64_t>(1, pbatch / range);
         uint64_t bp_max = range;
         if (it_block < 64 && it_block < n_items) {
             it_block = n_items;
-            bp_max = std::max<uint64_t>(mb, batch / n_items / mb * mb);
+            bp_max = std::max<uint64_t>(mb, pbatch / n_items / mb * mb);
         }
         it_block = std::min<uint64_t>(it_block, n_items);
         bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / it_block / mb * mb);
         if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many items for one piece");
-        if (dc.n_checks > 1 && bp_max < range) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
+        const bool split = bp_max < range;
+        if (dc.n_checks > 1 && split) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
+        const uint64_t n_pieces = ((n_items + it_block - 1) / it_block) * ((range + bp_max - 1) / bp_max);
+        // Split sample ranges of one item must be accumulated in order: they
+        // stay on one stream.
+        const bool two = c->s2 != nullptr && n_pieces > 1 && !split;
+        if (two) {
+            hip_check(hipEventRecord(c->ev_fork, s), "fork");
+            hip_check(hipStreamWaitEvent(c->s2, c->ev_fork, 0), "fork wait");
+        }
+        uint32_t piece = 0;
         for (uint32_t a0 = 0; a0 < n_items; a0 += (uint32_t)it_block) {
             const uint32_t na = (uint32_t)std::min<uint64_t>(it_block, n_items - a0);
             for (uint32_t s0 = n_prev; s0 < hi;) {
@@ -635,12 +650,19 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
                 pc.rs_a = bp;
                 pc.rs_i = na * bp;
                 pc.cams = fb.b_cams.as<DevCamera>();
-                ensure_buffers(c, npx, pc.n_paths, rp.n_slots);
-                pc.rad = fb.lane[0].rad.as<float>();
-                trace_piece(c, pc, sc, rp, o, s, prof);
-                launch_batch_accumulate(s, pc, rp, dc, npx, a0, wf_n, wf_mean, wf_m2, wf_ysum, snap);
+                const int ln = two ? (int)(piece & 1u) : 0;
+                hipStream_t ps = ln ? c->s2 : s;
+                ++piece;
+                ensure_buffers(c, npx, pc.n_paths, rp.n_slots, ln);
+                pc.rad = fb.lane[ln].rad.as<float>();
+                trace_piece(c, pc, sc, rp, o, ps, prof, ln);
+                launch_batch_accumulate(ps, pc, rp, dc, npx, a0, wf_n, wf_mean, wf_m2, wf_ysum, snap);
                 s0 += bp;
             }
+        }
+        if (two) {
+            hip_check(hipEventRecord(c->ev_join, c->s2), "join");
+            hip_check(hipStreamWaitEvent(s, c->ev_join, 0), "join wait");
         }
         launch_batch_decide(s, dc, act_in, nA, npx, pair_items, items, wf_n, wf_mean, wf_m2, wf_ysum, snap,
                             act_out, cnt, outs);

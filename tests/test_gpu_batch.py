@@ -49,12 +49,15 @@ def _batch_vs_pairs(rend, sc, P, times, **kw):
     return b, paths_batch, paths_pairs
 
 
-@pytest.mark.parametrize("variant", ["default", "small_pieces", "fixed", "two_tailed", "mb8", "key_base"])
+@pytest.mark.parametrize("variant", ["default", "small_pieces", "split_samples", "fixed", "two_tailed", "mb8",
+                                     "key_base"])
 def test_batch_equals_single_pairs(rend, variant):
     P = dict(scenes.TINY_PARAMS)
     kw = {}
     if variant == "small_pieces":
         kw = dict(ray_batch=1 << 14)
+    elif variant == "split_samples":
+        kw = dict(ray_batch=512)
     elif variant == "fixed":
         kw = dict(mode=ev.MODE_FIXED)
     elif variant == "two_tailed":

@@ -193,7 +193,7 @@ def _compare(g, r, pixels, C):
 
 
 @pytest.mark.parametrize("variant", ["default", "fixed", "ref_full", "two_tailed", "mean_only", "mb1", "mb8",
-                                     "lds_treelet", "small_pieces"])
+                                     "lds_treelet", "small_pieces", "split_samples"])
 def test_tiny_frame_parity(rend, torch_cuda, variant):
     sc = scenes.tiny_box()
     rend.set_scene(sc)
@@ -214,6 +214,8 @@ def test_tiny_frame_parity(rend, torch_cuda, variant):
         params["lds_nodes"] = 64
     elif variant == "small_pieces":
         params["ray_batch"] = 40000   # many pieces per round
+    elif variant == "split_samples":
+        params["ray_batch"] = 512     # pieces cut each pixel block's samples
     _say(f"tiny frame variant={variant}")
     g, st = _frame(rend, sc, params, 0.0, 1.0)
     with oracle.Frame(sc, 0.0, 1.0) as f:
