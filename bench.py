@@ -42,13 +42,18 @@ OPS_PER_TRI = 52.0    # watertight test: translate, permute, shear, 3 edge funct
 # 16 lanes x 2.4 GHz.
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
-# HBM bytes per closest-hit launch of this workload: FETCH_SIZE and
-# WRITE_SIZE (one rocprofv3 --pmc pass each, summed over the frame's
-# launches) scaled by what the same counters read for a 256 MiB device copy
-# (x1.9997 and x1.0000), divided by the launches.  It holds for the kernel
-# sources it was taken with and is reported as null for any others.
-TRAFFIC = {"sources_sha256": "346ce64e0357800d8820237e2a8c55ebf8e0cdfa5dc2a298cede39b3a986a092",
-           "bytes_per_launch": 216973428.6}
+# From rocprofv3 counter passes over one frame of this workload (summaries
+# in profiles/): HBM bytes per closest-hit launch (FETCH_SIZE and WRITE_SIZE
+# summed over the frame's launches, scaled by what the same counters read
+# for a 256 MiB device copy, x1.9997 and x1.0000, divided by the launches),
+# and the VALU busy fraction (SQ_ACTIVE_INST_VALU x 4 cycles over 1024 SIMDs
+# and the dispatches' GRBM_GUI_ACTIVE, which sums the 8 XCDs) and VALU lane
+# utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
+# traversal kernels.  They hold for the kernel sources they were taken with
+# and are reported as null for any others.
+TRAFFIC = {"sources_sha256": "3d4c075b15f7a664b6c0caf090e66482dc6a0c8e19a653e9f94f22063d2db3a4",
+           "bytes_per_launch": 512536302.3,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6503, "valu_lane_utilization": 0.4495}, "k_trace_shadow": {"valu_busy": 0.5657, "valu_lane_utilization": 0.4456}, "k_shade": {"valu_busy": 0.3325, "valu_lane_utilization": 0.588}}}
 
 
 def kernel_sources_digest() -> str:
@@ -288,7 +293,15 @@ def main() -> int:
     ops_per_launch = ops_closest / max(1.0, launches_per_frame)
     achieved = ops_per_launch / (ms_per_closest * 1e-3) if ms_per_closest > 0 else 0.0
 
-    traffic = TRAFFIC["bytes_per_launch"] if kernel_sources_digest() == TRAFFIC["sources_sha256"] else None
+    measured = kernel_sources_digest() == TRAFFIC["sources_sha256"]
+    traffic = TRAFFIC["bytes_per_launch"] if measured else None
+    counters = TRAFFIC.get("counters") if measured else None
+    # Both traversal kernels over the frame: their algorithmic lane-ops per
+    # frame over the frame time (the two lanes run concurrently, so the
+    # per-launch figure above counts each launch's time shared with the
+    # other lane's kernels).
+    ops_frame = ops_closest + cst["node_visits_shadow"] * OPS_PER_NODE + cst["tri_tests_shadow"] * OPS_PER_TRI
+    frame_frac = ops_frame / (elapsed / args.steps) / PEAK_LANE_OPS
 
     adaptive_map = out["polarity"].cpu().numpy()
     adaptive_paths = out["n_paths"].cpu().numpy().astype(np.int64)
@@ -413,6 +426,8 @@ def main() -> int:
             "shadow_ms_per_launch": ms_shadow / max(1, n_shadow),
             "closest_ms_per_frame": ms_closest / args.steps,
             "shadow_ms_per_frame": ms_shadow / args.steps,
+            "traversal_frac_over_frame": frame_frac,
+            "counters": counters,
         },
         "cpu_baseline": cpu,
         "scene_build_and_warmup_s": build_ms,

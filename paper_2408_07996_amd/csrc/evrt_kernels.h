@@ -44,12 +44,16 @@ void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const Ren
                    const RayQueue &q, uint32_t *cnt);
 // Traversal and shading kernels take the per-region counts cnt_in[0..1],
 // the region size and the number of regions; grids must be multiples of 8.
+// ev_start / ev_stop (may be null) are recorded by the dispatch itself, so
+// they time the kernel's execution and not its wait in the queue.
 void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                           const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
-                          float2 *hit, int stat_kind, unsigned long long *stat);
+                          float2 *hit, int stat_kind, unsigned long long *stat, hipEvent_t ev_start = nullptr,
+                          hipEvent_t ev_stop = nullptr);
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
-                         uint32_t n_split, float *rad, unsigned long long *stat);
+                         uint32_t n_split, float *rad, unsigned long long *stat, hipEvent_t ev_start = nullptr,
+                         hipEvent_t ev_stop = nullptr);
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,

@@ -13,6 +13,8 @@
 // and statistics are FP64.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "evrt_kernels.h"
 
 namespace evrt {
@@ -1553,40 +1555,43 @@ void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const Ren
 
 void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                           const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
-                          float2 *hit, int stat_kind, unsigned long long *stat)
+                          float2 *hit, int stat_kind, unsigned long long *stat, hipEvent_t ev_start,
+                          hipEvent_t ev_stop)
 {
+    // Start / stop events (when given) are written by the dispatch itself.
     const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
     if (count && lds)
-        hipLaunchKernelGGL((k_trace_closest<true, true>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
-                           n_split, hit, stat_kind, stat);
+        hipExtLaunchKernelGGL((k_trace_closest<true, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
+                              q, cnt_in, region, n_split, hit, stat_kind, stat);
     else if (count)
-        hipLaunchKernelGGL((k_trace_closest<true, false>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
-                           n_split, hit, stat_kind, stat);
+        hipExtLaunchKernelGGL((k_trace_closest<true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
+                              q, cnt_in, region, n_split, hit, stat_kind, stat);
     else if (lds)
-        hipLaunchKernelGGL((k_trace_closest<false, true>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
-                           n_split, hit, stat_kind, stat);
+        hipExtLaunchKernelGGL((k_trace_closest<false, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
+                              q, cnt_in, region, n_split, hit, stat_kind, stat);
     else
-        hipLaunchKernelGGL((k_trace_closest<false, false>), dim3(blocks), dim3(kTB), 0, s, sc, q, cnt_in, region,
-                           n_split, hit, stat_kind, stat);
+        hipExtLaunchKernelGGL((k_trace_closest<false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0,
+                              sc, q, cnt_in, region, n_split, hit, stat_kind, stat);
 }
 
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
-                         uint32_t n_split, float *rad, unsigned long long *stat)
+                         uint32_t n_split, float *rad, unsigned long long *stat, hipEvent_t ev_start,
+                         hipEvent_t ev_stop)
 {
     const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
     if (count && lds)
-        hipLaunchKernelGGL((k_trace_shadow<true, true>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
-                           region, n_split, rad, stat);
+        hipExtLaunchKernelGGL((k_trace_shadow<true, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
+                              sq, n_slots, cnt_in, region, n_split, rad, stat);
     else if (count)
-        hipLaunchKernelGGL((k_trace_shadow<true, false>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
-                           region, n_split, rad, stat);
+        hipExtLaunchKernelGGL((k_trace_shadow<true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
+                              sq, n_slots, cnt_in, region, n_split, rad, stat);
     else if (lds)
-        hipLaunchKernelGGL((k_trace_shadow<false, true>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
-                           region, n_split, rad, stat);
+        hipExtLaunchKernelGGL((k_trace_shadow<false, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
+                              sq, n_slots, cnt_in, region, n_split, rad, stat);
     else
-        hipLaunchKernelGGL((k_trace_shadow<false, false>), dim3(blocks), dim3(kTB), 0, s, sc, sq, n_slots, cnt_in,
-                           region, n_split, rad, stat);
+        hipExtLaunchKernelGGL((k_trace_shadow<false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0,
+                              sc, sq, n_slots, cnt_in, region, n_split, rad, stat);
 }
 
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,

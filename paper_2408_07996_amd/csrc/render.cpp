@@ -174,9 +174,10 @@ struct Profiler {
     bool on;
     size_t used = 0;
     std::vector<int> kind;  // 0 closest, 1 shadow
-    void begin(int k, hipStream_t s)
+    // Events for the next traversal launch of this kind (null when off).
+    EventPair take(int k)
     {
-        if (!on) return;
+        if (!on) return EventPair{};
         if (used == c->events.size()) {
             EventPair e;
             hip_check(hipEventCreate(&e.a), "hipEventCreate");
@@ -184,13 +185,7 @@ struct Profiler {
             c->events.push_back(e);
         }
         kind.push_back(k);
-        hip_check(hipEventRecord(c->events[used].a, s), "hipEventRecord");
-    }
-    void end(hipStream_t s)
-    {
-        if (!on) return;
-        hip_check(hipEventRecord(c->events[used].b, s), "hipEventRecord");
-        ++used;
+        return c->events[used++];
     }
     void collect(evrt_frame_stats &st)
     {
@@ -226,18 +221,16 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
     for (uint32_t d = 1; d <= rp.max_depth; ++d) {
         const RayQueue &qin = q[(d - 1) & 1];
         const RayQueue &qout = q[d & 1];
-        prof.begin(0, s);
+        const EventPair ec = prof.take(0);
         launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + 2 * (d - 1), pc.region, pc.n_inst,
-                             L.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat);
-        prof.end(s);
+                             L.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat, ec.a, ec.b);
         c->stats.n_closest_launches++;
         launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), L.hit.as<float2>(), qout,
                      cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d);
         if (rp.nee) {
-            prof.begin(1, s);
+            const EventPair es = prof.take(1);
             launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
-                                pc.n_inst, pc.rad, stat);
-            prof.end(s);
+                                pc.n_inst, pc.rad, stat, es.a, es.b);
             c->stats.n_shadow_launches++;
         }
     }
