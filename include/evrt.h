@@ -142,7 +142,8 @@ typedef struct {
     uint8_t profile;         /* 1: time traversal launches with HIP events         */
     uint8_t count_work;      /* 1: count BVH node visits and triangle tests        */
     uint8_t lds_nodes;       /* top BVH nodes staged in LDS per block, 0..64 (0)   */
-    uint32_t ray_batch;      /* max paths in flight per wavefront piece (0: auto)  */
+    uint32_t ray_batch;      /* paths in flight per round, split over two
+                                pieces on two streams (0: 64 M)                   */
     uint32_t key_base;       /* frame index of instant t0 in the random-number
                                 keys; t1 is key_base + 1 (default 0)              */
     uint32_t trace_blocks_per_cu; /* traversal blocks per CU (0: occupancy max)    */
@@ -213,13 +214,19 @@ typedef struct {
     uint64_t node_visits, tri_tests;  /* closest-hit traversal, when
                                          count_work was set (else 0)         */
     uint64_t node_visits_shadow, tri_tests_shadow; /* any-hit traversal      */
-    uint64_t paths;                   /* camera paths traced                 */
-    uint32_t rounds;                  /* decision rounds                     */
+    uint64_t paths;                   /* camera paths traced (a round traces
+                                         every checkpoint it covers for each
+                                         active pixel, so paths past a
+                                         pixel's stop are counted)           */
+    uint32_t rounds;                  /* scheduling rounds (each covers one
+                                         or more decision checkpoints)       */
     uint32_t pieces;                  /* wavefront pieces launched           */
     uint32_t n_closest_launches, n_shadow_launches;
     double ms_wall;                   /* host wall time of the call          */
-    double ms_closest, ms_shadow;     /* HIP-event time of traversal launches
-                                         (when profile was set, else 0)      */
+    double ms_closest, ms_shadow;     /* summed duration of traversal
+                                         launches, from events recorded by
+                                         the dispatches (when profile was
+                                         set, else 0)                        */
     double ms_build;                  /* geometry/BVH build done in the call */
     uint32_t active_after_round[64];  /* active pixels after rounds 0..63    */
 } evrt_frame_stats;
