@@ -253,23 +253,6 @@ __device__ __forceinline__ void box2(const TRay &r, float4 n0, float4 n1, float4
     tr = rnear <= rfar ? rnear : INFINITY;
 }
 
-struct InstSel {
-    const float4 *nodes;
-    const float4 *tris;
-    int32_t root;
-    uint32_t n_lds;
-};
-
-__device__ __forceinline__ InstSel select_inst(const DevScene &sc, uint32_t inst)
-{
-    InstSel s;
-    s.nodes = inst ? sc.inst[1].nodes : sc.inst[0].nodes;
-    s.tris = inst ? sc.inst[1].tris : sc.inst[0].tris;
-    s.root = inst ? sc.inst[1].root : sc.inst[0].root;
-    s.n_lds = inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
-    return s;
-}
-
 // Traversal block shape: kTB threads, a top treelet of kLdsNodes nodes per
 // instant staged in LDS, and a per-lane stack whose first kStackLds entries
 // live in LDS (deeper entries spill to private memory).
