@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 
 # FP32 VALU lane-operations of the intended math per unit of traversal work
 # (counted from the kernel's gfx950 ISA for the box and triangle tests).
-OPS_PER_NODE = 39.0   # two child slab tests (12 FMA, 24 min/max, 2 compares) + ordering
+OPS_PER_NODE = 62.0   # 4-wide node: four slab tests (6 FMA, 6 min/max, 1 compare each) + 4-key sort (10)
 OPS_PER_TRI = 52.0    # watertight test: translate, permute, shear, 3 edge functions, signs
 # Peak FP32 VALU issue of MI355X without packed math: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz.

@@ -141,7 +141,7 @@ typedef struct {
     uint8_t ref_mode;        /* EVRT_REF_*                                         */
     uint8_t profile;         /* 1: time traversal launches with HIP events         */
     uint8_t count_work;      /* 1: count BVH node visits and triangle tests        */
-    uint8_t lds_nodes;       /* top BVH nodes staged in LDS per block, 0..64 (0)   */
+    uint8_t lds_nodes;       /* top 4-wide BVH nodes staged in LDS, 0..32 (0)      */
     uint32_t ray_batch;      /* paths in flight per round, split over two
                                 pieces on two streams (0: 64 M)                   */
     uint32_t key_base;       /* frame index of instant t0 in the random-number
@@ -211,7 +211,8 @@ int evrt_render_event_batch(evrt_ctx *ctx, uint32_t n_pairs, const double *times
 /* Counters of the last render call on ctx. */
 typedef struct {
     uint64_t camera_rays, extension_rays, shadow_rays; /* rays traced        */
-    uint64_t node_visits, tri_tests;  /* closest-hit traversal, when
+    uint64_t node_visits, tri_tests;  /* closest-hit traversal (4-wide node
+                                         visits, triangle tests), when
                                          count_work was set (else 0)         */
     uint64_t node_visits_shadow, tri_tests_shadow; /* any-hit traversal      */
     uint64_t paths;                   /* camera paths traced (a round traces
@@ -302,12 +303,15 @@ typedef struct {
 int evrt_event_loss_grad(evrt_ctx *ctx, double t0, double t1, float C, float tau, uint32_t spp,
                          const evrt_render_opts *opts, const evrt_diff_out *out, void *stream);
 
-/* Host-side build of the scene at time t (world triangles and BVH2, no
- * device work) with a structural check of the BVH: every primitive in
- * exactly one leaf, every vertex inside its padded leaf box, every node
- * reachable once, depth within the traversal stack.  Works on host-only
- * contexts.  Returns EVRT_E_INVALID (message in evrt_last_error) when a
- * check fails. */
+/* Host-side build of the scene at time t (world triangles and the 4-wide
+ * BVH, no device work) with a structural check of the BVH: every primitive
+ * in exactly one leaf, every vertex inside the padded boxes of all its
+ * ancestors, every node reachable once, unused child slots empty, depth
+ * within the traversal stack.  Works on host-only contexts.  Returns
+ * EVRT_E_INVALID (message in evrt_last_error) when a check fails.
+ * n_nodes counts 4-wide inner nodes (0 when the root is a leaf), depth
+ * their levels, sah_cost is the SAH cost of the binary tree the 4-wide
+ * tree is collapsed from, in root-box traversals. */
 typedef struct {
     uint32_t n_tri, n_nodes, n_lds, depth, n_emit;
     float box_pad;

@@ -549,7 +549,7 @@ int evrt_scene_info_at(evrt_ctx *c, double t, evrt_scene_info *out)
         build_bvh(h, (uint32_t)lds_treelet_nodes(), pad);
         std::memset(out, 0, sizeof(*out));
         out->n_tri = (uint32_t)(h.tri.size() / 9);
-        out->n_nodes = (uint32_t)(h.nodes.size() / 4);
+        out->n_nodes = (uint32_t)(h.nodes.size() / 8);
         out->n_lds = h.n_lds;
         out->depth = h.depth;
         out->n_emit = (uint32_t)h.emit_prim.size();

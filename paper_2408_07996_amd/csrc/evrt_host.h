@@ -71,12 +71,12 @@ struct HostInstant {
     float emit_S = 0.0f;
     DevCamera cam;
     // BVH
-    std::vector<float4> nodes;   // 4 per inner node
+    std::vector<float4> nodes;   // 8 per 4-wide inner node
     std::vector<float4> tris;    // 3 per triangle in leaf order
     int32_t root = kEmptyRef;
     uint32_t n_lds = 0;
-    uint32_t depth = 0;
-    double sah_cost = 0.0;
+    uint32_t depth = 0;          // inner levels of the 4-wide tree
+    double sah_cost = 0.0;       // SAH cost of the binary tree
 };
 
 struct DevInstantBufs {

@@ -48,12 +48,12 @@ void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const Ren
 // they time the kernel's execution and not its wait in the queue.
 void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                           const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
-                          float2 *hit, int stat_kind, unsigned long long *stat, hipEvent_t ev_start = nullptr,
-                          hipEvent_t ev_stop = nullptr);
+                          uint32_t inst_base, float2 *hit, int stat_kind, unsigned long long *stat,
+                          hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
-                         uint32_t n_split, float *rad, unsigned long long *stat, hipEvent_t ev_start = nullptr,
-                         hipEvent_t ev_stop = nullptr);
+                         uint32_t n_split, uint32_t inst_base, float *rad, unsigned long long *stat,
+                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
@@ -112,7 +112,7 @@ void launch_batch_decide(hipStream_t s, const Decide &dc, const uint32_t *act, u
 
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu);
 int traverse_block_threads();
-int lds_treelet_nodes();
-int traverse_max_depth();
+int lds_treelet_nodes();   // 4-wide nodes a block can stage in LDS per instant
+int traverse_max_depth();  // deepest 4-wide tree (inner levels) the traversal stack holds
 
 }  // namespace evrt

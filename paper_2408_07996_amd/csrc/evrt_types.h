@@ -14,16 +14,19 @@ constexpr float kInvPi = 0.318309886183790671538f;
 constexpr double kTwoPi = 6.283185307179586476925;
 constexpr uint32_t kInstBit = 0x80000000u;  // instant flag in queue path words
 
-// BVH2 node: 64 bytes = four float4.  Child boxes are stored side by side;
-// child references are int32: >= 0 an inner node, < 0 a leaf whose
-// complement packs (first_triangle << 3) | (count - 1).
-//   n[0] = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)
-//   n[1] = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
-//   n[2] = (R.lo.z, R.hi.x, R.hi.y, R.hi.z)
-//   n[3] = (ref L, ref R, 0, 0) as int bits
+// 4-wide BVH node: 128 bytes = eight float4, child slot j in component j:
+//   n[0] = lo.x, n[1] = hi.x, n[2] = lo.y, n[3] = hi.y, n[4] = lo.z,
+//   n[5] = hi.z, n[6] = child references (int bits), n[7] = 0.
+// A reference >= 0 is an inner node, < 0 a leaf whose complement packs
+// (first_triangle << 3) | (count - 1).  Unused slots hold the box
+// (+inf, -inf), which no ray with finite components enters, and
+// kEmptySlotRef, a leaf inside every non-empty triangle array.
 constexpr int kLeafCountBits = 3;
 constexpr uint32_t kMaxLeafTris = 1u << kLeafCountBits;
-constexpr int32_t kEmptyRef = -1;  // ~0: a leaf with zero triangles is never built
+// Root of a scene without geometry: never decoded.  With fewer than 2^28
+// triangles no leaf has this reference (it would end past 2^28).
+constexpr int32_t kEmptyRef = INT32_MIN;
+constexpr int32_t kEmptySlotRef = -1;  // the leaf {triangle 0}
 
 // Unsigned division by a runtime constant for n < 2^31 (round-up method):
 // q = (umulhi(n, m) + n) >> s.
@@ -38,7 +41,7 @@ struct DevCamera {
 
 // Geometry of the scene at one instant, device pointers.
 struct DevInstant {
-    const float4 *nodes;     // 4 per inner node
+    const float4 *nodes;     // 8 per 4-wide inner node
     const float4 *tris;      // 3 per triangle in leaf order: (v0, prim bits), (v1, 0), (v2, 0)
     const float4 *prim;      // per primitive: (unit normal xyz, material bits)
     const float *emit_cdf;   // per emitter

@@ -95,6 +95,7 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter)
 struct BlockAppend {
     uint32_t wc[2][2][4];
     uint32_t base[2][2];
+    uint32_t bin[2][8];   // block_append_binned: per-bin counts, then slots
 };
 
 __device__ __forceinline__ void block_append2(BlockAppend &sm, uint32_t par, bool pa, bool pb, uint32_t *ca,
@@ -123,6 +124,41 @@ __device__ __forceinline__ void block_append2(BlockAppend &sm, uint32_t par, boo
     sb = ob + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
 }
 
+// As block_append2, but the block's entries of the second queue are laid
+// out grouped by a 3-bit key (the slot order within a group is arbitrary),
+// so that rays of one block with similar directions are traced by the same
+// waves.  Bins of parity par must be zero on entry: clear both parities
+// (followed by a barrier) before the first call; each call clears the other
+// parity's bins after every thread has finished the previous call.
+__device__ __forceinline__ void block_append_binned(BlockAppend &sm, uint32_t par, bool pa, bool pb, uint32_t key,
+                                                    uint32_t *ca, uint32_t *cb, uint32_t &sa, uint32_t &sb)
+{
+    const unsigned long long ma = __ballot(pa);
+    const uint32_t w = threadIdx.x >> 6;
+    if (__lane_id() == 0) sm.wc[par][0][w] = (uint32_t)__popcll(ma);
+    uint32_t rb = 0;
+    if (pb) rb = atomicAdd(&sm.bin[par][key & 7u], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t ta = (sm.wc[par][0][0] + sm.wc[par][0][1]) + (sm.wc[par][0][2] + sm.wc[par][0][3]);
+        sm.base[par][0] = ta ? atomicAdd(ca, ta) : 0u;
+        uint32_t tb = 0;
+        for (int b = 0; b < 8; ++b) tb += sm.bin[par][b];
+        uint32_t off = tb ? atomicAdd(cb, tb) : 0u;
+        for (int b = 0; b < 8; ++b) {
+            const uint32_t c = sm.bin[par][b];
+            sm.bin[par][b] = off;
+            off += c;
+        }
+        for (int b = 0; b < 8; ++b) sm.bin[par ^ 1u][b] = 0u;
+    }
+    __syncthreads();
+    uint32_t oa = sm.base[par][0];
+    for (uint32_t v = 0; v < w; ++v) oa += sm.wc[par][0][v];
+    sa = oa + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+    sb = pb ? sm.bin[par][key & 7u] + rb : 0u;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
 #pragma unroll
@@ -136,6 +172,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // second's: each XCD's L2 then caches one instant's geometry.
 struct Part {
     uint32_t base, n, lb, lgrid;
+    uint32_t r;  // region index
 };
 
 __device__ __forceinline__ Part partition(const uint32_t *cnt2, uint32_t region, uint32_t n_split)
@@ -151,6 +188,7 @@ __device__ __forceinline__ Part partition(const uint32_t *cnt2, uint32_t region,
         p.lb = blockIdx.x;
         p.lgrid = gridDim.x;
     }
+    p.r = r;
     p.base = r * region;
     p.n = cnt2[r];
     return p;
@@ -165,6 +203,7 @@ struct TRay {
     float okx, oky, okz;    // origin permuted into the watertight frame
     float Sx, Sy, Sz;       // shear constants
     uint32_t kperm;         // kx | ky << 2 | kz << 4
+    uint32_t onx, ony, onz; // byte offsets of the near-plane rows of a 4-wide node
 };
 
 __device__ __forceinline__ float safe_dir(float d)
@@ -185,6 +224,11 @@ __device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx
     r.nox = -(ox * r.ix);
     r.noy = -(oy * r.iy);
     r.noz = -(oz * r.iz);
+    // Near planes: lo rows for a positive direction component, hi rows for
+    // a negative one; the far row of an axis is the other row of its pair.
+    r.onx = r.ix < 0.0f ? 16u : 0u;
+    r.ony = r.iy < 0.0f ? 48u : 32u;
+    r.onz = r.iz < 0.0f ? 80u : 64u;
     const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
     int kz = 0;
     float m = ax;
@@ -233,34 +277,43 @@ __device__ __forceinline__ bool tri_test(const TRay &r, float4 v0, float4 v1, fl
     return true;
 }
 
-// Slab test of both children.  Boxes are padded on the host by more than
-// the rounding of the fused products, so no triangle the exact test hits
-// is culled.  Returns entry distances; a miss gives +inf.
-__device__ __forceinline__ void box2(const TRay &r, float4 n0, float4 n1, float4 n2, float tmin,
-                                     float tfar, float &tl, float &tr)
+// Slab test of the four child boxes of a 4-wide node against the segment
+// (tmin, tfar).  Boxes are padded on the host by more than the rounding of
+// the fused products, so no triangle the exact test hits is culled.  The
+// result per slot is a sort key: ~0u for a miss, else the bits of the entry
+// distance (>= tmin > 0, so unsigned order is distance order) with the slot
+// index in the two low bits.
+__device__ __forceinline__ uint32_t slot_key(float tn, float tf, uint32_t j)
 {
-    const float lx0 = __builtin_fmaf(n0.x, r.ix, r.nox), lx1 = __builtin_fmaf(n0.w, r.ix, r.nox);
-    const float ly0 = __builtin_fmaf(n0.y, r.iy, r.noy), ly1 = __builtin_fmaf(n1.x, r.iy, r.noy);
-    const float lz0 = __builtin_fmaf(n0.z, r.iz, r.noz), lz1 = __builtin_fmaf(n1.y, r.iz, r.noz);
-    const float rx0 = __builtin_fmaf(n1.z, r.ix, r.nox), rx1 = __builtin_fmaf(n2.y, r.ix, r.nox);
-    const float ry0 = __builtin_fmaf(n1.w, r.iy, r.noy), ry1 = __builtin_fmaf(n2.z, r.iy, r.noy);
-    const float rz0 = __builtin_fmaf(n2.x, r.iz, r.noz), rz1 = __builtin_fmaf(n2.w, r.iz, r.noz);
-    const float lnear = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fmaxf(fminf(lz0, lz1), tmin));
-    const float lfar = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fminf(fmaxf(lz0, lz1), tfar));
-    const float rnear = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fmaxf(fminf(rz0, rz1), tmin));
-    const float rfar = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fminf(fmaxf(rz0, rz1), tfar));
-    tl = lnear <= lfar ? lnear : INFINITY;
-    tr = rnear <= rfar ? rnear : INFINITY;
+    return tn <= tf ? ((__float_as_uint(tn) & ~3u) | j) : ~0u;
+}
+
+__device__ __forceinline__ void box4(const TRay &r, float4 nx, float4 fx, float4 ny, float4 fy, float4 nz,
+                                     float4 fz, float tmin, float tfar, uint32_t (&k)[4])
+{
+#define EVRT_SLOT(c, j)                                                                              \
+    {                                                                                                \
+        const float tn = fmaxf(fmaxf(fmaxf(__builtin_fmaf(nx.c, r.ix, r.nox), __builtin_fmaf(ny.c, r.iy, r.noy)), \
+                                     __builtin_fmaf(nz.c, r.iz, r.noz)), tmin);                      \
+        const float tf = fminf(fminf(fminf(__builtin_fmaf(fx.c, r.ix, r.nox), __builtin_fmaf(fy.c, r.iy, r.noy)), \
+                                     __builtin_fmaf(fz.c, r.iz, r.noz)), tfar);                      \
+        k[j] = slot_key(tn, tf, j);                                                                  \
+    }
+    EVRT_SLOT(x, 0)
+    EVRT_SLOT(y, 1)
+    EVRT_SLOT(z, 2)
+    EVRT_SLOT(w, 3)
+#undef EVRT_SLOT
 }
 
 // Traversal block shape: kTB threads, a top treelet of kLdsNodes nodes per
 // instant staged in LDS, and a per-lane stack whose first kStackLds entries
 // live in LDS (deeper entries spill to private memory).
 #ifndef EVRT_STACK_LDS
-#define EVRT_STACK_LDS 12
+#define EVRT_STACK_LDS 16
 #endif
 #ifndef EVRT_LDS_NODES
-#define EVRT_LDS_NODES 64
+#define EVRT_LDS_NODES 32
 #endif
 #ifndef EVRT_TRACE_WAVES
 #define EVRT_TRACE_WAVES 8
@@ -268,7 +321,9 @@ __device__ __forceinline__ void box2(const TRay &r, float4 n0, float4 n1, float4
 constexpr int kTB = 256;
 constexpr int kLdsNodes = EVRT_LDS_NODES;
 constexpr int kStackLds = EVRT_STACK_LDS;
-constexpr int kStackMax = 64;
+// A visit pushes at most three children, so a tree of D inner levels needs
+// at most 3 D entries; the builder's depth bound keeps D <= kStackMax / 3.
+constexpr int kStackMax = 96;
 
 
 // Per-lane traversal state: the ray, the open segment (tmin, tmax), the
@@ -280,12 +335,37 @@ struct Trav {
     uint32_t skip, best_p;
     int32_t ref;
     int sp;
-    uint32_t inst;
 };
 
-__device__ __forceinline__ void trav_begin(Trav &T, const DevScene &sc, uint32_t inst, float ox, float oy,
-                                           float oz, float dx, float dy, float dz, float tmin, float tmax,
-                                           uint32_t skip)
+// LDS-typed pointers keep LDS accesses as ds_read/ds_write (a generic
+// pointer that may also point elsewhere compiles to flat accesses).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) float lds_f32;
+
+// The geometry one traversal reads: the node and triangle arrays of an
+// instant, its root, and the first n_lds nodes staged in LDS at lds.  The
+// trace kernels take one instant per block, so that these are uniform.
+struct Geo {
+    const float4 *nodes;
+    const float4 *tris;
+    const lds_f32 *lds;
+    uint32_t n_lds;
+    int32_t root;
+};
+
+__device__ __forceinline__ Geo make_geo(const DevScene &sc, uint32_t inst, const lds_f32 *lds)
+{
+    Geo g;
+    g.nodes = inst ? sc.inst[1].nodes : sc.inst[0].nodes;
+    g.tris = inst ? sc.inst[1].tris : sc.inst[0].tris;
+    g.n_lds = inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
+    g.root = inst ? sc.inst[1].root : sc.inst[0].root;
+    g.lds = lds;
+    return g;
+}
+
+__device__ __forceinline__ void trav_begin(Trav &T, int32_t root, float ox, float oy, float oz, float dx,
+                                           float dy, float dz, float tmin, float tmax, uint32_t skip)
 {
     T.r = make_tray(ox, oy, oz, dx, dy, dz);
     T.tmin = tmin;
@@ -293,15 +373,9 @@ __device__ __forceinline__ void trav_begin(Trav &T, const DevScene &sc, uint32_t
     T.tfar = tmax;
     T.skip = skip;
     T.best_p = kNoPrim;
-    T.inst = inst;
-    T.ref = inst ? sc.inst[1].root : sc.inst[0].root;
+    T.ref = root;
     T.sp = 0;
 }
-
-// LDS-typed pointers keep LDS accesses as ds_read/ds_write (a generic
-// pointer that may also point elsewhere compiles to flat accesses).
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-typedef __attribute__((address_space(3))) float lds_f32;
 
 __device__ __forceinline__ float4 lds_load4(const lds_f32 *p)
 {
@@ -318,27 +392,59 @@ __device__ __forceinline__ int32_t stack_pop(int sp, const lds_u32 *lds_stack, c
     return v;
 }
 
-// Ordered descent through one inner node: test both child boxes, go to the
-// nearer hit child and push the farther one, or pop when neither is hit.
-// Returns false when the stack is empty (traversal complete).
-__device__ __forceinline__ bool visit_node(Trav &T, float4 n0, float4 n1, float4 n2, float4 n3,
-                                           lds_u32 *lds_stack, int32_t *spill)
+__device__ __forceinline__ void stack_push(int &sp, int32_t v, lds_u32 *lds_stack, int32_t *spill)
 {
-    float tl, tr;
-    box2(T.r, n0, n1, n2, T.tmin, T.tfar, tl, tr);
-    const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-    const bool hl = tl != INFINITY, hr = tr != INFINITY;
-    if (hl && hr) {
-        const bool lfirst = tl <= tr;
-        const int32_t far = lfirst ? cr : cl;
-        T.ref = lfirst ? cl : cr;
-        if (T.sp < kStackLds) lds_stack[T.sp * kTB] = (uint32_t)far;
-        else spill[T.sp - kStackLds] = far;
-        ++T.sp;
-        return true;
+    if (sp < kStackLds) lds_stack[sp * kTB] = (uint32_t)v;
+    else spill[sp - kStackLds] = v;
+    ++sp;
+}
+
+// Ordered descent through one 4-wide node given its near/far plane rows and
+// child references: go to the nearest hit child and push the other hit
+// children farthest first, or pop when none is hit.  Returns false when the
+// stack is empty (traversal complete).
+__device__ __forceinline__ bool visit_node(Trav &T, float4 nx, float4 fx, float4 ny, float4 fy, float4 nz,
+                                           float4 fz, float4 refs, lds_u32 *lds_stack, int32_t *spill)
+{
+    uint32_t k[4];
+    box4(T.r, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
+    int32_t c[4] = {__float_as_int(refs.x), __float_as_int(refs.y), __float_as_int(refs.z), __float_as_int(refs.w)};
+    // Sorting network on (key, reference) pairs; misses sort last.
+#define EVRT_CSWAP(a, b)                                   \
+    {                                                      \
+        const bool sw = k[b] < k[a];                       \
+        const uint32_t ka = sw ? k[b] : k[a];              \
+        const uint32_t kb = sw ? k[a] : k[b];              \
+        const int32_t ca = sw ? c[b] : c[a];               \
+        const int32_t cb = sw ? c[a] : c[b];               \
+        k[a] = ka;                                         \
+        k[b] = kb;                                         \
+        c[a] = ca;                                         \
+        c[b] = cb;                                         \
     }
-    if (hl || hr) {
-        T.ref = hl ? cl : cr;
+    EVRT_CSWAP(0, 1)
+    EVRT_CSWAP(2, 3)
+    EVRT_CSWAP(0, 2)
+    EVRT_CSWAP(1, 3)
+    EVRT_CSWAP(1, 2)
+#undef EVRT_CSWAP
+    if (k[0] != ~0u) {
+        T.ref = c[0];
+        if (T.sp + 3 <= kStackLds) {
+            // Hits are sorted first: write all three candidates, advancing
+            // only past hits (a miss is overwritten by the next write or
+            // left above the stack top).
+            lds_stack[T.sp * kTB] = (uint32_t)c[3];
+            T.sp += k[3] != ~0u;
+            lds_stack[T.sp * kTB] = (uint32_t)c[2];
+            T.sp += k[2] != ~0u;
+            lds_stack[T.sp * kTB] = (uint32_t)c[1];
+            T.sp += k[1] != ~0u;
+        } else {
+            if (k[3] != ~0u) stack_push(T.sp, c[3], lds_stack, spill);
+            if (k[2] != ~0u) stack_push(T.sp, c[2], lds_stack, spill);
+            if (k[1] != ~0u) stack_push(T.sp, c[1], lds_stack, spill);
+        }
         return true;
     }
     if (T.sp == 0) return false;
@@ -347,34 +453,43 @@ __device__ __forceinline__ bool visit_node(Trav &T, float4 n0, float4 n1, float4
     return true;
 }
 
+// Row of a node array at a 32-bit byte offset (a uniform base plus one
+// 32-bit offset register per load).
+__device__ __forceinline__ float4 row_at(const float4 *base, uint32_t off)
+{
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
+}
+
 // One outer iteration of the while-while traversal: inner nodes of the LDS
 // treelet, inner nodes in global memory, then one leaf.  ANY stops at the
 // first accepted hit.  Returns false when the ray is finished; the result is
 // T.tfar / T.best_p.
-// LDS: the instants' top treelets are staged in LDS (else every node is
-// read from global memory and the treelet loop is compiled out).
+// LDS: the top treelet is staged in LDS (else every node is read from
+// global memory and the treelet loop is compiled out).
 template <bool ANY, bool COUNT, bool LDS = true>
-__device__ __forceinline__ bool traverse_step(Trav &T, const DevScene &sc, const lds_f32 *s_nodes,
-                                              lds_u32 *lds_stack, int32_t *spill, uint32_t &visits,
-                                              uint32_t &tests)
+__device__ __forceinline__ bool traverse_step(Trav &T, const Geo &g, lds_u32 *lds_stack, int32_t *spill,
+                                              uint32_t &visits, uint32_t &tests)
 {
-    const uint32_t n_lds = LDS ? (T.inst ? sc.inst[1].n_lds : sc.inst[0].n_lds) : 0u;
-    const float4 *nodes = T.inst ? sc.inst[1].nodes : sc.inst[0].nodes;
-    const float4 *tris = T.inst ? sc.inst[1].tris : sc.inst[0].tris;
+    const uint32_t n_lds = LDS ? g.n_lds : 0u;
     bool live = true;
     if (LDS) {
-        const lds_f32 *lds = s_nodes + T.inst * 16 * kLdsNodes;
         while (live && T.ref >= 0 && (uint32_t)T.ref < n_lds) {
-            const lds_f32 *p = lds + 16 * T.ref;
+            const lds_f32 *p = g.lds + 32 * T.ref;
             if (COUNT) ++visits;
-            live = visit_node(T, lds_load4(p), lds_load4(p + 4), lds_load4(p + 8), lds_load4(p + 12), lds_stack,
-                              spill);
+            live = visit_node(T, lds_load4(p + T.r.onx / 4), lds_load4(p + (T.r.onx ^ 16u) / 4),
+                              lds_load4(p + T.r.ony / 4), lds_load4(p + (T.r.ony ^ 16u) / 4),
+                              lds_load4(p + T.r.onz / 4), lds_load4(p + (T.r.onz ^ 16u) / 4), lds_load4(p + 24),
+                              lds_stack, spill);
         }
     }
     while (live && T.ref >= 0 && (!LDS || (uint32_t)T.ref >= n_lds)) {
-        const float4 *p = nodes + 4 * (size_t)T.ref;
+        // 32-bit byte offsets: the host keeps node arrays below 4 GiB.
+        const uint32_t b = (uint32_t)T.ref << 7;
         if (COUNT) ++visits;
-        live = visit_node(T, p[0], p[1], p[2], p[3], lds_stack, spill);
+        live = visit_node(T, row_at(g.nodes, b + T.r.onx), row_at(g.nodes, b + (T.r.onx ^ 16u)),
+                          row_at(g.nodes, b + T.r.ony), row_at(g.nodes, b + (T.r.ony ^ 16u)),
+                          row_at(g.nodes, b + T.r.onz), row_at(g.nodes, b + (T.r.onz ^ 16u)), row_at(g.nodes, b + 96u),
+                          lds_stack, spill);
     }
     if (!live) return false;
     // A pop in the global loop can return a treelet node: not a leaf yet.
@@ -383,7 +498,7 @@ __device__ __forceinline__ bool traverse_step(Trav &T, const DevScene &sc, const
     const uint32_t first = packed >> kLeafCountBits;
     const uint32_t count = (packed & (kMaxLeafTris - 1)) + 1;
     for (uint32_t k = 0; k < count; ++k) {
-        const float4 *tp = tris + 3 * (size_t)(first + k);
+        const float4 *tp = g.tris + 3 * (size_t)(first + k);
         const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
         const uint32_t prim = fbits(v0.w);
         if (COUNT) tests += prim != T.skip;
@@ -410,12 +525,12 @@ __device__ __forceinline__ bool traverse_step(Trav &T, const DevScene &sc, const
 
 // Full traversal of one ray.
 template <bool ANY, bool COUNT>
-__device__ __forceinline__ void traverse(Trav &T, const DevScene &sc, const lds_f32 *s_nodes,
-                                         lds_u32 *lds_stack, uint32_t &visits, uint32_t &tests)
+__device__ __forceinline__ void traverse(Trav &T, const Geo &g, lds_u32 *lds_stack, uint32_t &visits,
+                                         uint32_t &tests)
 {
     if (T.ref == kEmptyRef) return;
     int32_t spill[kStackMax - kStackLds];
-    while (traverse_step<ANY, COUNT>(T, sc, s_nodes, lds_stack, spill, visits, tests)) {
+    while (traverse_step<ANY, COUNT>(T, g, lds_stack, spill, visits, tests)) {
     }
 }
 
@@ -463,12 +578,14 @@ __device__ __forceinline__ uint32_t wave_refill(WaveRange &wr, bool busy)
     return (!busy && j < wr.n) ? j : ~0u;
 }
 
-__device__ __forceinline__ void load_treelets(const DevScene &sc, float4 *s_nodes)
+// Stages the treelets of instants [i0, i1) at s_nodes + (inst - i0) slots
+// of kLdsNodes nodes; all threads of the block call it.
+__device__ __forceinline__ void load_treelets(const DevScene &sc, uint32_t i0, uint32_t i1, float4 *s_nodes)
 {
-    for (int inst = 0; inst < 2; ++inst) {
+    for (uint32_t inst = i0; inst < i1; ++inst) {
         const uint32_t n = inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
         const float4 *src = inst ? sc.inst[1].nodes : sc.inst[0].nodes;
-        for (uint32_t i = threadIdx.x; i < 4 * n; i += kTB) s_nodes[inst * 4 * kLdsNodes + i] = src[i];
+        for (uint32_t i = threadIdx.x; i < 8 * n; i += kTB) s_nodes[(inst - i0) * 8 * kLdsNodes + i] = src[i];
     }
     __syncthreads();
 }
@@ -543,15 +660,18 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
 
 // Closest hit of the queued rays; hit[i] = (t, prim bits), prim = kNoPrim on
 // a miss.  Grid-stride over the device-side queue count, one ray per lane.
+// Region r of the queue holds rays of instant inst_base + r only.
 template <bool COUNT, bool LDS>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_closest(DevScene sc, RayQueue q, const uint32_t *cnt_in,
-                                                       uint32_t region, uint32_t n_split, float2 *hit,
-                                                       int stat_kind, unsigned long long *stat)
+                                                       uint32_t region, uint32_t n_split, uint32_t inst_base,
+                                                       float2 *hit, int stat_kind, unsigned long long *stat)
 {
-    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
-    if (LDS) load_treelets(sc, s_nodes);
     const Part pt = partition(cnt_in, region, n_split);
+    const uint32_t inst = inst_base + pt.r;
+    if (LDS) load_treelets(sc, inst, inst + 1, s_nodes);
+    const Geo g = make_geo(sc, inst, (const lds_f32 *)s_nodes);
     if (pt.lb == 0 && threadIdx.x == 0 && pt.n) atomicAdd(stat + stat_kind, (unsigned long long)pt.n);
     uint32_t visits = 0, tests = 0;
     int32_t spill[kStackMax - kStackLds];
@@ -565,8 +685,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
         if (j != ~0u) {
             cur = pt.base + j;
             const float4 o = q.o[cur], d = q.d[cur];
-            const uint32_t inst = fbits(d.w) >> 31;
-            trav_begin(T, sc, inst, o.x, o.y, o.z, d.x, d.y, d.z, kRayTmin, INFINITY, q.skip[cur]);
+            trav_begin(T, g.root, o.x, o.y, o.z, d.x, d.y, d.z, kRayTmin, INFINITY, q.skip[cur]);
             busy = T.ref != kEmptyRef;
             if (!busy) hit[cur] = make_float2(T.tfar, bitsf(T.best_p));
         }
@@ -574,7 +693,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             if (wr.done()) break;
             continue;
         }
-        if (busy && !traverse_step<false, COUNT, LDS>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
+        if (busy && !traverse_step<false, COUNT, LDS>(T, g, lds_stack, spill, visits, tests)) {
             busy = false;
             hit[cur] = make_float2(T.tfar, bitsf(T.best_p));
         }
@@ -594,13 +713,15 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
 template <bool COUNT, bool LDS>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
                                                       const uint32_t *cnt_in, uint32_t region,
-                                                      uint32_t n_split, float *rad,
+                                                      uint32_t n_split, uint32_t inst_base, float *rad,
                                                       unsigned long long *stat)
 {
-    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
-    if (LDS) load_treelets(sc, s_nodes);
     const Part pt = partition(cnt_in, region, n_split);
+    const uint32_t inst = inst_base + pt.r;
+    if (LDS) load_treelets(sc, inst, inst + 1, s_nodes);
+    const Geo g = make_geo(sc, inst, (const lds_f32 *)s_nodes);
     uint32_t visits = 0, tests = 0, rays = 0;
     int32_t spill[kStackMax - kStackLds];
     lds_u32 *lds_stack = (lds_u32 *)s_stack + threadIdx.x;
@@ -632,7 +753,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
                 const float4 o = sq.o[e];
                 const float4 w = sq.dir[slot * sq.cap + e];
                 const uint32_t meta = sq.meta[e];
-                trav_begin(T, sc, meta >> 31, o.x, o.y, o.z, w.x, w.y, w.z, kRayTmin, w.w, meta & ~kInstBit);
+                trav_begin(T, g.root, o.x, o.y, o.z, w.x, w.y, w.z, kRayTmin, w.w, meta & ~kInstBit);
                 ++rays;
                 tracing = T.ref != kEmptyRef;
                 if (!tracing) {
@@ -647,7 +768,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             if (wr.done()) break;
             continue;
         }
-        if (tracing && !traverse_step<true, COUNT, LDS>(T, sc, (const lds_f32 *)s_nodes, lds_stack, spill, visits, tests)) {
+        if (tracing && !traverse_step<true, COUNT, LDS>(T, g, lds_stack, spill, visits, tests)) {
             tracing = false;
             if (T.best_p == kNoPrim) sum = sum + c;
             ++slot;
@@ -699,6 +820,8 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
     const Part pt = partition(cnt_in, pc.region, pc.n_inst);
     __shared__ BlockAppend s_app;
     uint32_t par = 0;
+    if (threadIdx.x < 16) s_app.bin[threadIdx.x >> 3][threadIdx.x & 7] = 0u;
+    __syncthreads();
     // Block-uniform trip count: the appends synchronize the block.
     for (uint32_t j0 = pt.lb * blockDim.x; j0 < pt.n; j0 += pt.lgrid * blockDim.x, par ^= 1u) {
         const uint32_t j = j0 + threadIdx.x;
@@ -813,7 +936,9 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
         }
         const uint32_t r = pt.base / max(pc.region, 1u);
         uint32_t se, xe;
-        block_append2(s_app, par, want_shadow, want_ext, cnt_sh + r, cnt_out + r, se, xe);
+        // Extension rays are grouped by direction octant within the block.
+        const uint32_t oct = (ndx < 0.0f ? 1u : 0u) | (ndy < 0.0f ? 2u : 0u) | (ndz < 0.0f ? 4u : 0u);
+        block_append_binned(s_app, par, want_shadow, want_ext, oct, cnt_sh + r, cnt_out + r, se, xe);
         se += pt.base;
         xe += pt.base;
         if (want_shadow) {
@@ -1223,15 +1348,16 @@ template <bool ANY>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_hook_trace(DevScene sc, RayQueue q, const float *tminmax,
                                                     uint32_t n, float *t_out, uint32_t *p_out)
 {
-    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
-    load_treelets(sc, s_nodes);
+    load_treelets(sc, 0, 1, s_nodes);
+    const Geo g = make_geo(sc, 0, (const lds_f32 *)s_nodes);
     uint32_t visits = 0, tests = 0;
     for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
         const float4 o = q.o[i], d = q.d[i];
         Trav T;
-        trav_begin(T, sc, 0, o.x, o.y, o.z, d.x, d.y, d.z, tminmax[2 * i], tminmax[2 * i + 1], q.skip[i]);
-        traverse<ANY, false>(T, sc, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
+        trav_begin(T, g.root, o.x, o.y, o.z, d.x, d.y, d.z, tminmax[2 * i], tminmax[2 * i + 1], q.skip[i]);
+        traverse<ANY, false>(T, g, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
         if (ANY) {
             p_out[i] = T.best_p != kNoPrim ? 1u : 0u;
         } else {
@@ -1352,6 +1478,7 @@ __device__ float replay_path(const DevScene &sc, const RenderParams &rp, const l
 {
     const DevInstant &I = inst ? sc.inst[1] : sc.inst[0];
     const DevCamera &cam = I.cam;
+    const Geo g = make_geo(sc, inst, s_nodes + inst * 32 * kLdsNodes);
     const uint32_t py = fdiv(sc.div_w, pixel);
     const uint32_t px = pixel - py * sc.width;
     float j0 = 0.5f, j1 = 0.5f;
@@ -1377,8 +1504,8 @@ __device__ float replay_path(const DevScene &sc, const RenderParams &rp, const l
     uint32_t visits = 0, tests = 0;
     for (uint32_t depth = 1; depth <= rp.max_depth; ++depth) {
         Trav T;
-        trav_begin(T, sc, inst, ox, oy, oz, dx, dy, dz, kRayTmin, INFINITY, skip);
-        traverse<false, false>(T, sc, s_nodes, lds_stack, visits, tests);
+        trav_begin(T, g.root, ox, oy, oz, dx, dy, dz, kRayTmin, INFINITY, skip);
+        traverse<false, false>(T, g, lds_stack, visits, tests);
         const uint32_t prim = T.best_p;
         if (prim == kNoPrim) break;
         const float t = T.tfar;
@@ -1427,8 +1554,8 @@ __device__ float replay_path(const DevScene &sc, const RenderParams &rp, const l
                         const float c0 = ((((beta * fr) * cx) * cy) * I.emit_S) / r2;
                         if (c0 > 0.0f) {
                             Trav S;
-                            trav_begin(S, sc, inst, Px, Py, Pz, wix, wiy, wiz, kRayTmin, rl * kShadowScale, prim);
-                            traverse<true, false>(S, sc, s_nodes, lds_stack, visits, tests);
+                            trav_begin(S, g.root, Px, Py, Pz, wix, wiy, wiz, kRayTmin, rl * kShadowScale, prim);
+                            traverse<true, false>(S, g, lds_stack, visits, tests);
                             if (S.best_p == kNoPrim) {
                                 sum = sum + c0;
                                 const uint32_t emat = fbits(I.prim[fbits(en.w)].w);
@@ -1443,8 +1570,8 @@ __device__ float replay_path(const DevScene &sc, const RenderParams &rp, const l
                 const float ck = point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta, fr, dk);
                 if (!(ck > 0.0f)) continue;
                 Trav S;
-                trav_begin(S, sc, inst, Px, Py, Pz, dk.x, dk.y, dk.z, kRayTmin, dk.w, prim);
-                traverse<true, false>(S, sc, s_nodes, lds_stack, visits, tests);
+                trav_begin(S, g.root, Px, Py, Pz, dk.x, dk.y, dk.z, kRayTmin, dk.w, prim);
+                traverse<true, false>(S, g, lds_stack, visits, tests);
                 if (S.best_p == kNoPrim) sum = sum + ck;
             }
             L = L + sum;
@@ -1489,11 +1616,11 @@ __global__ __launch_bounds__(kTB) void k_adjoint(DevScene sc, RenderParams rp, u
                                                  const float *Lfwd, const double *W, uint32_t n_mat, double *g,
                                                  uint32_t *mismatch)
 {
-    __shared__ float4 s_nodes[2 * 4 * kLdsNodes];
+    __shared__ float4 s_nodes[2 * 8 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
     extern __shared__ double s_acc[];
     for (uint32_t k = threadIdx.x; k < 2 * n_mat; k += kTB) s_acc[k] = 0.0;
-    load_treelets(sc, s_nodes);
+    load_treelets(sc, 0, 2, s_nodes);
     const uint32_t mb = rp.minibatch, m = spp / mb;
     const uint64_t n = (uint64_t)npx * 2u * spp;
     uint32_t bad = 0;
@@ -1538,43 +1665,43 @@ void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const Ren
 
 void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                           const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
-                          float2 *hit, int stat_kind, unsigned long long *stat, hipEvent_t ev_start,
-                          hipEvent_t ev_stop)
+                          uint32_t inst_base, float2 *hit, int stat_kind, unsigned long long *stat,
+                          hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     // Start / stop events (when given) are written by the dispatch itself.
     const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
     if (count && lds)
         hipExtLaunchKernelGGL((k_trace_closest<true, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              q, cnt_in, region, n_split, hit, stat_kind, stat);
+                              q, cnt_in, region, n_split, inst_base, hit, stat_kind, stat);
     else if (count)
         hipExtLaunchKernelGGL((k_trace_closest<true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              q, cnt_in, region, n_split, hit, stat_kind, stat);
+                              q, cnt_in, region, n_split, inst_base, hit, stat_kind, stat);
     else if (lds)
         hipExtLaunchKernelGGL((k_trace_closest<false, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              q, cnt_in, region, n_split, hit, stat_kind, stat);
+                              q, cnt_in, region, n_split, inst_base, hit, stat_kind, stat);
     else
         hipExtLaunchKernelGGL((k_trace_closest<false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0,
-                              sc, q, cnt_in, region, n_split, hit, stat_kind, stat);
+                              sc, q, cnt_in, region, n_split, inst_base, hit, stat_kind, stat);
 }
 
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
-                         uint32_t n_split, float *rad, unsigned long long *stat, hipEvent_t ev_start,
-                         hipEvent_t ev_stop)
+                         uint32_t n_split, uint32_t inst_base, float *rad, unsigned long long *stat,
+                         hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
     if (count && lds)
         hipExtLaunchKernelGGL((k_trace_shadow<true, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              sq, n_slots, cnt_in, region, n_split, rad, stat);
+                              sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
     else if (count)
         hipExtLaunchKernelGGL((k_trace_shadow<true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              sq, n_slots, cnt_in, region, n_split, rad, stat);
+                              sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
     else if (lds)
         hipExtLaunchKernelGGL((k_trace_shadow<false, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              sq, n_slots, cnt_in, region, n_split, rad, stat);
+                              sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
     else
         hipExtLaunchKernelGGL((k_trace_shadow<false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0,
-                              sc, sq, n_slots, cnt_in, region, n_split, rad, stat);
+                              sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
 }
 
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
@@ -1727,6 +1854,6 @@ void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu)
 
 int traverse_block_threads() { return kTB; }
 int lds_treelet_nodes() { return kLdsNodes; }
-int traverse_max_depth() { return kStackMax; }
+int traverse_max_depth() { return kStackMax / 3; }
 
 }  // namespace evrt

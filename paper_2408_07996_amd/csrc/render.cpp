@@ -52,6 +52,9 @@ std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s
     build_world(c->scene, t, h);
     const float pad = bvh_padding(c->scene, h, h);
     build_bvh(h, (uint32_t)lds_treelet_nodes(), pad);
+    if (h.depth > (uint32_t)traverse_max_depth()) fail(EVRT_E_UNSUPPORTED, "BVH deeper than the traversal stack");
+    // Traversal addresses nodes by 32-bit byte offsets (128 bytes a node).
+    if (h.nodes.size() / 8 >= (1u << 25)) fail(EVRT_E_UNSUPPORTED, "more than 2^25 BVH nodes");
     bi->nodes.upload(h.nodes.data(), h.nodes.size() * sizeof(float4), s);
     bi->tris.upload(h.tris.data(), h.tris.size() * sizeof(float4), s);
     bi->prim.upload(h.prim.data(), h.prim.size() * sizeof(float4), s);
@@ -76,7 +79,7 @@ std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s
     v.emit_cdf = bi->emit_cdf.as<const float>();
     v.emit = bi->emit.as<const float4>();
     v.root = h.root;
-    v.n_nodes = (uint32_t)(h.nodes.size() / 4);
+    v.n_nodes = (uint32_t)(h.nodes.size() / 8);
     v.n_lds = h.n_lds;
     v.n_emit = (uint32_t)h.emit_prim.size();
     v.emit_S = h.emit_S;
@@ -223,14 +226,15 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
         const RayQueue &qout = q[d & 1];
         const EventPair ec = prof.take(0);
         launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + 2 * (d - 1), pc.region, pc.n_inst,
-                             L.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat, ec.a, ec.b);
+                             pc.inst_base, L.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat, ec.a,
+                             ec.b);
         c->stats.n_closest_launches++;
         launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), L.hit.as<float2>(), qout,
                      cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d);
         if (rp.nee) {
             const EventPair es = prof.take(1);
             launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
-                                pc.n_inst, pc.rad, stat, es.a, es.b);
+                                pc.n_inst, pc.inst_base, pc.rad, stat, es.a, es.b);
             c->stats.n_shadow_launches++;
         }
     }

@@ -1,7 +1,8 @@
 // scene.cpp -- host construction of the scene at an instant: FP64
 // keyframe interpolation of instances and camera, FP32 world triangles,
 // per-primitive normals, the emitter table for next-event estimation, and
-// a binned-SAH BVH2 whose top treelet is laid out first for LDS staging.
+// a binned-SAH binary BVH collapsed into a 4-wide BVH whose top treelet is
+// laid out first for LDS staging.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -169,7 +170,7 @@ float bvh_padding(const SceneDesc &sd, const HostInstant &a, const HostInstant &
 }
 
 // ---------------------------------------------------------------------------
-// Binned SAH BVH2.
+// Binned SAH binary BVH, collapsed into a 4-wide BVH.
 
 namespace {
 
@@ -210,7 +211,6 @@ struct Builder {
     std::vector<float> cen;  // [n][3]
     std::vector<uint32_t> ref;
     std::vector<BNode> nodes;
-    uint32_t max_depth_seen = 0;
 
     explicit Builder(const std::vector<float> &t) : tri(t) {}
 
@@ -223,7 +223,6 @@ struct Builder {
 
     int32_t build(uint32_t b, uint32_t e, uint32_t depth)
     {
-        max_depth_seen = std::max(max_depth_seen, depth);
         const int32_t id = (int32_t)nodes.size();
         nodes.emplace_back();
         Box bb, cb;
@@ -359,7 +358,6 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
     }
     B.nodes.reserve(2 * (size_t)nt / Builder::kLeafTarget + 16);
     const int32_t broot = B.build(0, nt, 0);
-    h.depth = B.max_depth_seen;
 
     // Triangles in leaf order.
     h.tris.resize(3 * (size_t)nt);
@@ -374,66 +372,103 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
     auto leaf_ref = [&](const BNode &n) -> int32_t {
         return (int32_t) ~((n.first << kLeafCountBits) | (n.count - 1));
     };
+    // SAH cost of the binary tree (a build-quality statistic).
+    double cost = 0.0;
+    const double root_area = B.nodes[broot].box.area();
+    for (const BNode &n : B.nodes) cost += n.box.area() / root_area * (n.count ? (double)n.count : 1.0);
+    h.sah_cost = cost;
     if (B.nodes[broot].count > 0) {
         h.root = leaf_ref(B.nodes[broot]);
         return;
     }
-    // Inner nodes: breadth-first for the first n_lds_max (the LDS treelet),
+    // 4-wide tree: the children of a wide node are the grandchildren of a
+    // binary inner node (a binary child that is a leaf stays itself), so
+    // every wide level consumes two binary levels and the wide depth is at
+    // most half the binary depth, rounded up.
+    auto wide_children = [&](int32_t b, int32_t out[4]) -> int {
+        int k = 0;
+        for (int c = 0; c < 2; ++c) {
+            const int32_t ch = B.nodes[b].child[c];
+            if (B.nodes[ch].count) {
+                out[k++] = ch;
+            } else {
+                out[k++] = B.nodes[ch].child[0];
+                out[k++] = B.nodes[ch].child[1];
+            }
+        }
+        return k;
+    };
+    // Wide nodes: breadth-first for the first n_lds_max (the LDS treelet),
     // then each remaining subtree depth-first.
     std::vector<int32_t> order;
     std::vector<int32_t> newid(B.nodes.size(), -1);
+    std::vector<uint32_t> wdepth(B.nodes.size(), 0);
     std::vector<int32_t> queue{broot};
+    wdepth[broot] = 1;
     size_t qh = 0;
+    int32_t ch[4];
     while (qh < queue.size() && order.size() < n_lds_max) {
         const int32_t b = queue[qh++];
         newid[b] = (int32_t)order.size();
         order.push_back(b);
-        for (int k = 0; k < 2; ++k) {
-            const int32_t c = B.nodes[b].child[k];
-            if (B.nodes[c].count == 0) queue.push_back(c);
-        }
+        const int k = wide_children(b, ch);
+        for (int i = 0; i < k; ++i)
+            if (B.nodes[ch[i]].count == 0) {
+                wdepth[ch[i]] = wdepth[b] + 1;
+                queue.push_back(ch[i]);
+            }
     }
     h.n_lds = (uint32_t)order.size();
     std::vector<int32_t> stack;
-    for (size_t k = qh; k < queue.size(); ++k) {
-        stack.push_back(queue[k]);
+    for (size_t q = qh; q < queue.size(); ++q) {
+        stack.push_back(queue[q]);
         while (!stack.empty()) {
             const int32_t b = stack.back();
             stack.pop_back();
             newid[b] = (int32_t)order.size();
             order.push_back(b);
-            for (int c = 1; c >= 0; --c) {
-                const int32_t ch = B.nodes[b].child[c];
-                if (B.nodes[ch].count == 0) stack.push_back(ch);
+            const int k = wide_children(b, ch);
+            for (int i = k - 1; i >= 0; --i)
+                if (B.nodes[ch[i]].count == 0) {
+                    wdepth[ch[i]] = wdepth[b] + 1;
+                    stack.push_back(ch[i]);
+                }
+        }
+    }
+    h.nodes.assign(8 * order.size(), make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+    uint32_t depth = 0;
+    for (size_t i = 0; i < order.size(); ++i) {
+        depth = std::max(depth, wdepth[order[i]]);
+        const int k = wide_children(order[i], ch);
+        float lo[3][4], hi[3][4];
+        uint32_t ref[4];
+        for (int j = 0; j < 4; ++j) {
+            if (j < k) {
+                const BNode &n = B.nodes[ch[j]];
+                for (int c = 0; c < 3; ++c) {
+                    lo[c][j] = pad_down(n.box.lo[c], pad);
+                    hi[c][j] = pad_up(n.box.hi[c], pad);
+                }
+                ref[j] = (uint32_t)(n.count ? leaf_ref(n) : newid[ch[j]]);
+            } else {
+                // Empty slot: its near plane is at +inf and its far plane
+                // at -inf for either sign of the ray direction.
+                for (int c = 0; c < 3; ++c) {
+                    lo[c][j] = INFINITY;
+                    hi[c][j] = -INFINITY;
+                }
+                ref[j] = (uint32_t)kEmptySlotRef;
             }
         }
-    }
-    h.nodes.resize(4 * order.size());
-    double cost = 0.0;
-    const double root_area = B.nodes[broot].box.area();
-    for (size_t i = 0; i < order.size(); ++i) {
-        const BNode &n = B.nodes[order[i]];
-        const BNode &L = B.nodes[n.child[0]];
-        const BNode &R = B.nodes[n.child[1]];
-        float l[6], r[6];
+        float4 *o = &h.nodes[8 * i];
         for (int c = 0; c < 3; ++c) {
-            l[c] = pad_down(L.box.lo[c], pad);
-            l[3 + c] = pad_up(L.box.hi[c], pad);
-            r[c] = pad_down(R.box.lo[c], pad);
-            r[3 + c] = pad_up(R.box.hi[c], pad);
+            o[2 * c] = make_float4(lo[c][0], lo[c][1], lo[c][2], lo[c][3]);
+            o[2 * c + 1] = make_float4(hi[c][0], hi[c][1], hi[c][2], hi[c][3]);
         }
-        const int32_t rl = L.count ? leaf_ref(L) : newid[n.child[0]];
-        const int32_t rr = R.count ? leaf_ref(R) : newid[n.child[1]];
-        h.nodes[4 * i + 0] = make_float4(l[0], l[1], l[2], l[3]);
-        h.nodes[4 * i + 1] = make_float4(l[4], l[5], r[0], r[1]);
-        h.nodes[4 * i + 2] = make_float4(r[2], r[3], r[4], r[5]);
-        h.nodes[4 * i + 3] = make_float4(u2f((uint32_t)rl), u2f((uint32_t)rr), 0.0f, 0.0f);
-        cost += n.box.area() / root_area;
-        if (L.count) cost += L.box.area() / root_area * L.count;
-        if (R.count) cost += R.box.area() / root_area * R.count;
+        o[6] = make_float4(u2f(ref[0]), u2f(ref[1]), u2f(ref[2]), u2f(ref[3]));
     }
     h.root = 0;
-    h.sah_cost = cost;
+    h.depth = depth;
 }
 
 std::string check_bvh(const HostInstant &h, float pad)
@@ -441,22 +476,21 @@ std::string check_bvh(const HostInstant &h, float pad)
     const uint32_t nt = (uint32_t)(h.tri.size() / 9);
     if (nt == 0) return h.root == kEmptyRef ? "" : "empty scene with a root";
     std::vector<uint32_t> seen(nt, 0);
-    const uint32_t n_nodes = (uint32_t)(h.nodes.size() / 4);
+    const uint32_t n_nodes = (uint32_t)(h.nodes.size() / 8);
     std::vector<uint32_t> visited(n_nodes, 0);
-    // (ref, box lo/hi that must contain it)
+    // (ref, intersection of the padded boxes of all its ancestors' slots,
+    // wide depth of the node that holds it)
     struct Item {
         int32_t ref;
         float lo[3], hi[3];
         uint32_t depth;
     };
     std::vector<Item> st;
-    Item root{h.root, {-INFINITY, -INFINITY, -INFINITY}, {INFINITY, INFINITY, INFINITY}, 1};
-    st.push_back(root);
+    st.push_back(Item{h.root, {-INFINITY, -INFINITY, -INFINITY}, {INFINITY, INFINITY, INFINITY}, 0});
     uint32_t max_depth = 0;
     while (!st.empty()) {
-        Item it = st.back();
+        const Item it = st.back();
         st.pop_back();
-        max_depth = std::max(max_depth, it.depth);
         if (it.ref < 0) {
             const uint32_t packed = ~(uint32_t)it.ref;
             const uint32_t first = packed >> kLeafCountBits, count = (packed & (kMaxLeafTris - 1)) + 1;
@@ -473,26 +507,46 @@ std::string check_bvh(const HostInstant &h, float pad)
                     for (int c = 0; c < 3; ++c) {
                         const float x = v[3 * j + c];
                         if (!((double)x - it.lo[c] >= (double)pad * 0.5 && (double)it.hi[c] - x >= (double)pad * 0.5))
-                            return "triangle not inside its padded leaf box";
+                            return "triangle not inside the padded boxes of its ancestors";
                     }
             }
             continue;
         }
         if ((uint32_t)it.ref >= n_nodes) return "node index out of bounds";
         if (visited[it.ref]++) return "node reached twice";
-        const float4 *n = &h.nodes[4 * (size_t)it.ref];
-        const float l[6] = {n[0].x, n[0].y, n[0].z, n[0].w, n[1].x, n[1].y};
-        const float r[6] = {n[1].z, n[1].w, n[2].x, n[2].y, n[2].z, n[2].w};
-        Item a{(int32_t)f2u(n[3].x), {l[0], l[1], l[2]}, {l[3], l[4], l[5]}, it.depth + 1};
-        Item b{(int32_t)f2u(n[3].y), {r[0], r[1], r[2]}, {r[3], r[4], r[5]}, it.depth + 1};
-        st.push_back(a);
-        st.push_back(b);
+        const uint32_t depth = it.depth + 1;
+        max_depth = std::max(max_depth, depth);
+        const float4 *n = &h.nodes[8 * (size_t)it.ref];
+        const float *lo[3] = {&n[0].x, &n[2].x, &n[4].x};
+        const float *hi[3] = {&n[1].x, &n[3].x, &n[5].x};
+        const float *rf = &n[6].x;
+        int used = 0;
+        for (int j = 0; j < 4; ++j) {
+            const bool empty = lo[0][j] == INFINITY;
+            if (empty) {
+                for (int c = 0; c < 3; ++c)
+                    if (lo[c][j] != INFINITY || hi[c][j] != -INFINITY) return "empty slot with a box";
+                if ((int32_t)f2u(rf[j]) != kEmptySlotRef) return "empty slot with a child";
+                continue;
+            }
+            ++used;
+            Item ci{(int32_t)f2u(rf[j]), {0, 0, 0}, {0, 0, 0}, depth};
+            for (int c = 0; c < 3; ++c) {
+                if (!(lo[c][j] <= hi[c][j])) return "inverted child box";
+                ci.lo[c] = std::max(it.lo[c], lo[c][j]);
+                ci.hi[c] = std::min(it.hi[c], hi[c][j]);
+            }
+            st.push_back(ci);
+        }
+        if (used < 2) return "inner node with fewer than two children";
+        if (n[7].x != 0.0f || n[7].y != 0.0f || n[7].z != 0.0f || n[7].w != 0.0f) return "padding row not zero";
     }
     for (uint32_t p = 0; p < nt; ++p)
         if (seen[p] != 1) return "primitive missing or duplicated";
     for (uint32_t i = 0; i < n_nodes; ++i)
         if (!visited[i]) return "unreachable node";
-    if (max_depth >= (uint32_t)traverse_max_depth()) return "tree deeper than the traversal stack";
+    if (max_depth != h.depth) return "recorded depth differs from the tree";
+    if (max_depth > (uint32_t)traverse_max_depth()) return "tree deeper than the traversal stack";
     return "";
 }
 

@@ -480,6 +480,19 @@ def plane_point_light(albedo: float = 0.7, intensity: float = 5.0, h: float = 1.
     return b.build()
 
 
+def single_triangle(albedo: float = 0.6, intensity: float = 4.0, width: int = 12,
+                    height: int = 10) -> Scene:
+    """One triangle in the plane y = 0 (the whole scene is a single leaf)
+    under a point light at (0.2, 1.2, 0.1); the camera at (0, 2, 2.5)."""
+    b = SceneBuilder()
+    m = b.material(albedo)
+    tri = np.array([[-1.5, 0.0, -1.0], [0.0, 0.0, 1.5], [1.5, 0.0, -1.0]], dtype=np.float32)
+    b.static(b.mesh(tri, np.array([[0, 1, 2]]), m))
+    b.point_light((0.2, 1.2, 0.1), intensity)
+    b.set_camera(width, height, 60.0, [0.0], [[0.0, 2.0, 2.5, 0, 0, 0, 0, 1, 0]])
+    return b.build()
+
+
 def plane_area_light(albedo: float = 0.6, emission: float = 4.0, width: int = 8,
                      height: int = 8) -> Scene:
     """Plane y = 0 under one triangular emitter at y = 1 facing down."""

@@ -211,7 +211,7 @@ def test_tiny_frame_parity(rend, torch_cuda, variant):
     elif variant == "mb8":
         params.update(minibatch=8, spp_init=16, spp_batch=24, spp_max=256)
     elif variant == "lds_treelet":
-        params["lds_nodes"] = 64
+        params["lds_nodes"] = 32
     elif variant == "small_pieces":
         params["ray_batch"] = 40000   # many pieces per round
     elif variant == "split_samples":
@@ -229,7 +229,7 @@ def test_tiny_frame_invariants_and_determinism(rend, torch_cuda):
     rend.set_scene(sc)
     P = scenes.TINY_PARAMS
     a, st = _frame(rend, sc, P, 0.0, 1.0)
-    b, _ = _frame(rend, sc, P, 0.0, 1.0, ray_batch=1 << 15, lds_nodes=64)
+    b, _ = _frame(rend, sc, P, 0.0, 1.0, ray_batch=1 << 15, lds_nodes=32)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
     n = a["n_paths"]
@@ -261,6 +261,7 @@ def test_edge_cases(rend, torch_cuda):
         ("empty", scenes.empty(9, 7), P),
         ("depth1", scenes.tiny_box(width=20, height=20), {**P, "max_depth": 1}),
         ("static_pair", scenes.tiny_box(width=24, height=24), P),
+        ("one_triangle", scenes.single_triangle(), {**P, "jitter": 0}),
     ]
     for name, sc, params in cases:
         _say(f"edge case {name}")
