@@ -407,6 +407,11 @@ __device__ __forceinline__ bool visit_node(Trav &T, float4 nx, float4 fx, float4
                                            float4 fz, float4 refs, lds_u32 *lds_stack, int32_t *spill)
 {
     uint32_t k[4];
+    // An empty statement that takes the reference row as an input: the row
+    // is then loaded with the plane rows instead of being sunk into the hit
+    // branch, which would add a dependent memory round trip to most visits
+    // (134.6 vs 137.0 ms per sensor frame).
+    asm volatile("" ::"v"(refs.x), "v"(refs.y), "v"(refs.z), "v"(refs.w));
     box4(T.r, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
     int32_t c[4] = {__float_as_int(refs.x), __float_as_int(refs.y), __float_as_int(refs.z), __float_as_int(refs.w)};
     // Sorting network on (key, reference) pairs; misses sort last.
