@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "ce4a9e155fbc7db71f94b75d3f1d58fcf124966d81afab97b6d7aa63851bcd34",
-           "bytes_per_launch": 483329498.9,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6649, "valu_lane_utilization": 0.4805}, "k_trace_shadow": {"valu_busy": 0.6062, "valu_lane_utilization": 0.4629}, "k_shade": {"valu_busy": 0.3129, "valu_lane_utilization": 0.6361}}}
+TRAFFIC = {"sources_sha256": "4f984beba7f2cee4e8c57ade3da73c478672d5f17bcceeeed4ab4b7d2cb4e68e",
+           "bytes_per_launch": 492389630.3,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6986, "valu_lane_utilization": 0.5584}, "k_trace_shadow": {"valu_busy": 0.6134, "valu_lane_utilization": 0.5289}, "k_shade": {"valu_busy": 0.3123, "valu_lane_utilization": 0.636}}}
 
 
 def kernel_sources_digest() -> str:
