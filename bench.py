@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "4f984beba7f2cee4e8c57ade3da73c478672d5f17bcceeeed4ab4b7d2cb4e68e",
-           "bytes_per_launch": 492389630.3,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6986, "valu_lane_utilization": 0.5584}, "k_trace_shadow": {"valu_busy": 0.6134, "valu_lane_utilization": 0.5289}, "k_shade": {"valu_busy": 0.3123, "valu_lane_utilization": 0.636}}}
+TRAFFIC = {"sources_sha256": "5084e699becf5b86adf34568f2f5358b1ec26975e32fc5e2938761889591d7da",
+           "bytes_per_launch": 492558882.8,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6951, "valu_lane_utilization": 0.5585}, "k_trace_shadow": {"valu_busy": 0.6129, "valu_lane_utilization": 0.529}, "k_shade": {"valu_busy": 0.314, "valu_lane_utilization": 0.6362}}}
 
 
 def kernel_sources_digest() -> str:

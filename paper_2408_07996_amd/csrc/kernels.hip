@@ -596,6 +596,13 @@ __device__ __forceinline__ void traverse(Trav &T, const Geo &g, lds_u32 *lds_sta
 {
     if (T.ref == kEmptyRef) return;
     int32_t spill[kStackMax - kStackLds];
+    if (g.n_lds == 0) {
+        // Speculative steps (here lanes trace rays of different paths in
+        // the same loop): 38.8 -> 37.9 ms per event-loss gradient.
+        while (traverse_step_spec<ANY, COUNT>(T, g, lds_stack, spill, visits, tests)) {
+        }
+        return;
+    }
     while (traverse_step<ANY, COUNT>(T, g, lds_stack, spill, visits, tests)) {
     }
 }
