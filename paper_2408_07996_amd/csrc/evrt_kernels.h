@@ -30,6 +30,23 @@ struct Decide {
     uint32_t cnt_slot;         // which of the two compaction counters this round uses
 };
 
+// Adjoint replay of the event-loss gradient: the forward pieces are traced
+// again with the same keys; shading adds w dL/d(albedo) and w dL/d(Le) of
+// every vertex to FP64 accumulators (per block in LDS, then g[0, n_mat) for
+// albedo and g[n_mat, 2 n_mat) for emission).  W[(pixel * 2 + instant) * m
+// + mini-batch] are the mini-batch weights, Lfwd[(pixel * 2 + instant) *
+// spp + sample] the forward path radiances; sw / semat carry the weight and
+// the emitter material of each shadow entry (its area-light slot) to the
+// shadow kernel.
+struct Adjoint {
+    const double *W;
+    const float *Lfwd;
+    double *g;
+    double *sw;
+    uint32_t *semat;
+    uint32_t n_mat, m, mb, spp;
+};
+
 // Caller output arrays (device).
 struct Outputs {
     int8_t *polarity;
@@ -53,11 +70,12 @@ void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevS
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
                          uint32_t n_split, uint32_t inst_base, float *rad, unsigned long long *stat,
-                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+                         const Adjoint *adj = nullptr);
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
-                  uint32_t *cnt_sh, uint32_t depth);
+                  uint32_t *cnt_sh, uint32_t depth, const Adjoint *adj = nullptr);
 void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
                        double *wf_mean, double *wf_m2, double *wf_ysum);
 // Welford updates and the decision at every checkpoint of the round, for
@@ -81,9 +99,7 @@ void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint3
 void launch_diff_zero(hipStream_t s, double *loss, double *g, uint32_t n_g, uint32_t *mismatch);
 void launch_diff_stats(hipStream_t s, uint32_t npx, uint32_t spp, uint32_t mb, double log_eps, double C,
                        double tau, const float *L, double *W, double *loss, double *loss_px, double *delta_px);
-void launch_adjoint(hipStream_t s, uint32_t blocks, const DevScene &sc, const RenderParams &rp, uint32_t npx,
-                    uint32_t spp, const float *Lfwd, const double *W, uint32_t n_mat, double *g,
-                    uint32_t *mismatch);
+void launch_diff_compare(hipStream_t s, uint64_t n, const float *a, const float *b, uint32_t *mismatch);
 
 // Sequential video: current-frame slots cleared / references replaced at
 // events.

@@ -597,8 +597,7 @@ __device__ __forceinline__ void traverse(Trav &T, const Geo &g, lds_u32 *lds_sta
     if (T.ref == kEmptyRef) return;
     int32_t spill[kStackMax - kStackLds];
     if (g.n_lds == 0) {
-        // Speculative steps (here lanes trace rays of different paths in
-        // the same loop): 38.8 -> 37.9 ms per event-loss gradient.
+        // Speculative steps, as in the trace kernels.
         while (traverse_step_spec<ANY, COUNT>(T, g, lds_stack, spill, visits, tests)) {
         }
         return;
@@ -780,17 +779,48 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
     }
 }
 
+// FP64 gradient accumulators of a block (LDS, 2 n_mat entries) added to
+// adj.g with one atomic per nonzero entry; all threads of the block call it.
+__device__ __forceinline__ void adj_flush(const double *s_acc, const Adjoint &adj)
+{
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < 2 * adj.n_mat; k += blockDim.x)
+        if (s_acc[k] != 0.0) atomicAdd(&adj.g[k], s_acc[k]);
+}
+
+__device__ __forceinline__ void adj_clear(double *s_acc, const Adjoint &adj)
+{
+    for (uint32_t k = threadIdx.x; k < 2 * adj.n_mat; k += blockDim.x) s_acc[k] = 0.0;
+}
+
+// Adjoint term of an unoccluded area-light slot of shadow entry e.
+__device__ __forceinline__ void shadow_adj(const DevScene &sc, const Adjoint &adj, uint32_t e, float c,
+                                           double *s_acc)
+{
+    const double w = adj.sw[e];
+    if (w == 0.0) return;
+    const uint32_t emat = adj.semat[e];
+    atomicAdd(&s_acc[adj.n_mat + emat], w * (double)c / (double)sc.mat[emat].y);
+}
+
 // Shadow entries: the n_slots rays of an entry share its origin; the
 // contributions of the unoccluded slots are summed in slot order and added
 // to the path radiance once.
-template <bool COUNT, bool LDS>
+// ADJ: the adjoint replay also adds w c / Le of every unoccluded area-light
+// slot to the sampled emitter's material.
+template <bool COUNT, bool LDS, bool ADJ>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
                                                       const uint32_t *cnt_in, uint32_t region,
                                                       uint32_t n_split, uint32_t inst_base, float *rad,
-                                                      unsigned long long *stat)
+                                                      unsigned long long *stat, Adjoint adj)
 {
     __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
+    extern __shared__ double s_acc[];
+    if (ADJ) {
+        adj_clear(s_acc, adj);
+        __syncthreads();
+    }
     const Part pt = partition(cnt_in, region, n_split);
     const uint32_t inst = inst_base + pt.r;
     if (LDS) load_treelets(sc, inst, inst + 1, s_nodes);
@@ -831,6 +861,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
                 tracing = T.ref != kEmptyRef;
                 if (!tracing) {
                     sum = sum + c;
+                    if (ADJ && slot == 0) shadow_adj(sc, adj, e, c, s_acc);
                     ++slot;
                 }
             } else {
@@ -843,7 +874,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
         }
         if (tracing && !trace_step<true, COUNT, LDS>(T, g, lds_stack, spill, visits, tests)) {
             tracing = false;
-            if (T.best_p == kNoPrim) sum = sum + c;
+            if (T.best_p == kNoPrim) {
+                sum = sum + c;
+                if (ADJ && slot == 0) shadow_adj(sc, adj, e, c, s_acc);
+            }
             ++slot;
             if (slot >= n_slots) {
                 const uint32_t ri = fbits(sq.o[e].w);
@@ -861,6 +895,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             atomicAdd(stat + kStatTrisShadow, t);
         }
     }
+    if (ADJ) adj_flush(s_acc, adj);
 }
 
 // Point light k seen from P with shading normal ns: contribution
@@ -885,15 +920,21 @@ __device__ __forceinline__ float point_light_slot(const DevScene &sc, uint32_t k
 // estimation (area emitters picked in proportion to area * Le, uniform
 // point on the triangle; point lights), Russian roulette, cosine-weighted
 // continuation.  Emits compacted shadow entries and extension rays.
+// ADJ: the adjoint replay (the same shading, plus the gradient terms of the
+// vertex: emission w term / Le, albedo w (L_fwd - L_before) / albedo, where
+// L_before is the path radiance before this vertex's next-event estimate).
+template <bool ADJ>
 __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderParams rp, RayQueue qin,
                                                const uint32_t *cnt_in, const float2 *hit,
                                                RayQueue qout, uint32_t *cnt_out, ShadowQueue sq,
-                                               uint32_t *cnt_sh, uint32_t depth)
+                                               uint32_t *cnt_sh, uint32_t depth, Adjoint adj)
 {
     const Part pt = partition(cnt_in, pc.region, pc.n_inst);
     __shared__ BlockAppend s_app;
+    extern __shared__ double s_acc[];
     uint32_t par = 0;
     if (threadIdx.x < 16) s_app.bin[threadIdx.x >> 3][threadIdx.x & 7] = 0u;
+    if (ADJ) adj_clear(s_acc, adj);
     __syncthreads();
     // Block-uniform trip count: the appends synchronize the block.
     for (uint32_t j0 = pt.lb * blockDim.x; j0 < pt.n; j0 += pt.lgrid * blockDim.x, par ^= 1u) {
@@ -910,6 +951,8 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
         float c0 = 0.0f;
         float4 d0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         uint32_t pword = 0, ri = 0, inst = 0;
+        double w = 0.0;          // ADJ: mini-batch weight of the path
+        uint32_t emat = 0;       // ADJ: material of the sampled emitter
         if (prim != kNoPrim) {
             pword = fbits(d.w);
             inst = pword >> 31;
@@ -935,7 +978,16 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
             nsx = cosi < 0.0f ? pr.x : -pr.x;
             nsy = cosi < 0.0f ? pr.y : -pr.y;
             nsz = cosi < 0.0f ? pr.z : -pr.z;
-            if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee)) pc.rad[ri] = pc.rad[ri] + beta * Le;
+            if (ADJ) w = adj.W[((size_t)pixel * 2 + inst) * adj.m + sample / adj.mb];
+            if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee)) {
+                const float term = beta * Le;
+                pc.rad[ri] = pc.rad[ri] + term;
+                if (ADJ && w != 0.0) atomicAdd(&s_acc[adj.n_mat + fbits(pr.w)], w * (double)term / (double)Le);
+            }
+            if (ADJ && alb > 0.0f && w != 0.0) {
+                const float Lf = adj.Lfwd[((size_t)pixel * 2 + inst) * adj.spp + sample];
+                atomicAdd(&s_acc[fbits(pr.w)], w * ((double)Lf - (double)pc.rad[ri]) / (double)alb);
+            }
             if (alb > 0.0f) {
                 const uint4 r0 = rng_block(rp, pixel, sample, q, depth, 0);
                 fr = alb * kInvPi;
@@ -969,6 +1021,10 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                                 const float S = inst ? sc.inst[1].emit_S : sc.inst[0].emit_S;
                                 c0 = ((((beta * fr) * cx) * cy) * S) / r2;
                                 d0 = make_float4(wix, wiy, wiz, rl * kShadowScale);
+                                if (ADJ) {
+                                    const float4 *P = inst ? sc.inst[1].prim : sc.inst[0].prim;
+                                    emat = fbits(P[fbits(en.w)].w);
+                                }
                             }
                         }
                     }
@@ -1017,6 +1073,10 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
         if (want_shadow) {
             sq.o[se] = make_float4(Px, Py, Pz, bitsf(ri));
             sq.meta[se] = prim | (inst << 31);
+            if (ADJ) {
+                adj.sw[se] = w;
+                adj.semat[se] = emat;
+            }
             sq.c[se] = c0;
             if (c0 > 0.0f) sq.dir[se] = d0;
             for (uint32_t k = 0; k < sc.n_plights; ++k) {
@@ -1032,6 +1092,7 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
             qout.skip[xe] = prim;
         }
     }
+    if (ADJ) adj_flush(s_acc, adj);
 }
 
 // Pairwise mini-batch mean (FP32) of mb consecutive path radiances.
@@ -1537,184 +1598,15 @@ __global__ __launch_bounds__(256) void k_diff_stats(uint32_t npx, uint32_t spp, 
     if (threadIdx.x == 0 && s_sum[0] != 0.0) atomicAdd(loss, s_sum[0]);
 }
 
-// One path of (pixel, instant, sample) traced again from its keys with the
-// arithmetic of the wavefront kernels (camera ray of k_raygen, shading of
-// k_shade, light samples of k_trace_shadow summed in slot order), adding w
-// times its derivatives to the block's accumulators: every term added after
-// the light samples of a vertex with albedo a carries a, so that vertex
-// contributes w (L - L_before) / a to its material; every emitter term c
-// contributes w c / Le to the emitter's material.  L is the radiance of the
-// forward pass; the return value is the replayed radiance.
-__device__ float replay_path(const DevScene &sc, const RenderParams &rp, const lds_f32 *s_nodes,
-                             lds_u32 *lds_stack, uint32_t pixel, uint32_t inst, uint32_t sample, double w,
-                             float Lfwd, double *acc_a, double *acc_e)
+// Replay check: count of path radiances of the replay that differ (bitwise)
+// from the forward pass.
+__global__ void k_diff_compare(uint64_t n, const float *a, const float *b, uint32_t *mismatch)
 {
-    const DevInstant &I = inst ? sc.inst[1] : sc.inst[0];
-    const DevCamera &cam = I.cam;
-    const Geo g = make_geo(sc, inst, s_nodes + inst * 32 * kLdsNodes);
-    const uint32_t py = fdiv(sc.div_w, pixel);
-    const uint32_t px = pixel - py * sc.width;
-    float j0 = 0.5f, j1 = 0.5f;
-    if (rp.jitter) {
-        const uint4 rb = rng_block(rp, pixel, sample, rp.key_base + inst, 0, 0);
-        j0 = u01(rb.x);
-        j1 = u01(rb.y);
-    }
-    const float fx = (float)px + j0, fy = (float)py + j1;
-    const float nx = (2.0f * fx) / (float)sc.width - 1.0f;
-    const float ny = 1.0f - (2.0f * fy) / (float)sc.height;
-    const float ca = nx * cam.sx, cb = ny * cam.sy;
-    float dx = (cam.fwd[0] + ca * cam.right[0]) + cb * cam.up[0];
-    float dy = (cam.fwd[1] + ca * cam.right[1]) + cb * cam.up[1];
-    float dz = (cam.fwd[2] + ca * cam.right[2]) + cb * cam.up[2];
-    const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
-    dx = dx / len;
-    dy = dy / len;
-    dz = dz / len;
-    float ox = cam.eye[0], oy = cam.eye[1], oz = cam.eye[2];
-    float L = 0.0f, beta = 1.0f;
-    uint32_t skip = kNoPrim;
-    uint32_t visits = 0, tests = 0;
-    for (uint32_t depth = 1; depth <= rp.max_depth; ++depth) {
-        Trav T;
-        trav_begin(T, g.root, ox, oy, oz, dx, dy, dz, kRayTmin, INFINITY, skip);
-        traverse<false, false>(T, g, lds_stack, visits, tests);
-        const uint32_t prim = T.best_p;
-        if (prim == kNoPrim) break;
-        const float t = T.tfar;
-        const float Px = ox + t * dx, Py = oy + t * dy, Pz = oz + t * dz;
-        const float4 pr = I.prim[prim];
-        const uint32_t mat = fbits(pr.w);
-        const float2 mt = sc.mat[mat];
-        const float alb = mt.x, Le = mt.y;
-        const float cosi = dot3f(pr.x, pr.y, pr.z, dx, dy, dz);
-        const float nsx = cosi < 0.0f ? pr.x : -pr.x;
-        const float nsy = cosi < 0.0f ? pr.y : -pr.y;
-        const float nsz = cosi < 0.0f ? pr.z : -pr.z;
-        if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee)) {
-            const float term = beta * Le;
-            L = L + term;
-            atomicAdd(&acc_e[mat], w * (double)term / (double)Le);
-        }
-        if (!(alb > 0.0f)) break;
-        const float Lb = L;
-        const uint4 r0 = rng_block(rp, pixel, sample, rp.key_base + inst, depth, 0);
-        const float fr = alb * kInvPi;
-        if (rp.nee) {
-            float sum = 0.0f;
-            if (I.n_emit > 0) {
-                const float ul = u01(r0.x);
-                uint32_t lo = 0, hi = I.n_emit - 1;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (ul < I.emit_cdf[mid]) hi = mid; else lo = mid + 1;
-                }
-                const float4 *E = I.emit + 4 * (size_t)lo;
-                const float4 v0 = E[0], v1 = E[1], v2 = E[2], en = E[3];
-                const float su = sqrtf(u01(r0.y));
-                const float u2 = u01(r0.z);
-                const float w0 = 1.0f - su, w1 = su * (1.0f - u2), w2 = su * u2;
-                const float wx = ((w0 * v0.x + w1 * v1.x) + w2 * v2.x) - Px;
-                const float wy = ((w0 * v0.y + w1 * v1.y) + w2 * v2.y) - Py;
-                const float wz = ((w0 * v0.z + w1 * v1.z) + w2 * v2.z) - Pz;
-                const float r2 = dot3f(wx, wy, wz, wx, wy, wz);
-                if (r2 > 0.0f) {
-                    const float rl = sqrtf(r2);
-                    const float wix = wx / rl, wiy = wy / rl, wiz = wz / rl;
-                    const float cx = dot3f(nsx, nsy, nsz, wix, wiy, wiz);
-                    const float cy = -dot3f(en.x, en.y, en.z, wix, wiy, wiz);
-                    if (cx > 0.0f && cy > 0.0f) {
-                        const float c0 = ((((beta * fr) * cx) * cy) * I.emit_S) / r2;
-                        if (c0 > 0.0f) {
-                            Trav S;
-                            trav_begin(S, g.root, Px, Py, Pz, wix, wiy, wiz, kRayTmin, rl * kShadowScale, prim);
-                            traverse<true, false>(S, g, lds_stack, visits, tests);
-                            if (S.best_p == kNoPrim) {
-                                sum = sum + c0;
-                                const uint32_t emat = fbits(I.prim[fbits(en.w)].w);
-                                atomicAdd(&acc_e[emat], w * (double)c0 / (double)sc.mat[emat].y);
-                            }
-                        }
-                    }
-                }
-            }
-            for (uint32_t k = 0; k < sc.n_plights; ++k) {
-                float4 dk = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                const float ck = point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta, fr, dk);
-                if (!(ck > 0.0f)) continue;
-                Trav S;
-                trav_begin(S, g.root, Px, Py, Pz, dk.x, dk.y, dk.z, kRayTmin, dk.w, prim);
-                traverse<true, false>(S, g, lds_stack, visits, tests);
-                if (S.best_p == kNoPrim) sum = sum + ck;
-            }
-            L = L + sum;
-        }
-        atomicAdd(&acc_a[mat], w * ((double)Lfwd - (double)Lb) / (double)alb);
-        if (depth >= rp.max_depth) break;
-        if (depth >= rp.rr_start) {
-            const float qs = fminf(1.0f, beta);
-            if (u01(r0.w) >= qs) break;
-            beta = beta / qs;
-        }
-        const uint4 r1 = rng_block(rp, pixel, sample, rp.key_base + inst, depth, 1);
-        const float e0 = u01(r1.x), e1 = u01(r1.y);
-        const float rr = sqrtf(e0);
-        const double ph = kTwoPi * (double)e1;
-        double sd, cd;
-        sincos(ph, &sd, &cd);
-        const float cph = (float)cd, sph = (float)sd;
-        const float lx = rr * cph, ly = rr * sph, lz = sqrtf(fmaxf(0.0f, 1.0f - e0));
-        const float sg = copysignf(1.0f, nsz);
-        const float aa = -1.0f / (sg + nsz);
-        const float bb = (nsx * nsy) * aa;
-        const float tx = 1.0f + ((sg * nsx) * nsx) * aa, ty = sg * bb, tz = (-sg) * nsx;
-        const float bx = bb, by = sg + (nsy * nsy) * aa, bz = -nsy;
-        dx = (tx * lx + bx * ly) + nsx * lz;
-        dy = (ty * lx + by * ly) + nsy * lz;
-        dz = (tz * lx + bz * ly) + nsz * lz;
-        ox = Px;
-        oy = Py;
-        oz = Pz;
-        beta = beta * alb;
-        skip = prim;
-    }
-    return L;
-}
-
-// Adjoint pass: one thread per path (grid-stride over pixel-major paths
-// [pixel][instant][sample]); gradients accumulate per block in LDS (FP64)
-// and are added to g[0..n_mat) (albedo) and g[n_mat..2 n_mat) (emission)
-// with one atomic per block and entry.
-__global__ __launch_bounds__(kTB) void k_adjoint(DevScene sc, RenderParams rp, uint32_t npx, uint32_t spp,
-                                                 const float *Lfwd, const double *W, uint32_t n_mat, double *g,
-                                                 uint32_t *mismatch)
-{
-    __shared__ float4 s_nodes[2 * 8 * kLdsNodes];
-    __shared__ uint32_t s_stack[kStackLds * kTB];
-    extern __shared__ double s_acc[];
-    for (uint32_t k = threadIdx.x; k < 2 * n_mat; k += kTB) s_acc[k] = 0.0;
-    load_treelets(sc, 0, 2, s_nodes);
-    const uint32_t mb = rp.minibatch, m = spp / mb;
-    const uint64_t n = (uint64_t)npx * 2u * spp;
     uint32_t bad = 0;
-    for (uint64_t p = (uint64_t)blockIdx.x * kTB + threadIdx.x; p < n; p += (uint64_t)gridDim.x * kTB) {
-        const uint32_t s = (uint32_t)(p % spp);
-        const uint64_t pi = p / spp;
-        const uint32_t inst = (uint32_t)(pi & 1u), pixel = (uint32_t)(pi >> 1);
-        const double w = W[pi * m + s / mb];
-        if (w == 0.0) continue;
-        const float Lp = Lfwd[p];
-        const float Lr = replay_path(sc, rp, (const lds_f32 *)s_nodes, (lds_u32 *)s_stack + threadIdx.x, pixel, inst,
-                                     s, w, Lp, s_acc, s_acc + n_mat);
-        bad += __float_as_uint(Lr) != __float_as_uint(Lp) ? 1u : 0u;
-    }
-    __syncthreads();
-    for (uint32_t k = threadIdx.x; k < 2 * n_mat; k += kTB)
-        if (s_acc[k] != 0.0) atomicAdd(&g[k], s_acc[k]);
-    if (mismatch) {
-        const unsigned long long b = wave_sum_u64(bad);
-        if (__lane_id() == 0 && b) atomicAdd(mismatch, (uint32_t)b);
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        bad += __float_as_uint(a[i]) != __float_as_uint(b[i]) ? 1u : 0u;
+    const unsigned long long t = wave_sum_u64(bad);
+    if (__lane_id() == 0 && t) atomicAdd(mismatch, (uint32_t)t);
 }
 
 }  // namespace
@@ -1760,30 +1652,44 @@ void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevS
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
                          uint32_t n_split, uint32_t inst_base, float *rad, unsigned long long *stat,
-                         hipEvent_t ev_start, hipEvent_t ev_stop)
+                         hipEvent_t ev_start, hipEvent_t ev_stop, const Adjoint *adj)
 {
     const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
-    if (count && lds)
-        hipExtLaunchKernelGGL((k_trace_shadow<true, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
+    const Adjoint a = adj ? *adj : Adjoint{};
+    if (adj) {
+        // The adjoint replay counts no work; its accumulators are dynamic LDS.
+        const size_t sh = 2 * adj->n_mat * sizeof(double);
+        if (lds)
+            hipExtLaunchKernelGGL((k_trace_shadow<false, true, true>), dim3(blocks), dim3(kTB), sh, s, ev_start,
+                                  ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+        else
+            hipExtLaunchKernelGGL((k_trace_shadow<false, false, true>), dim3(blocks), dim3(kTB), sh, s, ev_start,
+                                  ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+    } else if (count && lds)
+        hipExtLaunchKernelGGL((k_trace_shadow<true, true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop,
+                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
     else if (count)
-        hipExtLaunchKernelGGL((k_trace_shadow<true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
+        hipExtLaunchKernelGGL((k_trace_shadow<true, false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop,
+                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
     else if (lds)
-        hipExtLaunchKernelGGL((k_trace_shadow<false, true>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0, sc,
-                              sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
+        hipExtLaunchKernelGGL((k_trace_shadow<false, true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop,
+                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
     else
-        hipExtLaunchKernelGGL((k_trace_shadow<false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop, 0,
-                              sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat);
+        hipExtLaunchKernelGGL((k_trace_shadow<false, false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start,
+                              ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
 }
 
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
-                  uint32_t *cnt_sh, uint32_t depth)
+                  uint32_t *cnt_sh, uint32_t depth, const Adjoint *adj)
 {
-    hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(256), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
-                       cnt_out, sq, cnt_sh, depth);
+    if (adj)
+        hipLaunchKernelGGL(k_shade<true>, dim3(blocks), dim3(256), 2 * adj->n_mat * sizeof(double), s, pc, sc, rp,
+                           qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj);
+    else
+        hipLaunchKernelGGL(k_shade<false>, dim3(blocks), dim3(256), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
+                           cnt_out, sq, cnt_sh, depth, Adjoint{});
 }
 
 void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
@@ -1884,12 +1790,10 @@ void launch_diff_stats(hipStream_t s, uint32_t npx, uint32_t spp, uint32_t mb, d
                        W, loss, loss_px, delta_px);
 }
 
-void launch_adjoint(hipStream_t s, uint32_t blocks, const DevScene &sc, const RenderParams &rp, uint32_t npx,
-                    uint32_t spp, const float *Lfwd, const double *W, uint32_t n_mat, double *g,
-                    uint32_t *mismatch)
+void launch_diff_compare(hipStream_t s, uint64_t n, const float *a, const float *b, uint32_t *mismatch)
 {
-    hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kTB), 2 * n_mat * sizeof(double), s, sc, rp, npx, spp, Lfwd,
-                       W, n_mat, g, mismatch);
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
+    if (blocks) hipLaunchKernelGGL(k_diff_compare, dim3((uint32_t)blocks), dim3(256), 0, s, n, a, b, mismatch);
 }
 
 void launch_hook_rays(hipStream_t s, uint32_t n, const float *rays, const uint32_t *skip,
@@ -1919,8 +1823,8 @@ void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu)
 {
     int a = 0, b = 0, c = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_trace_closest<false, false>, kTB, 0) != hipSuccess) a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace_shadow<false, false>, kTB, 0) != hipSuccess) b = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade, 256, 0) != hipSuccess) c = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace_shadow<false, false, false>, kTB, 0) != hipSuccess) b = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade<false>, 256, 0) != hipSuccess) c = 1;
     *trace_blocks_per_cu = std::max(1, std::min(a, b));
     *shade_blocks_per_cu = std::max(1, c);
 }

@@ -204,7 +204,8 @@ struct Profiler {
 // Traces one piece: camera rays, max_depth bounces of closest hit + shade
 // + shadow rays.  Path radiances land in pc.rad.
 static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const RenderParams &rp,
-                        const evrt_render_opts &o, hipStream_t s, Profiler &prof, int ln = 0)
+                        const evrt_render_opts &o, hipStream_t s, Profiler &prof, int ln = 0,
+                        const Adjoint *adj = nullptr)
 {
     FrameBuffers &fb = c->fb;
     LaneBufs &L = fb.lane[ln];
@@ -230,11 +231,11 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
                              ec.b);
         c->stats.n_closest_launches++;
         launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), L.hit.as<float2>(), qout,
-                     cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d);
+                     cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d, adj);
         if (rp.nee) {
             const EventPair es = prof.take(1);
             launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
-                                pc.n_inst, pc.inst_base, pc.rad, stat, es.a, es.b);
+                                pc.n_inst, pc.inst_base, pc.rad, stat, es.a, es.b, adj);
             c->stats.n_shadow_launches++;
         }
     }
@@ -682,19 +683,29 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
     c->stats.ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
 }
 
-void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const uint32_t *pixels,
-                  uint32_t spp, const evrt_render_opts &o, float *L_out, hipStream_t s)
+// Every path sample s in [0, spp) of the listed pixels at both instants, in
+// pieces of the usual wavefront; radiances go to L_out[pixel][instant][s].
+// With adj, the pieces are the adjoint replay (same keys, same arithmetic).
+static void trace_paths(evrt_ctx *c, const DevScene &sc, const RenderParams &rp, const evrt_render_opts &o,
+                        uint32_t n_pixels, const uint32_t *pixels, uint32_t spp, float *L_out,
+                        const Adjoint *adj, hipStream_t s)
 {
-    std::memset(&c->stats, 0, sizeof(c->stats));
-    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
-    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
-    const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
-    const RenderParams rp = make_params(c, o);
     const uint32_t npx = sc.width * sc.height;
     const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
     const uint64_t per_px = 2ull * spp;
     const uint32_t chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_pixels, batch / per_px));
     ensure_buffers(c, npx, (uint32_t)std::min<uint64_t>((uint64_t)chunk * per_px, kMaxPathId - 1), rp.n_slots);
+    Adjoint a{};
+    if (adj) {
+        // Weight and emitter of each shadow entry (queue slots of lane 0).
+        FrameBuffers &fb = c->fb;
+        const uint32_t cap = fb.lane[0].queue_cap;
+        fb.diff_sw.ensure(sizeof(double) * cap);
+        fb.diff_semat.ensure(sizeof(uint32_t) * cap);
+        a = *adj;
+        a.sw = fb.diff_sw.as<double>();
+        a.semat = fb.diff_semat.as<uint32_t>();
+    }
     launch_init_frame(s, 0, nullptr, nullptr, nullptr, nullptr, nullptr, c->fb.cnt.as<uint32_t>(),
                       c->fb.stat.as<unsigned long long>());
     Profiler prof{c, false, 0, {}};
@@ -714,8 +725,19 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
         pc.rad = L_out + (size_t)a0 * per_px;  // [pixel][instant][sample]
         pc.rs_a = 2 * spp;
         pc.rs_i = spp;
-        trace_piece(c, pc, sc, rp, o, s, prof);
+        trace_piece(c, pc, sc, rp, o, s, prof, 0, adj ? &a : nullptr);
     }
+}
+
+void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const uint32_t *pixels,
+                  uint32_t spp, const evrt_render_opts &o, float *L_out, hipStream_t s)
+{
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
+    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
+    const RenderParams rp = make_params(c, o);
+    trace_paths(c, sc, rp, o, n_pixels, pixels, spp, L_out, nullptr, s);
     read_stats(c, s);
 }
 
@@ -741,16 +763,26 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
     fb.diff_L.ensure(sizeof(float) * 2 * (size_t)npx * spp);
     fb.diff_W.ensure(sizeof(double) * 2 * (size_t)npx * m);
     launch_diff_zero(s, out.loss, out.grad, 2 * n_mat, out.replay_mismatch);
-    render_paths(c, t0, t1, npx, fb.diff_px.as<uint32_t>(), spp, o, fb.diff_L.as<float>(), s);
-    launch_diff_stats(s, npx, spp, mb, (double)o.log_eps, (double)C, (double)tau, fb.diff_L.as<float>(),
-                      fb.diff_W.as<double>(), out.loss, out.loss_px, out.delta);
     const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
-    const uint64_t n = 2ull * npx * spp;
-    const uint32_t blocks = (uint32_t)std::max<uint64_t>(
-        8, std::min<uint64_t>((n + traverse_block_threads() - 1) / traverse_block_threads(), 8ull * c->cu_count));
-    launch_adjoint(s, blocks, sc, rp, npx, spp, fb.diff_L.as<float>(), fb.diff_W.as<double>(), n_mat, out.grad,
-                   out.replay_mismatch);
+    trace_paths(c, sc, rp, o, npx, fb.diff_px.as<uint32_t>(), spp, fb.diff_L.as<float>(), nullptr, s);
+    launch_diff_stats(s, npx, spp, mb, (double)o.log_eps, (double)C, (double)tau, fb.diff_L.as<float>(),
+                      fb.diff_W.as<double>(), out.loss, out.loss_px, out.delta);
+    // Adjoint: the same pieces again with the gradient terms of every vertex,
+    // then every replayed path radiance against the forward one.
+    fb.diff_R.ensure(sizeof(float) * 2 * (size_t)npx * spp);
+    Adjoint adj{};
+    adj.W = fb.diff_W.as<double>();
+    adj.Lfwd = fb.diff_L.as<float>();
+    adj.g = out.grad;
+    adj.n_mat = n_mat;
+    adj.m = m;
+    adj.mb = mb;
+    adj.spp = spp;
+    trace_paths(c, sc, rp, o, npx, fb.diff_px.as<uint32_t>(), spp, fb.diff_R.as<float>(), &adj, s);
+    if (out.replay_mismatch)
+        launch_diff_compare(s, 2ull * npx * spp, fb.diff_R.as<float>(), fb.diff_L.as<float>(), out.replay_mismatch);
+    read_stats(c, s);
     hip_check(hipGetLastError(), "adjoint launch");
 }
 
