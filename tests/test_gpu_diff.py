@@ -18,8 +18,12 @@ def _say(msg):
 
 
 def _opts(P):
-    return dict(seed=P.get("seed", 0), max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
-                minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    o = dict(seed=P.get("seed", 0), max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    for k in ("ray_batch", "lds_nodes"):
+        if k in P:
+            o[k] = P[k]
+    return o
 
 
 def _oracle_params(P):
@@ -57,6 +61,22 @@ def test_event_loss_gradient_matches_oracle_small():
     P = dict(scenes.DIFF_PARAMS, spp=32)
     g, r = _compare(scenes.diff_scene(width=32, height=24), P)
     assert np.abs(r["grad_albedo"]).max() > 0 and np.abs(r["grad_emission"]).max() > 0
+
+
+@pytest.mark.parametrize("variant", ["pieces", "lds_treelet", "no_nee"])
+def test_event_loss_gradient_variants(variant):
+    """The replay in several pieces per pass (small ray batch: the shadow
+    entries' weights are per piece), with the LDS treelet, and without
+    next-event estimation (emission differentiated at every hit)."""
+    P = dict(scenes.DIFF_PARAMS, spp=32)
+    if variant == "pieces":
+        P["ray_batch"] = 4096
+    elif variant == "lds_treelet":
+        P["lds_nodes"] = 32
+    else:
+        P["nee"] = 0
+    g, r = _compare(scenes.diff_scene(width=24, height=20), P)
+    assert np.abs(r["grad_emission"]).max() > 0
 
 
 def test_event_loss_gradient_matches_oracle_point_lights_mb8():
