@@ -260,6 +260,18 @@ static double crit_value(evrt_ctx *c, double p, uint32_t df)
 // with the whole sample range when that fits, otherwise every pixel with a
 // sub-range of whole mini-batches.  Each pixel's samples are accumulated in
 // increasing order either way.
+// Entries per block when a round's n entries (pixels or items, each with
+// its whole sample range) are cut into blocks of at most `block`: with two
+// lanes, an even number (at least two) of equal blocks, so that both lanes
+// get the same work and finish together.
+static uint64_t balanced_block(const evrt_ctx *c, uint64_t n, uint64_t block)
+{
+    if (!c->s2 || n < 128) return block;
+    uint64_t nb = (n + block - 1) / block;
+    nb = std::max<uint64_t>(2, nb + (nb & 1));
+    return (n + nb - 1) / nb;
+}
+
 static bool trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t n_inst, uint32_t inst_base,
                         uint32_t lo, uint32_t hi, const DevScene &sc, const RenderParams &rp,
                         const evrt_render_opts &o, hipStream_t s, Profiler &prof, const Decide *dc = nullptr,
@@ -281,6 +293,7 @@ static bool trace_range(evrt_ctx *c, const uint32_t *act, uint32_t nA, uint32_t 
     px_block = std::min<uint64_t>(px_block, nA);
     bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / (px_block * n_inst) / mb * mb);
     if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many pixels for one piece");
+    if (bp_max >= range) px_block = balanced_block(c, nA, px_block);
     // Pieces that hold the whole range of their pixels also take the
     // decisions; split sample ranges leave them to a separate kernel.
     const bool fused = dc != nullptr && bp_max >= range;
@@ -620,6 +633,7 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
         bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / it_block / mb * mb);
         if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many items for one piece");
         const bool split = bp_max < range;
+        if (!split) it_block = balanced_block(c, n_items, it_block);
         if (dc.n_checks > 1 && split) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
         const uint64_t n_pieces = ((n_items + it_block - 1) / it_block) * ((range + bp_max - 1) / bp_max);
         // Split sample ranges of one item must be accumulated in order: they
