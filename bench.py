@@ -151,7 +151,7 @@ def bench_batch(ev, scenes, args) -> dict:
         at = autotune.autotune(r, 0.0, 1.0, o)
         o = at["opts"]
         tuned = dict(ray_batch=o["ray_batch"], trace_blocks_per_cu=o["trace_blocks_per_cu"],
-                     table=[list(x) for x in at["table"]])
+                     calibration_spp=at["spp"], table=[list(x) for x in at["table"]])
     times = [float(k) for k in range(K + 1)]
     print(f"[bench] batch of {K} pairs", file=sys.stderr, flush=True)
     torch.cuda.synchronize()

@@ -35,3 +35,49 @@ def test_rmse_and_psnr_of_single_differences():
     flip[0], ref2 = -1, ref.copy()
     ref2[0] = 1         # opposite polarity: difference 1
     assert metrics.rmse(flip, ref2) == pytest.approx(1 / math.sqrt(n))
+
+
+def test_autotune_calibration_spp():
+    """The calibration frame holds at least four batches of the largest
+    paths in flight (clamped to [32, 512], a multiple of the mini-batch)."""
+    from paper_2408_07996_amd.autotune import calibration_spp
+    for w, h in ((1280, 720), (640, 480), (37, 23)):
+        spp = calibration_spp(w, h)
+        assert spp % 4 == 0 and 32 <= spp <= 512
+        assert spp == 512 or 2 * w * h * spp >= 4 * (1 << 26)
+    assert calibration_spp(1280, 720) == 148
+    assert calibration_spp(8, 8, minibatch=8) % 8 == 0
+
+
+def test_autotune_prefers_more_work_in_flight_on_ties():
+    """Shapes within 2 % of the fastest count as tied; the tie goes to the
+    larger batch, then the more blocks per CU."""
+    import paper_2408_07996_amd.autotune as at
+
+    class FakeRenderer:
+        scene = None
+
+        def __init__(self, times):
+            self.times, self.calls, self.cur = times, 0, None
+
+        def render_event_frame(self, t0, t1, C, a, s0, s1, s2, o, extras=False):
+            import time as _t
+            key = (o.get("ray_batch"), o.get("trace_blocks_per_cu"))
+            if key in self.times:
+                _t.sleep(self.times[key])
+
+    times = {(1 << 24, 4): 0.140, (1 << 25, 4): 0.120, (1 << 26, 4): 0.100, (1 << 26, 8): 0.1005,
+             (1 << 24, 8): 0.150, (1 << 25, 8): 0.130}
+    import types, sys
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None))
+    saved = sys.modules.get("torch")
+    sys.modules["torch"] = fake_torch
+    try:
+        r = at.autotune(FakeRenderer(times), 0.0, 1.0, {}, spp=32, ray_batch=(1 << 24, 1 << 25, 1 << 26),
+                        blocks_per_cu=(4, 8), repeats=2)
+    finally:
+        if saved is not None:
+            sys.modules["torch"] = saved
+        else:
+            del sys.modules["torch"]
+    assert (r["opts"]["ray_batch"], r["opts"]["trace_blocks_per_cu"]) == (1 << 26, 8)
