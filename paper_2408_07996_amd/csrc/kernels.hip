@@ -95,7 +95,7 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter)
 struct BlockAppend {
     uint32_t wc[2][2][4];
     uint32_t base[2][2];
-    uint32_t bin[2][8];   // block_append_binned: per-bin counts, then slots
+    uint32_t bin[2][2][8];  // block_append_binned: [parity][queue][bin] counts, then slots
 };
 
 __device__ __forceinline__ void block_append2(BlockAppend &sm, uint32_t par, bool pa, bool pb, uint32_t *ca,
@@ -124,39 +124,37 @@ __device__ __forceinline__ void block_append2(BlockAppend &sm, uint32_t par, boo
     sb = ob + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
 }
 
-// As block_append2, but the block's entries of the second queue are laid
-// out grouped by a 3-bit key (the slot order within a group is arbitrary),
-// so that rays of one block with similar directions are traced by the same
+// As block_append2, but the block's entries of each queue are laid out
+// grouped by a 3-bit key (the slot order within a group is arbitrary), so
+// that rays of one block with similar directions are traced by the same
 // waves.  Bins of parity par must be zero on entry: clear both parities
 // (followed by a barrier) before the first call; each call clears the other
 // parity's bins after every thread has finished the previous call.
-__device__ __forceinline__ void block_append_binned(BlockAppend &sm, uint32_t par, bool pa, bool pb, uint32_t key,
-                                                    uint32_t *ca, uint32_t *cb, uint32_t &sa, uint32_t &sb)
+__device__ __forceinline__ void block_append_binned(BlockAppend &sm, uint32_t par, bool pa, uint32_t key_a,
+                                                    bool pb, uint32_t key_b, uint32_t *ca, uint32_t *cb,
+                                                    uint32_t &sa, uint32_t &sb)
 {
-    const unsigned long long ma = __ballot(pa);
-    const uint32_t w = threadIdx.x >> 6;
-    if (__lane_id() == 0) sm.wc[par][0][w] = (uint32_t)__popcll(ma);
-    uint32_t rb = 0;
-    if (pb) rb = atomicAdd(&sm.bin[par][key & 7u], 1u);
+    uint32_t ra = 0, rb = 0;
+    if (pa) ra = atomicAdd(&sm.bin[par][0][key_a & 7u], 1u);
+    if (pb) rb = atomicAdd(&sm.bin[par][1][key_b & 7u], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t ta = (sm.wc[par][0][0] + sm.wc[par][0][1]) + (sm.wc[par][0][2] + sm.wc[par][0][3]);
-        sm.base[par][0] = ta ? atomicAdd(ca, ta) : 0u;
-        uint32_t tb = 0;
-        for (int b = 0; b < 8; ++b) tb += sm.bin[par][b];
-        uint32_t off = tb ? atomicAdd(cb, tb) : 0u;
-        for (int b = 0; b < 8; ++b) {
-            const uint32_t c = sm.bin[par][b];
-            sm.bin[par][b] = off;
-            off += c;
+        uint32_t *const cq[2] = {ca, cb};
+        for (int q = 0; q < 2; ++q) {
+            uint32_t t = 0;
+            for (int b = 0; b < 8; ++b) t += sm.bin[par][q][b];
+            uint32_t off = t ? atomicAdd(cq[q], t) : 0u;
+            for (int b = 0; b < 8; ++b) {
+                const uint32_t c = sm.bin[par][q][b];
+                sm.bin[par][q][b] = off;
+                off += c;
+            }
+            for (int b = 0; b < 8; ++b) sm.bin[par ^ 1u][q][b] = 0u;
         }
-        for (int b = 0; b < 8; ++b) sm.bin[par ^ 1u][b] = 0u;
     }
     __syncthreads();
-    uint32_t oa = sm.base[par][0];
-    for (uint32_t v = 0; v < w; ++v) oa += sm.wc[par][0][v];
-    sa = oa + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
-    sb = pb ? sm.bin[par][key & 7u] + rb : 0u;
+    sa = pa ? sm.bin[par][0][key_a & 7u] + ra : 0u;
+    sb = pb ? sm.bin[par][1][key_b & 7u] + rb : 0u;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -933,7 +931,7 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
     __shared__ BlockAppend s_app;
     extern __shared__ double s_acc[];
     uint32_t par = 0;
-    if (threadIdx.x < 16) s_app.bin[threadIdx.x >> 3][threadIdx.x & 7] = 0u;
+    if (threadIdx.x < 32) s_app.bin[threadIdx.x >> 4][(threadIdx.x >> 3) & 1][threadIdx.x & 7] = 0u;
     if (ADJ) adj_clear(s_acc, adj);
     __syncthreads();
     // Block-uniform trip count: the appends synchronize the block.
@@ -953,6 +951,7 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
         uint32_t pword = 0, ri = 0, inst = 0;
         double w = 0.0;          // ADJ: mini-batch weight of the path
         uint32_t emat = 0;       // ADJ: material of the sampled emitter
+        uint32_t light = 0;      // the sampled emitter triangle (groups shadow entries)
         if (prim != kNoPrim) {
             pword = fbits(d.w);
             inst = pword >> 31;
@@ -1003,6 +1002,7 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
                             const uint32_t mid = (lo + hi) >> 1;
                             if (ul < cdf[mid]) hi = mid; else lo = mid + 1;
                         }
+                        light = lo;
                         const float4 *E = (inst ? sc.inst[1].emit : sc.inst[0].emit) + 4 * (size_t)lo;
                         const float4 v0 = E[0], v1 = E[1], v2 = E[2], en = E[3];
                         const float su = sqrtf(u01(r0.y));
@@ -1065,9 +1065,10 @@ __global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderPara
         }
         const uint32_t r = pt.base / max(pc.region, 1u);
         uint32_t se, xe;
-        // Extension rays are grouped by direction octant within the block.
+        // Within the block, shadow entries are grouped by the sampled emitter
+        // and extension rays by direction octant.
         const uint32_t oct = (ndx < 0.0f ? 1u : 0u) | (ndy < 0.0f ? 2u : 0u) | (ndz < 0.0f ? 4u : 0u);
-        block_append_binned(s_app, par, want_shadow, want_ext, oct, cnt_sh + r, cnt_out + r, se, xe);
+        block_append_binned(s_app, par, want_shadow, light, want_ext, oct, cnt_sh + r, cnt_out + r, se, xe);
         se += pt.base;
         xe += pt.base;
         if (want_shadow) {
