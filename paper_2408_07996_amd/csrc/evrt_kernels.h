@@ -128,6 +128,7 @@ void launch_batch_decide(hipStream_t s, const Decide &dc, const uint32_t *act, u
 
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu);
 int traverse_block_threads();
+int shade_block_threads();
 int lds_treelet_nodes();   // 4-wide nodes a block can stage in LDS per instant
 int traverse_max_depth();  // deepest 4-wide tree (inner levels) the traversal stack holds
 

@@ -921,8 +921,15 @@ __device__ __forceinline__ float point_light_slot(const DevScene &sc, uint32_t k
 // ADJ: the adjoint replay (the same shading, plus the gradient terms of the
 // vertex: emission w term / Le, albedo w (L_fwd - L_before) / albedo, where
 // L_before is the path radiance before this vertex's next-event estimate).
+// Shade blocks of 512 threads: the appends group a block's rays by key, and
+// a larger block gives waves of fewer distinct keys (256 / 512 / 1024
+// threads: 120.0 / 116.4 / 118.7 ms per sensor frame).
+#ifndef EVRT_SHADE_TB
+#define EVRT_SHADE_TB 512
+#endif
+constexpr int kShadeTB = EVRT_SHADE_TB;
 template <bool ADJ>
-__global__ __launch_bounds__(256) void k_shade(Piece pc, DevScene sc, RenderParams rp, RayQueue qin,
+__global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, RenderParams rp, RayQueue qin,
                                                const uint32_t *cnt_in, const float2 *hit,
                                                RayQueue qout, uint32_t *cnt_out, ShadowQueue sq,
                                                uint32_t *cnt_sh, uint32_t depth, Adjoint adj)
@@ -1689,10 +1696,10 @@ void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScen
                   uint32_t *cnt_sh, uint32_t depth, const Adjoint *adj)
 {
     if (adj)
-        hipLaunchKernelGGL(k_shade<true>, dim3(blocks), dim3(256), 2 * adj->n_mat * sizeof(double), s, pc, sc, rp,
+        hipLaunchKernelGGL(k_shade<true>, dim3(blocks), dim3(kShadeTB), 2 * adj->n_mat * sizeof(double), s, pc, sc, rp,
                            qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj);
     else
-        hipLaunchKernelGGL(k_shade<false>, dim3(blocks), dim3(256), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
+        hipLaunchKernelGGL(k_shade<false>, dim3(blocks), dim3(kShadeTB), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
                            cnt_out, sq, cnt_sh, depth, Adjoint{});
 }
 
@@ -1828,11 +1835,12 @@ void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu)
     int a = 0, b = 0, c = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_trace_closest<false, false>, kTB, 0) != hipSuccess) a = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace_shadow<false, false, false>, kTB, 0) != hipSuccess) b = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade<false>, 256, 0) != hipSuccess) c = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade<false>, kShadeTB, 0) != hipSuccess) c = 1;
     *trace_blocks_per_cu = std::max(1, std::min(a, b));
     *shade_blocks_per_cu = std::max(1, c);
 }
 
+int shade_block_threads() { return kShadeTB; }
 int traverse_block_threads() { return kTB; }
 int lds_treelet_nodes() { return kLdsNodes; }
 int traverse_max_depth() { return kStackMax / 3; }

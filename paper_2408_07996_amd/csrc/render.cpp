@@ -220,7 +220,8 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
     const uint32_t tper = o.trace_blocks_per_cu ? std::min(o.trace_blocks_per_cu, c->trace_blocks_per_cu)
                                                 : c->trace_blocks_per_cu;
     const uint32_t tblocks = blocks_for(tper, c->cu_count, pc.n_paths, tb);
-    const uint32_t sblocks = blocks_for(c->shade_blocks_per_cu, c->cu_count, pc.n_paths, 256);
+    const uint32_t sblocks = blocks_for(c->shade_blocks_per_cu, c->cu_count, pc.n_paths,
+                                        (uint32_t)shade_block_threads());
     const bool count = o.count_work != 0;
     for (uint32_t d = 1; d <= rp.max_depth; ++d) {
         const RayQueue &qin = q[(d - 1) & 1];
