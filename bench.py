@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "ef5e1e521428898472f6529cdd4de7f7971e9f4ece8e3bf3a210e6a8538717eb",
-           "bytes_per_launch": 496038084.1,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6987, "valu_lane_utilization": 0.5587}, "k_trace_shadow": {"valu_busy": 0.6076, "valu_lane_utilization": 0.5597}, "k_shade": {"valu_busy": 0.3138, "valu_lane_utilization": 0.6261}}}
+TRAFFIC = {"sources_sha256": "bc2ad865be3af636f1808dc2ab179298630501b53ce988ff36a7bd09563f1ed0",
+           "bytes_per_launch": 490724718.3,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6788, "valu_lane_utilization": 0.5639}, "k_trace_shadow": {"valu_busy": 0.6039, "valu_lane_utilization": 0.5658}, "k_shade": {"valu_busy": 0.4511, "valu_lane_utilization": 0.6639}}}
 
 
 def kernel_sources_digest() -> str:
