@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "bc2ad865be3af636f1808dc2ab179298630501b53ce988ff36a7bd09563f1ed0",
-           "bytes_per_launch": 490724718.3,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6788, "valu_lane_utilization": 0.5639}, "k_trace_shadow": {"valu_busy": 0.6039, "valu_lane_utilization": 0.5658}, "k_shade": {"valu_busy": 0.4511, "valu_lane_utilization": 0.6639}}}
+TRAFFIC = {"sources_sha256": "a32f6bc38883625e283016fb32edb844513ec77d65d296635aa160d93ebc89d1",
+           "bytes_per_launch": 488894261.9,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6927, "valu_lane_utilization": 0.563}, "k_trace_shadow": {"valu_busy": 0.5995, "valu_lane_utilization": 0.5656}, "k_shade": {"valu_busy": 0.454, "valu_lane_utilization": 0.6431}}}
 
 
 def kernel_sources_digest() -> str:
