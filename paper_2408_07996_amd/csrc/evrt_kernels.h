@@ -75,7 +75,7 @@ void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevSc
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
-                  uint32_t *cnt_sh, uint32_t depth, const Adjoint *adj = nullptr);
+                  uint32_t *cnt_sh, uint32_t depth, uint32_t threads, const Adjoint *adj = nullptr);
 void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
                        double *wf_mean, double *wf_m2, double *wf_ysum);
 // Welford updates and the decision at every checkpoint of the round, for
@@ -128,7 +128,7 @@ void launch_batch_decide(hipStream_t s, const Decide &dc, const uint32_t *act, u
 
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu);
 int traverse_block_threads();
-int shade_block_threads();
+int shade_block_threads();  // largest shade block (the kernel's launch bound)
 int lds_treelet_nodes();   // 4-wide nodes a block can stage in LDS per instant
 int traverse_max_depth();  // deepest 4-wide tree (inner levels) the traversal stack holds
 

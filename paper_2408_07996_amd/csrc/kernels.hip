@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter)
 // must call it the same number of times; par alternates between calls so
 // that a wave running ahead cannot overwrite counts still being read.
 struct BlockAppend {
-    uint32_t wc[2][2][4];
+    uint32_t wc[2][2][16];  // block_append2: [parity][queue][wave] counts, up to 1024-thread blocks
     uint32_t base[2][2];
 // Keys per queue of the grouped appends (16 / 32 bins with 512-thread
 // shade blocks: 116.3 / 115.9 ms per sensor frame).
@@ -114,8 +114,12 @@ __device__ __forceinline__ void block_append2(BlockAppend &sm, uint32_t par, boo
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t ta = (sm.wc[par][0][0] + sm.wc[par][0][1]) + (sm.wc[par][0][2] + sm.wc[par][0][3]);
-        const uint32_t tb = (sm.wc[par][1][0] + sm.wc[par][1][1]) + (sm.wc[par][1][2] + sm.wc[par][1][3]);
+        const uint32_t nw = blockDim.x >> 6;
+        uint32_t ta = 0, tb = 0;
+        for (uint32_t v = 0; v < nw; ++v) {
+            ta += sm.wc[par][0][v];
+            tb += sm.wc[par][1][v];
+        }
         sm.base[par][0] = ta ? atomicAdd(ca, ta) : 0u;
         sm.base[par][1] = tb ? atomicAdd(cb, tb) : 0u;
     }
@@ -926,9 +930,12 @@ __device__ __forceinline__ float point_light_slot(const DevScene &sc, uint32_t k
 // ADJ: the adjoint replay (the same shading, plus the gradient terms of the
 // vertex: emission w term / Le, albedo w (L_fwd - L_before) / albedo, where
 // L_before is the path radiance before this vertex's next-event estimate).
-// Shade blocks of 512 threads: the appends group a block's rays by key, and
-// a larger block gives waves of fewer distinct keys (256 / 512 / 1024
-// threads: 120.0 / 116.4 / 118.7 ms per sensor frame).
+// Largest shade block: 512 threads.  The appends group a block's rays by
+// key, and a larger block gives waves of fewer distinct keys while the
+// block still spans few pixels (256 / 512 / 1024 threads: 120.0 / 116.4 /
+// 118.7 ms per sensor frame).  Pieces with fewer than 64 samples per
+// pixel, where a block spans many pixels, run 256-thread blocks whose
+// appends keep the pixel order instead.
 #ifndef EVRT_SHADE_TB
 #define EVRT_SHADE_TB 512
 #endif
@@ -1086,7 +1093,13 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
         const uint32_t oct = (ndx < 0.0f ? 1u : 0u) | (ndy < 0.0f ? 2u : 0u) | (ndz < 0.0f ? 4u : 0u) |
                              (ay >= fabsf(ndx) && ay >= fabsf(ndz) ? 8u : 0u) |
                              (EVRT_BINS >= 32 && fabsf(ndx) >= fabsf(ndz) ? 16u : 0u);
-        block_append_binned(s_app, par, want_shadow, light, want_ext, oct, cnt_sh + r, cnt_out + r, se, xe);
+        // With fewer than 64 samples per pixel a block spans many pixels,
+        // and the original (pixel-major) order keeps rays of one pixel
+        // together instead.
+        if (pc.bp >= 64)
+            block_append_binned(s_app, par, want_shadow, light, want_ext, oct, cnt_sh + r, cnt_out + r, se, xe);
+        else
+            block_append2(s_app, par, want_shadow, want_ext, cnt_sh + r, cnt_out + r, se, xe);
         se += pt.base;
         xe += pt.base;
         if (want_shadow) {
@@ -1701,13 +1714,14 @@ void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevSc
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
-                  uint32_t *cnt_sh, uint32_t depth, const Adjoint *adj)
+                  uint32_t *cnt_sh, uint32_t depth, uint32_t threads, const Adjoint *adj)
 {
+    // threads: a multiple of 64 up to kShadeTB (the kernel is block-size agnostic).
     if (adj)
-        hipLaunchKernelGGL(k_shade<true>, dim3(blocks), dim3(kShadeTB), 2 * adj->n_mat * sizeof(double), s, pc, sc, rp,
-                           qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj);
+        hipLaunchKernelGGL(k_shade<true>, dim3(blocks), dim3(threads), 2 * adj->n_mat * sizeof(double), s, pc, sc,
+                           rp, qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj);
     else
-        hipLaunchKernelGGL(k_shade<false>, dim3(blocks), dim3(kShadeTB), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
+        hipLaunchKernelGGL(k_shade<false>, dim3(blocks), dim3(threads), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
                            cnt_out, sq, cnt_sh, depth, Adjoint{});
 }
 
