@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "a32f6bc38883625e283016fb32edb844513ec77d65d296635aa160d93ebc89d1",
-           "bytes_per_launch": 488894261.9,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6927, "valu_lane_utilization": 0.563}, "k_trace_shadow": {"valu_busy": 0.5995, "valu_lane_utilization": 0.5656}, "k_shade": {"valu_busy": 0.454, "valu_lane_utilization": 0.6431}}}
+TRAFFIC = {"sources_sha256": "381ec9a4e0481ec41d500efad3888c13b1f2c08ce6b1a7c163bb328158f10a26",
+           "bytes_per_launch": 488328066.6,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6915, "valu_lane_utilization": 0.5631}, "k_trace_shadow": {"valu_busy": 0.6019, "valu_lane_utilization": 0.5658}, "k_shade": {"valu_busy": 0.4547, "valu_lane_utilization": 0.6351}}}
 
 
 def kernel_sources_digest() -> str:
