@@ -147,7 +147,10 @@ typedef struct {
     uint32_t key_base;       /* frame index of instant t0 in the random-number
                                 keys; t1 is key_base + 1 (default 0)              */
     uint32_t trace_blocks_per_cu; /* traversal blocks per CU (0: occupancy max)    */
-    uint32_t reserved;       /* must be 0                                          */
+    uint32_t replay_retrace; /* evrt_event_loss_grad: 1 = the replay traces its
+                                rays again; 0 (default) = it reads the closest
+                                hits and shadow visibility the forward pass
+                                logged, when the log fits in 16 GiB          */
 } evrt_render_opts;
 
 /* Fills *opts with the defaults listed above (seed 0). */
@@ -273,10 +276,13 @@ int evrt_decide_stats(evrt_ctx *ctx, const double *x0, const double *x1, uint32_
  *   loss  = sum over pixels of softplus((|Delta| - C) / tau), tau > 0,
  * a smooth stand-in for the count of events.  The gradient with respect to
  * every material's albedo and emitted radiance is computed by replaying
- * each path from its random-number keys (nothing per path is stored
- * besides its radiance) and differentiating its radiance with every
- * sampling decision held fixed: light pick, Russian roulette and scattering
- * directions.  This estimates the gradient of the expected loss terms
+ * each path from its random-number keys and differentiating its radiance
+ * with every sampling decision held fixed: light pick, Russian roulette and
+ * scattering directions.  The replay re-shades every vertex; its ray
+ * queries come from a log of the forward pass (closest hit, 8 bytes per
+ * path and vertex; shadow visibility, 4 bytes, with at most 31 point
+ * lights, count_work 0 and lds_nodes 0) unless opts->replay_retrace is 1 or
+ * the log would exceed 16 GiB, in which case they are traced again.  This estimates the gradient of the expected loss terms
  * without bias; it is reported for materials with albedo > 0 (albedo) and
  * emission > 0 (emission), zero elsewhere.
  *
@@ -290,8 +296,8 @@ int evrt_decide_stats(evrt_ctx *ctx, const double *x0, const double *x1, uint32_
  * Errors: EVRT_E_INVALID for tau <= 0, C < 0, non-finite arguments, spp not
  * a positive multiple of the mini-batch, NULL loss or grad;
  * EVRT_E_UNSUPPORTED for more than 2048 materials or 2^31 paths.  The
- * library keeps per-path radiances and weights (12 bytes per path) in its
- * own buffers between calls. */
+ * library keeps per-path radiances and weights (12 bytes per path) and the
+ * ray log in its own buffers between calls. */
 typedef struct {
     double *loss;
     double *grad;

@@ -61,7 +61,7 @@ void validate_opts(const evrt_render_opts &o)
     if (o.ref_mode > EVRT_REF_FULL) fail(EVRT_E_INVALID, "unknown ref_mode");
     if (o.lds_nodes > (uint32_t)lds_treelet_nodes()) fail(EVRT_E_INVALID, "lds_nodes above the treelet capacity");
     if (o.key_base > (1u << 24)) fail(EVRT_E_INVALID, "key_base above 2^24");
-    if (o.reserved != 0) fail(EVRT_E_INVALID, "reserved option field must be 0");
+    if (o.replay_retrace > 1) fail(EVRT_E_INVALID, "replay_retrace must be 0 or 1");
 }
 
 }  // namespace evrt

@@ -126,6 +126,7 @@ struct FrameBuffers {
     DevBuf hook_tm;
     DevBuf diff_px, diff_L, diff_W;  // event-loss gradient: pixel list, path radiance, weights
     DevBuf diff_R, diff_sw, diff_semat;  // adjoint replay: radiance, per-shadow-entry weight and emitter
+    DevBuf diff_hitlog, diff_vislog;     // ray log: closest hits, shadow visibility masks
     // Frame batches: per-(frame, pixel) state and item index, item list,
     // active pairs (two lists) with their items, checkpoint snapshots,
     // per-frame cameras.

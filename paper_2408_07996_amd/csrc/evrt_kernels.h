@@ -67,15 +67,23 @@ void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevS
                           const RayQueue &q, const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
                           uint32_t inst_base, float2 *hit, int stat_kind, unsigned long long *stat,
                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// Ray log of a gradient: vis_log (per-vertex slice indexed by radiance
+// index) is written by the forward pass (adj null: the tracing kernel also
+// stores each entry's mask of unoccluded slots) and read by the replay (adj
+// set: no tracing, the masks decide).  With vis_log: n_slots <= 32, count
+// false and no LDS treelet.  hit_log (per-vertex slice indexed by path id)
+// likewise: the forward shade writes each ray's hit, the replay shade reads
+// it in place of `hit`.
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
                          uint32_t n_split, uint32_t inst_base, float *rad, unsigned long long *stat,
                          hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
-                         const Adjoint *adj = nullptr);
+                         const Adjoint *adj = nullptr, uint32_t *vis_log = nullptr);
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
-                  uint32_t *cnt_sh, uint32_t depth, uint32_t threads, const Adjoint *adj = nullptr);
+                  uint32_t *cnt_sh, uint32_t depth, uint32_t threads, const Adjoint *adj = nullptr,
+                  float2 *hit_log = nullptr);
 void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
                        double *wf_mean, double *wf_m2, double *wf_ysum);
 // Welford updates and the decision at every checkpoint of the round, for

@@ -815,11 +815,13 @@ __device__ __forceinline__ void shadow_adj(const DevScene &sc, const Adjoint &ad
 // to the path radiance once.
 // ADJ: the adjoint replay also adds w c / Le of every unoccluded area-light
 // slot to the sampled emitter's material.
-template <bool COUNT, bool LDS, bool ADJ>
+// LOG: vis_log[radiance index] receives the entry's mask of unoccluded
+// slots (n_slots <= 32), which k_shadow_replay reads back.
+template <bool COUNT, bool LDS, bool ADJ, bool LOG = false>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_WAVES))) void k_trace_shadow(DevScene sc, ShadowQueue sq, uint32_t n_slots,
                                                       const uint32_t *cnt_in, uint32_t region,
                                                       uint32_t n_split, uint32_t inst_base, float *rad,
-                                                      unsigned long long *stat, Adjoint adj)
+                                                      unsigned long long *stat, Adjoint adj, uint32_t *vis_log)
 {
     __shared__ float4 s_nodes[8 * kLdsNodes];
     __shared__ uint32_t s_stack[kStackLds * kTB];
@@ -837,7 +839,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
     lds_u32 *lds_stack = (lds_u32 *)s_stack + threadIdx.x;
     WaveRange wr = wave_range(pt);
     Trav T;
-    uint32_t e = 0, slot = 0;
+    uint32_t e = 0, slot = 0, vmask = 0;
     float sum = 0.0f, c = 0.0f;
     bool busy = false;     // an entry is in progress
     bool tracing = false;  // its slot `slot` is being traced
@@ -847,6 +849,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             e = pt.base + j;
             slot = 0;
             sum = 0.0f;
+            if (LOG) vmask = 0;
             busy = true;
         }
         // Start the next slot with a contribution, or end the entry after
@@ -855,6 +858,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             if (slot >= n_slots) {
                 const uint32_t ri = fbits(sq.o[e].w);
                 rad[ri] = rad[ri] + sum;
+                if (LOG) vis_log[ri] = vmask;
                 busy = false;
                 break;
             }
@@ -868,6 +872,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
                 tracing = T.ref != kEmptyRef;
                 if (!tracing) {
                     sum = sum + c;
+                    if (LOG) vmask |= 1u << slot;
                     if (ADJ && slot == 0) shadow_adj(sc, adj, e, c, s_acc);
                     ++slot;
                 }
@@ -883,12 +888,14 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
             tracing = false;
             if (T.best_p == kNoPrim) {
                 sum = sum + c;
+                if (LOG) vmask |= 1u << slot;
                 if (ADJ && slot == 0) shadow_adj(sc, adj, e, c, s_acc);
             }
             ++slot;
             if (slot >= n_slots) {
                 const uint32_t ri = fbits(sq.o[e].w);
                 rad[ri] = rad[ri] + sum;
+                if (LOG) vis_log[ri] = vmask;
                 busy = false;
             }
         }
@@ -903,6 +910,36 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
         }
     }
     if (ADJ) adj_flush(s_acc, adj);
+}
+
+// Adjoint replay of the shadow entries from the visibility masks a logging
+// forward pass wrote (k_trace_shadow with LOG): the same sums in slot order
+// and the same adjoint terms, without tracing.
+__global__ __launch_bounds__(256) void k_shadow_replay(DevScene sc, ShadowQueue sq, uint32_t n_slots,
+                                                       const uint32_t *cnt_in, uint32_t region, uint32_t n_split,
+                                                       float *rad, Adjoint adj, const uint32_t *vis_log)
+{
+    extern __shared__ double s_acc[];
+    adj_clear(s_acc, adj);
+    __syncthreads();
+    for (uint32_t r = 0; r < n_split; ++r) {
+        const uint32_t n = cnt_in[r];
+        for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+            const uint32_t e = r * region + j;
+            const uint32_t ri = fbits(sq.o[e].w);
+            const uint32_t vm = vis_log[ri];
+            float sum = 0.0f;
+            for (uint32_t slot = 0; slot < n_slots; ++slot) {
+                const float c = sq.c[slot * sq.cap + e];
+                if (c > 0.0f && ((vm >> slot) & 1u)) {
+                    sum = sum + c;
+                    if (slot == 0) shadow_adj(sc, adj, e, c, s_acc);
+                }
+            }
+            rad[ri] = rad[ri] + sum;
+        }
+    }
+    adj_flush(s_acc, adj);
 }
 
 // Point light k seen from P with shading normal ns: contribution
@@ -944,7 +981,7 @@ template <bool ADJ>
 __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, RenderParams rp, RayQueue qin,
                                                const uint32_t *cnt_in, const float2 *hit,
                                                RayQueue qout, uint32_t *cnt_out, ShadowQueue sq,
-                                               uint32_t *cnt_sh, uint32_t depth, Adjoint adj)
+                                               uint32_t *cnt_sh, uint32_t depth, Adjoint adj, float2 *hit_log)
 {
     const Part pt = partition(cnt_in, pc.region, pc.n_inst);
     __shared__ BlockAppend s_app;
@@ -959,8 +996,13 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
         const uint32_t j = j0 + threadIdx.x;
         const bool valid = j < pt.n;
         const uint32_t i = pt.base + (valid ? j : 0u);
-        const float2 h = hit[i];
         const float4 o = qin.o[i], d = qin.d[i];
+        // hit_log (per-vertex slice, by path id): the replay reads the hit the
+        // logging forward pass wrote instead of a traced one.
+        float2 h;
+        if (ADJ && hit_log) h = hit_log[fbits(d.w) & ~kInstBit];
+        else h = hit[i];
+        if (!ADJ && hit_log && valid) hit_log[fbits(d.w) & ~kInstBit] = h;
         const uint32_t prim = valid ? fbits(h.y) : kNoPrim;
         bool want_shadow = false, want_ext = false;
         float Px = 0.0f, Py = 0.0f, Pz = 0.0f;
@@ -1684,45 +1726,57 @@ void launch_trace_closest(hipStream_t s, uint32_t blocks, bool count, const DevS
 void launch_trace_shadow(hipStream_t s, uint32_t blocks, bool count, const DevScene &sc,
                          const ShadowQueue &sq, uint32_t n_slots, const uint32_t *cnt_in, uint32_t region,
                          uint32_t n_split, uint32_t inst_base, float *rad, unsigned long long *stat,
-                         hipEvent_t ev_start, hipEvent_t ev_stop, const Adjoint *adj)
+                         hipEvent_t ev_start, hipEvent_t ev_stop, const Adjoint *adj, uint32_t *vis_log)
 {
     const bool lds = sc.inst[0].n_lds > 0 || sc.inst[1].n_lds > 0;
     const Adjoint a = adj ? *adj : Adjoint{};
+    if (vis_log) {
+        if (adj) {
+            const uint32_t bl = blocks ? blocks : 1u;
+            hipLaunchKernelGGL(k_shadow_replay, dim3(bl), dim3(256), 2 * adj->n_mat * sizeof(double), s, sc, sq,
+                               n_slots, cnt_in, region, n_split, rad, a, (const uint32_t *)vis_log);
+        } else {
+            hipExtLaunchKernelGGL((k_trace_shadow<false, false, false, true>), dim3(blocks), dim3(kTB), 0, s,
+                                  ev_start, ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad,
+                                  stat, a, vis_log);
+        }
+        return;
+    }
     if (adj) {
         // The adjoint replay counts no work; its accumulators are dynamic LDS.
         const size_t sh = 2 * adj->n_mat * sizeof(double);
         if (lds)
             hipExtLaunchKernelGGL((k_trace_shadow<false, true, true>), dim3(blocks), dim3(kTB), sh, s, ev_start,
-                                  ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+                                  ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a, nullptr);
         else
             hipExtLaunchKernelGGL((k_trace_shadow<false, false, true>), dim3(blocks), dim3(kTB), sh, s, ev_start,
-                                  ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+                                  ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a, nullptr);
     } else if (count && lds)
         hipExtLaunchKernelGGL((k_trace_shadow<true, true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop,
-                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a, nullptr);
     else if (count)
         hipExtLaunchKernelGGL((k_trace_shadow<true, false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop,
-                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a, nullptr);
     else if (lds)
         hipExtLaunchKernelGGL((k_trace_shadow<false, true, false>), dim3(blocks), dim3(kTB), 0, s, ev_start, ev_stop,
-                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+                              0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a, nullptr);
     else
         hipExtLaunchKernelGGL((k_trace_shadow<false, false, false>), dim3(blocks), dim3(kTB), 0, s, ev_start,
-                              ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a);
+                              ev_stop, 0, sc, sq, n_slots, cnt_in, region, n_split, inst_base, rad, stat, a, nullptr);
 }
 
 void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScene &sc,
                   const RenderParams &rp, const RayQueue &qin, const uint32_t *cnt_in,
                   const float2 *hit, const RayQueue &qout, uint32_t *cnt_out, const ShadowQueue &sq,
-                  uint32_t *cnt_sh, uint32_t depth, uint32_t threads, const Adjoint *adj)
+                  uint32_t *cnt_sh, uint32_t depth, uint32_t threads, const Adjoint *adj, float2 *hit_log)
 {
     // threads: a multiple of 64 up to kShadeTB (the kernel is block-size agnostic).
     if (adj)
         hipLaunchKernelGGL(k_shade<true>, dim3(blocks), dim3(threads), 2 * adj->n_mat * sizeof(double), s, pc, sc,
-                           rp, qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj);
+                           rp, qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj, hit_log);
     else
         hipLaunchKernelGGL(k_shade<false>, dim3(blocks), dim3(threads), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
-                           cnt_out, sq, cnt_sh, depth, Adjoint{});
+                           cnt_out, sq, cnt_sh, depth, Adjoint{}, hit_log);
 }
 
 void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,

@@ -18,6 +18,7 @@ namespace evrt {
 static constexpr uint32_t kDefaultRayBatch = 1u << 26;
 static constexpr uint32_t kMaxPathId = 1u << 31;
 static constexpr size_t kCacheInstants = 4;
+static constexpr uint64_t kMaxRayLog = 16ull << 30;  // bytes of a gradient's ray log
 
 static void cache_insert(evrt_ctx *c, double t, const std::shared_ptr<DevInstantBufs> &bi)
 {
@@ -201,11 +202,22 @@ struct Profiler {
     }
 };
 
+// Ray log of one piece of a gradient: slices of pc.n_paths entries per
+// vertex, the closest hit by path id and the shadow entry's mask of
+// unoccluded slots by radiance index (vis null: shadows are traced in both
+// passes).  The forward pass writes it; the replay (replay true) reads it
+// and traces nothing.
+struct RayLog {
+    float2 *hit;
+    uint32_t *vis;
+    bool replay;
+};
+
 // Traces one piece: camera rays, max_depth bounces of closest hit + shade
 // + shadow rays.  Path radiances land in pc.rad.
 static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const RenderParams &rp,
                         const evrt_render_opts &o, hipStream_t s, Profiler &prof, int ln = 0,
-                        const Adjoint *adj = nullptr)
+                        const Adjoint *adj = nullptr, const RayLog *log = nullptr)
 {
     FrameBuffers &fb = c->fb;
     LaneBufs &L = fb.lane[ln];
@@ -233,18 +245,23 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
     for (uint32_t d = 1; d <= rp.max_depth; ++d) {
         const RayQueue &qin = q[(d - 1) & 1];
         const RayQueue &qout = q[d & 1];
-        const EventPair ec = prof.take(0);
-        launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + 2 * (d - 1), pc.region, pc.n_inst,
-                             pc.inst_base, L.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat, ec.a,
-                             ec.b);
-        c->stats.n_closest_launches++;
+        const size_t slice = (size_t)(d - 1) * pc.n_paths;
+        float2 *hit_log = log ? log->hit + slice : nullptr;
+        uint32_t *vis_log = log && log->vis ? log->vis + slice : nullptr;
+        if (!(log && log->replay)) {
+            const EventPair ec = prof.take(0);
+            launch_trace_closest(s, tblocks, count, sc, qin, cnt + kCntRay0 + 2 * (d - 1), pc.region, pc.n_inst,
+                                 pc.inst_base, L.hit.as<float2>(), d == 1 ? kStatCamera : kStatExtension, stat,
+                                 ec.a, ec.b);
+            c->stats.n_closest_launches++;
+        }
         launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), L.hit.as<float2>(), qout,
-                     cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d, sthreads, adj);
+                     cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d, sthreads, adj, hit_log);
         if (rp.nee) {
             const EventPair es = prof.take(1);
             launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
-                                pc.n_inst, pc.inst_base, pc.rad, stat, es.a, es.b, adj);
-            c->stats.n_shadow_launches++;
+                                pc.n_inst, pc.inst_base, pc.rad, stat, es.a, es.b, adj, vis_log);
+            if (!(vis_log && adj)) c->stats.n_shadow_launches++;
         }
     }
     c->stats.pieces++;
@@ -708,9 +725,11 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
 // Every path sample s in [0, spp) of the listed pixels at both instants, in
 // pieces of the usual wavefront; radiances go to L_out[pixel][instant][s].
 // With adj, the pieces are the adjoint replay (same keys, same arithmetic).
+// log: the gradient's ray log over all pieces (piece at pixel a0 starts
+// at entry a0 * 2 spp * max_depth), or null.
 static void trace_paths(evrt_ctx *c, const DevScene &sc, const RenderParams &rp, const evrt_render_opts &o,
                         uint32_t n_pixels, const uint32_t *pixels, uint32_t spp, float *L_out,
-                        const Adjoint *adj, hipStream_t s)
+                        const Adjoint *adj, hipStream_t s, const RayLog *log = nullptr)
 {
     const uint32_t npx = sc.width * sc.height;
     const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
@@ -747,7 +766,14 @@ static void trace_paths(evrt_ctx *c, const DevScene &sc, const RenderParams &rp,
         pc.rad = L_out + (size_t)a0 * per_px;  // [pixel][instant][sample]
         pc.rs_a = 2 * spp;
         pc.rs_i = spp;
-        trace_piece(c, pc, sc, rp, o, s, prof, 0, adj ? &a : nullptr);
+        RayLog pl{};
+        if (log) {
+            const size_t base = (size_t)a0 * per_px * rp.max_depth;
+            pl.hit = log->hit + base;
+            pl.vis = log->vis ? log->vis + base : nullptr;
+            pl.replay = log->replay;
+        }
+        trace_piece(c, pc, sc, rp, o, s, prof, 0, adj ? &a : nullptr, log ? &pl : nullptr);
     }
 }
 
@@ -787,7 +813,25 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
     launch_diff_zero(s, out.loss, out.grad, 2 * n_mat, out.replay_mismatch);
     const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
-    trace_paths(c, sc, rp, o, npx, fb.diff_px.as<uint32_t>(), spp, fb.diff_L.as<float>(), nullptr, s);
+    // Ray log: the forward pass keeps every ray's closest hit (8 bytes per
+    // path and vertex) and, for up to 32 shadow slots without work counting
+    // or an LDS treelet, each shadow entry's visibility mask (4 bytes), so
+    // that the replay re-shades without tracing.  Above kMaxRayLog bytes, or
+    // with replay_retrace set, the replay traces its rays again.
+    const uint64_t log_n = 2ull * npx * spp * rp.max_depth;
+    const bool vis_ok = rp.nee && rp.n_slots <= 32 && !o.count_work && o.lds_nodes == 0;
+    const bool use_log = !o.replay_retrace && log_n * (8 + (vis_ok ? 4 : 0)) <= kMaxRayLog;
+    RayLog log{};
+    if (use_log) {
+        fb.diff_hitlog.ensure(sizeof(float2) * log_n);
+        log.hit = fb.diff_hitlog.as<float2>();
+        if (vis_ok) {
+            fb.diff_vislog.ensure(sizeof(uint32_t) * log_n);
+            log.vis = fb.diff_vislog.as<uint32_t>();
+        }
+    }
+    trace_paths(c, sc, rp, o, npx, fb.diff_px.as<uint32_t>(), spp, fb.diff_L.as<float>(), nullptr, s,
+                use_log ? &log : nullptr);
     launch_diff_stats(s, npx, spp, mb, (double)o.log_eps, (double)C, (double)tau, fb.diff_L.as<float>(),
                       fb.diff_W.as<double>(), out.loss, out.loss_px, out.delta);
     // Adjoint: the same pieces again with the gradient terms of every vertex,
@@ -801,7 +845,9 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
     adj.m = m;
     adj.mb = mb;
     adj.spp = spp;
-    trace_paths(c, sc, rp, o, npx, fb.diff_px.as<uint32_t>(), spp, fb.diff_R.as<float>(), &adj, s);
+    log.replay = true;
+    trace_paths(c, sc, rp, o, npx, fb.diff_px.as<uint32_t>(), spp, fb.diff_R.as<float>(), &adj, s,
+                use_log ? &log : nullptr);
     if (out.replay_mismatch)
         launch_diff_compare(s, 2ull * npx * spp, fb.diff_R.as<float>(), fb.diff_L.as<float>(), out.replay_mismatch);
     read_stats(c, s);

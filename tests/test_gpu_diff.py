@@ -20,7 +20,7 @@ def _say(msg):
 def _opts(P):
     o = dict(seed=P.get("seed", 0), max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
              minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
-    for k in ("ray_batch", "lds_nodes"):
+    for k in ("ray_batch", "lds_nodes", "replay_retrace"):
         if k in P:
             o[k] = P[k]
     return o
@@ -63,16 +63,20 @@ def test_event_loss_gradient_matches_oracle_small():
     assert np.abs(r["grad_albedo"]).max() > 0 and np.abs(r["grad_emission"]).max() > 0
 
 
-@pytest.mark.parametrize("variant", ["pieces", "lds_treelet", "no_nee"])
+@pytest.mark.parametrize("variant", ["pieces", "lds_treelet", "no_nee", "retrace"])
 def test_event_loss_gradient_variants(variant):
     """The replay in several pieces per pass (small ray batch: the shadow
-    entries' weights are per piece), with the LDS treelet, and without
-    next-event estimation (emission differentiated at every hit)."""
+    entries' weights and the ray log are per piece), with the LDS treelet
+    (closest hits logged, shadow rays traced again), without next-event
+    estimation (emission differentiated at every hit), and with every ray
+    of the replay traced again instead of read from the log."""
     P = dict(scenes.DIFF_PARAMS, spp=32)
     if variant == "pieces":
         P["ray_batch"] = 4096
     elif variant == "lds_treelet":
         P["lds_nodes"] = 32
+    elif variant == "retrace":
+        P["replay_retrace"] = 1
     else:
         P["nee"] = 0
     g, r = _compare(scenes.diff_scene(width=24, height=20), P)
