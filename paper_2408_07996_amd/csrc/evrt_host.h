@@ -125,7 +125,8 @@ struct FrameBuffers {
     LaneBufs lane[2];
     DevBuf hook_tm;
     DevBuf diff_px, diff_L, diff_W;  // event-loss gradient: pixel list, path radiance, weights
-    DevBuf diff_R, diff_sw, diff_semat;  // adjoint replay: radiance, per-shadow-entry weight and emitter
+    DevBuf diff_R;                       // adjoint replay: radiance
+    DevBuf diff_sw[2], diff_semat[2];    // per lane: weight and emitter of each shadow entry
     DevBuf diff_hitlog, diff_vislog;     // ray log: closest hits, shadow visibility masks
     // Frame batches: per-(frame, pixel) state and item index, item list,
     // active pairs (two lists) with their items, checkpoint snapshots,

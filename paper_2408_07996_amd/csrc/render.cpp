@@ -726,7 +726,9 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
 // pieces of the usual wavefront; radiances go to L_out[pixel][instant][s].
 // With adj, the pieces are the adjoint replay (same keys, same arithmetic).
 // log: the gradient's ray log over all pieces (piece at pixel a0 starts
-// at entry a0 * 2 spp * max_depth), or null.
+// at entry a0 * 2 spp * max_depth), or null.  Pieces alternate between the
+// caller's stream and the second lane's, in an even number of equal pixel
+// blocks, as in the frame.
 static void trace_paths(evrt_ctx *c, const DevScene &sc, const RenderParams &rp, const evrt_render_opts &o,
                         uint32_t n_pixels, const uint32_t *pixels, uint32_t spp, float *L_out,
                         const Adjoint *adj, hipStream_t s, const RayLog *log = nullptr)
@@ -734,22 +736,32 @@ static void trace_paths(evrt_ctx *c, const DevScene &sc, const RenderParams &rp,
     const uint32_t npx = sc.width * sc.height;
     const uint32_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
     const uint64_t per_px = 2ull * spp;
-    const uint32_t chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_pixels, batch / per_px));
-    ensure_buffers(c, npx, (uint32_t)std::min<uint64_t>((uint64_t)chunk * per_px, kMaxPathId - 1), rp.n_slots);
-    Adjoint a{};
+    const uint64_t block = std::max<uint64_t>(1, std::min<uint64_t>(n_pixels, batch / per_px));
+    const uint32_t chunk = (uint32_t)balanced_block(c, n_pixels, block);
+    const bool two = c->s2 != nullptr && n_pixels > chunk;
+    const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)chunk * per_px, kMaxPathId - 1);
+    for (int ln = 0; ln < (two ? 2 : 1); ++ln) ensure_buffers(c, npx, cap, rp.n_slots, ln);
+    Adjoint a[2]{};
     if (adj) {
-        // Weight and emitter of each shadow entry (queue slots of lane 0).
+        // Weight and emitter of each shadow entry (queue slots of the lane).
         FrameBuffers &fb = c->fb;
-        const uint32_t cap = fb.lane[0].queue_cap;
-        fb.diff_sw.ensure(sizeof(double) * cap);
-        fb.diff_semat.ensure(sizeof(uint32_t) * cap);
-        a = *adj;
-        a.sw = fb.diff_sw.as<double>();
-        a.semat = fb.diff_semat.as<uint32_t>();
+        for (int ln = 0; ln < (two ? 2 : 1); ++ln) {
+            const uint32_t qcap = fb.lane[ln].queue_cap;
+            fb.diff_sw[ln].ensure(sizeof(double) * qcap);
+            fb.diff_semat[ln].ensure(sizeof(uint32_t) * qcap);
+            a[ln] = *adj;
+            a[ln].sw = fb.diff_sw[ln].as<double>();
+            a[ln].semat = fb.diff_semat[ln].as<uint32_t>();
+        }
     }
     launch_init_frame(s, 0, nullptr, nullptr, nullptr, nullptr, nullptr, c->fb.cnt.as<uint32_t>(),
                       c->fb.stat.as<unsigned long long>());
+    if (two) {
+        hip_check(hipEventRecord(c->ev_fork, s), "fork");
+        hip_check(hipStreamWaitEvent(c->s2, c->ev_fork, 0), "fork wait");
+    }
     Profiler prof{c, false, 0, {}};
+    uint32_t piece = 0;
     for (uint32_t a0 = 0; a0 < n_pixels; a0 += chunk) {
         const uint32_t na = std::min(chunk, n_pixels - a0);
         Piece pc{};
@@ -773,7 +785,13 @@ static void trace_paths(evrt_ctx *c, const DevScene &sc, const RenderParams &rp,
             pl.vis = log->vis ? log->vis + base : nullptr;
             pl.replay = log->replay;
         }
-        trace_piece(c, pc, sc, rp, o, s, prof, 0, adj ? &a : nullptr, log ? &pl : nullptr);
+        const int ln = two ? (int)(piece & 1u) : 0;
+        ++piece;
+        trace_piece(c, pc, sc, rp, o, ln ? c->s2 : s, prof, ln, adj ? &a[ln] : nullptr, log ? &pl : nullptr);
+    }
+    if (two) {
+        hip_check(hipEventRecord(c->ev_join, c->s2), "join");
+        hip_check(hipStreamWaitEvent(s, c->ev_join, 0), "join wait");
     }
 }
 
