@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "c9571c3f182e16814bc7f29ea2169c313745a156c7523f5419f0a91d2f3eb8fc",
-           "bytes_per_launch": 488071092.3,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6915, "valu_lane_utilization": 0.563}, "k_trace_shadow": {"valu_busy": 0.6013, "valu_lane_utilization": 0.5656}, "k_shade": {"valu_busy": 0.4601, "valu_lane_utilization": 0.629}}}
+TRAFFIC = {"sources_sha256": "861c15a3b41d8da31e87716b9156e7e5833621f9048cc74bfe820a47ca0b1a1b",
+           "bytes_per_launch": 488028208.7,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6921, "valu_lane_utilization": 0.5627}, "k_trace_shadow": {"valu_busy": 0.6011, "valu_lane_utilization": 0.5654}, "k_shade": {"valu_busy": 0.4578, "valu_lane_utilization": 0.6283}}}
 
 
 def kernel_sources_digest() -> str:
