@@ -122,6 +122,8 @@ struct FrameBuffers {
     DevBuf wf_n, wf_mean, wf_m2, wf_ysum, act0, act1;
     DevBuf cnt, stat;
     DevBuf cnt1;  // per-bounce queue counts of lane 1 (lane 0 uses cnt)
+    DevBuf row_order;                   // first-round row order (first_rows)
+    std::vector<uint32_t> row_order_h;  // its host copy (the upload's source)
     LaneBufs lane[2];
     DevBuf hook_tm;
     DevBuf diff_px, diff_L, diff_W;  // event-loss gradient: pixel list, path radiance, weights

@@ -55,8 +55,12 @@ struct Outputs {
     uint8_t *flags;
 };
 
+// The first active list holds every pixel: in pixel order, or with rows
+// (device, rows[k] = image row at list row k, npx / width entries) row by
+// row in that order.
 void launch_init_frame(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
-                       double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat);
+                       double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat,
+                       uint32_t width = 1, const uint32_t *rows = nullptr);
 void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const RenderParams &rp,
                    const RayQueue &q, uint32_t *cnt);
 // Traversal and shading kernels take the per-region counts cnt_in[0..1],
@@ -112,7 +116,8 @@ void launch_diff_compare(hipStream_t s, uint64_t n, const float *a, const float 
 // Sequential video: current-frame slots cleared / references replaced at
 // events.
 void launch_video_frame_init(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
-                             double *wf_ysum, uint32_t *act, uint32_t *cnt);
+                             double *wf_ysum, uint32_t *act, uint32_t *cnt, uint32_t width = 1,
+                             const uint32_t *rows = nullptr);
 void launch_video_update(hipStream_t s, uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,
                          double *wf_m2, double *wf_ysum);
 

@@ -672,10 +672,21 @@ __device__ __forceinline__ void load_treelets(const DevScene &sc, uint32_t i0, u
 // ------------------------------------------------------------------------
 // Kernels.
 
+// Active-list entry i of a frame's first round: pixel i, or with a row
+// order (rows[k] = image row at list row k) the same column of row
+// rows[i / width].
+__device__ __forceinline__ uint32_t first_entry(uint32_t i, uint32_t width, const uint32_t *rows)
+{
+    if (!rows) return i;
+    const uint32_t k = i / width;
+    return rows[k] * width + (i - k * width);
+}
+
 // Clears the per-pixel accumulators, fills the active list with every
 // pixel and clears the frame counters.
-__global__ void k_init_frame(uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
-                             double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat)
+__global__ void k_init_frame(uint32_t npx, uint32_t width, const uint32_t *rows, uint32_t *wf_n, double *wf_mean,
+                             double *wf_m2, double *wf_ysum, uint32_t *act, uint32_t *cnt,
+                             unsigned long long *stat)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 2 * npx) {
@@ -684,7 +695,7 @@ __global__ void k_init_frame(uint32_t npx, uint32_t *wf_n, double *wf_mean, doub
         wf_m2[i] = 0.0;
         wf_ysum[i] = 0.0;
     }
-    if (i < npx) act[i] = i;
+    if (i < npx) act[i] = first_entry(i, width, rows);
     if (i == 0) {
         cnt[kCntActive] = 0;
         cnt[kCntActive + 1] = 0;
@@ -1345,8 +1356,8 @@ __global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParam
 
 // Start of a video frame: the current frame's statistics (second slot of
 // every pixel) cleared and every pixel active; the reference slot is kept.
-__global__ void k_video_frame_init(uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
-                                   double *wf_ysum, uint32_t *act, uint32_t *cnt)
+__global__ void k_video_frame_init(uint32_t npx, uint32_t width, const uint32_t *rows, uint32_t *wf_n,
+                                   double *wf_mean, double *wf_m2, double *wf_ysum, uint32_t *act, uint32_t *cnt)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < npx) {
@@ -1354,7 +1365,7 @@ __global__ void k_video_frame_init(uint32_t npx, uint32_t *wf_n, double *wf_mean
         wf_mean[2 * i + 1] = 0.0;
         wf_m2[2 * i + 1] = 0.0;
         wf_ysum[2 * i + 1] = 0.0;
-        act[i] = i;
+        act[i] = first_entry(i, width, rows);
     }
     if (i == 0) {
         cnt[kCntActive] = 0;
@@ -1689,11 +1700,12 @@ __global__ void k_diff_compare(uint64_t n, const float *a, const float *b, uint3
 // Launch wrappers.
 
 void launch_init_frame(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
-                       double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat)
+                       double *wf_ysum, uint32_t *act, uint32_t *cnt, unsigned long long *stat, uint32_t width,
+                       const uint32_t *rows)
 {
     const uint32_t n = 2 * npx;
-    hipLaunchKernelGGL(k_init_frame, dim3(std::max(1u, (n + 255) / 256)), dim3(256), 0, s, npx, wf_n,
-                       wf_mean, wf_m2, wf_ysum, act, cnt, stat);
+    hipLaunchKernelGGL(k_init_frame, dim3(std::max(1u, (n + 255) / 256)), dim3(256), 0, s, npx,
+                       std::max(1u, width), rows, wf_n, wf_mean, wf_m2, wf_ysum, act, cnt, stat);
 }
 
 void launch_raygen(hipStream_t s, const Piece &pc, const DevScene &sc, const RenderParams &rp,
@@ -1805,10 +1817,10 @@ void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_
 }
 
 void launch_video_frame_init(hipStream_t s, uint32_t npx, uint32_t *wf_n, double *wf_mean, double *wf_m2,
-                             double *wf_ysum, uint32_t *act, uint32_t *cnt)
+                             double *wf_ysum, uint32_t *act, uint32_t *cnt, uint32_t width, const uint32_t *rows)
 {
-    hipLaunchKernelGGL(k_video_frame_init, dim3(std::max(1u, (npx + 255) / 256)), dim3(256), 0, s, npx, wf_n,
-                       wf_mean, wf_m2, wf_ysum, act, cnt);
+    hipLaunchKernelGGL(k_video_frame_init, dim3(std::max(1u, (npx + 255) / 256)), dim3(256), 0, s, npx,
+                       std::max(1u, width), rows, wf_n, wf_mean, wf_m2, wf_ysum, act, cnt);
 }
 
 void launch_video_update(hipStream_t s, uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,

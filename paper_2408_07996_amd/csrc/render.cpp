@@ -478,6 +478,31 @@ static void frame_buffers(evrt_ctx *c, uint32_t npx, uint32_t spp_max, const evr
     ensure_buffers(c, npx, (uint32_t)cap, n_slots);
 }
 
+// Row order of a frame's first active list: rows by their bit-reversed
+// index (van der Corput order), so that cutting the list into 2, 4, 8 ...
+// equal blocks gives each block rows spread over the whole image and the
+// two lanes' pieces of the first round alike work (with the rows in image
+// order the lanes of the sensor frame's first round ended 3.6 ms apart).
+static const uint32_t *first_rows(evrt_ctx *c, uint32_t height, hipStream_t s)
+{
+    FrameBuffers &fb = c->fb;
+    if (fb.row_order_h.size() != height) {
+        uint32_t bits = 0;
+        while ((1u << bits) < height) ++bits;
+        std::vector<std::pair<uint32_t, uint32_t>> key(height);
+        for (uint32_t r = 0; r < height; ++r) {
+            uint32_t v = 0;
+            for (uint32_t b = 0; b < bits; ++b) v |= ((r >> b) & 1u) << (bits - 1 - b);
+            key[r] = {v, r};
+        }
+        std::sort(key.begin(), key.end());
+        fb.row_order_h.resize(height);
+        for (uint32_t k = 0; k < height; ++k) fb.row_order_h[k] = key[k].second;
+        fb.row_order.upload(fb.row_order_h.data(), sizeof(uint32_t) * height, s);
+    }
+    return fb.row_order.as<uint32_t>();
+}
+
 void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
                   uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o,
                   const evrt_frame_out &out, hipStream_t s)
@@ -491,9 +516,10 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
     const uint32_t npx = sc.width * sc.height;
     frame_buffers(c, npx, spp_max, o, rp.n_slots);
     FrameBuffers &fb = c->fb;
+    const uint32_t *rows = first_rows(c, sc.height, s);
     launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
                       fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
-                      fb.stat.as<unsigned long long>());
+                      fb.stat.as<unsigned long long>(), sc.width, rows);
     Profiler prof{c, o.profile != 0, 0, {}};
     const bool ref_full = o.ref_mode == EVRT_REF_FULL;
     if (ref_full) {
@@ -523,9 +549,10 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
     const uint32_t npx = sc0.width * sc0.height;
     frame_buffers(c, npx, spp_max, o, rp0.n_slots);
     FrameBuffers &fb = c->fb;
+    const uint32_t *rows = first_rows(c, sc0.height, s);
     launch_init_frame(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
                       fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(),
-                      fb.stat.as<unsigned long long>());
+                      fb.stat.as<unsigned long long>(), sc0.width, rows);
     Profiler prof{c, o.profile != 0, 0, {}};
     trace_range(c, fb.act0.as<uint32_t>(), npx, 1, 0, 0, spp_max, sc0, rp0, o, s, prof);
     for (uint32_t k = 1; k < n_frames; ++k) {
@@ -535,7 +562,8 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
         ok.key_base = o.key_base + k - 1;  // the second instant is frame key_base + k
         const RenderParams rp = make_params(c, ok);
         launch_video_frame_init(s, npx, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(), fb.wf_m2.as<double>(),
-                                fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>());
+                                fb.wf_ysum.as<double>(), fb.act0.as<uint32_t>(), fb.cnt.as<uint32_t>(), sc.width,
+                                rows);
         const size_t f = (size_t)(k - 1) * npx;
         Outputs outs{out.polarity + f, out.n_paths + f, out.mean + 2 * f, out.var + 2 * f,
                      out.t_last ? out.t_last + f : nullptr, out.mean_radiance ? out.mean_radiance + 2 * f : nullptr,
