@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "861c15a3b41d8da31e87716b9156e7e5833621f9048cc74bfe820a47ca0b1a1b",
-           "bytes_per_launch": 488028208.7,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6921, "valu_lane_utilization": 0.5627}, "k_trace_shadow": {"valu_busy": 0.6011, "valu_lane_utilization": 0.5654}, "k_shade": {"valu_busy": 0.4578, "valu_lane_utilization": 0.6283}}}
+TRAFFIC = {"sources_sha256": "778f53fd95fa8739efb75d5cbf1425a57cf7b64dfefc7b9af4e21828bdcf3d08",
+           "bytes_per_launch": 519883778.9,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6981, "valu_lane_utilization": 0.5594}, "k_trace_shadow": {"valu_busy": 0.5994, "valu_lane_utilization": 0.5642}, "k_shade": {"valu_busy": 0.4568, "valu_lane_utilization": 0.6278}}}
 
 
 def kernel_sources_digest() -> str:
