@@ -203,6 +203,8 @@ def main() -> int:
                     help="run only the timed adaptive frames (for profiler runs)")
     ap.add_argument("--ray-batch", type=int, default=0, help="paths in flight per piece (0: library default)")
     ap.add_argument("--lds-nodes", type=int, default=0, help="top BVH nodes staged in LDS")
+    ap.add_argument("--trace-blocks", type=int, default=0,
+                    help="traversal blocks per CU of the sensor frame (0: occupancy max)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
     ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video"), default="all",
@@ -243,7 +245,8 @@ def main() -> int:
     P = dict(scenes.SENSOR_PARAMS, C=args.C)
     base_opts = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
                      minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"],
-                     ray_batch=args.ray_batch, lds_nodes=args.lds_nodes)
+                     ray_batch=args.ray_batch, lds_nodes=args.lds_nodes,
+                     trace_blocks_per_cu=args.trace_blocks)
     r = ev.Renderer(0)
     t_build = time.perf_counter()
     r.set_scene(sc)
