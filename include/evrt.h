@@ -150,7 +150,8 @@ typedef struct {
     uint32_t replay_retrace; /* evrt_event_loss_grad: 1 = the replay traces its
                                 rays again; 0 (default) = it reads the closest
                                 hits and shadow visibility the forward pass
-                                logged, when the log fits in 16 GiB          */
+                                logged, when the log fits (see
+                                evrt_event_loss_grad)                        */
 } evrt_render_opts;
 
 /* Fills *opts with the defaults listed above (seed 0). */
@@ -282,7 +283,8 @@ int evrt_decide_stats(evrt_ctx *ctx, const double *x0, const double *x1, uint32_
  * queries come from a log of the forward pass (closest hit, 8 bytes per
  * path and vertex; shadow visibility, 4 bytes, with at most 31 point
  * lights, count_work 0 and lds_nodes 0) unless opts->replay_retrace is 1 or
- * the log would exceed 16 GiB, in which case they are traced again.  This estimates the gradient of the expected loss terms
+ * the log would exceed 16 GiB or half of the free device memory, in which
+ * case they are traced again.  This estimates the gradient of the expected loss terms
  * without bias; it is reported for materials with albedo > 0 (albedo) and
  * emission > 0 (emission), zero elsewhere.
  *

@@ -862,11 +862,16 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
     // Ray log: the forward pass keeps every ray's closest hit (8 bytes per
     // path and vertex) and, for up to 32 shadow slots without work counting
     // or an LDS treelet, each shadow entry's visibility mask (4 bytes), so
-    // that the replay re-shades without tracing.  Above kMaxRayLog bytes, or
+    // that the replay re-shades without tracing.  Above kMaxRayLog bytes or
+    // half of the free device memory (besides the log's current buffers), or
     // with replay_retrace set, the replay traces its rays again.
     const uint64_t log_n = 2ull * npx * spp * rp.max_depth;
     const bool vis_ok = rp.nee && rp.n_slots <= 32 && !o.count_work && o.lds_nodes == 0;
-    const bool use_log = !o.replay_retrace && log_n * (8 + (vis_ok ? 4 : 0)) <= kMaxRayLog;
+    size_t free_b = 0, total_b = 0;
+    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const uint64_t room =
+        std::min<uint64_t>(kMaxRayLog, fb.diff_hitlog.bytes + fb.diff_vislog.bytes + free_b / 2);
+    const bool use_log = !o.replay_retrace && log_n * (8 + (vis_ok ? 4 : 0)) <= room;
     RayLog log{};
     if (use_log) {
         fb.diff_hitlog.ensure(sizeof(float2) * log_n);
