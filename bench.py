@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "778f53fd95fa8739efb75d5cbf1425a57cf7b64dfefc7b9af4e21828bdcf3d08",
-           "bytes_per_launch": 519883778.9,
-           "counters": {"k_trace_closest": {"valu_busy": 0.6981, "valu_lane_utilization": 0.5594}, "k_trace_shadow": {"valu_busy": 0.5994, "valu_lane_utilization": 0.5642}, "k_shade": {"valu_busy": 0.4568, "valu_lane_utilization": 0.6278}}}
+TRAFFIC = {"sources_sha256": "9828ed330fbdc678e046dad601a89a841397c88d8041a45dc084b476002e12a3",
+           "bytes_per_launch": 519786291.2,
+           "counters": {"k_trace_closest": {"valu_busy": 0.6984, "valu_lane_utilization": 0.5594}, "k_trace_shadow": {"valu_busy": 0.5986, "valu_lane_utilization": 0.5641}, "k_shade": {"valu_busy": 0.4572, "valu_lane_utilization": 0.6278}}}
 
 
 def kernel_sources_digest() -> str:
