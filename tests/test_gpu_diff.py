@@ -92,6 +92,20 @@ def test_event_loss_gradient_matches_oracle_point_lights_mb8():
     _compare(sc, P)
 
 
+def test_event_loss_gradient_many_point_lights():
+    # 40 point lights: 41 shadow slots per vertex, more than a visibility
+    # mask holds, so the replay reads the logged closest hits and traces its
+    # shadow rays again.
+    sc = scenes.tiny_box(width=16, height=12)
+    import dataclasses
+    rng = np.random.default_rng(5)
+    pos = np.stack([rng.uniform(-0.8, 0.8, 40), rng.uniform(0.6, 1.8, 40), rng.uniform(-0.8, 0.8, 40)], 1)
+    sc = dataclasses.replace(sc, pl_pos=pos.astype(np.float32),
+                             pl_intensity=rng.uniform(0.05, 0.2, 40).astype(np.float32))
+    P = dict(scenes.DIFF_PARAMS, spp=16, max_depth=3)
+    _compare(sc, P)
+
+
 def test_autograd_matches_central_differences():
     import torch
     sc = scenes.tiny_box(width=16, height=12)
