@@ -402,7 +402,9 @@ class Renderer:
         """Smoothed event loss sum softplus((|Delta| - C) / tau) at spp paths
         per pixel and instant, and its path-replay gradient (float64 device
         tensors): loss [1], grad_albedo [n_mat], grad_emission [n_mat],
-        replay_mismatch [1]; with per_pixel also loss_px and delta [H*W]."""
+        replay_mismatch [1]; with per_pixel also loss_px and delta [H*W].
+        The replay re-shades from the forward pass's ray log; opts
+        replay_retrace=1 makes it trace its rays again."""
         import torch
         o = self._opts(opts)
         dev = torch.device("cuda", self.device)
