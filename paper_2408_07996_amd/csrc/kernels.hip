@@ -555,6 +555,15 @@ __device__ __forceinline__ bool traverse_step(Trav &T, const Geo &g, lds_u32 *ld
     return true;
 }
 
+// Lanes still looking for their leaf below which the speculative node loop
+// hands over to the leaf tests (1 / 2 / 4 / 6 / 8 / 12 / 16: 113.3 / 110.6 /
+// 109.0 / 108.3 / 108.3 / 108.6 / 110.0 ms per sensor frame; 1 waits for
+// every lane).
+#ifndef EVRT_SPEC_LACK
+#define EVRT_SPEC_LACK 8
+#endif
+constexpr int kSpecLack = EVRT_SPEC_LACK;
+
 // The same step with speculation (nodes in global memory only): a lane
 // that reaches a leaf sets it aside and goes on with its stack while other
 // lanes of the wave still look for their leaf; the set-aside leaves are
@@ -576,7 +585,14 @@ __device__ __forceinline__ bool traverse_step_spec(Trav &T, const Geo &g, lds_u3
             }
         }
         const bool node = T.ref >= 0;
-        if (!__any(node && leaf == kEmptyRef)) break;
+        // The node loop ends when no lane still looks for its leaf, or when
+        // fewer than kSpecLack lanes do and some lane holds one: the wave
+        // then tests the leaves it has and the lanes still looking go on in
+        // the next step, instead of the wave following a few lanes' long
+        // searches.  Every step visits a node or tests a leaf.
+        const unsigned long long lack = __ballot(node && leaf == kEmptyRef);
+        if (lack == 0ull) break;
+        if (__popcll(lack) < kSpecLack && __any(leaf != kEmptyRef)) break;
         if (node) {
             const uint32_t b = (uint32_t)T.ref << 7;
             if (COUNT) ++visits;
@@ -591,8 +607,7 @@ __device__ __forceinline__ bool traverse_step_spec(Trav &T, const Geo &g, lds_u3
     // through an empty statement makes the test below read each lane's own
     // register instead of a lane mask formed inside the loop.
     asm volatile("" : "+v"(leaf));
-    if (leaf == kEmptyRef) return false;
-    if (test_leaf<ANY, COUNT>(T, g, leaf, tests)) return false;
+    if (leaf != kEmptyRef && test_leaf<ANY, COUNT>(T, g, leaf, tests)) return false;
     return T.ref != kEmptyRef;
 }
 
