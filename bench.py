@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "05ca3e6706d7909751938abb2092beef9d2ab0eac340e9c951d999c5bcd1b080",
-           "bytes_per_launch": 516956348.8,
-           "counters": {"k_trace_closest": {"valu_busy": 0.7035, "valu_lane_utilization": 0.5554}, "k_trace_shadow": {"valu_busy": 0.6039, "valu_lane_utilization": 0.5669}, "k_shade": {"valu_busy": 0.4794, "valu_lane_utilization": 0.6405}}}
+TRAFFIC = {"sources_sha256": "9356c0c29b152b08253bb6d28358f65a3ee2eca0c83972c68d343947b2a4894c",
+           "bytes_per_launch": 521074170.7,
+           "counters": {"k_trace_closest": {"valu_busy": 0.7211, "valu_lane_utilization": 0.6019}, "k_trace_shadow": {"valu_busy": 0.6097, "valu_lane_utilization": 0.5949}, "k_shade": {"valu_busy": 0.4791, "valu_lane_utilization": 0.6405}}}
 
 
 def kernel_sources_digest() -> str:
