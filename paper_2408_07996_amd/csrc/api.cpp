@@ -156,8 +156,6 @@ int evrt_create(int hip_device, evrt_ctx **out)
             hip_check(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
             hip_check(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "hipEventCreate");
 #endif
-            for (int ln = 0; ln < 2; ++ln)
-                hip_check(hipStreamCreateWithFlags(&c->s_sh[ln], hipStreamNonBlocking), "hipStreamCreate");
             void *p = nullptr;
             hip_check(hipHostMalloc(&p, 64, hipHostMallocDefault), "hipHostMalloc");
             c->h_pinned = static_cast<uint32_t *>(p);
@@ -189,10 +187,6 @@ void evrt_destroy(evrt_ctx *c)
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_join) (void)hipEventDestroy(c->ev_join);
         if (c->s2) (void)hipStreamDestroy(c->s2);
-        for (int ln = 0; ln < 2; ++ln) {
-            for (hipEvent_t e : c->ev_lane[ln]) (void)hipEventDestroy(e);
-            if (c->s_sh[ln]) (void)hipStreamDestroy(c->s_sh[ln]);
-        }
     }
     delete c;
 }

@@ -158,8 +158,6 @@ struct evrt_ctx {
     evrt::FrameBuffers fb;
     hipStream_t s2 = nullptr;                // second lane's stream (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipStream_t s_sh[2] = {nullptr, nullptr};  // per lane: the shadow traces' stream (default priority)
-    std::vector<hipEvent_t> ev_lane[2];          // per lane: events ordering shade and shadow traces
     uint32_t *h_pinned = nullptr;            // pinned readback words
     unsigned long long *h_stat = nullptr;    // pinned stat readback
     std::vector<evrt::EventPair> events;

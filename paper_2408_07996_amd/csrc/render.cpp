@@ -213,24 +213,8 @@ struct RayLog {
     bool replay;
 };
 
-// Event i of lane ln's pool (created on first use).
-static hipEvent_t lane_event(evrt_ctx *c, int ln, size_t i)
-{
-    std::vector<hipEvent_t> &v = c->ev_lane[ln];
-    while (v.size() <= i) {
-        hipEvent_t e = nullptr;
-        hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
-        v.push_back(e);
-    }
-    return v[i];
-}
-
 // Traces one piece: camera rays, max_depth bounces of closest hit + shade
 // + shadow rays.  Path radiances land in pc.rad.
-// The shadow traces run on the lane's shadow stream: the shadow rays of
-// bounce d are traced while the closest hits of bounce d + 1 are, and shade
-// d + 1 waits for them (both add to the path radiance, and shade d + 1
-// refills the shadow queue); the piece ends joined back on stream s.
 static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const RenderParams &rp,
                         const evrt_render_opts &o, hipStream_t s, Profiler &prof, int ln = 0,
                         const Adjoint *adj = nullptr, const RayLog *log = nullptr)
@@ -258,11 +242,6 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
     const uint32_t sblocks = blocks_for(c->shade_blocks_per_cu * (smax / sthreads), c->cu_count, pc.n_paths,
                                         sthreads);
     const bool count = o.count_work != 0;
-#ifndef EVRT_SHADOW_STREAM
-#define EVRT_SHADOW_STREAM 1
-#endif
-    hipStream_t ss = c->s_sh[ln];
-    const bool split = EVRT_SHADOW_STREAM && ss != nullptr && rp.nee;
     for (uint32_t d = 1; d <= rp.max_depth; ++d) {
         const RayQueue &qin = q[(d - 1) & 1];
         const RayQueue &qout = q[d & 1];
@@ -276,24 +255,15 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
                                  ec.a, ec.b);
             c->stats.n_closest_launches++;
         }
-        if (split && d > 1) hip_check(hipStreamWaitEvent(s, lane_event(c, ln, 2 * (d - 1) + 1), 0), "shadow wait");
         launch_shade(s, sblocks, pc, sc, rp, qin, cnt + kCntRay0 + 2 * (d - 1), L.hit.as<float2>(), qout,
                      cnt + kCntRay0 + 2 * d, sq, cnt + kCntShadow0 + 2 * d, d, sthreads, adj, hit_log);
         if (rp.nee) {
-            hipStream_t sd = s;
-            if (split) {
-                hip_check(hipEventRecord(lane_event(c, ln, 2 * d), s), "shade done");
-                hip_check(hipStreamWaitEvent(ss, lane_event(c, ln, 2 * d), 0), "shade wait");
-                sd = ss;
-            }
             const EventPair es = prof.take(1);
-            launch_trace_shadow(sd, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
+            launch_trace_shadow(s, tblocks, count, sc, sq, rp.n_slots, cnt + kCntShadow0 + 2 * d, pc.region,
                                 pc.n_inst, pc.inst_base, pc.rad, stat, es.a, es.b, adj, vis_log);
-            if (split) hip_check(hipEventRecord(lane_event(c, ln, 2 * d + 1), ss), "shadow done");
             if (!(vis_log && adj)) c->stats.n_shadow_launches++;
         }
     }
-    if (split) hip_check(hipStreamWaitEvent(s, lane_event(c, ln, 2 * rp.max_depth + 1), 0), "shadow join");
     c->stats.pieces++;
     c->stats.paths += pc.n_paths;
 }
