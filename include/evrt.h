@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define EVRT_ABI_VERSION 2
+#define EVRT_ABI_VERSION 3
 
 enum {
     EVRT_OK = 0,
@@ -56,6 +56,15 @@ enum {
     EVRT_MODE_ADAPTIVE_2T = 2, /* stop on either tail at alpha/2                  */
     EVRT_MODE_MEAN_ONLY = 3    /* stop once |gap| <= C                            */
 };
+/* Degrees of freedom of the t-test (the paper states none, Sec. 3.2):
+ * STUDENT = pooled m0 + m1 - 2 (m0, m1 = mini-batches per instant; with
+ * equal counts Eq. 7 is then the pooled two-sample t statistic), compared
+ * with critical values of the schedule's counts.  WELCH = Welch-Satterthwaite
+ * for the variance estimate (s0^2 + s1^2) / m1 of Eq. 7,
+ * df = (s0^2 + s1^2)^2 / (s0^4 / (m0 - 1) + s1^4 / (m1 - 1)) (the pooled
+ * value when both variances are 0), real-valued and per pixel: each pixel
+ * compares its own lower-tail probability, from an FP64 Student t
+ * distribution function evaluated on the device, with alpha. */
 enum { EVRT_DF_STUDENT = 0, EVRT_DF_WELCH = 1 };
 /* LOCKSTEP: both instants hold the same sample count.  REF_FULL: the first
  * instant is rendered at spp_max and only the second one is adaptive (the
@@ -172,11 +181,25 @@ typedef struct {
 
 /* Renders one event frame for the instants (t0, t1) with threshold C >= 0,
  * significance 0 < alpha < 1 and the schedule spp_init, spp_init +
- * spp_batch, ... (clamped to spp_max) paths per instant.  spp_init,
- * spp_batch and spp_max must be multiples of opts->minibatch, spp_init at
- * least two mini-batches and at most spp_max.  opts NULL = defaults.
- * FIXED mode traces spp_max paths everywhere and applies only the event
- * rule. */
+ * spp_batch, ... (clamped to spp_max) paths per instant: Algorithm 1 for
+ * one pair of instants, per pixel.  Each path is the tracePaths estimator
+ * of Algorithm 1 (a path tracer as in Sec. 3.3); the mini-batch
+ * log-luminance samples give per-instant means and variances (Eq. 3-4);
+ * after every batch the t value of Eq. 7 is tested (Sec. 3.2: one-tailed,
+ * lower tail, by default) and a pixel whose gap is significantly below C
+ * stops with polarity 0; at spp_max the event rule of Algorithm 1 gives
+ * polarity sign(gap) when |gap| > C.  The first test runs at spp_init and
+ * later ones after every spp_batch (the schedule of Sec. 3.3).
+ * spp_init, spp_batch and spp_max must be multiples of opts->minibatch,
+ * spp_init at least two mini-batches and at most spp_max.  opts NULL =
+ * defaults.  FIXED mode traces spp_max paths everywhere and applies only
+ * the event rule (the comparison renderer of Sec. 4).
+ * Errors: EVRT_E_INVALID for a NULL required output, C < 0 or non-finite,
+ * alpha outside (0, 1), a schedule that breaks the rules above or bad
+ * options; EVRT_E_STATE before a scene commit; EVRT_E_UNSUPPORTED for
+ * spp_max above 2^24 or an image too large for one piece;
+ * EVRT_E_NOMEM / EVRT_E_DEVICE from the device.  All argument errors are
+ * reported before any device work. */
 int evrt_render_event_frame(evrt_ctx *ctx, double t0, double t1, float C, float alpha,
                             uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
                             const evrt_render_opts *opts, const evrt_frame_out *out,
@@ -185,10 +208,13 @@ int evrt_render_event_frame(evrt_ctx *ctx, double t0, double t1, float C, float 
 /* Sequential event video (Algorithm 1 over a sequence of frames): frame 0
  * at times[0] is rendered at spp_max and becomes every pixel's reference;
  * each frame k = 1 .. n_frames - 1 is sampled adaptively against the
- * pixel's reference, held at the full count (the test of REF_FULL mode:
- * Eq. 7 with N = the current frame's count, df = m_ref + m - 2), and where
- * it fires an event (which happens only at spp_max) it replaces the
- * reference.  Frame k is keyed opts->key_base + k; opts->ref_mode is not
+ * pixel's reference (the test of REF_FULL mode: Eq. 7 with N = the current
+ * frame's count, df = m_ref + m - 2 or Welch), and where it fires an event
+ * it replaces the reference with the frame's statistics at the count where
+ * the frame stopped.  Under the one-tailed and mean-only rules events
+ * happen only at spp_max; the two-tailed rule can fire early (upper tail),
+ * so a reference may hold fewer samples and the tests then take each
+ * pixel's own reference count into its degrees of freedom.  Frame k is keyed opts->key_base + k; opts->ref_mode is not
  * used.  Any scene motion is allowed.  Outputs as for one frame,
  * frame-major with n_frames - 1 entries per pixel: entry (k - 1) * width *
  * height + pixel holds frame k against its reference (x2 arrays: reference
@@ -258,12 +284,19 @@ int evrt_render_paths(evrt_ctx *ctx, double t0, double t1, uint32_t n_pixels,
                       float *L_out, void *stream);
 
 /* Runs the accumulator and decision kernels on caller log-luminance
- * samples: x0, x1 device double[n_pixels][m] (m >= 2).  Writes t_out[n]
- * (Eq. 7), stop_out[n] (1 when the rule of `mode` stops sampling) and
- * polarity_out[n] (event rule).  Student degrees of freedom 2m - 2. */
+ * samples (Eq. 3-4 statistics, the Eq. 7 test of Sec. 3.2, the event rule
+ * of Algorithm 1): x0, x1 device double[n_pixels][m] (m >= 2), pixel-major.
+ * Writes t_out[n] (Eq. 7 with N = m), stop_out[n] (1 when the rule of
+ * `mode` stops sampling at this count) and polarity_out[n] (event rule
+ * |gap| > C).  df_mode: EVRT_DF_STUDENT (2m - 2) or EVRT_DF_WELCH.  p_out
+ * (optional, NULL ok): device double[n], the lower-tail probability
+ * P(T <= t) at each pixel's degrees of freedom from the device's FP64 t
+ * distribution function.  All outputs are caller-owned device arrays.
+ * Errors: EVRT_E_INVALID for m < 2, C < 0, alpha outside (0, 1), an unknown
+ * mode or df_mode, or a NULL required array (n_pixels = 0 does nothing). */
 int evrt_decide_stats(evrt_ctx *ctx, const double *x0, const double *x1, uint32_t n_pixels,
-                      uint32_t m, float C, float alpha, uint8_t mode, double *t_out,
-                      uint8_t *stop_out, int8_t *polarity_out, void *stream);
+                      uint32_t m, float C, float alpha, uint8_t mode, uint8_t df_mode, double *t_out,
+                      uint8_t *stop_out, int8_t *polarity_out, double *p_out, void *stream);
 
 /* ---- Differentiation: a smoothed event loss and its gradient ---------
  *

@@ -125,7 +125,9 @@ def lib():
                                   _u32p, _u8p, _u32p, _f32p, ctypes.c_int]
     L.evo_decide.argtypes = [_f64p, ctypes.c_uint32, _f64p, ctypes.c_uint32, ctypes.c_float,
                              ctypes.c_float, ctypes.c_int, ctypes.c_int, _f64p, _f64p, _f64p,
-                             ctypes.POINTER(ctypes.c_int)]
+                             ctypes.POINTER(ctypes.c_int), _f64p]
+    L.evo_crit_margin.restype = ctypes.c_double
+    L.evo_crit_margin.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_int]
     L.evo_render.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _u32p, ctypes.c_uint32,
                              ctypes.c_int, ctypes.POINTER(_PixelOut)]
     L.evo_render_video.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.POINTER(Params),
@@ -168,20 +170,27 @@ def ibeta(a: float, b: float, x: float) -> float:
 
 def decide(x0, x1, C: float, alpha: float, df_mode: int = DF_STUDENT,
            mode: int = MODE_ADAPTIVE_1T) -> Dict[str, float]:
-    """t statistic (Eq. 7), lower-tail p-value, degrees of freedom and the
-    stop decision for two sets of log-luminance samples."""
+    """t statistic (Eq. 7), lower-tail p-value, degrees of freedom, the
+    stop decision and the exemption margin (distance of t from the
+    critical value(s) of `mode`) for two sets of log-luminance samples."""
     a = np.ascontiguousarray(x0, dtype=np.float64)
     b = np.ascontiguousarray(x1, dtype=np.float64)
     t = ctypes.c_double()
     p = ctypes.c_double()
     df = ctypes.c_double()
     stop = ctypes.c_int()
+    margin = ctypes.c_double()
     rc = lib().evo_decide(_ptr(a, ctypes.c_double), len(a), _ptr(b, ctypes.c_double), len(b),
                           float(C), float(alpha), int(df_mode), int(mode), ctypes.byref(t),
-                          ctypes.byref(p), ctypes.byref(df), ctypes.byref(stop))
+                          ctypes.byref(p), ctypes.byref(df), ctypes.byref(stop), ctypes.byref(margin))
     if rc != 0:
         raise ValueError("decide needs at least two samples per instant")
-    return dict(t=t.value, p=p.value, df=df.value, stop=bool(stop.value))
+    return dict(t=t.value, p=p.value, df=df.value, stop=bool(stop.value), margin=margin.value)
+
+
+def crit_margin(mode: int, t: float, df: float, alpha: float, final_check: bool = False) -> float:
+    """Exemption margin of one executed decision (see evo_crit_margin)."""
+    return float(lib().evo_crit_margin(int(mode), float(t), float(df), float(alpha), int(final_check)))
 
 
 def make_params(**kw) -> Params:

@@ -123,8 +123,6 @@ int evo_any_hit(const evo_frame *f, int instant, const float o[3], const float d
 float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
                         int instant, uint32_t sample);
 
-/* Decision on given logL sample sets (m0 samples at the reference instant,
- * m1 at the second); writes t, the p-value and the stop flag. */
 /* Record of one path for the derivatives of its radiance L with respect to
  * material albedos and emitted radiances, with every sampling decision
  * (light pick, Russian roulette, directions) held fixed: vertex k with
@@ -164,9 +162,17 @@ int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau
 int evo_render_video(const evo_frame *const *pairs, uint32_t n_frames, const evo_params *p,
                      const uint32_t *pixels, uint32_t n_pixels, int n_threads, evo_pixel_out *out);
 
+/* Decision on given logL sample sets (m0 samples at the reference instant,
+ * m1 at the second): t of Eq. 7, its lower-tail p-value, the degrees of
+ * freedom, the stop flag of `mode`, and (margin_out may be NULL) the
+ * exemption margin of this test as a checkpoint before the last count. */
 int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
                float C, float alpha, int df_mode, int mode,
-               double *t_out, double *p_out, double *df_out, int *stop_out);
+               double *t_out, double *p_out, double *df_out, int *stop_out, double *margin_out);
+
+/* Exemption margin of one executed decision (|t - critical value| for the
+ * boundaries of `mode`; |t| for the event rule at the last count). */
+double evo_crit_margin(int mode, double t, double df, float alpha, int final_check);
 
 int evo_paths_batch(const evo_frame *f, const evo_params *p, uint32_t n, const uint32_t *pixel,
                     const uint8_t *instant, const uint32_t *sample, float *out, int n_threads);

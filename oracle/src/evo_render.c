@@ -249,21 +249,16 @@ typedef struct {
     double *y[2];
 } pixel_scratch;
 
-static void update_margin(double *margin, double value)
-{
-    if (value < *margin) *margin = value;
-}
-
-/* Algorithm 1 for one pixel and one pair of instants. */
-/* One pixel of one pair.  ref_given: the first instant's samples are
- * already in ws->x[0] / ws->y[0] at the full count (a carried reference). */
+/* Algorithm 1 for one pixel and one pair of instants.  ref_n > 0: the
+ * first instant's samples are already in ws->x[0] / ws->y[0], ref_n paths
+ * of them (a carried reference), and are not sampled further. */
 static void render_pixel(const evo_frame *f, const evo_params *p, uint32_t pixel,
-                         pixel_scratch *ws, evo_pixel_out *o, int ref_given)
+                         pixel_scratch *ws, evo_pixel_out *o, uint32_t ref_n)
 {
     const uint32_t mb = p->minibatch;
-    const int full_ref = ref_given || p->ref_mode == EVO_REF_FULL;
+    const int full_ref = ref_n > 0 || p->ref_mode == EVO_REF_FULL;
     const int fixed = p->mode == EVO_MODE_FIXED;
-    uint32_t n_prev[2] = {ref_given ? p->spp_max : 0u, 0};
+    uint32_t n_prev[2] = {ref_n, 0};
     uint32_t n1 = fixed ? p->spp_max : p->spp_init;
     double margin = INFINITY;
     double mean[2] = {0, 0}, var[2] = {0, 0}, t = 0.0, df = 0.0, pl = 0.0;
@@ -272,7 +267,7 @@ static void render_pixel(const evo_frame *f, const evo_params *p, uint32_t pixel
     memset(o, 0, sizeof(*o));
 
     for (;;) {
-        uint32_t target[2] = {full_ref ? p->spp_max : n1, n1};
+        uint32_t target[2] = {ref_n > 0 ? ref_n : (full_ref ? p->spp_max : n1), n1};
         for (int i = 0; i < 2; ++i) {
             for (uint32_t s = n_prev[i]; s < target[i]; ++s)
                 ws->L[i][s] = evo_path_radiance(f, p, pixel, i, s);
@@ -286,19 +281,13 @@ static void render_pixel(const evo_frame *f, const evo_params *p, uint32_t pixel
         ++rounds;
         const uint32_t m0 = target[0] / mb, m1 = target[1] / mb;
         evo__stats_decide(ws->x[0], m0, ws->x[1], m1, p, mean, var, &t, &df, &pl, &stop);
-        if (n1 >= p->spp_max) {
+        const int final_check = n1 >= p->spp_max;
+        const double mg = evo_crit_margin(p->mode, t, df, p->alpha, final_check);
+        if (mg < margin) margin = mg;
+        if (final_check) {
             /* Final event rule |gap| > C, i.e. t > 0. */
-            update_margin(&margin, fabs(t));
             stop = 0;
             break;
-        }
-        if (p->mode == EVO_MODE_ADAPTIVE_1T) {
-            update_margin(&margin, fabs(t - evo_t_ppf((double)p->alpha, df)));
-        } else if (p->mode == EVO_MODE_ADAPTIVE_2T) {
-            update_margin(&margin, fabs(t - evo_t_ppf(0.5 * (double)p->alpha, df)));
-            update_margin(&margin, fabs(t - evo_t_ppf(1.0 - 0.5 * (double)p->alpha, df)));
-        } else if (p->mode == EVO_MODE_MEAN_ONLY) {
-            update_margin(&margin, fabs(t));
         }
         if (stop) break;
         n1 = n1 + p->spp_batch < p->spp_max ? n1 + p->spp_batch : p->spp_max;
@@ -346,7 +335,7 @@ static void *render_worker(void *arg)
     for (;;) {
         uint32_t k = __atomic_fetch_add(&job->next, 1u, __ATOMIC_RELAXED);
         if (k >= job->n_pixels) break;
-        render_pixel(job->f, p, job->pixels[k], &ws, &job->out[k], 0);
+        render_pixel(job->f, p, job->pixels[k], &ws, &job->out[k], 0u);
     }
     for (int i = 0; i < 2; ++i) { free(ws.L[i]); free(ws.x[i]); free(ws.y[i]); }
     return NULL;
@@ -403,15 +392,23 @@ static void *video_worker(void *arg)
     for (;;) {
         uint32_t i = __atomic_fetch_add(&job->next, 1u, __ATOMIC_RELAXED);
         if (i >= job->n_pixels) break;
+        /* Paths in the pixel's reference: 0 before frame 0 is rendered (the
+         * first pair renders it at the full count). */
+        uint32_t ref_n = 0;
         for (uint32_t k = 1; k < job->n_frames; ++k) {
             evo_params pk = *p;
             pk.ref_mode = EVO_REF_FULL;
             pk.key_base = p->key_base + k - 1;
             evo_pixel_out *o = &job->out[(size_t)(k - 1) * job->n_pixels + i];
-            render_pixel(job->pairs[k - 1], &pk, job->pixels[i], &ws, o, k > 1);
+            render_pixel(job->pairs[k - 1], &pk, job->pixels[i], &ws, o, ref_n);
+            ref_n = o->n_paths_ref;
             if (o->polarity != 0) {
-                memcpy(ws.x[0], ws.x[1], sizeof(double) * mmax);
-                memcpy(ws.y[0], ws.y[1], sizeof(double) * mmax);
+                /* The frame's samples up to its stop become the reference
+                 * (a two-tailed test can fire before spp_max). */
+                const uint32_t m = o->n_paths / p->minibatch;
+                memcpy(ws.x[0], ws.x[1], sizeof(double) * m);
+                memcpy(ws.y[0], ws.y[1], sizeof(double) * m);
+                ref_n = o->n_paths;
             }
         }
     }

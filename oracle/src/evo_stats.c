@@ -195,9 +195,31 @@ static int stop_rule(int mode, double t, double p_lower, double gap_abs, double 
     }
 }
 
+/* Exemption margin of one executed decision: the distance of t from the
+ * critical value(s) that decide it, so that a pixel whose t lies within
+ * rounding noise of a boundary may legitimately go either way.  At the last
+ * count only the event rule |gap| > C applies, i.e. the boundary t = 0.
+ * One-tailed: t_alpha(df); two-tailed: t_{alpha/2}(df) and
+ * t_{1-alpha/2}(df); mean-only: |gap| <= C, again t = 0; fixed mode tests
+ * nothing before the last count. */
+double evo_crit_margin(int mode, double t, double df, float alpha, int final_check)
+{
+    if (final_check) return fabs(t);
+    switch (mode) {
+    case EVO_MODE_ADAPTIVE_1T: return fabs(t - evo_t_ppf((double)alpha, df));
+    case EVO_MODE_ADAPTIVE_2T: {
+        double lo = fabs(t - evo_t_ppf(0.5 * (double)alpha, df));
+        double hi = fabs(t - evo_t_ppf(1.0 - 0.5 * (double)alpha, df));
+        return lo < hi ? lo : hi;
+    }
+    case EVO_MODE_MEAN_ONLY: return fabs(t);
+    default: return INFINITY;
+    }
+}
+
 int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
                float C, float alpha, int df_mode, int mode,
-               double *t_out, double *p_out, double *df_out, int *stop_out)
+               double *t_out, double *p_out, double *df_out, int *stop_out, double *margin_out)
 {
     if (m0 < 2 || m1 < 2) return -1;
     double mean0, var0, mean1, var1;
@@ -210,6 +232,7 @@ int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
     *p_out = p;
     *df_out = df;
     *stop_out = stop_rule(mode, t, p, fabs(mean1 - mean0), (double)C, (double)alpha);
+    if (margin_out) *margin_out = evo_crit_margin(mode, t, df, alpha, 0);
     return 0;
 }
 

@@ -21,7 +21,7 @@ from typing import Dict, Optional
 import numpy as np
 
 __all__ = ["Renderer", "EvrtError", "default_opts", "load_library", "MODE_ADAPTIVE_1T", "MODE_FIXED",
-           "MODE_ADAPTIVE_2T", "MODE_MEAN_ONLY", "REF_LOCKSTEP", "REF_FULL"]
+           "MODE_ADAPTIVE_2T", "MODE_MEAN_ONLY", "DF_STUDENT", "DF_WELCH", "REF_LOCKSTEP", "REF_FULL"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # EVRT_LIBRARY may point at another build of the same library (tuning runs).
@@ -110,7 +110,8 @@ SIGNATURES = [
     ("evrt_render_paths", ctypes.c_int,
      [_c_p, ctypes.c_double, ctypes.c_double, _u32, _c_p, _u32, ctypes.POINTER(RenderOpts), _c_p, _c_p]),
     ("evrt_decide_stats", ctypes.c_int,
-     [_c_p, _c_p, _c_p, _u32, _u32, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, _c_p, _c_p, _c_p, _c_p]),
+     [_c_p, _c_p, _c_p, _u32, _u32, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, ctypes.c_uint8, _c_p, _c_p,
+      _c_p, _c_p, _c_p]),
     ("evrt_event_loss_grad", ctypes.c_int,
      [_c_p, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float, _u32, ctypes.POINTER(RenderOpts),
       ctypes.POINTER(DiffOut), _c_p]),
@@ -424,8 +425,11 @@ class Renderer:
             res.update(loss_px=lpx, delta=dpx)
         return res
 
-    def decide_stats(self, x0, x1, C: float, alpha: float, mode: int = MODE_ADAPTIVE_1T, stream=None):
-        """Decision kernels on caller log-luminance samples [n, m] (float64)."""
+    def decide_stats(self, x0, x1, C: float, alpha: float, mode: int = MODE_ADAPTIVE_1T,
+                     df_mode: int = DF_STUDENT, want_p: bool = False, stream=None):
+        """Decision kernels on caller log-luminance samples [n, m] (float64).
+        Returns (t, stop, polarity) and, with want_p, the lower-tail
+        probability of t at each pixel's degrees of freedom (device CDF)."""
         import torch
         dev = torch.device("cuda", self.device)
         a = torch.as_tensor(x0, dtype=torch.float64).to(dev).contiguous()
@@ -434,10 +438,11 @@ class Renderer:
         t = torch.empty(n, dtype=torch.float64, device=dev)
         stop = torch.empty(n, dtype=torch.uint8, device=dev)
         pol = torch.empty(n, dtype=torch.int8, device=dev)
+        p = torch.empty(n, dtype=torch.float64, device=dev) if want_p else None
         self._check(load_library().evrt_decide_stats(self._h, _dptr(a), _dptr(b), n, m, float(C), float(alpha),
-                                                     int(mode), _dptr(t), _dptr(stop), _dptr(pol),
-                                                     _stream_ptr(stream)))
-        return t, stop, pol
+                                                     int(mode), int(df_mode), _dptr(t), _dptr(stop), _dptr(pol),
+                                                     _dptr(p) if p is not None else None, _stream_ptr(stream)))
+        return (t, stop, pol, p) if want_p else (t, stop, pol)
 
 
 # ---------------------------------------------------------------------------

@@ -379,7 +379,6 @@ static void validate_frame_args(const evrt_render_opts &o, float C, float alpha,
     if (spp_batch == 0 && spp_init < spp_max && o.mode != EVRT_MODE_FIXED)
         fail(EVRT_E_INVALID, "spp_batch must be positive");
     if (spp_max > (1u << 24)) fail(EVRT_E_UNSUPPORTED, "spp_max above 2^24");
-    if (o.df_mode == EVRT_DF_WELCH) fail(EVRT_E_UNSUPPORTED, "Welch degrees of freedom are not implemented");
 }
 
 int evrt_render_event_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
@@ -519,8 +518,8 @@ int evrt_event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, 
 }
 
 int evrt_decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n_pixels, uint32_t m, float C,
-                      float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *polarity_out,
-                      void *stream)
+                      float alpha, uint8_t mode, uint8_t df_mode, double *t_out, uint8_t *stop_out,
+                      int8_t *polarity_out, double *p_out, void *stream)
 {
     return guarded(c, [&] {
         need_ctx(c);
@@ -528,10 +527,11 @@ int evrt_decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t 
         if (!std::isfinite(C) || C < 0.0f) fail(EVRT_E_INVALID, "C must be finite and >= 0");
         if (!(alpha > 0.0f && alpha < 1.0f)) fail(EVRT_E_INVALID, "alpha must be in (0, 1)");
         if (mode > EVRT_MODE_MEAN_ONLY) fail(EVRT_E_INVALID, "unknown mode");
+        if (df_mode > EVRT_DF_WELCH) fail(EVRT_E_INVALID, "unknown df_mode");
         if (n_pixels == 0) return;
         if (!x0 || !x1 || !t_out || !stop_out || !polarity_out) fail(EVRT_E_INVALID, "NULL array");
         need_device(c);
-        decide_stats(c, x0, x1, n_pixels, m, C, alpha, mode, t_out, stop_out, polarity_out,
+        decide_stats(c, x0, x1, n_pixels, m, C, alpha, mode, df_mode, t_out, stop_out, polarity_out, p_out,
                      static_cast<hipStream_t>(stream));
     });
 }

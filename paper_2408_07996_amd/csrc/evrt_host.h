@@ -180,8 +180,8 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
 void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip, int any,
                 float *t_out, uint32_t *p_out, hipStream_t s);
 void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
-                  float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
-                  hipStream_t s);
+                  float alpha, uint8_t mode, uint8_t df_mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
+                  double *p_out, hipStream_t s);
 void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, float alpha, uint32_t spp_init,
                   uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o, const evrt_frame_out &out,
                   hipStream_t s);

@@ -19,12 +19,18 @@ constexpr int kCntSize = 320;
 // of the mini-batch schedule: checkpoint j ends at sample count ck_end[j]
 // at the second instant and is tested with crit_lo[j] / crit_hi[j].
 constexpr uint32_t kMaxChecks = 32;
+// With df_per_pixel set the tests do not use the critical values: each
+// pixel's degrees of freedom (Welch, or pooled over the pixel's own counts)
+// give the lower-tail probability of its t, compared with alpha.
 struct Decide {
     double C;
+    double alpha;
     double crit_lo[kMaxChecks], crit_hi[kMaxChecks];  // t critical values (lower, upper tail)
     uint32_t ck_end[kMaxChecks];
     uint32_t n_checks;
     uint32_t mode;             // EVRT_MODE_*
+    uint32_t df_mode;          // EVRT_DF_* (with df_per_pixel)
+    uint32_t df_per_pixel;
     uint32_t final_round;      // 1 when the last checkpoint is spp_max: event rule only
     uint32_t minibatch;
     uint32_t cnt_slot;         // which of the two compaction counters this round uses
@@ -103,8 +109,10 @@ void launch_hook_rays(hipStream_t s, uint32_t n, const float *rays, const uint32
                       const RayQueue &q, float *tminmax, uint32_t *cnt);
 void launch_hook_trace(hipStream_t s, uint32_t blocks, bool any, const DevScene &sc, const RayQueue &q,
                        const float *tminmax, uint32_t n, float *t_out, uint32_t *p_out);
+// p_out (may be null): lower-tail probability of each t at the pixel's
+// degrees of freedom (dc.df_mode), from the device CDF.
 void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint32_t n, uint32_t m,
-                        const Decide &dc, double *t_out, uint8_t *stop_out, int8_t *pol_out);
+                        const Decide &dc, double *t_out, uint8_t *stop_out, int8_t *pol_out, double *p_out);
 
 // Event loss and its gradient: zeroing, per-pixel statistics and weights,
 // path-replay adjoint (g = [albedo gradients | emission gradients]).

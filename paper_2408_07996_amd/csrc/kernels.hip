@@ -15,6 +15,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "../../include/evrt.h"
 #include "evrt_kernels.h"
 
 namespace evrt {
@@ -1280,9 +1281,108 @@ __device__ __forceinline__ double t_value(double mean0, double var0, double mean
     return gap / sqrt(S / (double)m1);
 }
 
+// ------------------------------------------------------------------------
+// Student t lower tail P(T <= t) for real degrees of freedom df > 0, FP64,
+// for tests whose df varies per pixel.  For t < 0 it is I_x(df/2, 1/2) / 2
+// with x = df / (df + t^2) (the t distribution function as a regularized
+// incomplete beta function), and I_x(a, b) is summed from its hypergeometric
+// representation (DLMF 8.17(ii)):
+//   I_x(a, b) = x^a (1 - x)^b / (a B(a, b)) * sum_n [(a + b)_n / (a + 1)_n] x^n,
+// whose terms shrink at least by the factor x.  For x > 0.9 the complement
+// I_x(a, 1/2) = 1 - I_y(1/2, a), y = 1 - x, is summed the same way in y.
+// Relative error below 1e-10 for 1e-4 < p < 0.5, where the decisions fall,
+// and below 1e-8 for p >= 1e-6; deeper in the tails the complement's
+// cancellation leaves an absolute error below 1e-13 (there p << alpha).
+
+// ln Gamma(a + 1/2) - ln Gamma(a): for a >= 40 the difference of Stirling's
+// series (three correction terms, then a log1p form that keeps the O(1/a)
+// remainder exact), so that large a does not cancel two large lgammas.
+__device__ double lgamma_half_diff(double a)
+{
+    if (a < 40.0) return lgamma(a + 0.5) - lgamma(a);
+    const double z = a + 0.5;
+    const double iz = 1.0 / z, ia = 1.0 / a;
+    const double iz2 = iz * iz, ia2 = ia * ia;
+    double d = a * log1p(0.5 * ia) - 0.5 + 0.5 * log(a);
+    d = d + (iz - ia) / 12.0;
+    d = d - (iz * iz2 - ia * ia2) / 360.0;
+    d = d + (iz * iz2 * iz2 - ia * ia2 * ia2) / 1260.0;
+    return d;
+}
+
+__device__ double t_lower_tail(double t, double df)
+{
+    if (isnan(t) || !(df > 0.0)) return NAN;
+    if (t == 0.0) return 0.5;
+    if (isinf(t)) return t < 0.0 ? 0.0 : 1.0;
+    const bool upper = t > 0.0;   // P(T <= t) = 1 - P(T <= -t)
+    const double a = 0.5 * df;
+    const double t2 = t * t;
+    const double lx = -log1p(t2 / df);           // ln x
+    const double x = exp(lx);
+    const double y = t2 / (df + t2);
+    const double ly = log(y);
+    const double ln_beta = 0.5723649429247001 - lgamma_half_diff(a);  // ln B(a, 1/2); ln sqrt(pi)
+    double tail;                                  // P(T <= -|t|)
+    if (x <= 0.9) {
+        double term = 1.0, sum = 1.0;
+        for (int n = 0; n < 1000; ++n) {
+            term = term * ((a + 0.5 + n) / (a + 1.0 + n) * x);
+            sum = sum + term;
+            if (term < 1e-17 * sum) break;
+        }
+        tail = 0.5 * exp(a * lx + 0.5 * ly - log(a) - ln_beta) * sum;
+    } else if ((a + 0.5) * y > 200.0) {
+        // |t| > sqrt(400 x): below 1e-80 at every df this branch can reach.
+        tail = 0.0;
+    } else {
+        double term = 1.0, sum = 1.0;
+        for (int n = 0; n < 1000; ++n) {
+            term = term * ((a + 0.5 + n) / (1.5 + n) * y);
+            sum = sum + term;
+            if (term < 1e-17 * sum) break;
+        }
+        // I_y(1/2, a) = y^(1/2) x^a / ((1/2) B(a, 1/2)) * sum
+        const double comp = exp(0.5 * ly + a * lx + 0.6931471805599453 - ln_beta) * sum;
+        tail = 0.5 * (1.0 - comp);
+    }
+    return upper ? 1.0 - tail : tail;
+}
+
+// Degrees of freedom of the test on (m0, var0) and (m1, var1) mini-batch
+// samples: pooled m0 + m1 - 2, or Welch-Satterthwaite for the variance
+// estimate (var0 + var1) / m1 of Eq. 7, (var0 + var1)^2 / (var0^2 / (m0 - 1)
+// + var1^2 / (m1 - 1)); the pooled value when both variances are zero.
+__device__ __forceinline__ double test_df(uint32_t df_mode, uint32_t m0, double var0, uint32_t m1, double var1)
+{
+    const double pooled = (double)m0 + (double)m1 - 2.0;
+    if (df_mode != EVRT_DF_WELCH) return pooled;
+    const double S = var0 + var1;
+    const double den = var0 * var0 / (double)(m0 - 1) + var1 * var1 / (double)(m1 - 1);
+    return den > 0.0 ? S * S / den : pooled;
+}
+
+// Stopping rule at checkpoint j (Sec. 3.2): one-tailed, stop when t lies in
+// the lower alpha tail (|gap| significantly below C); two-tailed, alpha / 2
+// in either tail; mean-only, once |gap| <= C; fixed, never.
+__device__ __forceinline__ bool stop_rule(const Decide &dc, uint32_t j, double t, double gap, uint32_t m0,
+                                          double var0, uint32_t m1, double var1)
+{
+    if (dc.mode == EVRT_MODE_MEAN_ONLY) return fabs(gap) <= dc.C;
+    if (dc.mode != EVRT_MODE_ADAPTIVE_1T && dc.mode != EVRT_MODE_ADAPTIVE_2T) return false;
+    if (!dc.df_per_pixel) {
+        if (dc.mode == EVRT_MODE_ADAPTIVE_1T) return t < dc.crit_lo[j];
+        return t < dc.crit_lo[j] || t > dc.crit_hi[j];
+    }
+    const double df = test_df(dc.df_mode, m0, var0, m1, var1);
+    if (dc.mode == EVRT_MODE_ADAPTIVE_1T) return t_lower_tail(t, df) < dc.alpha;
+    return t_lower_tail(t, df) < 0.5 * dc.alpha || t_lower_tail(-t, df) < 0.5 * dc.alpha;
+}
+
 // Decision for one pixel at checkpoint j of the round (Eq. 7 against the
-// checkpoint's critical values; at the last checkpoint of the schedule only
-// the event rule of Alg. 1).  A finished pixel writes its outputs.
+// checkpoint's critical values, or each pixel's own tail probability; at the
+// last checkpoint of the schedule only the event rule of Alg. 1).  A
+// finished pixel writes its outputs.
 __device__ __forceinline__ bool decide_pixel(const Decide &dc, uint32_t j, bool final_ck, uint32_t pixel,
                                              const Welford &w0, const Welford &w1, const Outputs &out)
 {
@@ -1291,12 +1391,7 @@ __device__ __forceinline__ bool decide_pixel(const Decide &dc, uint32_t j, bool 
     const double var1 = m1 > 1 ? w1.m2 / (double)(m1 - 1) : 0.0;
     const double t = t_value(w0.mean, var0, w1.mean, var1, m1, dc.C);
     const double gap = w1.mean - w0.mean;
-    bool stop = false;
-    if (!final_ck) {
-        if (dc.mode == 0) stop = t < dc.crit_lo[j];
-        else if (dc.mode == 2) stop = t < dc.crit_lo[j] || t > dc.crit_hi[j];
-        else if (dc.mode == 3) stop = fabs(gap) <= dc.C;
-    }
+    const bool stop = !final_ck && stop_rule(dc, j, t, gap, m0, var0, m1, var1);
     const bool done = stop || final_ck;
     if (done) {
         out.polarity[pixel] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
@@ -1613,9 +1708,9 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
 }
 
 // Decision hook: Welford over caller samples, then the decision kernel's
-// arithmetic.
+// stopping and event rules; optionally the lower-tail probability of t.
 __global__ void k_hook_decide(const double *x0, const double *x1, uint32_t n, uint32_t m, Decide dc,
-                              double *t_out, uint8_t *stop_out, int8_t *pol_out)
+                              double *t_out, uint8_t *stop_out, int8_t *pol_out, double *p_out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1633,13 +1728,11 @@ __global__ void k_hook_decide(const double *x0, const double *x1, uint32_t n, ui
     }
     const double t = t_value(mean[0], var[0], mean[1], var[1], m, dc.C);
     const double gap = mean[1] - mean[0];
-    bool stop = false;
-    if (dc.mode == 0) stop = t < dc.crit_lo[0];
-    else if (dc.mode == 2) stop = t < dc.crit_lo[0] || t > dc.crit_hi[0];
-    else if (dc.mode == 3) stop = fabs(gap) <= dc.C;
+    const bool stop = stop_rule(dc, 0, t, gap, m, var[0], m, var[1]);
     t_out[i] = t;
     stop_out[i] = stop ? 1 : 0;
     pol_out[i] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
+    if (p_out) p_out[i] = t_lower_tail(t, test_df(dc.df_mode, m, var[0], m, var[1]));
 }
 
 // ------------------------------------------------------------------------
@@ -1938,10 +2031,10 @@ void launch_hook_trace(hipStream_t s, uint32_t blocks, bool any, const DevScene 
 }
 
 void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint32_t n, uint32_t m,
-                        const Decide &dc, double *t_out, uint8_t *stop_out, int8_t *pol_out)
+                        const Decide &dc, double *t_out, uint8_t *stop_out, int8_t *pol_out, double *p_out)
 {
     hipLaunchKernelGGL(k_hook_decide, dim3((n + 255) / 256), dim3(256), 0, s, x0, x1, n, m, dc, t_out,
-                       stop_out, pol_out);
+                       stop_out, pol_out, p_out);
 }
 
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu)

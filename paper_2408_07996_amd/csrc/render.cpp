@@ -280,6 +280,33 @@ static double crit_value(evrt_ctx *c, double p, uint32_t df)
     return q;
 }
 
+// Tests of a round's checkpoints.  Pooled degrees of freedom that follow
+// from the schedule (m0 mini-batches at the first instant: the checkpoint's
+// own count in lock step, m0_fixed when the first instant holds a fixed
+// count) become critical values per checkpoint; Welch degrees of freedom,
+// or a first instant whose count differs per pixel (a video reference),
+// make every pixel compare its own tail probability with alpha.
+static void set_tests(evrt_ctx *c, Decide &dc, const evrt_render_opts &o, float alpha, uint32_t spp_max,
+                      uint32_t m0_fixed, bool per_pixel_ref)
+{
+    dc.alpha = (double)alpha;
+    dc.df_mode = o.df_mode;
+    dc.df_per_pixel = (o.df_mode == EVRT_DF_WELCH || per_pixel_ref) ? 1u : 0u;
+    if (dc.df_per_pixel) return;
+    for (uint32_t j = 0; j < dc.n_checks; ++j) {
+        if (dc.ck_end[j] >= spp_max) break;
+        const uint32_t m1 = dc.ck_end[j] / dc.minibatch;
+        const uint32_t m0 = m0_fixed ? m0_fixed : m1;
+        const uint32_t df = m0 + m1 - 2;
+        if (o.mode == EVRT_MODE_ADAPTIVE_1T) {
+            dc.crit_lo[j] = crit_value(c, (double)alpha, df);
+        } else if (o.mode == EVRT_MODE_ADAPTIVE_2T) {
+            dc.crit_lo[j] = crit_value(c, 0.5 * (double)alpha, df);
+            dc.crit_hi[j] = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
+        }
+    }
+}
+
 // Pieces covering samples [lo, hi) of nA pixels at n_inst instants.  A
 // piece holds at most `ray_batch` paths: blocks of consecutive active pixels
 // with the whole sample range when that fits, otherwise every pixel with a
@@ -393,9 +420,12 @@ static void read_stats(evrt_ctx *c, hipStream_t s)
 // The adaptive rounds of one pair over the active list (every pixel of
 // fb.act0 at entry): both instants in lock step, or only the second one
 // against a first instant already held at the full count (ref_full).
+// ref_per_pixel: the first instant holds a count of its own per pixel (a
+// video reference), so the tests take each pixel's degrees of freedom.
 static void run_rounds(evrt_ctx *c, const DevScene &sc, const RenderParams &rp, const evrt_render_opts &o,
                        float C, float alpha, uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
-                       bool ref_full, uint32_t nA, const Outputs &outs, hipStream_t s, Profiler &prof)
+                       bool ref_full, uint32_t nA, const Outputs &outs, hipStream_t s, Profiler &prof,
+                       bool ref_per_pixel = false)
 {
     FrameBuffers &fb = c->fb;
     const uint32_t mb = o.minibatch;
@@ -428,18 +458,7 @@ static void run_rounds(evrt_ctx *c, const DevScene &sc, const RenderParams &rp, 
             dc.ck_end[dc.n_checks++] = hi;
         }
         dc.final_round = hi >= spp_max ? 1u : 0u;
-        for (uint32_t j = 0; j < dc.n_checks; ++j) {
-            if (dc.ck_end[j] >= spp_max) break;
-            const uint32_t m1 = dc.ck_end[j] / mb;
-            const uint32_t m0 = ref_full ? spp_max / mb : m1;
-            const uint32_t df = m0 + m1 - 2;
-            if (o.mode == EVRT_MODE_ADAPTIVE_1T) {
-                dc.crit_lo[j] = crit_value(c, (double)alpha, df);
-            } else if (o.mode == EVRT_MODE_ADAPTIVE_2T) {
-                dc.crit_lo[j] = crit_value(c, 0.5 * (double)alpha, df);
-                dc.crit_hi[j] = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
-            }
-        }
+        set_tests(c, dc, o, alpha, spp_max, ref_full ? spp_max / mb : 0u, ref_per_pixel);
         const bool fused = trace_range(c, act_in, nA, n_inst, inst_base, n_prev, hi, sc, rp, o, s, prof, &dc,
                                        act_out, &outs);
         if (!fused)
@@ -568,7 +587,10 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
         Outputs outs{out.polarity + f, out.n_paths + f, out.mean + 2 * f, out.var + 2 * f,
                      out.t_last ? out.t_last + f : nullptr, out.mean_radiance ? out.mean_radiance + 2 * f : nullptr,
                      out.flags ? out.flags + f : nullptr};
-        run_rounds(c, sc, rp, ok, C, alpha, spp_init, spp_batch, spp_max, true, npx, outs, s, prof);
+        // A two-tailed test can fire an event before spp_max (upper tail), so
+        // references then hold fewer samples than spp_max.
+        run_rounds(c, sc, rp, ok, C, alpha, spp_init, spp_batch, spp_max, true, npx, outs, s, prof,
+                   o.mode == EVRT_MODE_ADAPTIVE_2T);
         launch_video_update(s, npx, outs.polarity, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(),
                             fb.wf_m2.as<double>(), fb.wf_ysum.as<double>());
     }
@@ -654,16 +676,7 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
             dc.ck_end[dc.n_checks++] = hi;
         }
         dc.final_round = hi >= spp_max ? 1u : 0u;
-        for (uint32_t j = 0; j < dc.n_checks; ++j) {
-            if (dc.ck_end[j] >= spp_max) break;
-            const uint32_t df = 2 * (dc.ck_end[j] / mb) - 2;
-            if (o.mode == EVRT_MODE_ADAPTIVE_1T) {
-                dc.crit_lo[j] = crit_value(c, (double)alpha, df);
-            } else if (o.mode == EVRT_MODE_ADAPTIVE_2T) {
-                dc.crit_lo[j] = crit_value(c, 0.5 * (double)alpha, df);
-                dc.crit_hi[j] = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
-            }
-        }
+        set_tests(c, dc, o, alpha, spp_max, 0u, false);
         double *snap = nullptr;
         if (dc.n_checks > 1) {
             fb.b_snap.ensure(sizeof(double) * 3 * (size_t)n_items * dc.n_checks);
@@ -923,22 +936,20 @@ void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint
 }
 
 void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
-                  float alpha, uint8_t mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
-                  hipStream_t s)
+                  float alpha, uint8_t mode, uint8_t df_mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
+                  double *p_out, hipStream_t s)
 {
     Decide dc{};
     dc.C = (double)C;
     dc.mode = mode;
     dc.minibatch = 1;
     dc.n_checks = 1;
-    const uint32_t df = 2 * m - 2;
-    if (mode == EVRT_MODE_ADAPTIVE_1T) {
-        dc.crit_lo[0] = crit_value(c, (double)alpha, df);
-    } else if (mode == EVRT_MODE_ADAPTIVE_2T) {
-        dc.crit_lo[0] = crit_value(c, 0.5 * (double)alpha, df);
-        dc.crit_hi[0] = crit_value(c, 1.0 - 0.5 * (double)alpha, df);
-    }
-    launch_hook_decide(s, x0, x1, n, m, dc, t_out, stop_out, pol_out);
+    dc.ck_end[0] = m;
+    evrt_render_opts o{};
+    o.mode = mode;
+    o.df_mode = df_mode;
+    set_tests(c, dc, o, alpha, m + 1, 0u, false);
+    launch_hook_decide(s, x0, x1, n, m, dc, t_out, stop_out, pol_out, p_out);
     hip_check(hipStreamSynchronize(s), "decide hook");
 }
 

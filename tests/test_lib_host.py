@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
     bound = {s[0] for s in ev.SIGNATURES}
     assert set(names) == bound
-    assert L.evrt_abi_version() == 2
+    assert L.evrt_abi_version() == 3
 
 
 def test_default_opts():
@@ -113,8 +113,11 @@ def test_render_argument_validation_before_device_work(host_ctx):
         rc, msg = _render_rc(r, **kw)
         assert rc == ev.EVRT_E_INVALID, (kw, rc, msg)
         assert msg
+    rc, msg = _render_rc(r, df_mode=2)
+    assert rc == ev.EVRT_E_INVALID and "df_mode" in msg
+    # Welch degrees of freedom are served: valid options reach the device check.
     rc, msg = _render_rc(r, df_mode=ev.DF_WELCH)
-    assert rc == ev.EVRT_E_UNSUPPORTED
+    assert rc == ev.EVRT_E_DEVICE and "host-only" in msg
     # Valid arguments reach the device check last.
     rc, msg = _render_rc(r)
     assert rc == ev.EVRT_E_DEVICE and "host-only" in msg
