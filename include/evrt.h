@@ -276,6 +276,29 @@ int evrt_trace_rays(evrt_ctx *ctx, double t, uint32_t n, const float *rays,
                     const uint32_t *skip, int any_hit, float *t_out, uint32_t *prim_out,
                     void *stream);
 
+/* ---- Entry point that allocates nothing ---------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * ray queries as evrt_trace_rays (same arguments, same kernels, identical
+ * results), except that:
+ *   - n <= EVRT_NOALLOC_MAX_RAYS; larger n returns EVRT_E_INVALID before
+ *     any device work;
+ *   - the call allocates nothing: the rays are staged in a static device
+ *     array of the library (44 bytes per ray, 44 MiB + 256 bytes), which
+ *     every GPU the library runs on holds until the process ends;
+ *   - nothing is built: the scene at time t must already be resident on the
+ *     device (an earlier evrt_trace_rays or render call at t, or, when no
+ *     instance moves, at any time); otherwise EVRT_E_STATE;
+ *   - the call only enqueues its two kernels on `stream` and returns; the
+ *     outputs are valid once the stream has reached them.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on the
+ * same GPU (different streams or host threads, any contexts) race and must
+ * be serialized by the caller. */
+#define EVRT_NOALLOC_MAX_RAYS (1u << 20)
+int evrt_trace_rays_noalloc(evrt_ctx *ctx, double t, uint32_t n, const float *rays,
+                            const uint32_t *skip, int any_hit, float *t_out, uint32_t *prim_out,
+                            void *stream);
+
 /* Radiance of every path sample s in [0, spp) of the listed pixels at both
  * instants (the tracePaths estimator of Algorithm 1), written to device
  * L_out[n_pixels][2][spp].  pixels: device uint32[n_pixels]. */

@@ -107,6 +107,8 @@ SIGNATURES = [
       ctypes.POINTER(FrameOut), _c_p]),
     ("evrt_get_frame_stats", ctypes.c_int, [_c_p, ctypes.POINTER(FrameStats)]),
     ("evrt_trace_rays", ctypes.c_int, [_c_p, ctypes.c_double, _u32, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, _c_p]),
+    ("evrt_trace_rays_noalloc", ctypes.c_int,
+     [_c_p, ctypes.c_double, _u32, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, _c_p]),
     ("evrt_render_paths", ctypes.c_int,
      [_c_p, ctypes.c_double, ctypes.c_double, _u32, _c_p, _u32, ctypes.POINTER(RenderOpts), _c_p, _c_p]),
     ("evrt_decide_stats", ctypes.c_int,
@@ -397,6 +399,16 @@ class Renderer:
         self._check(load_library().evrt_trace_rays(self._h, float(t), n, _dptr(r), _dptr(sk), int(bool(any_hit)),
                                                    _dptr(tt), _dptr(prim), _stream_ptr(stream)))
         return prim if any_hit else (tt, prim)
+
+    def trace_rays_noalloc(self, t: float, rays, skip, any_hit: bool, t_out, prim_out, stream=None) -> None:
+        """evrt_trace_rays_noalloc on caller device tensors (rays float32
+        [n, 8], skip uint32/int32 [n] or None, t_out float32 [n] (None with
+        any_hit), prim_out int32 [n]): enqueues the query on the stream and
+        returns; allocates nothing."""
+        n = int(rays.shape[0])
+        self._check(load_library().evrt_trace_rays_noalloc(
+            self._h, float(t), n, _dptr(rays), _dptr(skip) if skip is not None else None, int(bool(any_hit)),
+            _dptr(t_out) if t_out is not None else None, _dptr(prim_out), _stream_ptr(stream)))
 
     def event_loss_grad(self, t0: float, t1: float, C: float, tau: float, spp: int, opts=None,
                         per_pixel: bool = False, stream=None) -> Dict:

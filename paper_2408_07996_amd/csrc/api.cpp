@@ -162,6 +162,7 @@ int evrt_create(int hip_device, evrt_ctx **out)
             hip_check(hipHostMalloc(&p, sizeof(unsigned long long) * kStatCount, hipHostMallocDefault),
                       "hipHostMalloc");
             c->h_stat = static_cast<unsigned long long *>(p);
+            hip_check(noalloc_scratch_address(hip_device, &c->noalloc_scratch), "hipGetSymbolAddress(scratch)");
         }
     });
     if (rc != EVRT_OK) {
@@ -472,6 +473,25 @@ int evrt_trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const 
         if (!rays || !prim_out || (!any_hit && !t_out)) fail(EVRT_E_INVALID, "NULL ray or output array");
         need_device(c);
         trace_rays(c, t, n, rays, skip, any_hit, t_out, prim_out, static_cast<hipStream_t>(stream));
+    });
+}
+
+static_assert(EVRT_NOALLOC_MAX_RAYS == kNoAllocRays, "header and library disagree on the no-alloc limit");
+
+int evrt_trace_rays_noalloc(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip,
+                            int any_hit, float *t_out, uint32_t *prim_out, void *stream)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
+        if (!std::isfinite(t)) fail(EVRT_E_INVALID, "t must be finite");
+        if (n == 0) return;
+        if (n > EVRT_NOALLOC_MAX_RAYS)
+            fail(EVRT_E_INVALID, "n = " + std::to_string(n) + " rays is above the no-alloc maximum of " +
+                                     std::to_string(EVRT_NOALLOC_MAX_RAYS));
+        if (!rays || !prim_out || (!any_hit && !t_out)) fail(EVRT_E_INVALID, "NULL ray or output array");
+        need_device(c);
+        trace_rays_noalloc(c, t, n, rays, skip, any_hit, t_out, prim_out, static_cast<hipStream_t>(stream));
     });
 }
 

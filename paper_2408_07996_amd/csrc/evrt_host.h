@@ -166,6 +166,7 @@ struct evrt_ctx {
     uint32_t cu_count = 0;
     uint32_t trace_blocks_per_cu = 0;
     uint32_t shade_blocks_per_cu = 0;
+    void *noalloc_scratch = nullptr;         // this device's static scratch array
 };
 
 namespace evrt {
@@ -179,6 +180,11 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
                   uint32_t spp, const evrt_render_opts &o, float *L_out, hipStream_t s);
 void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip, int any,
                 float *t_out, uint32_t *p_out, hipStream_t s);
+// The same ray queries with the rays staged in the device's static scratch
+// array: no allocation, no BVH build (the instant must be resident), no
+// synchronization.
+void trace_rays_noalloc(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip, int any,
+                        float *t_out, uint32_t *p_out, hipStream_t s);
 void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
                   float alpha, uint8_t mode, uint8_t df_mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
                   double *p_out, hipStream_t s);

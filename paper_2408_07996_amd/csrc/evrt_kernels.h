@@ -147,6 +147,23 @@ void launch_batch_decide(hipStream_t s, const Decide &dc, const uint32_t *act, u
                          const double *wf_mean, const double *wf_m2, const double *wf_ysum, const double *snap,
                          uint32_t *act_out, uint32_t *cnt, const Outputs &out);
 
+// Entry point that allocates nothing (evrt_trace_rays_noalloc): at most
+// kNoAllocRays rays per call, staged in a static device array of
+// kNoAllocScratchBytes (44 bytes per ray: origin and direction float4, skip
+// primitive, (tmin, tmax); then the counter words).  noalloc_scratch_address
+// returns the array's device address on `device`, which must be current;
+// it resolves the address once per device and keeps it.
+constexpr uint32_t kNoAllocRays = 1u << 20;
+constexpr size_t kNoAllocScratchBytes = 44 * (size_t)kNoAllocRays + 256;
+struct NoAllocScratch {
+    float4 *o, *d;
+    uint32_t *skip;
+    float *tminmax;
+    uint32_t *cnt;
+};
+NoAllocScratch noalloc_layout(void *base);
+hipError_t noalloc_scratch_address(int device, void **out);
+
 void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu);
 int traverse_block_threads();
 int shade_block_threads();  // largest shade block (the kernel's launch bound)

@@ -12,6 +12,8 @@
 // step; sin, cos and log are evaluated in FP64 (sin/cos rounded to FP32)
 // and statistics are FP64.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include <hip/hip_ext.h>
 
@@ -2051,5 +2053,48 @@ int shade_block_threads() { return kShadeTB; }
 int traverse_block_threads() { return kTB; }
 int lds_treelet_nodes() { return kLdsNodes; }
 int traverse_max_depth() { return kStackMax / 3; }
+
+}  // namespace evrt
+
+// ------------------------------------------------------------------------
+// Scratch of evrt_trace_rays_noalloc, for callers that cannot allocate: a
+// file-scope device array; every GPU the library runs on holds its own copy
+// until the process ends.  On the host the array's name only stands in for
+// the symbol: host code resolves each device's address with
+// hipGetSymbolAddress (once per device) and passes that address to kernels.
+static __device__ __align__(256) unsigned char scratch[evrt::kNoAllocScratchBytes];
+
+namespace evrt {
+
+NoAllocScratch noalloc_layout(void *base)
+{
+    unsigned char *b = static_cast<unsigned char *>(base);
+    const size_t n = kNoAllocRays;
+    NoAllocScratch l;
+    l.o = reinterpret_cast<float4 *>(b);
+    l.d = reinterpret_cast<float4 *>(b + 16 * n);
+    l.skip = reinterpret_cast<uint32_t *>(b + 32 * n);
+    l.tminmax = reinterpret_cast<float *>(b + 36 * n);
+    l.cnt = reinterpret_cast<uint32_t *>(b + 44 * n);
+    return l;
+}
+
+hipError_t noalloc_scratch_address(int device, void **out)
+{
+    static std::mutex mu;
+    static std::vector<void *> by_device;
+    std::lock_guard<std::mutex> lock(mu);
+    *out = nullptr;
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((size_t)device >= by_device.size()) by_device.resize((size_t)device + 1, nullptr);
+    if (!by_device[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        by_device[device] = p;
+    }
+    *out = by_device[device];
+    return hipSuccess;
+}
 
 }  // namespace evrt

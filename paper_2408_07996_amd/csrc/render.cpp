@@ -935,6 +935,28 @@ void trace_rays(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint
     hip_check(hipStreamSynchronize(s), "trace hook");
 }
 
+void trace_rays_noalloc(evrt_ctx *c, double t, uint32_t n, const float *rays, const uint32_t *skip, int any,
+                        float *t_out, uint32_t *p_out, hipStream_t s)
+{
+    // The geometry at t must already be on the device: cached by an earlier
+    // call at t, or, when no instance moves, any cached instant (the camera
+    // plays no part in ray queries).
+    const DevInstantBufs *g = nullptr;
+    auto it = c->cache.find(t);
+    if (it != c->cache.end()) g = it->second.get();
+    else if (c->static_geom && !c->cache.empty()) g = c->cache.begin()->second.get();
+    if (!g) fail(EVRT_E_STATE, "the scene at this time is not resident on the device (trace or render at it first)");
+    if (!c->noalloc_scratch) fail(EVRT_E_DEVICE, "no scratch array on this device");
+    const DevScene sc = make_dev_scene(c, *g, *g, (uint32_t)lds_treelet_nodes());
+    const NoAllocScratch l = noalloc_layout(c->noalloc_scratch);
+    RayQueue q{l.o, l.d, l.skip};
+    launch_hook_rays(s, n, rays, skip, q, l.tminmax, l.cnt);
+    const uint32_t tb = (uint32_t)traverse_block_threads();
+    launch_hook_trace(s, blocks_for(c->trace_blocks_per_cu, c->cu_count, n, tb), any != 0, sc, q, l.tminmax, n,
+                      t_out, p_out);
+    hip_check(hipGetLastError(), "trace hook launch");
+}
+
 void decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n, uint32_t m, float C,
                   float alpha, uint8_t mode, uint8_t df_mode, double *t_out, uint8_t *stop_out, int8_t *pol_out,
                   double *p_out, hipStream_t s)
