@@ -67,6 +67,57 @@ def kernel_sources_digest() -> str:
 
 from paper_2408_07996_amd.metrics import polarity_f1, video_scores  # noqa: E402
 
+# The paper's own per-frame figure (Table 2, "Cup of water" row; also the
+# teaser): 200x200 pixels, up to 4096 paths per pixel, on the hardware the
+# paper lists.  Context only: another scene, machine and renderer.
+PAPER_CONTEXT = {"scene": "Cup of water, 200x200 pixels, up to 4096 paths per pixel, one-tailed test alpha 0.05",
+                 "s_per_frame_fixed_4096": 40.81, "s_per_frame_adaptive": 4.55, "speedup": 8.98,
+                 "hardware": "Intel Core i9-13900K (24 cores) + NVIDIA RTX A6000, 128 GB RAM; the paper does "
+                             "not say which device ran its pbrt-v4-based renderer",
+                 "source": "Table 2"}
+
+# Host CPUs one GPU's share of the benchmark box may use for worker pools.
+HOST_SHARE_THREADS = 16
+
+
+def host_cpu() -> dict:
+    """CPU model, online CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return dict(model=model, nproc=os.cpu_count(), allowed=allowed)
+
+
+def stop_evidence(n_paths, polarity, spp_init: int, spp_max: int) -> dict:
+    """Where the adaptive frame spends its paths: the event fraction f_e
+    (events run to spp_max by definition), the non-event pixels that never
+    stop before spp_max, a histogram of paths per pixel, and the bound on
+    the speed-up over fixed spp_max that these imply,
+    S <= 1 / (f_e + (1 - f_e) nbar / spp_max), nbar = mean paths of the
+    non-event pixels (time taken as proportional to paths)."""
+    n = np.asarray(n_paths, np.int64)
+    ev = np.asarray(polarity) != 0
+    f_e = float(ev.mean())
+    nbar = float(n[~ev].mean()) if (~ev).any() else 0.0
+    edges = [spp_init, 2 * spp_init, 4 * spp_init, spp_max // 2, spp_max, spp_max + 1]
+    edges = sorted(set(e for e in edges if spp_init <= e <= spp_max + 1))
+    hist, _ = np.histogram(n, bins=edges)
+    return dict(event_fraction=f_e, never_stopped_non_event_fraction=float(((n >= spp_max) & ~ev).mean()),
+                stopped_at_first_test_fraction=float((n == spp_init).mean()),
+                mean_paths_non_event=nbar,
+                paths_histogram={f"[{edges[i]},{edges[i + 1]})": int(h) for i, h in enumerate(hist)},
+                speedup_bound=1.0 / (f_e + (1.0 - f_e) * nbar / spp_max))
+
 
 def bench_diff(ev, scenes, steps: int = 3) -> dict:
     """Event-loss gradient of the differentiation workload (256x256, 9,648
@@ -128,6 +179,44 @@ def bench_video(ev, scenes) -> dict:
                quality=video_scores(pol, ref["polarity"].cpu().numpy()))
     r.close()
     return out
+
+
+def bench_tiny(ev, scenes, steps: int = 20) -> dict:
+    """The tiny workload (64x64, 24 triangles, depth 4, schedule 16/16/256,
+    C = 0.2, alpha = 0.01): adaptive event frames/s on the GPU, where launch
+    latency and the per-round readback dominate."""
+    import torch
+    P = scenes.TINY_PARAMS
+    sc = scenes.tiny_box()
+    r = ev.Renderer(0)
+    r.set_scene(sc)
+    o = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    print("[bench] tiny workload", file=sys.stderr, flush=True)
+
+    def run(mode):
+        for _ in range(3):
+            out = r.render_event_frame(0.0, 1.0, P["C"], P["alpha"], P["spp_init"], P["spp_batch"],
+                                       P["spp_max"], dict(o, mode=mode), extras=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            out = r.render_event_frame(0.0, 1.0, P["C"], P["alpha"], P["spp_init"], P["spp_batch"],
+                                       P["spp_max"], dict(o, mode=mode), extras=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, out, r.frame_stats()
+
+    dt, out, st = run(ev.MODE_ADAPTIVE_1T)
+    dtf, _, _ = run(ev.MODE_FIXED)
+    rays = st["camera_rays"] + st["extension_rays"] + st["shadow_rays"]
+    res = dict(workload=f"tiny: {sc.width}x{sc.height}, {sc.n_tri_world} triangles, depth {P['max_depth']}, "
+                        f"spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}, C {P['C']}",
+               frames_per_s=1.0 / dt, ms_per_frame=1000.0 * dt, rounds=st["rounds"], rays_per_s=rays / dt,
+               fixed_frames_per_s=1.0 / dtf, speedup_vs_fixed_spp_max=dtf / dt,
+               stop_evidence=stop_evidence(out["n_paths"].cpu().numpy(), out["polarity"].cpu().numpy(),
+                                           P["spp_init"], P["spp_max"]))
+    r.close()
+    return res
 
 
 def bench_batch(ev, scenes, args) -> dict:
@@ -207,9 +296,9 @@ def main() -> int:
                     help="traversal blocks per CU of the sensor frame (0: occupancy max)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
-    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video"), default="all",
+    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny"), default="all",
                     help="which workloads to run (the headline is the frame workload)")
-    ap.add_argument("--batch-pairs", type=int, default=4, help="pairs of the frame-batch workload")
+    ap.add_argument("--batch-pairs", type=int, default=64, help="pairs of the frame-batch workload")
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -231,10 +320,12 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.only in ("diff", "batch", "video"):
+    if args.only in ("diff", "batch", "video", "tiny"):
         res = {"metric": "next-row workloads", "next_rows": {}}
         if args.only == "diff":
             res["next_rows"]["differentiation"] = bench_diff(ev, scenes)
+        elif args.only == "tiny":
+            res["tiny"] = bench_tiny(ev, scenes)
         elif args.only == "video":
             res["next_rows"]["sequential_video"] = bench_video(ev, scenes)
         else:
@@ -295,6 +386,13 @@ def main() -> int:
     launches_per_frame = n_closest / args.steps
     ops_per_launch = ops_closest / max(1.0, launches_per_frame)
     achieved = ops_per_launch / (ms_per_closest * 1e-3) if ms_per_closest > 0 else 0.0
+    ops_shadow = cst["node_visits_shadow"] * OPS_PER_NODE + cst["tri_tests_shadow"] * OPS_PER_TRI
+    ms_per_shadow = ms_shadow / max(1, n_shadow)
+    shadow_launches_per_frame = n_shadow / args.steps
+    achieved_shadow = (ops_shadow / max(1.0, shadow_launches_per_frame) / (ms_per_shadow * 1e-3)
+                       if ms_per_shadow > 0 else 0.0)
+    closest_rays_per_launch = (cst["camera_rays"] + cst["extension_rays"]) / max(1.0, launches_per_frame)
+    shadow_rays_per_launch = cst["shadow_rays"] / max(1.0, shadow_launches_per_frame)
 
     measured = kernel_sources_digest() == TRAFFIC["sources_sha256"]
     traffic = TRAFFIC["bytes_per_launch"] if measured else None
@@ -320,6 +418,23 @@ def main() -> int:
     torch.cuda.synchronize()
     t_fixed = (time.perf_counter() - tf) / nf
     t_adapt = elapsed / args.steps
+    # Paths per second: the ones the outputs use (n_paths at both instants)
+    # and all traced (a round traces past a pixel's stop).
+    # Rays per path differ between the two: the pixels that stop first are
+    # the cheap ones (no hit, or black), so the paths left to the adaptive
+    # rounds carry more rays; rays/s compares the renderers' efficiency.
+    used_adapt = 2.0 * float(adaptive_paths.sum())
+    rays_adapt = stats["camera_rays"] + stats["extension_rays"] + stats["shadow_rays"]
+    rays_fixed = fst["camera_rays"] + fst["extension_rays"] + fst["shadow_rays"]
+    throughput = dict(adaptive_used_paths_per_s=used_adapt / t_adapt,
+                      adaptive_traced_paths_per_s=stats["paths"] / t_adapt,
+                      traced_past_stop_fraction=1.0 - used_adapt / max(1.0, float(stats["paths"])),
+                      fixed_paths_per_s=fst["paths"] / t_fixed,
+                      adaptive_over_fixed_used=(used_adapt / t_adapt) / (fst["paths"] / t_fixed),
+                      adaptive_rays_per_s=rays_adapt / t_adapt, fixed_rays_per_s=rays_fixed / t_fixed,
+                      adaptive_rays_per_traced_path=rays_adapt / max(1.0, float(stats["paths"])),
+                      fixed_rays_per_path=rays_fixed / max(1.0, float(fst["paths"])),
+                      ray_weighted_speedup_bound=rays_fixed / max(1.0, rays_adapt * used_adapt / max(1.0, float(stats["paths"]))))
 
     def quality(C, adapt_map, t_ad):
         """Polarity F1 of the adaptive map and of fixed counts against a
@@ -367,23 +482,36 @@ def main() -> int:
         q2, s_eq2 = quality(C2, map2, t_ad2)
         second = dict(C=C2, frames_per_s=1.0 / t_ad2, ms_per_step=1000.0 * t_ad2,
                       mean_paths_per_pixel=float(o2["n_paths"].cpu().numpy().mean()),
+                      stop_evidence=stop_evidence(o2["n_paths"].cpu().numpy().astype(np.int64), map2,
+                                                  P["spp_init"], P["spp_max"]),
                       events=int((map2 != 0).sum()), speedup_vs_fixed_spp_max=t_fixed / t_ad2,
                       speedup_equal_quality=s_eq2, quality=q2)
 
     cpu = None
     if not args.no_cpu:
         import oracle
+        host = host_cpu()
+        # Every CPU the process may use, up to one GPU's host share of the box.
+        threads = max(1, min(HOST_SHARE_THREADS, host["allowed"]))
         px = scenes.subset_every(sc.width, sc.height, args.cpu_step)
-        threads = min(16, os.cpu_count() or 1)
         print(f"[bench] CPU oracle on {len(px)} pixels, {threads} threads", file=sys.stderr, flush=True)
         with oracle.Frame(sc, 0.0, 1.0) as f:
             tc = time.perf_counter()
             f.render(oracle.make_params(**P), px, threads=threads)
             t_cpu = time.perf_counter() - tc
         s_per_frame = t_cpu * sc.n_pixels / len(px)
+        # The tiny workload's full frame, not extrapolated.
+        tiny = scenes.tiny_box()
+        with oracle.Frame(tiny, 0.0, 1.0) as f:
+            tc = time.perf_counter()
+            f.render(oracle.make_params(**scenes.TINY_PARAMS), threads=threads)
+            t_tiny = time.perf_counter() - tc
         cpu = dict(value=1.0 / s_per_frame, unit="event frames/s", cores=threads, kind="oracle",
                    sample=f"every pixel whose x and y are multiples of {args.cpu_step} ({len(px)} of {sc.n_pixels} pixels, "
-                          f"adaptive, both instants), {t_cpu:.1f} s, scaled by {sc.n_pixels / len(px):.0f}")
+                          f"adaptive, both instants), {t_cpu:.1f} s, scaled by {sc.n_pixels / len(px):.0f}",
+                   cpu_model=host["model"], nproc=host["nproc"], cpus_allowed=host["allowed"],
+                   threads_rule=f"all CPUs the process may use, at most {HOST_SHARE_THREADS} (one GPU's host share)",
+                   tiny_full_frame_s=t_tiny, tiny_frames_per_s=1.0 / t_tiny)
 
     res = {
         "metric": "event frames/s + rays/s at oracle-matched events; speedup vs fixed-spp GPU",
@@ -407,6 +535,8 @@ def main() -> int:
         "mean_paths_per_pixel": float(adaptive_paths.mean()),
         "events": int((adaptive_map != 0).sum()),
         "rounds": stats["rounds"],
+        "throughput": throughput,
+        "stop_evidence": stop_evidence(adaptive_paths, adaptive_map, P["spp_init"], P["spp_max"]),
         "fixed_frames_per_s": 1.0 / t_fixed,
         "speedup_vs_fixed_spp_max": t_fixed / t_adapt,
         "speedup_equal_quality": s_eq,
@@ -426,6 +556,9 @@ def main() -> int:
             "launches_per_frame": launches_per_frame,
             "node_visits_per_frame": cst["node_visits"],
             "tri_tests_per_frame": cst["tri_tests"],
+            "closest_rays_per_launch": closest_rays_per_launch,
+            "shadow_frac": achieved_shadow / PEAK_LANE_OPS,
+            "shadow_rays_per_launch": shadow_rays_per_launch,
             "shadow_ms_per_launch": ms_shadow / max(1, n_shadow),
             "closest_ms_per_frame": ms_closest / args.steps,
             "shadow_ms_per_frame": ms_shadow / args.steps,
@@ -433,10 +566,12 @@ def main() -> int:
             "counters": counters,
         },
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "scene_build_and_warmup_s": build_ms,
     }
     if args.only == "all":
         r.close()
+        res["tiny"] = bench_tiny(ev, scenes)
         res["next_rows"] = {"differentiation": bench_diff(ev, scenes),
                             "batching": bench_batch(ev, scenes, args),
                             "sequential_video": bench_video(ev, scenes)}
