@@ -219,6 +219,62 @@ def bench_tiny(ev, scenes, steps: int = 20) -> dict:
     return res
 
 
+def bench_sensitivity(ev, scenes, C: float = 0.15) -> dict:
+    """How the speed-up over fixed spp_max depends on readings the paper
+    leaves open: the paths per log-luminance sample (mini-batch 1, 2, 4, 8)
+    and the significance (alpha 0.01, the workload's, and 0.05, the
+    paper's).  Per setting: adaptive frame time, mean paths per pixel, the
+    stop evidence and its bound, and the equal-quality speed-up against the
+    fixed count whose polarity F1 (vs a 4096-path fixed reference of the
+    same mini-batch) reaches the adaptive map's."""
+    import torch
+    P = scenes.SENSOR_PARAMS
+    sc = scenes.sensor()
+    r = ev.Renderer(0)
+    r.set_scene(sc)
+    base = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+                log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+
+    def timed(opts, alpha, spp_max, reps=2):
+        out = r.render_event_frame(0.0, 1.0, C, alpha, min(P["spp_init"], spp_max), P["spp_batch"], spp_max,
+                                   opts, extras=False)
+        torch.cuda.synchronize()
+        if reps == 0:
+            return 0.0, out
+        t = time.perf_counter()
+        for _ in range(reps):
+            out = r.render_event_frame(0.0, 1.0, C, alpha, min(P["spp_init"], spp_max), P["spp_batch"],
+                                       spp_max, opts, extras=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, out
+
+    rows = []
+    for mb in (1, 2, 4, 8):
+        o = dict(base, minibatch=mb)
+        t_fixed, _ = timed(dict(o, mode=ev.MODE_FIXED), 0.01, P["spp_max"])
+        _, ref = timed(dict(o, mode=ev.MODE_FIXED), 0.01, 4 * P["spp_max"], reps=0)
+        ref_map = ref["polarity"].cpu().numpy()
+        ladder = {}
+        for n in (64, 128, 256, 512, 1024, 2048):
+            tn, fo = timed(dict(o, mode=ev.MODE_FIXED), 0.01, n, reps=1)
+            ladder[n] = (tn, polarity_f1(fo["polarity"].cpu().numpy(), ref_map))
+        for alpha in (0.01, 0.05):
+            print(f"[bench] sensitivity minibatch {mb} alpha {alpha}", file=sys.stderr, flush=True)
+            ta, out = timed(dict(o, mode=ev.MODE_ADAPTIVE_1T), alpha, P["spp_max"])
+            amap = out["polarity"].cpu().numpy()
+            f1 = polarity_f1(amap, ref_map)
+            n_eq = next((n for n in sorted(ladder) if ladder[n][1] >= f1), None)
+            ev_ = stop_evidence(out["n_paths"].cpu().numpy(), amap, P["spp_init"], P["spp_max"])
+            rows.append(dict(minibatch=mb, alpha=alpha, ms_adaptive=1000 * ta, ms_fixed_spp_max=1000 * t_fixed,
+                             speedup_vs_fixed_spp_max=t_fixed / ta, f1_adaptive=f1, n_eq=n_eq,
+                             speedup_equal_quality=(ladder[n_eq][0] / ta) if n_eq else None,
+                             mean_paths_per_pixel=float(out["n_paths"].cpu().numpy().mean()),
+                             speedup_bound=ev_["speedup_bound"], event_fraction=ev_["event_fraction"],
+                             never_stopped_non_event_fraction=ev_["never_stopped_non_event_fraction"]))
+    r.close()
+    return dict(workload=f"sensor, C {C}, spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}", rows=rows)
+
+
 def bench_batch(ev, scenes, args) -> dict:
     """Frame-batch workload (1280x720, 977,290 triangles, camera panning
     0.5 degrees per frame, schedule 16/16/2048, depth 8): K consecutive pairs
@@ -296,7 +352,8 @@ def main() -> int:
                     help="traversal blocks per CU of the sensor frame (0: occupancy max)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
-    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny"), default="all",
+    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny", "sensitivity"),
+                    default="all",
                     help="which workloads to run (the headline is the frame workload)")
     ap.add_argument("--batch-pairs", type=int, default=64, help="pairs of the frame-batch workload")
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
@@ -320,9 +377,11 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.only in ("diff", "batch", "video", "tiny"):
+    if args.only in ("diff", "batch", "video", "tiny", "sensitivity"):
         res = {"metric": "next-row workloads", "next_rows": {}}
-        if args.only == "diff":
+        if args.only == "sensitivity":
+            res["sensitivity"] = bench_sensitivity(ev, scenes, args.C)
+        elif args.only == "diff":
             res["next_rows"]["differentiation"] = bench_diff(ev, scenes)
         elif args.only == "tiny":
             res["tiny"] = bench_tiny(ev, scenes)

@@ -309,6 +309,26 @@ int evrt_scene_reset(evrt_ctx *c)
     });
 }
 
+// Everything but the material values equal: meshes (with their triangle
+// materials), instances, camera and point lights.
+static bool same_geometry(const SceneDesc &a, const SceneDesc &b)
+{
+    if (a.meshes.size() != b.meshes.size() || a.instances.size() != b.instances.size()) return false;
+    for (size_t i = 0; i < a.meshes.size(); ++i) {
+        const MeshDesc &x = a.meshes[i], &y = b.meshes[i];
+        if (x.set != y.set || x.xyz != y.xyz || x.idx != y.idx || x.mat != y.mat) return false;
+    }
+    for (size_t i = 0; i < a.instances.size(); ++i) {
+        const InstanceDesc &x = a.instances[i], &y = b.instances[i];
+        if (x.set != y.set || x.mesh != y.mesh || x.kt != y.kt || x.kx != y.kx) return false;
+    }
+    const CameraDesc &x = a.cam, &y = b.cam;
+    if (x.set != y.set || x.width != y.width || x.height != y.height || x.vfov != y.vfov || x.kt != y.kt ||
+        x.elu != y.elu)
+        return false;
+    return a.pl_pos == b.pl_pos && a.pl_int == b.pl_int;
+}
+
 int evrt_scene_commit(evrt_ctx *c)
 {
     return guarded(c, [&] {
@@ -329,10 +349,18 @@ int evrt_scene_commit(evrt_ctx *c)
         for (const auto &m : p.meshes)
             for (uint32_t mt : m.mat)
                 if (mt >= p.albedo.size()) fail(EVRT_E_INVALID, "triangle material out of range");
+        // Only albedo and emission changed: geometry, BVHs and box padding
+        // stay valid, so the cached instants are kept and only their emitter
+        // tables are rebuilt (a material update of an optimization loop).
+        // (c->scene is the last committed scene; a commit needs a camera.)
+        const bool materials_only = c->scene.cam.set && !c->host_only && c->scene.albedo.size() == p.albedo.size() &&
+                                    same_geometry(c->scene, p);
         c->scene = p;
         c->static_geom = scene_static(p);
-        c->cache.clear();
-        c->cache_order.clear();
+        if (!materials_only) {
+            c->cache.clear();
+            c->cache_order.clear();
+        }
         ++c->scene_version;
         if (!c->host_only) {
             hip_check(hipSetDevice(c->device), "hipSetDevice");
@@ -344,7 +372,9 @@ int evrt_scene_commit(evrt_ctx *c)
                 pl[i] = make_float4(p.pl_pos[3 * i], p.pl_pos[3 * i + 1], p.pl_pos[3 * i + 2], p.pl_int[i]);
             c->plights.upload(pl.data(), pl.size() * sizeof(float4), nullptr);
             hip_check(hipStreamSynchronize(nullptr), "scene upload");
+            if (materials_only) refresh_emitters(c);
         }
+        c->materials_only_commits += materials_only ? 1u : 0u;
         c->committed = true;
     });
 }

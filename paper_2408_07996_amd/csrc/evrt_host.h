@@ -90,6 +90,9 @@ struct DevInstantBufs {
 
 // World geometry at time t (primitive order, FP64 transform, FP32 round).
 void build_world(const SceneDesc &sd, double t, HostInstant &out);
+// Emitter table of h (emit_prim, emit_cdf, emit_S) from its primitives'
+// materials and areas and the scene's emission values.
+void build_emitters(const SceneDesc &sd, HostInstant &h);
 // Camera basis at time t (FP64 interpolation, FP32 round).
 void camera_at(const SceneDesc &sd, double t, DevCamera &out);
 // True when every instance has the same transform at all n times.
@@ -167,11 +170,15 @@ struct evrt_ctx {
     uint32_t trace_blocks_per_cu = 0;
     uint32_t shade_blocks_per_cu = 0;
     void *noalloc_scratch = nullptr;         // this device's static scratch array
+    uint32_t materials_only_commits = 0;     // commits that kept the instants
 };
 
 namespace evrt {
 // Geometry of instant t on the device (built and cached on first use).
 std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s, double *ms_build);
+// After a commit that changed only albedo and emission: the emitter tables
+// of every cached instant rebuilt and uploaded; geometry and BVHs are kept.
+void refresh_emitters(evrt_ctx *c);
 DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b, uint32_t lds_nodes);
 void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint32_t spp_init,
                   uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o,

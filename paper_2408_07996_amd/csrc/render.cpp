@@ -31,6 +31,57 @@ static void cache_insert(evrt_ctx *c, double t, const std::shared_ptr<DevInstant
     c->cache_order.push_back(t);
 }
 
+// Emitter table of an instant on the device: the CDF and, per emitter, its
+// three vertices and (unit normal, primitive id); the view's emitter fields.
+static void upload_emitters(DevInstantBufs &bi, hipStream_t s)
+{
+    const HostInstant &h = bi.host;
+    bi.emit_cdf.upload(h.emit_cdf.data(), h.emit_cdf.size() * sizeof(float), s);
+    std::vector<float4> emit(4 * h.emit_prim.size());
+    for (size_t j = 0; j < h.emit_prim.size(); ++j) {
+        const uint32_t p = h.emit_prim[j];
+        const float *v = &h.tri[9 * (size_t)p];
+        emit[4 * j + 0] = make_float4(v[0], v[1], v[2], 0.0f);
+        emit[4 * j + 1] = make_float4(v[3], v[4], v[5], 0.0f);
+        emit[4 * j + 2] = make_float4(v[6], v[7], v[8], 0.0f);
+        float pw;
+        std::memcpy(&pw, &p, 4);
+        emit[4 * j + 3] = make_float4(h.prim[p].x, h.prim[p].y, h.prim[p].z, pw);
+    }
+    bi.emit.upload(emit.data(), emit.size() * sizeof(float4), s);
+    DevInstant &v = bi.view;
+    v.emit_cdf = bi.emit_cdf.as<const float>();
+    v.emit = bi.emit.as<const float4>();
+    v.n_emit = (uint32_t)h.emit_prim.size();
+    v.emit_S = h.emit_S;
+}
+
+void refresh_emitters(evrt_ctx *c)
+{
+    // Instants that own their buffers first (also an owner that left the
+    // cache while a time sharing its geometry stayed), then the times that
+    // share an owner's geometry (static scenes) take its new emitter fields.
+    std::vector<DevInstantBufs *> owners;
+    for (auto &kv : c->cache) {
+        DevInstantBufs *o = kv.second->geom ? kv.second->geom.get() : kv.second.get();
+        if (std::find(owners.begin(), owners.end(), o) == owners.end()) owners.push_back(o);
+    }
+    for (DevInstantBufs *o : owners) {
+        build_emitters(c->scene, o->host);
+        upload_emitters(*o, nullptr);
+    }
+    for (auto &kv : c->cache) {
+        DevInstantBufs &bi = *kv.second;
+        if (!bi.geom) continue;
+        const DevInstant &g = bi.geom->view;
+        bi.view.emit_cdf = g.emit_cdf;
+        bi.view.emit = g.emit;
+        bi.view.n_emit = g.n_emit;
+        bi.view.emit_S = g.emit_S;
+    }
+    hip_check(hipStreamSynchronize(nullptr), "emitter upload");
+}
+
 std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s, double *ms_build)
 {
     auto it = c->cache.find(t);
@@ -59,31 +110,15 @@ std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s
     bi->nodes.upload(h.nodes.data(), h.nodes.size() * sizeof(float4), s);
     bi->tris.upload(h.tris.data(), h.tris.size() * sizeof(float4), s);
     bi->prim.upload(h.prim.data(), h.prim.size() * sizeof(float4), s);
-    bi->emit_cdf.upload(h.emit_cdf.data(), h.emit_cdf.size() * sizeof(float), s);
-    std::vector<float4> emit(4 * h.emit_prim.size());
-    for (size_t j = 0; j < h.emit_prim.size(); ++j) {
-        const uint32_t p = h.emit_prim[j];
-        const float *v = &h.tri[9 * (size_t)p];
-        emit[4 * j + 0] = make_float4(v[0], v[1], v[2], 0.0f);
-        emit[4 * j + 1] = make_float4(v[3], v[4], v[5], 0.0f);
-        emit[4 * j + 2] = make_float4(v[6], v[7], v[8], 0.0f);
-        float pw;
-        std::memcpy(&pw, &p, 4);
-        emit[4 * j + 3] = make_float4(h.prim[p].x, h.prim[p].y, h.prim[p].z, pw);
-    }
-    bi->emit.upload(emit.data(), emit.size() * sizeof(float4), s);
+    upload_emitters(*bi, s);
     hip_check(hipStreamSynchronize(s), "geometry upload");
     DevInstant &v = bi->view;
     v.nodes = bi->nodes.as<const float4>();
     v.tris = bi->tris.as<const float4>();
     v.prim = bi->prim.as<const float4>();
-    v.emit_cdf = bi->emit_cdf.as<const float>();
-    v.emit = bi->emit.as<const float4>();
     v.root = h.root;
     v.n_nodes = (uint32_t)(h.nodes.size() / 8);
     v.n_lds = h.n_lds;
-    v.n_emit = (uint32_t)h.emit_prim.size();
-    v.emit_S = h.emit_S;
     v.cam = h.cam;
     // Keep only the world triangles needed for statistics; drop the rest.
     h.nodes.shrink_to_fit();

@@ -87,8 +87,15 @@ void build_world(const SceneDesc &sd, double t, HostInstant &h)
         }
     }
 
+    build_emitters(sd, h);
+    camera_at(sd, t, h.cam);
+}
+
+void build_emitters(const SceneDesc &sd, HostInstant &h)
+{
     // Emitters in primitive order: w_j = A_j * Le_j (FP32), prefix sums and
     // their total S in FP64, cdf_j = (float)(prefix_j / S), last entry 1.
+    const size_t nt = h.prim.size();
     h.emit_prim.clear();
     h.emit_cdf.clear();
     std::vector<double> pref;
@@ -105,8 +112,6 @@ void build_world(const SceneDesc &sd, double t, HostInstant &h)
     for (double v : pref) h.emit_cdf.push_back((float)(v / S));
     if (!h.emit_cdf.empty()) h.emit_cdf.back() = 1.0f;
     h.emit_S = (float)S;
-
-    camera_at(sd, t, h.cam);
 }
 
 bool instances_static(const SceneDesc &sd, const double *times, uint32_t n)

@@ -137,3 +137,50 @@ def test_event_loss_gradient_full_workload():
     # 256x256, 9,648 triangles, 32 albedos, 4 emitters, 256 paths per pixel
     # and instant: the GPU gradient against the oracle's full-image gradient.
     _compare(scenes.diff_scene(), dict(scenes.DIFF_PARAMS), threads=16)
+
+
+def test_material_update_builds_nothing_and_matches_a_fresh_scene():
+    """A material-only update (each step of an optimization through the
+    autograd function) keeps the cached geometry and BVHs: the next gradient
+    builds nothing (ms_build == 0) and equals the gradient of a renderer
+    given the new materials from scratch (per-pixel terms and frames bit for
+    bit, sums over blocks to rounding).  The update changes
+    the set of emitters too (a sphere material starts emitting)."""
+    import dataclasses
+    import torch
+    sc = scenes.diff_scene(width=48, height=40)
+    P = dict(scenes.DIFF_PARAMS, spp=32)
+    rend = ev.Renderer(0)
+    rend.set_scene(sc)
+    rend.event_loss_grad(0.0, 1.0, P["C"], P["tau"], P["spp"], _opts(P))
+    assert rend.frame_stats()["ms_build"] > 0.0
+    rng = np.random.default_rng(3)
+    alb = np.asarray(sc.albedo, np.float32).copy()
+    emi = np.asarray(sc.emission, np.float32).copy()
+    lit = alb > 0
+    alb[lit] = np.clip(alb[lit] * rng.uniform(0.8, 1.2, lit.sum()), 0.05, 0.95).astype(np.float32)
+    emi[emi > 0] = (emi[emi > 0] * rng.uniform(0.5, 2.0, (emi > 0).sum())).astype(np.float32)
+    emi[20] = np.float32(2.5)   # a sphere material becomes an emitter
+    for step in range(2):
+        rend.set_materials(alb, emi)
+        g1 = rend.event_loss_grad(0.0, 1.0, P["C"], P["tau"], P["spp"], _opts(P), per_pixel=True)
+        assert rend.frame_stats()["ms_build"] == 0.0
+        f1 = rend.render_event_frame(0.0, 1.0, 0.2, 0.01, 16, 16, 128, _opts(P))
+        assert rend.frame_stats()["ms_build"] == 0.0
+        fresh = ev.Renderer(0)
+        fresh.set_scene(dataclasses.replace(sc, albedo=alb.copy(), emission=emi.copy()))
+        g2 = fresh.event_loss_grad(0.0, 1.0, P["C"], P["tau"], P["spp"], _opts(P), per_pixel=True)
+        f2 = fresh.render_event_frame(0.0, 1.0, 0.2, 0.01, 16, 16, 128, _opts(P))
+        fresh.close()
+        # Per-pixel terms bit for bit; the sums over blocks (FP64 atomics,
+        # any order) to rounding.
+        for k in ("loss_px", "delta"):
+            assert torch.equal(g1[k], g2[k]), (step, k)
+        for k in ("loss", "grad_albedo", "grad_emission"):
+            a, b = g1[k].cpu().numpy(), g2[k].cpu().numpy()
+            np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max(), err_msg=f"{step} {k}")
+        for k in f1:
+            assert torch.equal(f1[k], f2[k]), (step, k)
+        emi = emi.copy()
+        emi[20] = np.float32(0.0)  # and back: the emitter set shrinks again
+    rend.close()
