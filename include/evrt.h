@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define EVRT_ABI_VERSION 3
+#define EVRT_ABI_VERSION 4
 
 enum {
     EVRT_OK = 0,
@@ -151,6 +151,14 @@ typedef struct {
     uint8_t profile;         /* 1: time traversal launches with HIP events         */
     uint8_t count_work;      /* 1: count BVH node visits and triangle tests        */
     uint8_t lds_nodes;       /* top 4-wide BVH nodes staged in LDS, 0..32 (0)      */
+    uint8_t mis;             /* 1: multiple importance sampling of area emitters:
+                                each light sample (at vertices that also sample
+                                a direction) and each BSDF-sampled hit of a
+                                front-facing emitter after the first vertex
+                                count with power-heuristic weights (pbrt's
+                                PathIntegrator, Sec. 3.3, combines the two);
+                                0 (default): light samples only.  Not
+                                supported by evrt_event_loss_grad             */
     uint32_t ray_batch;      /* paths in flight per round, split over two
                                 pieces on two streams (0: 64 M)                   */
     uint32_t key_base;       /* frame index of instant t0 in the random-number

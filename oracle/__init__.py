@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
         ("minibatch", ctypes.c_uint32), ("log_eps", ctypes.c_double),
         ("C", ctypes.c_float), ("alpha", ctypes.c_float),
         ("nee", ctypes.c_uint8), ("jitter", ctypes.c_uint8), ("mode", ctypes.c_uint8),
-        ("df_mode", ctypes.c_uint8), ("ref_mode", ctypes.c_uint8),
+        ("df_mode", ctypes.c_uint8), ("ref_mode", ctypes.c_uint8), ("mis", ctypes.c_uint8),
         ("key_base", ctypes.c_uint32),
     ]
 
@@ -196,7 +196,7 @@ def crit_margin(mode: int, t: float, df: float, alpha: float, final_check: bool 
 def make_params(**kw) -> Params:
     base = dict(seed=0, spp_init=16, spp_batch=16, spp_max=256, max_depth=4, rr_start_depth=2,
                 minibatch=4, log_eps=1e-4, C=0.2, alpha=0.01, nee=1, jitter=1, mode=0,
-                df_mode=0, ref_mode=0, key_base=0)
+                df_mode=0, ref_mode=0, key_base=0, mis=0)
     base.update(kw)
     p = Params()
     for k, v in base.items():

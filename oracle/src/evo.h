@@ -71,6 +71,8 @@ typedef struct {
     double log_eps;
     float C, alpha;
     uint8_t nee, jitter, mode, df_mode, ref_mode;
+    uint8_t mis;              /* 1: next-event estimation and BSDF sampling of
+                                 emitters combined by the power heuristic    */
     uint32_t key_base;        /* frame index of instant 0 in the keys */
 } evo_params;
 

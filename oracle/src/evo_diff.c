@@ -131,6 +131,7 @@ int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau
     const uint32_t mb = p->minibatch;
     if (mb != 1 && mb != 2 && mb != 4 && mb != 8) return -1;
     if (spp == 0 || spp % mb != 0 || !(tau > 0.0) || p->max_depth > EVO_REC_MAX) return -1;
+    if (p->mis) return -1; /* the gradient follows the estimator without MIS */
     if (!pixels) n_pixels = sd->width * sd->height;
     if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
     if (n_threads < 1) n_threads = 1;

@@ -85,6 +85,8 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
     for (int c = 0; c < 3; ++c) d[c] = d[c] / len;
 
     float L = 0.0f, beta = 1.0f;
+    float pb_prev = 0.0f; /* solid-angle pdf of the direction sampled at the
+                             previous vertex (cosine: cos / pi) */
     uint32_t skip = EVO_NO_PRIM;
     if (rec) {
         rec->n_vert = 0;
@@ -105,10 +107,19 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
         float ns[3];
         for (int c = 0; c < 3; ++c) ns[c] = cosi < 0.0f ? n[c] : -n[c];
 
-        /* Emission of a front-facing emitter: at the first vertex only
-         * when next-event estimation accounts for direct light. */
-        if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !p->nee)) {
-            const float term = beta * Le;
+        /* Emission of a front-facing emitter: at the first vertex, or at
+         * every vertex without next-event estimation.  With MIS, a later
+         * vertex reached by BSDF sampling adds it too, weighted by the power
+         * heuristic against the pdf with which next-event estimation would
+         * have sampled this point, in solid angle at the previous vertex:
+         * p_light = P_j / A_j * r^2 / cos_y = Le r^2 / (S cos_y). */
+        if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !p->nee || p->mis)) {
+            float term = beta * Le;
+            if (depth > 1 && p->nee) {
+                const float pl = (Le * (t * t)) / (I->emit_S * (-cosi));
+                const float ratio = pl / pb_prev;
+                term = term * (1.0f / (1.0f + ratio * ratio));
+            }
             L = L + term;
             if (rec) {
                 rec->tmat[rec->n_term] = m;
@@ -160,6 +171,16 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
                              * with P_j = A_j Le_j / S, i.e. the emitter terms
                              * collapse to S. */
                             float cval = ((((beta * fr) * cx) * cy) * I->emit_S) / r2;
+                            if (p->mis && depth < p->max_depth) {
+                                /* Power heuristic against the cosine-sampling
+                                 * pdf of the same direction; the last vertex
+                                 * samples no direction, so its light sample
+                                 * keeps the full weight. */
+                                const float Lej = sd->emission[I->mat[q]];
+                                const float pl = (Lej * r2) / (I->emit_S * cy);
+                                const float ratio = (cx * INV_PI_F) / pl;
+                                cval = cval * (1.0f / (1.0f + ratio * ratio));
+                            }
                             Dd = Dd + cval;
                             if (rec) {
                                 rec->tmat[rec->n_term] = f->inst[instant].mat[q];
@@ -202,6 +223,7 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
         const double ph = TWO_PI_D * (double)e1;
         const float cph = (float)cos(ph), sph = (float)sin(ph);
         const float lx = rr * cph, ly = rr * sph, lz = sqrtf(fmaxf(0.0f, 1.0f - e0));
+        pb_prev = lz * INV_PI_F;
         /* Orthonormal basis of Duff et al. 2017. */
         const float sg = copysignf(1.0f, ns[2]);
         const float aa = -1.0f / (sg + ns[2]);

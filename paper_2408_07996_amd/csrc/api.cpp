@@ -62,6 +62,7 @@ void validate_opts(const evrt_render_opts &o)
     if (o.lds_nodes > (uint32_t)lds_treelet_nodes()) fail(EVRT_E_INVALID, "lds_nodes above the treelet capacity");
     if (o.key_base > (1u << 24)) fail(EVRT_E_INVALID, "key_base above 2^24");
     if (o.replay_retrace > 1) fail(EVRT_E_INVALID, "replay_retrace must be 0 or 1");
+    if (o.mis > 1) fail(EVRT_E_INVALID, "mis must be 0 or 1");
 }
 
 }  // namespace evrt
@@ -559,6 +560,7 @@ int evrt_event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, 
         if (!std::isfinite(tau) || !(tau > 0.0f)) fail(EVRT_E_INVALID, "tau must be finite and > 0");
         if (spp == 0 || spp % o.minibatch != 0) fail(EVRT_E_INVALID, "spp must be a positive multiple of minibatch");
         if (!out || !out->loss || !out->grad) fail(EVRT_E_INVALID, "NULL loss or gradient output");
+        if (o.mis) fail(EVRT_E_UNSUPPORTED, "the gradient follows the estimator without MIS");
         if (c->scene.albedo.size() > 2048) fail(EVRT_E_UNSUPPORTED, "more than 2048 materials");
         const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;
         if (2ull * npx * spp >= (1ull << 31)) fail(EVRT_E_UNSUPPORTED, "more than 2^31 paths");

@@ -45,7 +45,7 @@ struct DevInstant {
     const float4 *tris;      // 3 per triangle in leaf order: (v0, prim bits), (v1, 0), (v2, 0)
     const float4 *prim;      // per primitive: (unit normal xyz, material bits)
     const float *emit_cdf;   // per emitter
-    const float4 *emit;      // 4 per emitter: v0, v1, v2, (unit normal xyz, prim bits)
+    const float4 *emit;      // 4 per emitter: (v0, Le), v1, v2, (unit normal xyz, prim bits)
     int32_t root;            // root reference (kEmptyRef: no geometry)
     uint32_t n_nodes, n_lds, n_emit;
     float emit_S;            // sum over emitters of area * Le
@@ -68,6 +68,8 @@ struct RenderParams {
     uint32_t minibatch;
     uint32_t n_slots;        // shadow rays per shade vertex: 1 + point lights
     uint32_t key_base;       // frame index of instant slot 0 in the keys
+    uint32_t mis;            // 1: light samples and BSDF-sampled emitter hits
+                             // weighted by the power heuristic
     double log_eps;
 };
 

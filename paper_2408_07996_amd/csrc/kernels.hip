@@ -1080,8 +1080,22 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
             nsy = cosi < 0.0f ? pr.y : -pr.y;
             nsz = cosi < 0.0f ? pr.z : -pr.z;
             if (ADJ) w = adj.W[((size_t)pixel * 2 + inst) * adj.m + sample / adj.mb];
-            if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee)) {
-                const float term = beta * Le;
+            if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee || rp.mis)) {
+                float term = beta * Le;
+                if (depth > 1 && rp.nee) {
+                    // MIS: this emitter point was reached by the cosine-sampled
+                    // direction of the previous vertex, whose pdf cos / pi is
+                    // the previous vertex's sample lz / pi (its random
+                    // numbers, drawn again); next-event estimation would have
+                    // sampled it with solid-angle pdf Le r^2 / (S cos_y).
+                    // Power heuristic, as 1 / (1 + ratio^2).
+                    const uint4 rq = rng_block(rp, pixel, sample, q, depth - 1, 1);
+                    const float pb = sqrtf(fmaxf(0.0f, 1.0f - u01(rq.x))) * kInvPi;
+                    const float S = inst ? sc.inst[1].emit_S : sc.inst[0].emit_S;
+                    const float pl = (Le * (t * t)) / (S * (-cosi));
+                    const float ratio = pl / pb;
+                    term = term * (1.0f / (1.0f + ratio * ratio));
+                }
                 pc.rad[ri] = pc.rad[ri] + term;
                 if (ADJ && w != 0.0) atomicAdd(&s_acc[adj.n_mat + fbits(pr.w)], w * (double)term / (double)Le);
             }
@@ -1122,6 +1136,14 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
                             if (cx > 0.0f && cy > 0.0f) {
                                 const float S = inst ? sc.inst[1].emit_S : sc.inst[0].emit_S;
                                 c0 = ((((beta * fr) * cx) * cy) * S) / r2;
+                                if (rp.mis && depth < rp.max_depth) {
+                                    // MIS against the cosine-sampling pdf of the
+                                    // same direction; the last vertex samples no
+                                    // direction and keeps the full weight.
+                                    const float pl = (v0.w * r2) / (S * cy);
+                                    const float ratio = (cx * kInvPi) / pl;
+                                    c0 = c0 * (1.0f / (1.0f + ratio * ratio));
+                                }
                                 d0 = make_float4(wix, wiy, wiz, rl * kShadowScale);
                                 if (ADJ) {
                                     const float4 *P = inst ? sc.inst[1].prim : sc.inst[0].prim;

@@ -32,8 +32,9 @@ static void cache_insert(evrt_ctx *c, double t, const std::shared_ptr<DevInstant
 }
 
 // Emitter table of an instant on the device: the CDF and, per emitter, its
-// three vertices and (unit normal, primitive id); the view's emitter fields.
-static void upload_emitters(DevInstantBufs &bi, hipStream_t s)
+// three vertices (the first with the emitted radiance in w) and (unit
+// normal, primitive id); the view's emitter fields.
+static void upload_emitters(DevInstantBufs &bi, const SceneDesc &sd, hipStream_t s)
 {
     const HostInstant &h = bi.host;
     bi.emit_cdf.upload(h.emit_cdf.data(), h.emit_cdf.size() * sizeof(float), s);
@@ -41,7 +42,9 @@ static void upload_emitters(DevInstantBufs &bi, hipStream_t s)
     for (size_t j = 0; j < h.emit_prim.size(); ++j) {
         const uint32_t p = h.emit_prim[j];
         const float *v = &h.tri[9 * (size_t)p];
-        emit[4 * j + 0] = make_float4(v[0], v[1], v[2], 0.0f);
+        uint32_t mat;
+        std::memcpy(&mat, &h.prim[p].w, 4);
+        emit[4 * j + 0] = make_float4(v[0], v[1], v[2], sd.emission[mat]);
         emit[4 * j + 1] = make_float4(v[3], v[4], v[5], 0.0f);
         emit[4 * j + 2] = make_float4(v[6], v[7], v[8], 0.0f);
         float pw;
@@ -68,7 +71,7 @@ void refresh_emitters(evrt_ctx *c)
     }
     for (DevInstantBufs *o : owners) {
         build_emitters(c->scene, o->host);
-        upload_emitters(*o, nullptr);
+        upload_emitters(*o, c->scene, nullptr);
     }
     for (auto &kv : c->cache) {
         DevInstantBufs &bi = *kv.second;
@@ -110,7 +113,7 @@ std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s
     bi->nodes.upload(h.nodes.data(), h.nodes.size() * sizeof(float4), s);
     bi->tris.upload(h.tris.data(), h.tris.size() * sizeof(float4), s);
     bi->prim.upload(h.prim.data(), h.prim.size() * sizeof(float4), s);
-    upload_emitters(*bi, s);
+    upload_emitters(*bi, c->scene, s);
     hip_check(hipStreamSynchronize(s), "geometry upload");
     DevInstant &v = bi->view;
     v.nodes = bi->nodes.as<const float4>();
@@ -157,6 +160,7 @@ static RenderParams make_params(const evrt_ctx *c, const evrt_render_opts &o)
     rp.minibatch = o.minibatch;
     rp.n_slots = 1 + (uint32_t)c->scene.pl_int.size();
     rp.key_base = o.key_base;
+    rp.mis = o.mis;
     rp.log_eps = o.log_eps;
     return rp;
 }

@@ -184,3 +184,16 @@ def test_material_update_builds_nothing_and_matches_a_fresh_scene():
         emi = emi.copy()
         emi[20] = np.float32(0.0)  # and back: the emitter set shrinks again
     rend.close()
+
+
+def test_gradient_refuses_mis():
+    """The gradient follows the estimator without MIS: asking for MIS is
+    refused before any device work."""
+    sc = scenes.diff_scene(width=16, height=12)
+    rend = ev.Renderer(0)
+    rend.set_scene(sc)
+    P = dict(scenes.DIFF_PARAMS, spp=8)
+    with pytest.raises(ev.EvrtError) as e:
+        rend.event_loss_grad(0.0, 1.0, P["C"], P["tau"], P["spp"], dict(_opts(P), mis=1))
+    assert e.value.code == ev.EVRT_E_UNSUPPORTED
+    rend.close()

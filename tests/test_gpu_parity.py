@@ -47,7 +47,7 @@ def _opts_from(params: dict, **kw):
     d = dict(params)
     d.update(kw)
     keys = ("seed", "max_depth", "rr_start_depth", "minibatch", "log_eps", "nee", "jitter", "mode",
-            "df_mode", "ref_mode", "lds_nodes", "ray_batch")
+            "df_mode", "ref_mode", "lds_nodes", "ray_batch", "mis")
     return {k: d[k] for k in keys if k in d}
 
 
@@ -103,6 +103,11 @@ PATH_CASES = {
     "point_light": (lambda: scenes.plane_point_light(), {**scenes.TINY_PARAMS, "jitter": 0}, 0.0, 0.0),
     "soup_lights": (lambda: scenes.triangle_soup(600, seed=5, moving=True, emitters=8, width=24, height=20),
                     {**scenes.TINY_PARAMS, "max_depth": 5, "seed": 0x123456789}, 0.0, 1.0),
+    "tiny_box_mis": (lambda: scenes.tiny_box(), {**scenes.TINY_PARAMS, "mis": 1, "max_depth": 5}, 0.0, 1.0),
+    "soup_lights_mis": (lambda: scenes.triangle_soup(600, seed=5, moving=True, emitters=8, width=24, height=20),
+                        {**scenes.TINY_PARAMS, "max_depth": 5, "seed": 0x123456789, "mis": 1}, 0.0, 1.0),
+    "area_light_mis": (lambda: scenes.plane_area_light(0.6, 4.0, 24, 24),
+                       {**scenes.TINY_PARAMS, "mis": 1, "max_depth": 3, "rr_start_depth": 9}, 0.0, 0.0),
 }
 
 
@@ -110,7 +115,7 @@ PATH_CASES = {
 def test_render_paths_bit_exact(rend, torch_cuda, case):
     make, params, t0, t1 = PATH_CASES[case]
     sc = make()
-    if case == "soup_lights":
+    if case.startswith("soup_lights"):
         b_pos = np.array([[0.5, 3.0, 1.0], [-2.0, 1.0, 2.5]], np.float32)
         sc.pl_pos, sc.pl_intensity = b_pos, np.array([4.0, 2.5], np.float32)
     rend.set_scene(sc)
@@ -253,7 +258,7 @@ def _compare(g, r, pixels, C):
 
 @pytest.mark.parametrize("variant", ["default", "fixed", "ref_full", "two_tailed", "mean_only", "mb1", "mb8",
                                      "lds_treelet", "small_pieces", "split_samples", "welch", "welch_two_tailed",
-                                     "welch_ref_full"])
+                                     "welch_ref_full", "mis"])
 def test_tiny_frame_parity(rend, torch_cuda, variant):
     sc = scenes.tiny_box()
     rend.set_scene(sc)
@@ -282,6 +287,8 @@ def test_tiny_frame_parity(rend, torch_cuda, variant):
         params.update(df_mode=ev.DF_WELCH, mode=ev.MODE_ADAPTIVE_2T)
     elif variant == "welch_ref_full":
         params.update(df_mode=ev.DF_WELCH, ref_mode=ev.REF_FULL)
+    elif variant == "mis":
+        params.update(mis=1, max_depth=5)
     _say(f"tiny frame variant={variant}")
     g, st = _frame(rend, sc, params, 0.0, 1.0)
     with oracle.Frame(sc, 0.0, 1.0) as f:
