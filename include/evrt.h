@@ -126,8 +126,33 @@ int evrt_scene_set_point_lights(evrt_ctx *ctx, const float *pos_xyz, const float
 int evrt_scene_set_camera(evrt_ctx *ctx, uint32_t width, uint32_t height, double vfov_deg,
                           uint32_t n_keys, const double *key_t, const double *eye_look_up);
 
+/* Environment seen by rays that leave the scene (the background of the
+ * paper's failure case, Sec. 5, is an environment map): a grey cube map of
+ * face_res x face_res texels per face, texels[6][face_res][face_res] (host,
+ * deep-copied), faces +x, -x, +y, -y, +z, -z, row j then column i.  The
+ * radiance in direction d is the texel nearest to d: the face of the major
+ * axis of d (ties x, then y, then z), face coordinates (sc, tc) = (-dz, -dy)
+ * on +x, (dz, -dy) on -x, (dx, dz) on +y, (dx, -dz) on -y, (dx, -dy) on +z,
+ * (-dx, -dy) on -z, i = floor(N (sc / |major| + 1) / 2), likewise j from
+ * tc, clamped to N - 1 (FP32 operations in that order).  A path that leaves
+ * the scene adds throughput times that radiance; light samples do not
+ * sample the environment.  face_res = 0 (default): black background.
+ * Errors: EVRT_E_INVALID for NULL texels or a negative or non-finite
+ * radiance; EVRT_E_UNSUPPORTED above 4096 texels per face edge. */
+int evrt_scene_set_environment(evrt_ctx *ctx, const float *texels, uint32_t face_res);
+
+/* Thin-lens camera (the depth of field of the paper's failure case,
+ * Sec. 5): a camera ray starts at the aperture point eye + rl cos(phi) r +
+ * rl sin(phi) u', rl = aperture_radius sqrt(u2), phi = 2 pi u3 (the third
+ * and fourth numbers of the pixel's jitter block), and aims at eye +
+ * focus_distance (f + a r + b u'), the pinhole ray's point on the plane in
+ * focus.  aperture_radius = 0 (default) is the pinhole camera.  Errors:
+ * EVRT_E_INVALID for a negative or non-finite radius or a non-positive
+ * focus distance. */
+int evrt_scene_set_lens(evrt_ctx *ctx, float aperture_radius, float focus_distance);
+
 /* Clears the pending scene description (materials, meshes, instances,
- * lights, camera).  The committed scene stays current until the next
+ * lights, camera, environment, lens).  The committed scene stays current until the next
  * successful evrt_scene_commit. */
 int evrt_scene_reset(evrt_ctx *ctx);
 

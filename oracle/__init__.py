@@ -44,6 +44,8 @@ class _SceneDesc(ctypes.Structure):
         ("n_plight", ctypes.c_uint32), ("pl_pos", _f32p), ("pl_intensity", _f32p),
         ("width", ctypes.c_uint32), ("height", ctypes.c_uint32), ("vfov_deg", ctypes.c_double),
         ("cam_nkeys", ctypes.c_uint32), ("cam_t", _f64p), ("cam_elu", _f64p),
+        ("env_res", ctypes.c_uint32), ("env", _f32p),
+        ("lens_radius", ctypes.c_float), ("focus_dist", ctypes.c_float),
     ]
 
 
@@ -126,6 +128,10 @@ def lib():
     L.evo_decide.argtypes = [_f64p, ctypes.c_uint32, _f64p, ctypes.c_uint32, ctypes.c_float,
                              ctypes.c_float, ctypes.c_int, ctypes.c_int, _f64p, _f64p, _f64p,
                              ctypes.POINTER(ctypes.c_int), _f64p]
+    L.evo_camera_ray.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32, ctypes.c_int,
+                                 ctypes.c_uint32, _f32p, _f32p]
+    L.evo_env_radiance.restype = ctypes.c_float
+    L.evo_env_radiance.argtypes = [ctypes.c_void_p, _f32p]
     L.evo_crit_margin.restype = ctypes.c_double
     L.evo_crit_margin.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_int]
     L.evo_render.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _u32p, ctypes.c_uint32,
@@ -258,6 +264,13 @@ class Frame:
         d.vfov_deg = scene.vfov_deg
         d.cam_nkeys = len(cam_t)
         d.cam_t = _ptr(cam_t, ctypes.c_double)
+        env = getattr(scene, "env", None)
+        if env is not None:
+            env = arr(env, np.float32)
+            d.env_res = env.shape[-1]
+            d.env = _ptr(env, ctypes.c_float)
+        d.lens_radius = float(getattr(scene, "lens_radius", 0.0))
+        d.focus_dist = float(getattr(scene, "focus_dist", 1.0))
         d.cam_elu = _ptr(cam_elu, ctypes.c_double)
         self._scene = L.evo_scene_new(ctypes.byref(d))
         self._keep = []
@@ -312,6 +325,18 @@ class Frame:
         return bool(lib().evo_any_hit(self._frame, int(instant), _ptr(o, ctypes.c_float),
                                       _ptr(d, ctypes.c_float), float(tmin), float(tmax), int(skip),
                                       int(bool(brute))))
+
+    def camera_ray(self, params: Params, pixel: int, instant: int, sample: int):
+        """(origin, unit direction) of a path sample's camera ray."""
+        o = np.zeros(3, np.float32)
+        d = np.zeros(3, np.float32)
+        lib().evo_camera_ray(self._frame, ctypes.byref(params), int(pixel), int(instant), int(sample),
+                             _ptr(o, ctypes.c_float), _ptr(d, ctypes.c_float))
+        return o, d
+
+    def env_radiance(self, d) -> float:
+        v = np.ascontiguousarray(d, np.float32)
+        return float(lib().evo_env_radiance(self._frame, _ptr(v, ctypes.c_float)))
 
     def path_radiance(self, params: Params, pixel: int, instant: int, sample: int) -> np.float32:
         return np.float32(lib().evo_path_radiance(self._frame, ctypes.byref(params), int(pixel),

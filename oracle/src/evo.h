@@ -62,6 +62,14 @@ typedef struct {
     uint32_t cam_nkeys;
     const double *cam_t;          /* [cam_nkeys]                               */
     const double *cam_elu;        /* [cam_nkeys][9] eye, look-at, up           */
+    /* Environment seen by rays that leave the scene: a grey cube map of
+     * env_res x env_res texels per face (0: black background), faces +x,
+     * -x, +y, -y, +z, -z, texel (i, j) at env[(face * N + j) * N + i]. */
+    uint32_t env_res;
+    const float *env;
+    /* Thin lens (0: pinhole): aperture radius and the distance of the plane
+     * in focus along the viewing direction. */
+    float lens_radius, focus_dist;
 } evo_scene_desc;
 
 typedef struct {
@@ -124,6 +132,13 @@ int evo_any_hit(const evo_frame *f, int instant, const float o[3], const float d
 
 float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
                         int instant, uint32_t sample);
+
+/* The camera ray of one path sample (origin on the lens, unit direction). */
+void evo_camera_ray(const evo_frame *f, const evo_params *p, uint32_t pixel, int instant,
+                    uint32_t sample, float o[3], float d[3]);
+
+/* Environment radiance in direction d (need not be unit length). */
+float evo_env_radiance(const evo_frame *f, const float d[3]);
 
 /* Record of one path for the derivatives of its radiance L with respect to
  * material albedos and emitted radiances, with every sampling decision

@@ -51,6 +51,86 @@ static float dot3(const float *a, const float *b)
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
 }
 
+/* Environment radiance: nearest texel of the cube map face of the major
+ * axis of d (ties: x before y before z), in the usual cube-map face
+ * coordinates (sc, tc) / |major|, mapped from [-1, 1] to [0, N) and
+ * truncated; plain FP32 operations. */
+float evo_env_radiance(const evo_frame *f, const float d[3])
+{
+    const evo_scene_desc *sd = &f->scene->d;
+    const uint32_t N = sd->env_res;
+    if (N == 0) return 0.0f;
+    const float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+    uint32_t face;
+    float ma, sc, tc;
+    if (ax >= ay && ax >= az) {
+        ma = ax;
+        face = d[0] >= 0.0f ? 0u : 1u;
+        sc = d[0] >= 0.0f ? -d[2] : d[2];
+        tc = -d[1];
+    } else if (ay >= az) {
+        ma = ay;
+        face = d[1] >= 0.0f ? 2u : 3u;
+        sc = d[0];
+        tc = d[1] >= 0.0f ? d[2] : -d[2];
+    } else {
+        ma = az;
+        face = d[2] >= 0.0f ? 4u : 5u;
+        sc = d[2] >= 0.0f ? d[0] : -d[0];
+        tc = -d[1];
+    }
+    if (!(ma > 0.0f)) return 0.0f;
+    const float s = ((sc / ma) + 1.0f) * 0.5f;
+    const float t = ((tc / ma) + 1.0f) * 0.5f;
+    uint32_t i = (uint32_t)(s * (float)N), j = (uint32_t)(t * (float)N);
+    if (i >= N) i = N - 1;
+    if (j >= N) j = N - 1;
+    return sd->env[((size_t)face * N + j) * N + i];
+}
+
+/* Camera ray of a path sample: pixel (x + u, y + v) with (u, v) from the
+ * vertex-0 block (or the centre), pinhole direction f + a r + b u'; with a
+ * thin lens the origin is the aperture point eye + rl cos(phi) r + rl
+ * sin(phi) u', rl = R sqrt(u2), phi = 2 pi u3 (words 2 and 3 of the same
+ * block), and the ray aims at eye + F (f + a r + b u'), the pinhole ray's
+ * point on the plane in focus (its forward component is F). */
+void evo_camera_ray(const evo_frame *f, const evo_params *p, uint32_t pixel, int instant,
+                    uint32_t sample, float o[3], float d[3])
+{
+    const evo_scene_desc *sd = &f->scene->d;
+    const evo_instant *I = &f->inst[instant];
+    const uint32_t W = sd->width, H = sd->height;
+    const uint32_t px = pixel % W, py = pixel / W;
+    uint32_t r[4] = {0, 0, 0, 0};
+    const int lens = sd->lens_radius > 0.0f;
+    if (p->jitter || lens) rng4(p, pixel, sample, instant, 0, 0, r);
+    float j0 = 0.5f, j1 = 0.5f;
+    if (p->jitter) {
+        j0 = evo_u01(r[0]);
+        j1 = evo_u01(r[1]);
+    }
+    float fx = (float)px + j0, fy = (float)py + j1;
+    float nx = (2.0f * fx) / (float)W - 1.0f;
+    float ny = 1.0f - (2.0f * fy) / (float)H;
+    float a = nx * I->sx, b = ny * I->sy;
+    for (int c = 0; c < 3; ++c) {
+        d[c] = (I->fwd[c] + a * I->right[c]) + b * I->up[c];
+        o[c] = I->eye[c];
+    }
+    if (lens) {
+        const float rl = sd->lens_radius * sqrtf(evo_u01(r[2]));
+        const double ph = TWO_PI_D * (double)evo_u01(r[3]);
+        const float lu = rl * (float)cos(ph), lv = rl * (float)sin(ph);
+        for (int c = 0; c < 3; ++c) {
+            const float focus = I->eye[c] + sd->focus_dist * d[c];
+            o[c] = (I->eye[c] + lu * I->right[c]) + lv * I->up[c];
+            d[c] = focus - o[c];
+        }
+    }
+    float len = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+    for (int c = 0; c < 3; ++c) d[c] = d[c] / len;
+}
+
 /* Radiance carried by one camera path, FP32.  Vertex d = 1..max_depth is
  * the d-th surface hit.  Random numbers come from Philox keyed by (pixel,
  * sample, instant, vertex, block): vertex 0 block 0 gives the pixel jitter;
@@ -61,28 +141,10 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
 {
     const evo_scene_desc *sd = &f->scene->d;
     const evo_instant *I = &f->inst[instant];
-    const uint32_t W = sd->width, H = sd->height;
-    const uint32_t px = pixel % W, py = pixel / W;
     const int brute = !f->use_bvh;
 
-    float j0 = 0.5f, j1 = 0.5f;
-    if (p->jitter) {
-        uint32_t r[4];
-        rng4(p, pixel, sample, instant, 0, 0, r);
-        j0 = evo_u01(r[0]);
-        j1 = evo_u01(r[1]);
-    }
-    float fx = (float)px + j0, fy = (float)py + j1;
-    float nx = (2.0f * fx) / (float)W - 1.0f;
-    float ny = 1.0f - (2.0f * fy) / (float)H;
-    float a = nx * I->sx, b = ny * I->sy;
     float d[3], o[3];
-    for (int c = 0; c < 3; ++c) {
-        d[c] = (I->fwd[c] + a * I->right[c]) + b * I->up[c];
-        o[c] = I->eye[c];
-    }
-    float len = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
-    for (int c = 0; c < 3; ++c) d[c] = d[c] / len;
+    evo_camera_ray(f, p, pixel, instant, sample, o, d);
 
     float L = 0.0f, beta = 1.0f;
     float pb_prev = 0.0f; /* solid-angle pdf of the direction sampled at the
@@ -97,7 +159,12 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
         evo__ray_setup(&ray, o, d);
         float t;
         uint32_t prim;
-        if (!evo__closest(f, instant, &ray, RAY_TMIN, INFINITY, skip, brute, &t, &prim)) break;
+        if (!evo__closest(f, instant, &ray, RAY_TMIN, INFINITY, skip, brute, &t, &prim)) {
+            /* Leaves the scene: the environment's radiance (found by this
+             * direction only; light samples do not sample it). */
+            if (sd->env_res) L = L + beta * evo_env_radiance(f, d);
+            break;
+        }
         float P[3];
         for (int c = 0; c < 3; ++c) P[c] = o[c] + t * d[c];
         const float *n = I->nrm + 3 * (size_t)prim;

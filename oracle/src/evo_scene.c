@@ -10,7 +10,9 @@
  *   - instance transform at time t: entry-wise linear interpolation of 3x4
  *     key matrices in FP64, vertices transformed in FP64 and rounded once
  *     to FP32;
- *   - pinhole camera with a box pixel filter;
+ *   - pinhole camera with a box pixel filter, or a thin lens (a point on
+ *     the aperture disk, the ray through the pinhole ray's point on the
+ *     plane in focus);
  *   - watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013) in FP32;
  *   - closest hit = lexicographic minimum of (t, primitive index) over all
  *     triangles other than the ray's origin primitive with tmin < t < tmax,
@@ -52,6 +54,7 @@ evo_scene *evo_scene_new(const evo_scene_desc *d)
     s->d.pl_intensity = dup_bytes(d->pl_intensity, sizeof(float) * d->n_plight);
     s->d.cam_t = dup_bytes(d->cam_t, sizeof(double) * d->cam_nkeys);
     s->d.cam_elu = dup_bytes(d->cam_elu, sizeof(double) * 9 * d->cam_nkeys);
+    s->d.env = dup_bytes(d->env, sizeof(float) * 6 * (size_t)d->env_res * d->env_res);
     return s;
 }
 
@@ -62,7 +65,7 @@ void evo_scene_free(evo_scene *s)
     free((void *)s->d.tri_idx); free((void *)s->d.tri_mat); free((void *)s->d.mesh_tri_off);
     free((void *)s->d.inst_mesh); free((void *)s->d.inst_key_off); free((void *)s->d.key_t);
     free((void *)s->d.key_xform); free((void *)s->d.pl_pos); free((void *)s->d.pl_intensity);
-    free((void *)s->d.cam_t); free((void *)s->d.cam_elu);
+    free((void *)s->d.cam_t); free((void *)s->d.cam_elu); free((void *)s->d.env);
     free(s);
 }
 

@@ -93,6 +93,8 @@ SIGNATURES = [
     ("evrt_scene_set_instance", ctypes.c_int, [_c_p, _u32, _u32, _u32, _c_p, _c_p]),
     ("evrt_scene_set_point_lights", ctypes.c_int, [_c_p, _c_p, _c_p, _u32]),
     ("evrt_scene_set_camera", ctypes.c_int, [_c_p, _u32, _u32, ctypes.c_double, _u32, _c_p, _c_p]),
+    ("evrt_scene_set_environment", ctypes.c_int, [_c_p, _c_p, _u32]),
+    ("evrt_scene_set_lens", ctypes.c_int, [_c_p, ctypes.c_float, ctypes.c_float]),
     ("evrt_scene_reset", ctypes.c_int, [_c_p]),
     ("evrt_scene_commit", ctypes.c_int, [_c_p]),
     ("evrt_default_opts", None, [ctypes.POINTER(RenderOpts)]),
@@ -268,6 +270,14 @@ class Renderer:
                                     sc.key_xform[koff[i]:koff[i + 1]])
         self.scene_set_point_lights(sc.pl_pos, sc.pl_intensity)
         self.scene_set_camera(sc.width, sc.height, sc.vfov_deg, sc.cam_t, sc.cam_elu)
+        env = getattr(sc, "env", None)
+        if env is not None:
+            e = np.ascontiguousarray(env, np.float32)
+            self._check(load_library().evrt_scene_set_environment(self._h, _np_ptr(e), int(e.shape[-1])))
+        else:
+            self._check(load_library().evrt_scene_set_environment(self._h, None, 0))
+        self._check(load_library().evrt_scene_set_lens(self._h, float(getattr(sc, "lens_radius", 0.0)),
+                                                       float(getattr(sc, "focus_dist", 1.0))))
         self.scene_commit()
         self.scene = sc
 

@@ -302,6 +302,36 @@ int evrt_scene_set_camera(evrt_ctx *c, uint32_t width, uint32_t height, double v
     });
 }
 
+int evrt_scene_set_environment(evrt_ctx *c, const float *texels, uint32_t face_res)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        if (face_res > 4096) fail(EVRT_E_UNSUPPORTED, "environment faces above 4096 x 4096 texels");
+        if (face_res && !texels) fail(EVRT_E_INVALID, "NULL environment texels");
+        const size_t n = 6 * (size_t)face_res * face_res;
+        for (size_t i = 0; i < n; ++i)
+            if (!(texels[i] >= 0.0f) || !std::isfinite(texels[i]))
+                fail(EVRT_E_INVALID, "environment radiance must be finite and >= 0");
+        c->pending.env.assign(texels, texels + n);
+        c->pending.env_res = face_res;
+        scene_changed(c);
+    });
+}
+
+int evrt_scene_set_lens(evrt_ctx *c, float aperture_radius, float focus_distance)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        if (!(aperture_radius >= 0.0f) || !std::isfinite(aperture_radius))
+            fail(EVRT_E_INVALID, "aperture radius must be finite and >= 0");
+        if (!(focus_distance > 0.0f) || !std::isfinite(focus_distance))
+            fail(EVRT_E_INVALID, "focus distance must be finite and > 0");
+        c->pending.lens_radius = aperture_radius;
+        c->pending.focus_dist = focus_distance;
+        scene_changed(c);
+    });
+}
+
 int evrt_scene_reset(evrt_ctx *c)
 {
     return guarded(c, [&] {
@@ -327,7 +357,8 @@ static bool same_geometry(const SceneDesc &a, const SceneDesc &b)
     if (x.set != y.set || x.width != y.width || x.height != y.height || x.vfov != y.vfov || x.kt != y.kt ||
         x.elu != y.elu)
         return false;
-    return a.pl_pos == b.pl_pos && a.pl_int == b.pl_int;
+    // The lens radius enters the box padding.
+    return a.pl_pos == b.pl_pos && a.pl_int == b.pl_int && a.lens_radius == b.lens_radius;
 }
 
 int evrt_scene_commit(evrt_ctx *c)
@@ -372,6 +403,7 @@ int evrt_scene_commit(evrt_ctx *c)
             for (size_t i = 0; i < p.pl_int.size(); ++i)
                 pl[i] = make_float4(p.pl_pos[3 * i], p.pl_pos[3 * i + 1], p.pl_pos[3 * i + 2], p.pl_int[i]);
             c->plights.upload(pl.data(), pl.size() * sizeof(float4), nullptr);
+            if (p.env_res) c->env.upload(p.env.data(), p.env.size() * sizeof(float), nullptr);
             hip_check(hipStreamSynchronize(nullptr), "scene upload");
             if (materials_only) refresh_emitters(c);
         }

@@ -59,6 +59,10 @@ struct SceneDesc {
     std::vector<InstanceDesc> instances;
     std::vector<float> pl_pos, pl_int;
     CameraDesc cam;
+    std::vector<float> env;      // [6][N][N] cube map (empty: black background)
+    uint32_t env_res = 0;
+    float lens_radius = 0.0f;    // thin lens aperture radius (0: pinhole)
+    float focus_dist = 1.0f;     // distance of the plane in focus
 };
 
 // World-space geometry of one instant, built on the host and uploaded.
@@ -157,7 +161,7 @@ struct evrt_ctx {
     uint64_t scene_version = 0;
     std::map<double, std::shared_ptr<evrt::DevInstantBufs>> cache;
     std::vector<double> cache_order;
-    evrt::DevBuf mat, plights;
+    evrt::DevBuf mat, plights, env;
     evrt::FrameBuffers fb;
     hipStream_t s2 = nullptr;                // second lane's stream (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;

@@ -56,8 +56,11 @@ struct DevScene {
     DevInstant inst[2];
     const float2 *mat;       // (albedo, emission)
     const float4 *plights;   // (position xyz, intensity)
+    const float *env;        // cube map [6][env_res][env_res] (env_res 0: none)
     uint32_t n_plights;
+    uint32_t env_res;
     uint32_t width, height;
+    float lens_radius, focus_dist;  // thin lens (radius 0: pinhole)
     FastDiv div_w;
 };
 

@@ -756,9 +756,11 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
     const DevCamera &cam = pc.cams ? pc.cams[e >> kPixBits] : (inst ? sc.inst[1].cam : sc.inst[0].cam);
     const uint32_t py = fdiv(sc.div_w, pixel);
     const uint32_t px = pixel - py * sc.width;
+    const bool lens = sc.lens_radius > 0.0f;
     float j0 = 0.5f, j1 = 0.5f;
+    uint4 rb = make_uint4(0u, 0u, 0u, 0u);
+    if (rp.jitter || lens) rb = rng_block(rp, pixel, sample, frame, 0, 0);
     if (rp.jitter) {
-        const uint4 rb = rng_block(rp, pixel, sample, frame, 0, 0);
         j0 = u01(rb.x);
         j1 = u01(rb.y);
     }
@@ -769,9 +771,29 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
     float dx = (cam.fwd[0] + ca * cam.right[0]) + cb * cam.up[0];
     float dy = (cam.fwd[1] + ca * cam.right[1]) + cb * cam.up[1];
     float dz = (cam.fwd[2] + ca * cam.right[2]) + cb * cam.up[2];
+    float ox = cam.eye[0], oy = cam.eye[1], oz = cam.eye[2];
+    if (lens) {
+        // Thin lens: a point of the aperture disk (radius R sqrt(u2), angle
+        // 2 pi u3 from the same block) toward the pinhole ray's point on the
+        // plane in focus, eye + F (f + a r + b u').
+        const float rl = sc.lens_radius * sqrtf(u01(rb.z));
+        const double ph = kTwoPi * (double)u01(rb.w);
+        double sd, cd;
+        sincos(ph, &sd, &cd);
+        const float lu = rl * (float)cd, lv = rl * (float)sd;
+        const float gx = cam.eye[0] + sc.focus_dist * dx;
+        const float gy = cam.eye[1] + sc.focus_dist * dy;
+        const float gz = cam.eye[2] + sc.focus_dist * dz;
+        ox = (cam.eye[0] + lu * cam.right[0]) + lv * cam.up[0];
+        oy = (cam.eye[1] + lu * cam.right[1]) + lv * cam.up[1];
+        oz = (cam.eye[2] + lu * cam.right[2]) + lv * cam.up[2];
+        dx = gx - ox;
+        dy = gy - oy;
+        dz = gz - oz;
+    }
     const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
     dx = dx / len; dy = dy / len; dz = dz / len;
-    q.o[p] = make_float4(cam.eye[0], cam.eye[1], cam.eye[2], 1.0f);
+    q.o[p] = make_float4(ox, oy, oz, 1.0f);
     q.d[p] = make_float4(dx, dy, dz, bitsf(p | (inst << 31)));
     q.skip[p] = kNoPrim;
     pc.rad[a * pc.rs_a + ii * pc.rs_i + s] = 0.0f;
@@ -1017,6 +1039,40 @@ __device__ __forceinline__ float point_light_slot(const DevScene &sc, uint32_t k
 #define EVRT_SHADE_TB 512
 #endif
 constexpr int kShadeTB = EVRT_SHADE_TB;
+// Radiance of the environment cube map in direction (dx, dy, dz): the
+// face of the major axis (ties x, then y, then z), face coordinates
+// (sc, tc) scaled by 1 / |major| from [-1, 1] to [0, N), truncated and
+// clamped, FP32 operations in that order.
+__device__ __forceinline__ float env_radiance(const DevScene &sc, float dx, float dy, float dz)
+{
+    const uint32_t N = sc.env_res;
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    uint32_t face;
+    float ma, u, v;
+    if (ax >= ay && ax >= az) {
+        ma = ax;
+        face = dx >= 0.0f ? 0u : 1u;
+        u = dx >= 0.0f ? -dz : dz;
+        v = -dy;
+    } else if (ay >= az) {
+        ma = ay;
+        face = dy >= 0.0f ? 2u : 3u;
+        u = dx;
+        v = dy >= 0.0f ? dz : -dz;
+    } else {
+        ma = az;
+        face = dz >= 0.0f ? 4u : 5u;
+        u = dz >= 0.0f ? dx : -dx;
+        v = -dy;
+    }
+    if (!(ma > 0.0f)) return 0.0f;
+    const float fs = ((u / ma) + 1.0f) * 0.5f;
+    const float ft = ((v / ma) + 1.0f) * 0.5f;
+    const uint32_t i = min((uint32_t)(fs * (float)N), N - 1u);
+    const uint32_t j = min((uint32_t)(ft * (float)N), N - 1u);
+    return sc.env[((size_t)face * N + j) * N + i];
+}
+
 template <bool ADJ>
 __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, RenderParams rp, RayQueue qin,
                                                const uint32_t *cnt_in, const float2 *hit,
@@ -1054,6 +1110,16 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
         double w = 0.0;          // ADJ: mini-batch weight of the path
         uint32_t emat = 0;       // ADJ: material of the sampled emitter
         uint32_t light = 0;      // the sampled emitter triangle (groups shadow entries)
+        if (valid && prim == kNoPrim && sc.env_res) {
+            // The ray leaves the scene: throughput times the environment's
+            // radiance in its direction (the path ends here).
+            const uint32_t p = fbits(d.w) & ~kInstBit;
+            const uint32_t qq = fdiv(pc.div_bp, p);
+            const uint32_t s = p - qq * pc.bp;
+            const uint32_t ii = fdiv(pc.div_nA, qq);
+            const uint32_t rm = (qq - ii * pc.nA) * pc.rs_a + ii * pc.rs_i + s;
+            pc.rad[rm] = pc.rad[rm] + o.w * env_radiance(sc, d.x, d.y, d.z);
+        }
         if (prim != kNoPrim) {
             pword = fbits(d.w);
             inst = pword >> 31;

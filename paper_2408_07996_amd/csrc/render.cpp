@@ -142,6 +142,10 @@ DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBu
     sc.mat = c->mat.as<const float2>();
     sc.plights = c->plights.as<const float4>();
     sc.n_plights = (uint32_t)c->scene.pl_int.size();
+    sc.env = c->env.as<const float>();
+    sc.env_res = c->scene.env_res;
+    sc.lens_radius = c->scene.lens_radius;
+    sc.focus_dist = c->scene.focus_dist;
     sc.width = c->scene.cam.width;
     sc.height = c->scene.cam.height;
     sc.div_w = make_fastdiv(sc.width);

@@ -46,6 +46,12 @@ class Scene:
     vfov_deg: float
     cam_t: np.ndarray           # float64 [n_cam_keys]
     cam_elu: np.ndarray         # float64 [n_cam_keys, 9] eye, look-at, up
+    # Environment cube map (grey radiance, faces +x, -x, +y, -y, +z, -z,
+    # [6, N, N] rows j then columns i; None: black background) and thin lens
+    # (aperture radius 0: pinhole; distance of the plane in focus).
+    env: Optional[np.ndarray] = None
+    lens_radius: float = 0.0
+    focus_dist: float = 1.0
 
     @property
     def n_tri_world(self) -> int:
@@ -440,6 +446,60 @@ def batch_scene(seed: int = 0, width: int = 1280, height: int = 720, grid: int =
     ct_, ce = _pan_keys((0.0, 4.0, 18.0), (0.0, 0.5, 0.0), (0, 1, 0), n_frames, deg_per_frame)
     b.set_camera(width, height, 45.0, list(ct_), [list(r) for r in ce])
     return b.build()
+
+
+def sky_cube_map(res: int = 32, sun_dir=(0.5, 0.6, -0.62), sun_radiance: float = 60.0,
+                 sky: float = 1.2, ground: float = 0.25) -> np.ndarray:
+    """Grey cube map [6, res, res] (faces +x, -x, +y, -y, +z, -z; row j,
+    column i) of a sky: brighter toward the zenith, a dim ground below the
+    horizon and a small bright sun, evaluated at texel centres."""
+    sc = 2.0 * (np.arange(res) + 0.5) / res - 1.0
+    tc = sc[:, None]
+    s_ = sc[None, :]
+    one = np.ones((res, res))
+    dirs = [np.stack([one, -tc * one, -s_ * one], -1), np.stack([-one, -tc * one, s_ * one], -1),
+            np.stack([s_ * one, one, tc * one], -1), np.stack([s_ * one, -one, -tc * one], -1),
+            np.stack([s_ * one, -tc * one, one], -1), np.stack([-s_ * one, -tc * one, -one], -1)]
+    d = np.stack(dirs)
+    d = d / np.linalg.norm(d, axis=-1, keepdims=True)
+    up = d[..., 1]
+    env = np.where(up > 0, sky * (0.4 + 0.6 * up), ground)
+    sd = np.asarray(sun_dir, np.float64)
+    sd = sd / np.linalg.norm(sd)
+    env = np.where(d @ sd > 0.995, sun_radiance, env)
+    return env.astype(np.float32)
+
+
+def lens_env(seed: int = 0, width: int = 96, height: int = 64, lens_radius: float = 0.08,
+             focus_dist: float = 5.0) -> Scene:
+    """The setting of the paper's failure case (Sec. 5): a background given
+    by an environment map (the sky cube map above), static boxes at several
+    depths whose contours stand against it, one sphere that moves by 0.1 in
+    x between t = 0 and t = 1 at the distance in focus, a floor, a small
+    area light, and a thin-lens camera (aperture radius lens_radius, focus
+    at focus_dist) at (0, 1.2, 5) looking at (0, 0.8, 0), 50 degrees."""
+    rng = np.random.default_rng(seed)
+    b = SceneBuilder()
+    floor_m = b.material(0.5)
+    v, t = oriented_quad([(-6, 0, -6), (6, 0, -6), (6, 0, 6), (-6, 0, 6)], (0, 1, 0))
+    b.static(b.mesh(v, t, floor_m))
+    cv, ct = box_mesh((-0.5, 0.0, -0.5), (0.5, 1.0, 0.5))
+    for (x, z, hgt) in ((-1.6, 2.0, 1.4), (1.3, -1.0, 2.0), (-0.6, -3.0, 2.6), (2.4, 1.5, 0.9)):
+        m = b.material(rng.uniform(0.2, 0.8))
+        b.instance(b.mesh(cv, ct, m), [0.0], [compose(np.diag([0.7, hgt, 0.7]), (x, 0.0, z))])
+    sv, st = icosphere(3)
+    sm = b.material(0.7)
+    b.instance(b.mesh(sv, st, sm), [0.0, 1.0], [compose(np.eye(3), (-0.2, 0.45, 0.0), 0.45),
+                                                compose(np.eye(3), (-0.1, 0.45, 0.0), 0.45)])
+    lm = b.material(0.0, 8.0)
+    lv, lt = oriented_quad([(-0.4, 3.5, -0.4), (0.4, 3.5, -0.4), (0.4, 3.5, 0.4), (-0.4, 3.5, 0.4)], (0, -1, 0))
+    b.static(b.mesh(lv, lt, lm))
+    b.set_camera(width, height, 50.0, [0.0], [[0.0, 1.2, 5.0, 0.0, 0.8, 0.0, 0, 1, 0]])
+    sc = b.build()
+    sc.env = sky_cube_map()
+    sc.lens_radius = float(lens_radius)
+    sc.focus_dist = float(focus_dist)
+    return sc
 
 
 # Frame-batch workload: 64 pairs, schedule 16/16/2048, depth 8.

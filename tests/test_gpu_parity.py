@@ -108,6 +108,9 @@ PATH_CASES = {
                         {**scenes.TINY_PARAMS, "max_depth": 5, "seed": 0x123456789, "mis": 1}, 0.0, 1.0),
     "area_light_mis": (lambda: scenes.plane_area_light(0.6, 4.0, 24, 24),
                        {**scenes.TINY_PARAMS, "mis": 1, "max_depth": 3, "rr_start_depth": 9}, 0.0, 0.0),
+    "lens_env": (lambda: scenes.lens_env(width=32, height=24), {**scenes.TINY_PARAMS, "max_depth": 5}, 0.0, 1.0),
+    "lens_env_mis_nojitter": (lambda: scenes.lens_env(width=32, height=24),
+                              {**scenes.TINY_PARAMS, "max_depth": 5, "mis": 1, "jitter": 0}, 0.0, 1.0),
 }
 
 
@@ -344,6 +347,21 @@ def test_edge_cases(rend, torch_cuda):
         with oracle.Frame(sc, 0.0, t1) as f:
             r = f.render(oracle.make_params(**params))
         _compare(g, r, np.arange(sc.n_pixels), params["C"])
+
+
+@pytest.mark.parametrize("variant", ["lens", "pinhole", "lens_mis"])
+def test_lens_env_frame_parity(rend, torch_cuda, variant):
+    """The failure-case setting of Sec. 5 (environment-map background,
+    thin-lens camera, a moving sphere in focus): full 96x64 frame."""
+    sc = scenes.lens_env(lens_radius=0.0 if variant == "pinhole" else 0.08)
+    rend.set_scene(sc)
+    params = dict(scenes.TINY_PARAMS, max_depth=5, mis=1 if variant == "lens_mis" else 0)
+    _say(f"lens/env frame variant={variant}")
+    g, _ = _frame(rend, sc, params, 0.0, 1.0)
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        r = f.render(oracle.make_params(**params))
+    s = _compare(g, r, np.arange(sc.n_pixels), params["C"])
+    assert s["events"] > 0
 
 
 @pytest.mark.slow
