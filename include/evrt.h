@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define EVRT_ABI_VERSION 4
+#define EVRT_ABI_VERSION 5
 
 enum {
     EVRT_OK = 0,
@@ -194,6 +194,14 @@ typedef struct {
                                 hits and shadow visibility the forward pass
                                 logged, when the log fits (see
                                 evrt_event_loss_grad)                        */
+    float normality_alpha;   /* > 0: normality pre-test (Sec. 5 suggests testing
+                                normality first when counts are small): an
+                                early stop also needs each instant's
+                                log-luminance samples to pass the Jarque-Bera
+                                test, exp(-JB/2) >= normality_alpha, JB =
+                                m/6 (g1^2 + g2^2/4) from the population
+                                skewness g1 and excess kurtosis g2; 0 (default):
+                                off.  Not supported by evrt_render_event_batch */
 } evrt_render_opts;
 
 /* Fills *opts with the defaults listed above (seed 0). */

@@ -58,7 +58,7 @@ class Params(ctypes.Structure):
         ("C", ctypes.c_float), ("alpha", ctypes.c_float),
         ("nee", ctypes.c_uint8), ("jitter", ctypes.c_uint8), ("mode", ctypes.c_uint8),
         ("df_mode", ctypes.c_uint8), ("ref_mode", ctypes.c_uint8), ("mis", ctypes.c_uint8),
-        ("key_base", ctypes.c_uint32),
+        ("key_base", ctypes.c_uint32), ("normality_alpha", ctypes.c_float),
     ]
 
 
@@ -132,6 +132,8 @@ def lib():
                                  ctypes.c_uint32, _f32p, _f32p]
     L.evo_env_radiance.restype = ctypes.c_float
     L.evo_env_radiance.argtypes = [ctypes.c_void_p, _f32p]
+    L.evo_jarque_bera.restype = ctypes.c_double
+    L.evo_jarque_bera.argtypes = [_f64p, ctypes.c_uint32]
     L.evo_crit_margin.restype = ctypes.c_double
     L.evo_crit_margin.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_int]
     L.evo_render.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _u32p, ctypes.c_uint32,
@@ -194,6 +196,12 @@ def decide(x0, x1, C: float, alpha: float, df_mode: int = DF_STUDENT,
     return dict(t=t.value, p=p.value, df=df.value, stop=bool(stop.value), margin=margin.value)
 
 
+def jarque_bera(x) -> float:
+    """Jarque-Bera statistic of a sample (normality pre-test)."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    return float(lib().evo_jarque_bera(_ptr(a, ctypes.c_double), len(a)))
+
+
 def crit_margin(mode: int, t: float, df: float, alpha: float, final_check: bool = False) -> float:
     """Exemption margin of one executed decision (see evo_crit_margin)."""
     return float(lib().evo_crit_margin(int(mode), float(t), float(df), float(alpha), int(final_check)))
@@ -202,7 +210,7 @@ def crit_margin(mode: int, t: float, df: float, alpha: float, final_check: bool 
 def make_params(**kw) -> Params:
     base = dict(seed=0, spp_init=16, spp_batch=16, spp_max=256, max_depth=4, rr_start_depth=2,
                 minibatch=4, log_eps=1e-4, C=0.2, alpha=0.01, nee=1, jitter=1, mode=0,
-                df_mode=0, ref_mode=0, key_base=0, mis=0)
+                df_mode=0, ref_mode=0, key_base=0, mis=0, normality_alpha=0.0)
     base.update(kw)
     p = Params()
     for k, v in base.items():

@@ -82,6 +82,9 @@ typedef struct {
     uint8_t mis;              /* 1: next-event estimation and BSDF sampling of
                                  emitters combined by the power heuristic    */
     uint32_t key_base;        /* frame index of instant 0 in the keys */
+    float normality_alpha;    /* > 0: a pixel stops early only if neither
+                                 instant's log-luminance samples reject
+                                 normality (Jarque-Bera) at this level      */
 } evo_params;
 
 typedef struct {
@@ -186,6 +189,11 @@ int evo_render_video(const evo_frame *const *pairs, uint32_t n_frames, const evo
 int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
                float C, float alpha, int df_mode, int mode,
                double *t_out, double *p_out, double *df_out, int *stop_out, double *margin_out);
+
+/* Jarque-Bera statistic of m samples: m/6 (g1^2 + g2^2 / 4), skewness g1
+ * and excess kurtosis g2 from the population central moments; 0 when the
+ * samples have no spread. */
+double evo_jarque_bera(const double *x, uint32_t m);
 
 /* Exemption margin of one executed decision (|t - critical value| for the
  * boundaries of `mode`; |t| for the event rule at the last count). */

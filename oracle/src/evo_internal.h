@@ -55,6 +55,6 @@ int evo__bvh_closest(const evo_instant *I, const evo_ray *r, float tmin, float t
 int evo__bvh_any(const evo_instant *I, const evo_ray *r, float tmin, float tmax, uint32_t skip);
 void evo__stats_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
                        const evo_params *p, double *mean, double *var, double *t_out,
-                       double *df_out, double *p_out, int *stop_out);
+                       double *df_out, double *p_out, int *stop_out, double *norm_margin);
 
 #endif

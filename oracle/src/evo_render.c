@@ -349,7 +349,7 @@ static void render_pixel(const evo_frame *f, const evo_params *p, uint32_t pixel
     const int fixed = p->mode == EVO_MODE_FIXED;
     uint32_t n_prev[2] = {ref_n, 0};
     uint32_t n1 = fixed ? p->spp_max : p->spp_init;
-    double margin = INFINITY;
+    double margin = INFINITY, norm_margin = INFINITY;
     double mean[2] = {0, 0}, var[2] = {0, 0}, t = 0.0, df = 0.0, pl = 0.0;
     int stop = 0;
     uint32_t rounds = 0;
@@ -369,7 +369,7 @@ static void render_pixel(const evo_frame *f, const evo_params *p, uint32_t pixel
         }
         ++rounds;
         const uint32_t m0 = target[0] / mb, m1 = target[1] / mb;
-        evo__stats_decide(ws->x[0], m0, ws->x[1], m1, p, mean, var, &t, &df, &pl, &stop);
+        evo__stats_decide(ws->x[0], m0, ws->x[1], m1, p, mean, var, &t, &df, &pl, &stop, &norm_margin);
         const int final_check = n1 >= p->spp_max;
         const double mg = evo_crit_margin(p->mode, t, df, p->alpha, final_check);
         if (mg < margin) margin = mg;
@@ -385,7 +385,9 @@ static void render_pixel(const evo_frame *f, const evo_params *p, uint32_t pixel
     const double gap = mean[1] - mean[0];
     o->polarity = fabs(gap) > (double)p->C ? (gap > 0.0 ? 1 : -1) : 0;
     o->decided_early = (uint8_t)stop;
-    o->near_crit = margin < 1e-4 ? 1 : 0;
+    /* Exempt: a t within 1e-4 of a critical value, or a normality
+     * statistic within 1e-6 (relative) of its critical value. */
+    o->near_crit = (margin < 1e-4 || norm_margin < 1e-6) ? 1 : 0;
     o->n_paths = n_prev[1];
     o->n_paths_ref = n_prev[0];
     o->rounds = rounds;

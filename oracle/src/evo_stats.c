@@ -154,6 +154,46 @@ static void mean_var(const double *x, uint32_t m, double *mean, double *var)
     *var = m > 1 ? q / (double)(m - 1) : 0.0;
 }
 
+/* Normality of a pixel's log-luminance samples (the pre-test suggested in
+ * Sec. 5 for small sample counts).  The paper names Shapiro-Wilk and
+ * Kolmogorov-Smirnov as examples; the Jarque-Bera test (Jarque and Bera
+ * 1980) is used because it needs only central moments, which a one-pass
+ * accumulator can carry: JB = m/6 (g1^2 + g2^2 / 4) with g1 = m3 / m2^(3/2),
+ * g2 = m4 / m2^2 - 3 and m_k = (1/m) sum (x - mean)^k; under normality JB
+ * is asymptotically chi^2 with 2 degrees of freedom, P(JB > x) = exp(-x/2).
+ * Plain two-pass sums here. */
+double evo_jarque_bera(const double *x, uint32_t m)
+{
+    double s = 0.0;
+    for (uint32_t k = 0; k < m; ++k) s += x[k];
+    const double mu = s / (double)m;
+    double c2 = 0.0, c3 = 0.0, c4 = 0.0;
+    for (uint32_t k = 0; k < m; ++k) {
+        const double dx = x[k] - mu;
+        const double d2 = dx * dx;
+        c2 += d2;
+        c3 += d2 * dx;
+        c4 += d2 * d2;
+    }
+    const double m2 = c2 / (double)m, m3 = c3 / (double)m, m4 = c4 / (double)m;
+    if (!(m2 > 0.0)) return 0.0;
+    const double g1sq = (m3 * m3) / (m2 * m2 * m2);
+    const double g2 = m4 / (m2 * m2) - 3.0;
+    return (double)m / 6.0 * (g1sq + 0.25 * g2 * g2);
+}
+
+/* The pre-test at level a: normality rejected when P(JB > jb) = exp(-jb/2)
+ * < a.  *margin (relative distance of jb from the critical value -2 ln a)
+ * is lowered for the exemption band. */
+static int normality_rejected(const double *x, uint32_t m, double a, double *margin)
+{
+    const double jb = evo_jarque_bera(x, m);
+    const double crit = -2.0 * log(a);
+    const double mg = fabs(jb - crit) / (crit > 1.0 ? crit : 1.0);
+    if (mg < *margin) *margin = mg;
+    return exp(-0.5 * jb) < a;
+}
+
 /* Eq. 7: t = (|mu_b - mu_a| - C) / sqrt((s_a^2 + s_b^2) / N) with N the
  * sample count at the second instant.  A zero variance sum gives -inf, +inf
  * or 0 according to the sign of |mu_b - mu_a| - C. */
@@ -239,7 +279,7 @@ int evo_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
 /* Internal entry for the render loop (same arithmetic as evo_decide). */
 void evo__stats_decide(const double *x0, uint32_t m0, const double *x1, uint32_t m1,
                        const evo_params *p, double *mean, double *var, double *t_out,
-                       double *df_out, double *p_out, int *stop_out)
+                       double *df_out, double *p_out, int *stop_out, double *norm_margin)
 {
     mean_var(x0, m0, &mean[0], &var[0]);
     mean_var(x1, m1, &mean[1], &var[1]);
@@ -251,4 +291,12 @@ void evo__stats_decide(const double *x0, uint32_t m0, const double *x1, uint32_t
     *p_out = pl;
     *stop_out = stop_rule(p->mode, t, pl, fabs(mean[1] - mean[0]), (double)p->C,
                           (double)p->alpha);
+    /* The pre-test gates an early stop only: a pixel the t-test would stop
+     * goes on sampling while either instant's samples reject normality. */
+    if (*stop_out && p->normality_alpha > 0.0f) {
+        const double a = (double)p->normality_alpha;
+        const int r0 = normality_rejected(x0, m0, a, norm_margin);
+        const int r1 = normality_rejected(x1, m1, a, norm_margin);
+        if (r0 || r1) *stop_out = 0;
+    }
 }

@@ -43,7 +43,8 @@ class RenderOpts(ctypes.Structure):
         ("log_eps", ctypes.c_double), ("nee", ctypes.c_uint8), ("jitter", ctypes.c_uint8),
         ("mode", ctypes.c_uint8), ("df_mode", ctypes.c_uint8), ("ref_mode", ctypes.c_uint8),
         ("profile", ctypes.c_uint8), ("count_work", ctypes.c_uint8), ("lds_nodes", ctypes.c_uint8),
-        ("mis", ctypes.c_uint8), ("ray_batch", _u32), ("key_base", _u32), ("trace_blocks_per_cu", _u32), ("replay_retrace", _u32),
+        ("mis", ctypes.c_uint8), ("ray_batch", _u32), ("key_base", _u32), ("trace_blocks_per_cu", _u32),
+        ("replay_retrace", _u32), ("normality_alpha", ctypes.c_float),
     ]
 
 

@@ -63,6 +63,8 @@ void validate_opts(const evrt_render_opts &o)
     if (o.key_base > (1u << 24)) fail(EVRT_E_INVALID, "key_base above 2^24");
     if (o.replay_retrace > 1) fail(EVRT_E_INVALID, "replay_retrace must be 0 or 1");
     if (o.mis > 1) fail(EVRT_E_INVALID, "mis must be 0 or 1");
+    if (!(o.normality_alpha >= 0.0f && o.normality_alpha < 1.0f))
+        fail(EVRT_E_INVALID, "normality_alpha must be in [0, 1)");
 }
 
 }  // namespace evrt
@@ -504,6 +506,7 @@ int evrt_render_event_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, 
             if (!std::isfinite(times[k])) fail(EVRT_E_INVALID, "times must be finite");
         validate_frame_args(o, C, alpha, spp_init, spp_batch, spp_max, out);
         if (o.ref_mode != EVRT_REF_LOCKSTEP) fail(EVRT_E_UNSUPPORTED, "frame batches sample in lock step only");
+        if (o.normality_alpha > 0.0f) fail(EVRT_E_UNSUPPORTED, "frame batches do not run the normality pre-test");
         if (n_pairs + 1 > kMaxBatchFrames) fail(EVRT_E_UNSUPPORTED, "more than 2047 pairs in one batch");
         if ((uint64_t)o.key_base + n_pairs > (1u << 24)) fail(EVRT_E_INVALID, "key_base + n_pairs above 2^24");
         const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;

@@ -127,6 +127,7 @@ struct LaneBufs {
 
 struct FrameBuffers {
     DevBuf wf_n, wf_mean, wf_m2, wf_ysum, act0, act1;
+    DevBuf wf_m34;                        // normality pre-test: m3, m4 per slot
     DevBuf cnt, stat;
     DevBuf cnt1;  // per-bounce queue counts of lane 1 (lane 0 uses cnt)
     DevBuf row_order;                   // first-round row order (first_rows)

@@ -31,6 +31,8 @@ struct Decide {
     uint32_t mode;             // EVRT_MODE_*
     uint32_t df_mode;          // EVRT_DF_* (with df_per_pixel)
     uint32_t df_per_pixel;
+    double normality_alpha;    // > 0: early stops need both instants' samples
+                               // to pass the Jarque-Bera test at this level
     uint32_t final_round;      // 1 when the last checkpoint is spp_max: event rule only
     uint32_t minibatch;
     uint32_t cnt_slot;         // which of the two compaction counters this round uses
@@ -101,8 +103,8 @@ void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, u
 void launch_accumulate_decide(hipStream_t s, const Piece &pc, const RenderParams &rp, const Decide &dc,
                               uint32_t *act_out, uint32_t *cnt, uint32_t *wf_n, double *wf_mean,
                               double *wf_m2, double *wf_ysum, const Outputs &out);
-void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_in, uint32_t nA,
-                           uint32_t *act_out, uint32_t *cnt, const uint32_t *wf_n,
+void launch_decide_compact(hipStream_t s, const RenderParams &rp, const Decide &dc, const uint32_t *act_in,
+                           uint32_t nA, uint32_t *act_out, uint32_t *cnt, const uint32_t *wf_n,
                            const double *wf_mean, const double *wf_m2, const double *wf_ysum,
                            const Outputs &out);
 void launch_hook_rays(hipStream_t s, uint32_t n, const float *rays, const uint32_t *skip,
@@ -127,7 +129,7 @@ void launch_video_frame_init(hipStream_t s, uint32_t npx, uint32_t *wf_n, double
                              double *wf_ysum, uint32_t *act, uint32_t *cnt, uint32_t width = 1,
                              const uint32_t *rows = nullptr);
 void launch_video_update(hipStream_t s, uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,
-                         double *wf_m2, double *wf_ysum);
+                         double *wf_m2, double *wf_ysum, double *wf_m34);
 
 // Frame batches (see k_batch_* in the kernels).
 void launch_batch_init(hipStream_t s, uint32_t n_frames, uint32_t npx, uint32_t *wf_n, double *wf_mean,

@@ -74,6 +74,9 @@ struct RenderParams {
     uint32_t mis;            // 1: light samples and BSDF-sampled emitter hits
                              // weighted by the power heuristic
     double log_eps;
+    // Third and fourth central-moment sums (2 per accumulator slot) for the
+    // normality pre-test; null when it is off.
+    double *wf_m34;
 };
 
 // A piece of a round: samples [s0, s0 + bp) of nA pixels (the active list)

@@ -1308,40 +1308,74 @@ __device__ __forceinline__ float minibatch_mean(const float *v, uint32_t mb)
 
 // Running (count, mean, M2) of x = ln(Y + eps) over mini-batch means Y of
 // one pixel at one instant, and the sum of Y.
+// With the normality pre-test also the third and fourth central-moment
+// sums m3, m4 (slot pairs of m34; a slot with n = 0 starts them at 0).
 struct Welford {
     uint32_t n;
     double mean, m2, ys;
+    double m3, m4;
 };
 
 __device__ __forceinline__ Welford welford_load(uint32_t slot, const uint32_t *wf_n, const double *wf_mean,
-                                                const double *wf_m2, const double *wf_ysum)
+                                                const double *wf_m2, const double *wf_ysum,
+                                                const double *m34 = nullptr)
 {
-    return Welford{wf_n[slot], wf_mean[slot], wf_m2[slot], wf_ysum[slot]};
+    Welford w{wf_n[slot], wf_mean[slot], wf_m2[slot], wf_ysum[slot], 0.0, 0.0};
+    if (m34 && w.n > 0) {
+        w.m3 = m34[2 * (size_t)slot];
+        w.m4 = m34[2 * (size_t)slot + 1];
+    }
+    return w;
 }
 
 __device__ __forceinline__ void welford_store(const Welford &w, uint32_t slot, uint32_t *wf_n, double *wf_mean,
-                                              double *wf_m2, double *wf_ysum)
+                                              double *wf_m2, double *wf_ysum, double *m34 = nullptr)
 {
     wf_n[slot] = w.n;
     wf_mean[slot] = w.mean;
     wf_m2[slot] = w.m2;
     wf_ysum[slot] = w.ys;
+    if (m34) {
+        m34[2 * (size_t)slot] = w.m3;
+        m34[2 * (size_t)slot + 1] = w.m4;
+    }
 }
 
 // Welford steps over len consecutive path radiances, mb per mini-batch, in
-// sample order.
+// sample order.  With moments, the one-pass updates of the third and
+// fourth central-moment sums (Pebay 2008), from the sums before the step.
 __device__ __forceinline__ void welford_run(Welford &w, const float *src, uint32_t len, uint32_t mb,
-                                            double log_eps)
+                                            double log_eps, bool moments = false)
 {
     for (uint32_t k = 0; k < len; k += mb) {
         const float Y = minibatch_mean(src + k, mb);
         const double x = log((double)Y + log_eps);
         w.n += 1;
         const double delta = x - w.mean;
+        if (moments) {
+            const double n = (double)w.n, dn = delta / n, dn2 = dn * dn, t1 = delta * dn * (n - 1.0);
+            w.m4 = w.m4 + t1 * dn2 * (n * n - 3.0 * n + 3.0) + 6.0 * dn2 * w.m2 - 4.0 * dn * w.m3;
+            w.m3 = w.m3 + t1 * dn * (n - 2.0) - 3.0 * dn * w.m2;
+        }
         w.mean = w.mean + delta / (double)w.n;
         w.m2 = w.m2 + delta * (x - w.mean);
         w.ys = w.ys + (double)Y;
     }
+}
+
+// Normality pre-test of one accumulator (Jarque-Bera): JB = n/6 (g1^2 +
+// g2^2 / 4) with skewness g1 and excess kurtosis g2 from the population
+// central moments; rejected when its chi^2 (2 df) tail exp(-JB/2) < a.
+// Samples without spread are not rejected.
+__device__ __forceinline__ bool normality_rejected(const Welford &w, double a)
+{
+    const double n = (double)w.n;
+    const double m2 = w.m2 / n, m3 = w.m3 / n, m4 = w.m4 / n;
+    if (!(m2 > 0.0)) return false;
+    const double g1sq = (m3 * m3) / (m2 * m2 * m2);
+    const double g2 = m4 / (m2 * m2) - 3.0;
+    const double jb = n / 6.0 * (g1sq + 0.25 * g2 * g2);
+    return exp(-0.5 * jb) < a;
 }
 
 // Welford update for each mini-batch of the piece, in sample order; one
@@ -1355,9 +1389,9 @@ __global__ void k_accumulate(Piece pc, RenderParams rp, uint32_t *wf_n, double *
     const uint32_t a = g - ii * pc.nA;
     const uint32_t pixel = pc.act[a];
     const uint32_t slot = 2 * pixel + pc.inst_base + ii;
-    Welford w = welford_load(slot, wf_n, wf_mean, wf_m2, wf_ysum);
-    welford_run(w, pc.rad + a * pc.rs_a + ii * pc.rs_i, pc.bp, rp.minibatch, rp.log_eps);
-    welford_store(w, slot, wf_n, wf_mean, wf_m2, wf_ysum);
+    Welford w = welford_load(slot, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
+    welford_run(w, pc.rad + a * pc.rs_a + ii * pc.rs_i, pc.bp, rp.minibatch, rp.log_eps, rp.wf_m34 != nullptr);
+    welford_store(w, slot, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
 }
 
 // Eq. 7 with N = samples at the second instant; zero variance gives -inf,
@@ -1481,7 +1515,11 @@ __device__ __forceinline__ bool decide_pixel(const Decide &dc, uint32_t j, bool 
     const double var1 = m1 > 1 ? w1.m2 / (double)(m1 - 1) : 0.0;
     const double t = t_value(w0.mean, var0, w1.mean, var1, m1, dc.C);
     const double gap = w1.mean - w0.mean;
-    const bool stop = !final_ck && stop_rule(dc, j, t, gap, m0, var0, m1, var1);
+    bool stop = !final_ck && stop_rule(dc, j, t, gap, m0, var0, m1, var1);
+    // The normality pre-test gates early stops only (Sec. 5).
+    if (stop && dc.normality_alpha > 0.0 &&
+        (normality_rejected(w0, dc.normality_alpha) || normality_rejected(w1, dc.normality_alpha)))
+        stop = false;
     const bool done = stop || final_ck;
     if (done) {
         out.polarity[pixel] = fabs(gap) > dc.C ? (gap > 0.0 ? 1 : -1) : 0;
@@ -1502,7 +1540,7 @@ __device__ __forceinline__ bool decide_pixel(const Decide &dc, uint32_t j, bool 
 
 // Decision after a round for every active pixel; finished pixels write
 // their outputs, the rest are compacted into act_out.
-__global__ __launch_bounds__(256) void k_decide_compact(Decide dc, const uint32_t *act_in, uint32_t nA,
+__global__ __launch_bounds__(256) void k_decide_compact(RenderParams rp, Decide dc, const uint32_t *act_in, uint32_t nA,
                                                         uint32_t *act_out, uint32_t *cnt,
                                                         const uint32_t *wf_n, const double *wf_mean,
                                                         const double *wf_m2, const double *wf_ysum,
@@ -1513,8 +1551,8 @@ __global__ __launch_bounds__(256) void k_decide_compact(Decide dc, const uint32_
     if (a == 0) cnt[kCntActive + (dc.cnt_slot ^ 1u)] = 0;
     if (a >= nA) return;
     const uint32_t pixel = act_in[a];
-    const Welford w0 = welford_load(2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
-    const Welford w1 = welford_load(2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
+    const Welford w0 = welford_load(2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
+    const Welford w1 = welford_load(2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
     const bool done = decide_pixel(dc, dc.n_checks - 1, dc.final_round != 0, pixel, w0, w1, out);
     const uint32_t slot = wave_append(!done, cnt + kCntActive + dc.cnt_slot);
     if (!done) act_out[slot] = pixel;
@@ -1535,8 +1573,9 @@ __global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParam
     if (a == 0) cnt[kCntActive + (dc.cnt_slot ^ 1u)] = 0;
     if (a >= pc.nA) return;
     const uint32_t pixel = pc.act[a];
-    Welford w0 = welford_load(2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
-    Welford w1 = welford_load(2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
+    Welford w0 = welford_load(2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
+    Welford w1 = welford_load(2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
+    const bool moments = rp.wf_m34 != nullptr;
     const uint32_t mb = rp.minibatch;
     const float *src = pc.rad + a * pc.rs_a;
     const bool both = pc.n_inst == 2;
@@ -1545,10 +1584,10 @@ __global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParam
     for (uint32_t j = 0; j < dc.n_checks; ++j) {
         const uint32_t end = dc.ck_end[j];
         if (both) {
-            welford_run(w0, src + (k - pc.s0), end - k, mb, rp.log_eps);
-            welford_run(w1, src + pc.rs_i + (k - pc.s0), end - k, mb, rp.log_eps);
+            welford_run(w0, src + (k - pc.s0), end - k, mb, rp.log_eps, moments);
+            welford_run(w1, src + pc.rs_i + (k - pc.s0), end - k, mb, rp.log_eps, moments);
         } else {
-            welford_run(w1, src + (k - pc.s0), end - k, mb, rp.log_eps);
+            welford_run(w1, src + (k - pc.s0), end - k, mb, rp.log_eps, moments);
         }
         k = end;
         const bool final_ck = dc.final_round != 0 && j + 1 == dc.n_checks;
@@ -1559,8 +1598,8 @@ __global__ __launch_bounds__(256) void k_accumulate_decide(Piece pc, RenderParam
     }
     // The state at the stop (or at the round's end) stays in memory: a
     // sequential video takes it as the pixel's next reference at an event.
-    if (both) welford_store(w0, 2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum);
-    welford_store(w1, 2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum);
+    if (both) welford_store(w0, 2 * pixel, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
+    welford_store(w1, 2 * pixel + 1, wf_n, wf_mean, wf_m2, wf_ysum, rp.wf_m34);
     const uint32_t slot = wave_append(!done, cnt + kCntActive + dc.cnt_slot);
     if (!done) act_out[slot] = pixel;
 }
@@ -1588,7 +1627,7 @@ __global__ void k_video_frame_init(uint32_t npx, uint32_t width, const uint32_t 
 // statistics as its reference (Algorithm 1 replaces the reference
 // log-luminance at events only).
 __global__ void k_video_update(uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,
-                               double *wf_m2, double *wf_ysum)
+                               double *wf_m2, double *wf_ysum, double *wf_m34)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npx || polarity[i] == 0) return;
@@ -1596,6 +1635,10 @@ __global__ void k_video_update(uint32_t npx, const int8_t *polarity, uint32_t *w
     wf_mean[2 * i] = wf_mean[2 * i + 1];
     wf_m2[2 * i] = wf_m2[2 * i + 1];
     wf_ysum[2 * i] = wf_ysum[2 * i + 1];
+    if (wf_m34) {
+        wf_m34[4 * (size_t)i] = wf_m34[4 * (size_t)i + 2];
+        wf_m34[4 * (size_t)i + 1] = wf_m34[4 * (size_t)i + 3];
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -2016,12 +2059,12 @@ void launch_accumulate_decide(hipStream_t s, const Piece &pc, const RenderParams
                        wf_n, wf_mean, wf_m2, wf_ysum, out);
 }
 
-void launch_decide_compact(hipStream_t s, const Decide &dc, const uint32_t *act_in, uint32_t nA,
-                           uint32_t *act_out, uint32_t *cnt, const uint32_t *wf_n,
+void launch_decide_compact(hipStream_t s, const RenderParams &rp, const Decide &dc, const uint32_t *act_in,
+                           uint32_t nA, uint32_t *act_out, uint32_t *cnt, const uint32_t *wf_n,
                            const double *wf_mean, const double *wf_m2, const double *wf_ysum,
                            const Outputs &out)
 {
-    hipLaunchKernelGGL(k_decide_compact, dim3((nA + 255) / 256), dim3(256), 0, s, dc, act_in, nA,
+    hipLaunchKernelGGL(k_decide_compact, dim3((nA + 255) / 256), dim3(256), 0, s, rp, dc, act_in, nA,
                        act_out, cnt, wf_n, wf_mean, wf_m2, wf_ysum, out);
 }
 
@@ -2033,10 +2076,10 @@ void launch_video_frame_init(hipStream_t s, uint32_t npx, uint32_t *wf_n, double
 }
 
 void launch_video_update(hipStream_t s, uint32_t npx, const int8_t *polarity, uint32_t *wf_n, double *wf_mean,
-                         double *wf_m2, double *wf_ysum)
+                         double *wf_m2, double *wf_ysum, double *wf_m34)
 {
     hipLaunchKernelGGL(k_video_update, dim3(std::max(1u, (npx + 255) / 256)), dim3(256), 0, s, npx, polarity, wf_n,
-                       wf_mean, wf_m2, wf_ysum);
+                       wf_mean, wf_m2, wf_ysum, wf_m34);
 }
 
 void launch_batch_init(hipStream_t s, uint32_t n_frames, uint32_t npx, uint32_t *wf_n, double *wf_mean,

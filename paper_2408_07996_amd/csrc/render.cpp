@@ -152,9 +152,15 @@ DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBu
     return sc;
 }
 
-static RenderParams make_params(const evrt_ctx *c, const evrt_render_opts &o)
+static RenderParams make_params(evrt_ctx *c, const evrt_render_opts &o)
 {
     RenderParams rp{};
+    if (o.normality_alpha > 0.0f) {
+        // Third and fourth moment sums of both accumulator slots per pixel.
+        const size_t npx = (size_t)c->scene.cam.width * c->scene.cam.height;
+        c->fb.wf_m34.ensure(sizeof(double) * 4 * npx);
+        rp.wf_m34 = c->fb.wf_m34.as<double>();
+    }
     rp.key0 = (uint32_t)(o.seed & 0xffffffffu);
     rp.key1 = (uint32_t)(o.seed >> 32);
     rp.max_depth = o.max_depth;
@@ -335,6 +341,7 @@ static void set_tests(evrt_ctx *c, Decide &dc, const evrt_render_opts &o, float 
     dc.alpha = (double)alpha;
     dc.df_mode = o.df_mode;
     dc.df_per_pixel = (o.df_mode == EVRT_DF_WELCH || per_pixel_ref) ? 1u : 0u;
+    dc.normality_alpha = (double)o.normality_alpha;
     if (dc.df_per_pixel) return;
     for (uint32_t j = 0; j < dc.n_checks; ++j) {
         if (dc.ck_end[j] >= spp_max) break;
@@ -505,7 +512,7 @@ static void run_rounds(evrt_ctx *c, const DevScene &sc, const RenderParams &rp, 
         const bool fused = trace_range(c, act_in, nA, n_inst, inst_base, n_prev, hi, sc, rp, o, s, prof, &dc,
                                        act_out, &outs);
         if (!fused)
-            launch_decide_compact(s, dc, act_in, nA, act_out, fb.cnt.as<uint32_t>(), fb.wf_n.as<uint32_t>(),
+            launch_decide_compact(s, rp, dc, act_in, nA, act_out, fb.cnt.as<uint32_t>(), fb.wf_n.as<uint32_t>(),
                                   fb.wf_mean.as<double>(), fb.wf_m2.as<double>(), fb.wf_ysum.as<double>(),
                                   outs);
         hip_check(hipMemcpyAsync(c->h_pinned, fb.cnt.as<uint32_t>() + kCntActive + dc.cnt_slot, sizeof(uint32_t),
@@ -635,7 +642,7 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
         run_rounds(c, sc, rp, ok, C, alpha, spp_init, spp_batch, spp_max, true, npx, outs, s, prof,
                    o.mode == EVRT_MODE_ADAPTIVE_2T);
         launch_video_update(s, npx, outs.polarity, fb.wf_n.as<uint32_t>(), fb.wf_mean.as<double>(),
-                            fb.wf_m2.as<double>(), fb.wf_ysum.as<double>());
+                            fb.wf_m2.as<double>(), fb.wf_ysum.as<double>(), rp.wf_m34);
     }
     read_stats(c, s);
     prof.collect(c->stats);

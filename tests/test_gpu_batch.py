@@ -149,3 +149,7 @@ def test_batch_rejects_moving_geometry_and_ref_full(rend):
         rend.render_event_batch([0.0, 1.0, 2.0], P["C"], P["alpha"], 16, 16, 64,
                                 _opts(P, ref_mode=ev.REF_FULL))
     assert e.value.code == ev.EVRT_E_UNSUPPORTED
+    with pytest.raises(ev.EvrtError) as e:
+        rend.render_event_batch([0.0, 1.0, 2.0], P["C"], P["alpha"], 16, 16, 64,
+                                _opts(P, normality_alpha=0.05))
+    assert e.value.code == ev.EVRT_E_UNSUPPORTED

@@ -47,7 +47,7 @@ def _opts_from(params: dict, **kw):
     d = dict(params)
     d.update(kw)
     keys = ("seed", "max_depth", "rr_start_depth", "minibatch", "log_eps", "nee", "jitter", "mode",
-            "df_mode", "ref_mode", "lds_nodes", "ray_batch", "mis")
+            "df_mode", "ref_mode", "lds_nodes", "ray_batch", "mis", "normality_alpha")
     return {k: d[k] for k in keys if k in d}
 
 
@@ -261,7 +261,7 @@ def _compare(g, r, pixels, C):
 
 @pytest.mark.parametrize("variant", ["default", "fixed", "ref_full", "two_tailed", "mean_only", "mb1", "mb8",
                                      "lds_treelet", "small_pieces", "split_samples", "welch", "welch_two_tailed",
-                                     "welch_ref_full", "mis"])
+                                     "welch_ref_full", "mis", "normality", "normality_split"])
 def test_tiny_frame_parity(rend, torch_cuda, variant):
     sc = scenes.tiny_box()
     rend.set_scene(sc)
@@ -292,6 +292,10 @@ def test_tiny_frame_parity(rend, torch_cuda, variant):
         params.update(df_mode=ev.DF_WELCH, ref_mode=ev.REF_FULL)
     elif variant == "mis":
         params.update(mis=1, max_depth=5)
+    elif variant == "normality":
+        params["normality_alpha"] = 0.05
+    elif variant == "normality_split":
+        params.update(normality_alpha=0.05, ray_batch=512)   # moments over split sample ranges
     _say(f"tiny frame variant={variant}")
     g, st = _frame(rend, sc, params, 0.0, 1.0)
     with oracle.Frame(sc, 0.0, 1.0) as f:

@@ -121,3 +121,16 @@ def test_reference_carried_on_gpu(rend):
     for k in range(1, len(TIMES) - 1):
         np.testing.assert_array_equal(mean[k][evk[k - 1], 0], mean[k - 1][evk[k - 1], 1])
         np.testing.assert_array_equal(mean[k][~evk[k - 1], 0], mean[k - 1][~evk[k - 1], 0])
+
+
+def test_normality_pretest_video_matches_oracle(rend):
+    """The normality pre-test in a sequential video: the reference's third
+    and fourth moments are carried with it."""
+    P = dict(scenes.TINY_PARAMS, normality_alpha=0.05)
+    sc = scenes.tiny_box(width=24, height=20)
+    rend.set_scene(sc)
+    g = rend.render_event_video(TIMES, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"],
+                                _opts(P, normality_alpha=0.05))
+    v = oracle.render_video(sc, TIMES, oracle.make_params(**P))
+    pol, _ = _video_parity(g, v)
+    assert (pol != 0).any()

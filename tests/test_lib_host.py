@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
     bound = {s[0] for s in ev.SIGNATURES}
     assert set(names) == bound
-    assert L.evrt_abi_version() == 4
+    assert L.evrt_abi_version() == 5
 
 
 def test_default_opts():
@@ -108,7 +108,8 @@ def test_render_argument_validation_before_device_work(host_ctx):
     bad = [dict(spp_init=6), dict(spp_init=4), dict(spp_init=512), dict(spp_batch=6), dict(alpha=0.0),
            dict(alpha=1.0), dict(C=-0.1), dict(C=math.inf), dict(t0=math.nan), dict(minibatch=3),
            dict(max_depth=0), dict(max_depth=65), dict(mode=9), dict(nee=2), dict(out="missing"),
-           dict(log_eps=-1.0), dict(rr_start_depth=0), dict(replay_retrace=2), dict(mis=2)]
+           dict(log_eps=-1.0), dict(rr_start_depth=0), dict(replay_retrace=2), dict(mis=2),
+           dict(normality_alpha=1.0), dict(normality_alpha=-0.1)]
     for kw in bad:
         rc, msg = _render_rc(r, **kw)
         assert rc == ev.EVRT_E_INVALID, (kw, rc, msg)

@@ -122,6 +122,22 @@ def test_mean_only_boundary_is_inclusive():
 
 
 # --------------------------------------------------------------------------
+# Normality pre-test (Jarque-Bera).
+
+def test_jarque_bera_matches_scipy_and_closed_form():
+    rng = np.random.default_rng(8)
+    for m in (4, 16, 64, 1000):
+        for draw in (rng.normal(0, 1, m), rng.exponential(1.0, m), np.log(rng.uniform(0, 1, m) + 1e-4)):
+            ref = stats.jarque_bera(draw).statistic
+            assert oracle.jarque_bera(draw) == pytest.approx(ref, rel=1e-10, abs=1e-12)
+    # Two-point data +-1: m2 = 1, m3 = 0, m4 = 1, excess kurtosis -2, JB = m / 6.
+    for m in (2, 10, 64):
+        x = np.tile([-1.0, 1.0], m // 2)
+        assert oracle.jarque_bera(x) == pytest.approx(len(x) / 6.0, rel=1e-15)
+    assert oracle.jarque_bera(np.full(8, 0.75)) == 0.0
+
+
+# --------------------------------------------------------------------------
 # Algorithm 1 per pixel, rerun in Python on the oracle's path radiances.
 
 def _mb_logs(L, mb, eps):
@@ -171,6 +187,11 @@ def _test(x0, x1, C, alpha, mode, welch):
     return t, abs(d) <= C, abs(t)
 
 
+def _normal_ok(x, a):
+    """Normality not rejected at level a (Jarque-Bera, chi^2 with 2 df)."""
+    return not (math.exp(-0.5 * stats.jarque_bera(x).statistic) < a)
+
+
 def _pixel_loop(x_ref, x_cur_full, P, mode, welch, m_ref_fixed=None):
     """One pixel of one pair: x_ref holds the first instant's logs (all of
     them in lock step, or a fixed reference of m_ref_fixed samples);
@@ -190,6 +211,9 @@ def _pixel_loop(x_ref, x_cur_full, P, mode, welch, m_ref_fixed=None):
             break
         t, stop, mg = _test(x0, x1, C, alpha, mode, welch)
         margin = min(margin, mg)
+        a_n = float(F32(P.get("normality_alpha", 0.0)))
+        if stop and a_n > 0 and not (_normal_ok(x0, a_n) and _normal_ok(x1, a_n)):
+            stop = False
         if stop:
             break
         n = min(n + P["spp_batch"], spp_max)
@@ -206,7 +230,7 @@ def _all_logs(f, params, P, pixels, instant):
     return [_mb_logs(L[i], P["minibatch"], P["log_eps"]) for i in range(len(pixels))]
 
 
-@pytest.mark.parametrize("variant", ["1t", "welch", "2t", "mean_only", "ref_full"])
+@pytest.mark.parametrize("variant", ["1t", "welch", "2t", "mean_only", "ref_full", "normality"])
 def test_render_loop_and_margin_match_python_rerun(variant):
     """Sample counts, early stops, polarity and the exemption margin of
     every pixel of a 16x12 frame equal a Python rerun of Algorithm 1 with
@@ -215,7 +239,8 @@ def test_render_loop_and_margin_match_python_rerun(variant):
     mode = {"2t": oracle.MODE_ADAPTIVE_2T, "mean_only": oracle.MODE_MEAN_ONLY}.get(variant, oracle.MODE_ADAPTIVE_1T)
     welch = variant == "welch"
     P = dict(scenes.TINY_PARAMS, spp_max=128, mode=mode, df_mode=int(welch),
-             ref_mode=oracle.REF_FULL if variant == "ref_full" else oracle.REF_LOCKSTEP)
+             ref_mode=oracle.REF_FULL if variant == "ref_full" else oracle.REF_LOCKSTEP,
+             normality_alpha=0.05 if variant == "normality" else 0.0)
     params = oracle.make_params(**P)
     pixels = np.arange(16 * 12, dtype=np.uint32)
     with oracle.Frame(sc, 0.0, 1.0) as f:
@@ -228,12 +253,22 @@ def test_render_loop_and_margin_match_python_rerun(variant):
         n, stop, margin, pol, _ = _pixel_loop(x0s[i], x1s[i], P, mode, welch, m_ref)
         got = out["crit_margin"][i]
         assert got == margin or abs(got - margin) <= 1e-8 * max(1.0, margin), (i, got, margin)
-        assert out["near_crit"][i] == (out["crit_margin"][i] < 1e-4)
+        if variant != "normality":
+            assert out["near_crit"][i] == (out["crit_margin"][i] < 1e-4)
+        if out["near_crit"][i]:
+            continue
         if margin < 1e-6:
             continue   # both answers are legitimate within rounding of the boundary
         assert out["n_paths"][i] == n and out["decided_early"][i] == stop and out["polarity"][i] == pol, i
         stops += stop
     assert stops > 0
+    if variant == "normality":
+        # the pre-test holds back some stops the t-test alone would make
+        plain = dict(P, normality_alpha=0.0)
+        with oracle.Frame(sc, 0.0, 1.0) as f:
+            ref = f.render(oracle.make_params(**plain), pixels)
+        assert out["decided_early"].sum() < ref["decided_early"].sum()
+        assert (out["n_paths"] >= ref["n_paths"]).all()
 
 
 def test_two_tailed_video_carries_reference_counts():
