@@ -270,9 +270,10 @@ int evrt_render_event_video(evrt_ctx *ctx, uint32_t n_frames, const double *time
  * would compute it, bit for bit.  The frame shared by pairs k - 1 and k is
  * sampled once, up to the larger count the two pairs need (its samples are
  * the same random-number stream in both), and all pairs advance through the
- * schedule together.  The geometry must not move across the batch (every
- * instance has the same transform at every time; the camera may move),
- * else EVRT_E_UNSUPPORTED; lock-step sampling only (ref_mode LOCKSTEP);
+ * schedule together.  Geometry and camera may move: when instances move
+ * across the batch, every frame's geometry and BVH is built (in parallel on
+ * the host) and kept on the device, and each round traces each frame's
+ * items with its own geometry; lock-step sampling only (ref_mode LOCKSTEP);
  * at most 2047 pairs and 2^21 pixels.  Outputs as for one frame, pair-major:
  * entry k * width * height + pixel (x2 arrays: two per entry). */
 int evrt_render_event_batch(evrt_ctx *ctx, uint32_t n_pairs, const double *times, float C, float alpha,

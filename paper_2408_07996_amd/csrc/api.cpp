@@ -512,8 +512,6 @@ int evrt_render_event_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, 
         const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;
         if (npx > kPixMask + 1ull) fail(EVRT_E_UNSUPPORTED, "more than 2^21 pixels per frame in a batch");
         if ((n_pairs + 1ull) * npx >= (1ull << 31)) fail(EVRT_E_UNSUPPORTED, "more than 2^31 (frame, pixel) items");
-        if (!instances_static(c->scene, times, n_pairs + 1))
-            fail(EVRT_E_UNSUPPORTED, "frame batches need geometry that does not move across the batch");
         need_device(c);
         render_batch(c, n_pairs, times, C, alpha, spp_init, spp_batch, spp_max, o, *out,
                      static_cast<hipStream_t>(stream));

@@ -143,6 +143,7 @@ struct FrameBuffers {
     // per-frame cameras.
     DevBuf b_wf_n, b_wf_mean, b_wf_m2, b_wf_ysum, b_item_idx, b_items, b_act0, b_act1, b_pair_items, b_snap,
         b_cams;
+    DevBuf b_sorted, b_sort_tmp, b_frame_start;  // moving geometry: items regrouped by frame
 };
 
 struct EventPair {
@@ -176,11 +177,16 @@ struct evrt_ctx {
     uint32_t shade_blocks_per_cu = 0;
     void *noalloc_scratch = nullptr;         // this device's static scratch array
     uint32_t materials_only_commits = 0;     // commits that kept the instants
+    size_t cache_cap = 0;                    // instants the cache holds (at least 4)
+    std::vector<uint32_t> h_frame_start;     // readback of a batch round's frame starts
 };
 
 namespace evrt {
 // Geometry of instant t on the device (built and cached on first use).
 std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s, double *ms_build);
+// Geometry of every time in times[0, n) on the device, the missing ones
+// built on all host threads; the cache grows to hold them all.
+void get_instants(evrt_ctx *c, const double *times, uint32_t n, hipStream_t s, double *ms_build);
 // After a commit that changed only albedo and emission: the emitter tables
 // of every cached instant rebuilt and uploaded; geometry and BVHs are kept.
 void refresh_emitters(evrt_ctx *c);

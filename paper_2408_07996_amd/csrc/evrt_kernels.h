@@ -141,6 +141,13 @@ void launch_batch_pair_items(hipStream_t s, const uint32_t *act, uint32_t nA, ui
                              const uint32_t *item_idx, uint2 *pair_items);
 void launch_batch_clear(hipStream_t s, const uint32_t *items, uint32_t n_items, uint32_t npx, uint32_t *item_idx,
                         uint32_t *cnt);
+// Batches of moving geometry: the round's items sorted by (frame, pixel)
+// (radix sort into `sorted`, temp storage of batch_sort_temp_bytes), item
+// indices renewed, first position of each frame in frame_start[nf]
+// (0xffffffff for frames without items).
+size_t batch_sort_temp_bytes(uint32_t n_items);
+void launch_batch_regroup(hipStream_t s, uint32_t *items, uint32_t n_items, uint32_t *sorted, void *temp,
+                          size_t temp_bytes, uint32_t npx, uint32_t *item_idx, uint32_t *frame_start, uint32_t nf);
 void launch_batch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, const Decide &dc,
                              uint32_t npx, uint32_t item_base, uint32_t *wf_n, double *wf_mean, double *wf_m2,
                              double *wf_ysum, double *snap);

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include <hip/hip_ext.h>
+#include <hipcub/device/device_radix_sort.hpp>
 
 #include "../../include/evrt.h"
 #include "evrt_kernels.h"
@@ -1707,6 +1708,28 @@ __global__ __launch_bounds__(256) void k_batch_items(const uint32_t *act, uint32
     }
 }
 
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Items of a round sorted by (frame, pixel), written back in that order:
+// every (frame, pixel) slot points at its new position, and frame_start
+// holds the first position of each frame that has items (others keep
+// 0xffffffff).
+__global__ void k_batch_regroup(const uint32_t *sorted, uint32_t n_items, uint32_t npx, uint32_t *items,
+                                uint32_t *item_idx, uint32_t *frame_start)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const uint32_t e = sorted[i];
+    const uint32_t f = e >> kPixBits;
+    items[i] = e;
+    item_idx[f * npx + (e & kPixMask)] = i;
+    if (i == 0 || (sorted[i - 1] >> kPixBits) != f) frame_start[f] = i;
+}
+
 // Item indices of both frames of every active pair.
 __global__ void k_batch_pair_items(const uint32_t *act, uint32_t nA, uint32_t npx, const uint32_t *item_idx,
                                    uint2 *pair_items)
@@ -2103,6 +2126,27 @@ void launch_batch_pair_items(hipStream_t s, const uint32_t *act, uint32_t nA, ui
 {
     hipLaunchKernelGGL(k_batch_pair_items, dim3(std::max(1u, (nA + 255) / 256)), dim3(256), 0, s, act, nA, npx,
                        item_idx, pair_items);
+}
+
+size_t batch_sort_temp_bytes(uint32_t n_items)
+{
+    size_t bytes = 0;
+    hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr, n_items, 0, 32);
+    return bytes;
+}
+
+void launch_batch_regroup(hipStream_t s, uint32_t *items, uint32_t n_items, uint32_t *sorted, void *temp,
+                          size_t temp_bytes, uint32_t npx, uint32_t *item_idx, uint32_t *frame_start, uint32_t nf)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(std::max(1u, (nf + 255) / 256)), dim3(256), 0, s, frame_start, nf,
+                       0xffffffffu);
+    if (n_items == 0) return;
+    size_t bytes = temp_bytes;
+    const hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, bytes, (const uint32_t *)items, sorted, n_items, 0,
+                                                           32, s);
+    if (e != hipSuccess) return;  // reported by the caller's next HIP check
+    hipLaunchKernelGGL(k_batch_regroup, dim3((n_items + 255) / 256), dim3(256), 0, s, sorted, n_items, npx, items,
+                       item_idx, frame_start);
 }
 
 void launch_batch_clear(hipStream_t s, const uint32_t *items, uint32_t n_items, uint32_t npx, uint32_t *item_idx,

@@ -7,9 +7,11 @@
 // outputs of finished pixels and compacts the rest into the next active
 // list.  The active count is read back once per round.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "evrt_host.h"
 
@@ -22,7 +24,7 @@ static constexpr uint64_t kMaxRayLog = 16ull << 30;  // bytes of a gradient's ra
 
 static void cache_insert(evrt_ctx *c, double t, const std::shared_ptr<DevInstantBufs> &bi)
 {
-    if (c->cache.size() >= kCacheInstants) {
+    if (c->cache.size() >= std::max<size_t>(kCacheInstants, c->cache_cap)) {
         const double victim = c->cache_order.front();
         c->cache_order.erase(c->cache_order.begin());
         c->cache.erase(victim);
@@ -30,6 +32,9 @@ static void cache_insert(evrt_ctx *c, double t, const std::shared_ptr<DevInstant
     c->cache[t] = bi;
     c->cache_order.push_back(t);
 }
+
+static void build_host_instant(const evrt_ctx *c, double t, HostInstant &h);
+static void upload_instant(evrt_ctx *c, DevInstantBufs &bi, hipStream_t s);
 
 // Emitter table of an instant on the device: the CDF and, per emitter, its
 // three vertices (the first with the emitted radiance in w) and (unit
@@ -103,32 +108,92 @@ std::shared_ptr<DevInstantBufs> get_instant(evrt_ctx *c, double t, hipStream_t s
             *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         return bi;
     }
-    HostInstant &h = bi->host;
+    build_host_instant(c, t, bi->host);
+    upload_instant(c, *bi, s);
+    cache_insert(c, t, bi);
+    if (ms_build)
+        *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return bi;
+}
+
+// World geometry and BVH of instant t on the host (reads only the committed
+// scene: several may run at once).
+static void build_host_instant(const evrt_ctx *c, double t, HostInstant &h)
+{
     build_world(c->scene, t, h);
     const float pad = bvh_padding(c->scene, h, h);
     build_bvh(h, (uint32_t)lds_treelet_nodes(), pad);
     if (h.depth > (uint32_t)traverse_max_depth()) fail(EVRT_E_UNSUPPORTED, "BVH deeper than the traversal stack");
     // Traversal addresses nodes by 32-bit byte offsets (128 bytes a node).
     if (h.nodes.size() / 8 >= (1u << 25)) fail(EVRT_E_UNSUPPORTED, "more than 2^25 BVH nodes");
-    bi->nodes.upload(h.nodes.data(), h.nodes.size() * sizeof(float4), s);
-    bi->tris.upload(h.tris.data(), h.tris.size() * sizeof(float4), s);
-    bi->prim.upload(h.prim.data(), h.prim.size() * sizeof(float4), s);
-    upload_emitters(*bi, c->scene, s);
+}
+
+static void upload_instant(evrt_ctx *c, DevInstantBufs &bi, hipStream_t s)
+{
+    HostInstant &h = bi.host;
+    bi.nodes.upload(h.nodes.data(), h.nodes.size() * sizeof(float4), s);
+    bi.tris.upload(h.tris.data(), h.tris.size() * sizeof(float4), s);
+    bi.prim.upload(h.prim.data(), h.prim.size() * sizeof(float4), s);
+    upload_emitters(bi, c->scene, s);
     hip_check(hipStreamSynchronize(s), "geometry upload");
-    DevInstant &v = bi->view;
-    v.nodes = bi->nodes.as<const float4>();
-    v.tris = bi->tris.as<const float4>();
-    v.prim = bi->prim.as<const float4>();
+    DevInstant &v = bi.view;
+    v.nodes = bi.nodes.as<const float4>();
+    v.tris = bi.tris.as<const float4>();
+    v.prim = bi.prim.as<const float4>();
     v.root = h.root;
     v.n_nodes = (uint32_t)(h.nodes.size() / 8);
     v.n_lds = h.n_lds;
     v.cam = h.cam;
-    // Keep only the world triangles needed for statistics; drop the rest.
-    h.nodes.shrink_to_fit();
-    cache_insert(c, t, bi);
+    // The host keeps the world triangles, primitives and areas (emitter
+    // tables of a material-only commit); the BVH lives on the device only.
+    std::vector<float4>().swap(h.nodes);
+    std::vector<float4>().swap(h.tris);
+}
+
+void get_instants(evrt_ctx *c, const double *times, uint32_t n, hipStream_t s, double *ms_build)
+{
+    c->cache_cap = std::max<size_t>(c->cache_cap, (size_t)n + 2);
+    std::vector<double> todo;
+    for (uint32_t k = 0; k < n; ++k)
+        if (!c->cache.count(times[k]) && std::find(todo.begin(), todo.end(), times[k]) == todo.end())
+            todo.push_back(times[k]);
+    if (todo.empty()) return;
+    if (c->static_geom || todo.size() == 1) {
+        for (double t : todo) get_instant(c, t, s, ms_build);
+        return;
+    }
+    // Host builds on every host thread (each one instant at a time), then
+    // the uploads in order.
+    const auto t_start = std::chrono::steady_clock::now();
+    std::vector<std::shared_ptr<DevInstantBufs>> bis(todo.size());
+    for (auto &b : bis) b = std::make_shared<DevInstantBufs>();
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const size_t nt = std::min<size_t>(hw, todo.size());
+    std::atomic<size_t> next{0};
+    std::vector<std::string> errs(nt);
+    std::vector<int> codes(nt, 0);
+    std::vector<std::thread> th;
+    for (size_t w = 0; w < nt; ++w)
+        th.emplace_back([&, w] {
+            try {
+                for (size_t k; (k = next.fetch_add(1)) < todo.size();) build_host_instant(c, todo[k], bis[k]->host);
+            } catch (const Error &e) {
+                codes[w] = e.code;
+                errs[w] = e.msg;
+            } catch (const std::exception &e) {
+                codes[w] = EVRT_E_NOMEM;
+                errs[w] = e.what();
+            }
+        });
+    for (auto &t : th) t.join();
+    for (size_t w = 0; w < nt; ++w)
+        if (codes[w]) fail(codes[w], errs[w]);
+    for (size_t k = 0; k < todo.size(); ++k) {
+        upload_instant(c, *bis[k], s);
+        cache_insert(c, todo[k], bis[k]);
+    }
     if (ms_build)
         *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    return bi;
 }
 
 DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b, uint32_t lds_nodes)
@@ -663,11 +728,22 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
 {
     const auto wall0 = std::chrono::steady_clock::now();
     std::memset(&c->stats, 0, sizeof(c->stats));
+    const uint32_t nf = n_pairs + 1;
+    // Geometry that moves across the batch: every frame's own instant, and
+    // each round's items grouped by frame so that a piece holds one frame.
+    const bool moving = !instances_static(c->scene, times, nf);
+    std::vector<DevScene> frame_sc;
+    if (moving) {
+        get_instants(c, times, nf, s, &c->stats.ms_build);
+        for (uint32_t f = 0; f < nf; ++f) {
+            auto gf = get_instant(c, times[f], s, &c->stats.ms_build);
+            frame_sc.push_back(make_dev_scene(c, *gf, *gf, o.lds_nodes));
+        }
+    }
     auto g = get_instant(c, times[0], s, &c->stats.ms_build);
     const DevScene sc = make_dev_scene(c, *g, *g, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
     const uint32_t npx = sc.width * sc.height;
-    const uint32_t nf = n_pairs + 1;
     const uint32_t mb = o.minibatch;
     const uint64_t batch = o.ray_batch ? o.ray_batch : kDefaultRayBatch;
     FrameBuffers &fb = c->fb;
@@ -684,6 +760,12 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
     fb.b_act0.ensure(sizeof(uint32_t) * npp);
     fb.b_act1.ensure(sizeof(uint32_t) * npp);
     fb.b_pair_items.ensure(sizeof(uint2) * npp);
+    if (moving) {
+        fb.b_sorted.ensure(sizeof(uint32_t) * nfp);
+        fb.b_sort_tmp.ensure(batch_sort_temp_bytes((uint32_t)nfp));
+        fb.b_frame_start.ensure(sizeof(uint32_t) * nf);
+        c->h_frame_start.resize(nf);
+    }
     ensure_buffers(c, npx, 1, rp.n_slots);
     uint32_t *cnt = fb.cnt.as<uint32_t>();
     uint32_t *wf_n = fb.b_wf_n.as<uint32_t>();
@@ -702,6 +784,9 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
     uint32_t n_prev = 0;
     uint32_t n_next = fixed ? spp_max : spp_init;
     Outputs outs{out.polarity, out.n_paths, out.mean, out.var, out.t_last, out.mean_radiance, out.flags};
+    // First item of each frame (round 0 holds every item in frame order).
+    std::vector<uint32_t> fstart(nf + 1);
+    for (uint32_t f = 0; f <= nf; ++f) fstart[f] = f * npx;
     for (uint32_t r = 0;; ++r) {
         if (r > 0) {
             launch_batch_items(s, act_in, nA, npx, item_idx, items, cnt);
@@ -709,6 +794,19 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
                       "item count readback");
             hip_check(hipStreamSynchronize(s), "batch items");
             n_items = c->h_pinned[0];
+            if (moving) {
+                launch_batch_regroup(s, items, n_items, fb.b_sorted.as<uint32_t>(), fb.b_sort_tmp.ptr,
+                                     fb.b_sort_tmp.bytes, npx, item_idx, fb.b_frame_start.as<uint32_t>(), nf);
+                hip_check(hipGetLastError(), "item regroup");
+                hip_check(hipMemcpyAsync(c->h_frame_start.data(), fb.b_frame_start.ptr, sizeof(uint32_t) * nf,
+                                         hipMemcpyDeviceToHost, s),
+                          "frame start readback");
+                hip_check(hipStreamSynchronize(s), "item regroup");
+                // Frames without items start where the next frame does.
+                fstart[nf] = n_items;
+                for (uint32_t f = nf; f-- > 0;)
+                    fstart[f] = c->h_frame_start[f] == 0xffffffffu ? fstart[f + 1] : c->h_frame_start[f];
+            }
             launch_batch_pair_items(s, act_in, nA, npx, item_idx, pair_items);
         }
         Decide dc{};
@@ -739,29 +837,62 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
         // streams, as in the single-pair rounds.
         const uint64_t range = hi - n_prev;
         const uint64_t pbatch = c->s2 ? (batch + 1) / 2 : batch;
-        uint64_t it_block = std::max<uint64_t>(1, pbatch / range);
-        uint64_t bp_max = range;
-        if (it_block < 64 && it_block < n_items) {
-            it_block = n_items;
-            bp_max = std::max<uint64_t>(mb, pbatch / n_items / mb * mb);
+        // Item ranges traced with one geometry: all items, or each frame's.
+        struct Span {
+            uint32_t a_begin, a_end;
+            const DevScene *scene;
+        };
+        std::vector<Span> spans;
+        if (moving) {
+            for (uint32_t f = 0; f < nf; ++f)
+                if (fstart[f + 1] > fstart[f]) spans.push_back({fstart[f], fstart[f + 1], &frame_sc[f]});
+        } else {
+            spans.push_back({0u, n_items, &sc});
         }
-        it_block = std::min<uint64_t>(it_block, n_items);
-        bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / it_block / mb * mb);
-        if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many items for one piece");
-        const bool split = bp_max < range;
-        if (!split) it_block = balanced_block(c, n_items, it_block);
-        if (dc.n_checks > 1 && split) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
-        const uint64_t n_pieces = ((n_items + it_block - 1) / it_block) * ((range + bp_max - 1) / bp_max);
+        // Blocks of items with the whole sample range, or every item of the
+        // span over sub-ranges when the blocks would be too small (then the
+        // round has one checkpoint).
+        struct Cut {
+            uint64_t it_block, bp_max;
+            bool split;
+        };
+        auto cut = [&](uint32_t n) {
+            uint64_t it_block = std::max<uint64_t>(1, pbatch / range);
+            uint64_t bp_max = range;
+            if (it_block < 64 && it_block < n) {
+                it_block = n;
+                bp_max = std::max<uint64_t>(mb, pbatch / n / mb * mb);
+            }
+            it_block = std::min<uint64_t>(it_block, n);
+            bp_max = std::min<uint64_t>(bp_max, (uint64_t)(kMaxPathId - 1) / it_block / mb * mb);
+            if (bp_max == 0) fail(EVRT_E_UNSUPPORTED, "too many items for one piece");
+            const bool split = bp_max < range;
+            // Two lanes of one span get equal blocks; many frames' spans
+            // alternate between the lanes anyway.
+            if (!split && !moving) it_block = balanced_block(c, n, it_block);
+            if (dc.n_checks > 1 && split) fail(EVRT_E_UNSUPPORTED, "checkpoints over split samples");
+            return Cut{it_block, bp_max, split};
+        };
+        uint64_t n_pieces = 0;
+        bool any_split = false;
+        for (const Span &sp : spans) {
+            const Cut ct = cut(sp.a_end - sp.a_begin);
+            n_pieces += ((sp.a_end - sp.a_begin + ct.it_block - 1) / ct.it_block) * ((range + ct.bp_max - 1) / ct.bp_max);
+            any_split = any_split || ct.split;
+        }
         // Split sample ranges of one item must be accumulated in order: they
         // stay on one stream.
-        const bool two = c->s2 != nullptr && n_pieces > 1 && !split;
+        const bool two = c->s2 != nullptr && n_pieces > 1 && !any_split;
         if (two) {
             hip_check(hipEventRecord(c->ev_fork, s), "fork");
             hip_check(hipStreamWaitEvent(c->s2, c->ev_fork, 0), "fork wait");
         }
         uint32_t piece = 0;
-        for (uint32_t a0 = 0; a0 < n_items; a0 += (uint32_t)it_block) {
-            const uint32_t na = (uint32_t)std::min<uint64_t>(it_block, n_items - a0);
+        for (const Span &sp : spans) {
+          const Cut ct = cut(sp.a_end - sp.a_begin);
+          const uint64_t it_block = ct.it_block, bp_max = ct.bp_max;
+          for (uint32_t a0 = sp.a_begin; a0 < sp.a_end; a0 += (uint32_t)it_block) {
+            const uint32_t na = (uint32_t)std::min<uint64_t>(it_block, sp.a_end - a0);
             for (uint32_t s0 = n_prev; s0 < hi;) {
                 const uint32_t bp = (uint32_t)std::min<uint64_t>(bp_max, hi - s0);
                 Piece pc{};
@@ -783,10 +914,11 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
                 ++piece;
                 ensure_buffers(c, npx, pc.n_paths, rp.n_slots, ln);
                 pc.rad = fb.lane[ln].rad.as<float>();
-                trace_piece(c, pc, sc, rp, o, ps, prof, ln);
+                trace_piece(c, pc, *sp.scene, rp, o, ps, prof, ln);
                 launch_batch_accumulate(ps, pc, rp, dc, npx, a0, wf_n, wf_mean, wf_m2, wf_ysum, snap);
                 s0 += bp;
             }
+          }
         }
         if (two) {
             hip_check(hipEventRecord(c->ev_join, c->s2), "join");

@@ -408,6 +408,31 @@ def panning(sc: Scene, n_frames: int, deg_per_frame: float) -> Scene:
                                cam_t=ct, cam_elu=ce)
 
 
+def moving_panning(width: int = 32, height: int = 24, n_frames: int = 5, deg_per_frame: float = 2.0,
+                   step: float = 0.05) -> Scene:
+    """The tiny box with its cube moving by `step` in x per frame and the
+    camera turning by deg_per_frame per frame, both keyed at t = 0, 1, ...,
+    n_frames - 1 (geometry and camera change every frame)."""
+    import dataclasses
+    sc = tiny_box(width=width, height=height)
+    koff = sc.inst_key_off.astype(np.int64)
+    cube = len(sc.inst_mesh) - 1
+    key_t, key_x = [], []
+    for i in range(len(sc.inst_mesh)):
+        if i == cube:
+            c0 = sc.key_xform[koff[i]][:, 3].copy()
+            key_t += [0.0, float(n_frames - 1)]
+            key_x += [translation(c0), translation(c0 + [step * (n_frames - 1), 0, 0])]
+        else:
+            key_t.append(0.0)
+            key_x.append(sc.key_xform[koff[i]])
+    off = np.concatenate([[0], np.cumsum([2 if i == cube else 1 for i in range(len(sc.inst_mesh))])])
+    e = sc.cam_elu[0]
+    ct, ce = _pan_keys(e[0:3], e[3:6], e[6:9], n_frames, deg_per_frame)
+    return dataclasses.replace(sc, key_t=np.asarray(key_t, np.float64), key_xform=np.asarray(key_x, np.float64),
+                               inst_key_off=off.astype(np.uint32), cam_t=ct, cam_elu=ce)
+
+
 def batch_scene(seed: int = 0, width: int = 1280, height: int = 720, grid: int = 24, n_cubes: int = 20000,
                 subdiv: int = 3, n_frames: int = 65, deg_per_frame: float = 0.5) -> Scene:
     """Frame-batch workload (1280x720, 977,290 triangles): a 40 x 40 ground

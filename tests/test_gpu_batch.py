@@ -138,12 +138,49 @@ def test_single_frame_key_base_matches_oracle(rend):
     assert not np.array_equal(r["mean"], r0["mean"])
 
 
-def test_batch_rejects_moving_geometry_and_ref_full(rend):
+@pytest.mark.parametrize("variant", ["default", "small_pieces", "split_samples", "two_tailed", "fixed"])
+def test_moving_batch_equals_single_pairs(rend, variant):
+    """Geometry and camera both change every frame: each frame's items are
+    traced with its own instant, and every pair equals the single-pair
+    renderer with the batch's keys, bit for bit."""
     P = dict(scenes.TINY_PARAMS)
-    rend.set_scene(scenes.tiny_box(width=8, height=8))
-    with pytest.raises(ev.EvrtError) as e:
-        rend.render_event_batch([0.0, 1.0], P["C"], P["alpha"], 16, 16, 64, _opts(P))
-    assert e.value.code == ev.EVRT_E_UNSUPPORTED
+    kw = {}
+    if variant == "small_pieces":
+        kw = dict(ray_batch=1 << 14)
+    elif variant == "split_samples":
+        kw = dict(ray_batch=512)
+    elif variant == "two_tailed":
+        kw = dict(mode=ev.MODE_ADAPTIVE_2T)
+    elif variant == "fixed":
+        kw = dict(mode=ev.MODE_FIXED)
+    sc = scenes.moving_panning(32, 24, 5)
+    _say(f"moving batch variant {variant}")
+    b, pb, pp = _batch_vs_pairs(rend, sc, P, [0.0, 1.0, 2.0, 3.0, 4.0], **kw)
+    assert pb < pp
+    assert rend.frame_stats()["rounds"] >= 1
+
+
+def test_moving_batch_matches_oracle(rend):
+    P = dict(scenes.TINY_PARAMS)
+    sc = scenes.moving_panning(24, 20, 4)
+    rend.set_scene(sc)
+    times = [0.0, 1.0, 2.0, 3.0]
+    b = rend.render_event_batch(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], _opts(P))
+    for k in range(3):
+        with oracle.Frame(sc, times[k], times[k + 1]) as f:
+            r = f.render(oracle.make_params(**P, key_base=k))
+        ok = ~r["near_crit"]
+        _say(f"  pair {k}: {int((~ok).sum())} of {ok.size} pixels exempt")
+        assert (~ok).sum() <= 0.01 * ok.size
+        np.testing.assert_array_equal(b["polarity"][k].cpu().numpy()[ok], r["polarity"][ok])
+        np.testing.assert_array_equal(b["n_paths"][k].cpu().numpy()[ok], r["n_paths"][ok])
+        m = b["mean"][k].cpu().numpy()
+        assert (np.abs(m - r["mean"]) <= 1e-4 * np.maximum(1.0, np.abs(r["mean"]))).all()
+        assert (r["polarity"] != 0).any()
+
+
+def test_batch_rejects_ref_full_and_normality(rend):
+    P = dict(scenes.TINY_PARAMS)
     rend.set_scene(scenes.panning(scenes.tiny_box(width=8, height=8), 3, 1.0))
     with pytest.raises(ev.EvrtError) as e:
         rend.render_event_batch([0.0, 1.0, 2.0], P["C"], P["alpha"], 16, 16, 64,
