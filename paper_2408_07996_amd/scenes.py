@@ -433,6 +433,88 @@ def moving_panning(width: int = 32, height: int = 24, n_frames: int = 5, deg_per
                                inst_key_off=off.astype(np.uint32), cam_t=ct, cam_elu=ce)
 
 
+def tessellated_box(n: int = 3):
+    """Unit box [0, 1]^3 with every face cut into n x n quads (12 n^2
+    triangles), faces wound outward."""
+    verts, tris = [], []
+    u = np.linspace(0.0, 1.0, n + 1)
+    faces = [((0, 1, 2), 0.0, -1), ((0, 1, 2), 1.0, 1), ((1, 2, 0), 0.0, -1), ((1, 2, 0), 1.0, 1),
+             ((2, 0, 1), 0.0, -1), ((2, 0, 1), 1.0, 1)]
+    for (a, b, c), cval, sgn in faces:
+        base = len(verts)
+        for i in range(n + 1):
+            for j in range(n + 1):
+                p = [0.0, 0.0, 0.0]
+                p[a], p[b], p[c] = u[i], u[j], cval
+                verts.append(p)
+        for i in range(n):
+            for j in range(n):
+                v00 = base + i * (n + 1) + j
+                v10, v01, v11 = v00 + n + 1, v00 + 1, v00 + n + 2
+                for t in ((v00, v10, v11), (v00, v11, v01)):
+                    P = np.array([verts[k] for k in t])
+                    nrm = np.cross(P[1] - P[0], P[2] - P[0])
+                    want = np.zeros(3)
+                    want[c] = sgn
+                    tris.append(t if nrm @ want > 0 else (t[0], t[2], t[1]))
+    return np.asarray(verts, np.float32), np.asarray(tris, np.int64)
+
+
+def city(seed: int = 0, width: int = 1920, height: int = 1080, grid: int = 200, n_frames: int = 121,
+         n_moving: int = 50, n_lights: int = 16) -> Scene:
+    """Stress workload (about 4.3M triangles): a grid x grid city of boxes
+    (footprint 0.6, pitch 1.0, height U[0.3, 4.0]) whose faces are cut 3 x 3
+    (108 triangles a box), 16 box materials of albedo U[0.1, 0.9], a ground
+    plane, n_lights 2 x 2 area lights at y = 12 (Le = 25) facing down,
+    n_moving boxes that each move by U[-0.03, 0.03] in x and z per frame,
+    and a camera flying over the city (eye from (-20, 9, 40) toward
+    (-20, 9, 28), looking 20 units ahead and 8 down), keyed at t = 0, 1,
+    ..., n_frames - 1; 50 degrees."""
+    rng = np.random.default_rng(seed)
+    b = SceneBuilder()
+    ground_m = b.material(0.4)
+    gv, gt = oriented_quad([(-110, 0, -110), (110, 0, -110), (110, 0, 110), (-110, 0, 110)], (0, 1, 0))
+    b.static(b.mesh(gv, gt, ground_m))
+    bv, bt = tessellated_box(3)
+    box_meshes = [b.mesh(bv, bt, b.material(rng.uniform(0.1, 0.9))) for _ in range(16)]
+    off = (grid - 1) / 2.0
+    heights = rng.uniform(0.3, 4.0, size=(grid, grid))
+    mesh_pick = rng.integers(0, 16, size=(grid, grid))
+    moving = set(map(int, rng.choice(grid * grid, size=n_moving, replace=False)))
+    last = float(n_frames - 1)
+    for i in range(grid):
+        for j in range(grid):
+            x, z = i - off - 0.3, j - off - 0.3
+            m = compose(np.diag([0.6, heights[i, j], 0.6]), (x, 0.0, z))
+            if i * grid + j in moving:
+                v = rng.uniform(-0.03, 0.03, size=2)
+                m1 = m.copy()
+                m1[0, 3] += v[0] * last
+                m1[2, 3] += v[1] * last
+                b.instance(box_meshes[mesh_pick[i, j]], [0.0, last], [m, m1])
+            else:
+                b.instance(box_meshes[mesh_pick[i, j]], [0.0], [m])
+    lm = b.material(0.0, 25.0)
+    for k in range(n_lights):
+        lx, lz = rng.uniform(-60, 60, size=2)
+        lv, lt = oriented_quad([(lx - 1, 12.0, lz - 1), (lx + 1, 12.0, lz - 1), (lx + 1, 12.0, lz + 1),
+                                (lx - 1, 12.0, lz + 1)], (0, -1, 0))
+        b.static(b.mesh(lv, lt, lm))
+    kt = np.arange(n_frames, dtype=np.float64)
+    keys = []
+    for k in range(n_frames):
+        ez = 40.0 - 12.0 * k / max(1, n_frames - 1)
+        keys.append([-20.0, 9.0, ez, -20.0, 1.0, ez - 20.0, 0.0, 1.0, 0.0])
+    b.set_camera(width, height, 50.0, kt, keys)
+    return b.build()
+
+
+# Stress workload: 120 pairs of the city, depth 12, schedule 64/64/4096,
+# C = 0.2, alpha = 0.001.
+CITY_PARAMS = dict(seed=0, max_depth=12, rr_start_depth=2, minibatch=4, log_eps=1e-4, nee=1, jitter=1,
+                   spp_init=64, spp_batch=64, spp_max=4096, C=0.2, alpha=0.001)
+
+
 def batch_scene(seed: int = 0, width: int = 1280, height: int = 720, grid: int = 24, n_cubes: int = 20000,
                 subdiv: int = 3, n_frames: int = 65, deg_per_frame: float = 0.5) -> Scene:
     """Frame-batch workload (1280x720, 977,290 triangles): a 40 x 40 ground

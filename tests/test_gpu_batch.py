@@ -122,6 +122,37 @@ def test_batch_workload_subset_matches_oracle(rend):
         assert (np.abs(tg[fin] - tr[fin]) <= 1e-4 * np.maximum(1.0, np.abs(tr[fin]))).all()
 
 
+@pytest.mark.slow
+def test_city_batch_subset_matches_oracle(rend):
+    """The stress workload at full size (1920x1080, 4.32M triangles, 16
+    area lights, 50 moving boxes, moving camera, depth 12, 64/64/4096,
+    alpha = 0.001): a batch of two pairs (three frames, each with its own
+    geometry) against the oracle on every 96th pixel in x and y."""
+    P = dict(scenes.CITY_PARAMS)
+    sc = scenes.city(n_frames=3)
+    rend.set_scene(sc)
+    times = [0.0, 1.0, 2.0]
+    _say("city batch: 2 pairs at 1920x1080")
+    b = rend.render_event_batch(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], _opts(P))
+    st = rend.frame_stats()
+    _say(f"  gpu rounds {st['rounds']} build {st['ms_build']:.0f} ms wall {st['ms_wall']:.0f} ms")
+    px = scenes.subset_every(sc.width, sc.height, 96)
+    for k in range(2):
+        with oracle.Frame(sc, times[k], times[k + 1]) as f:
+            r = f.render(oracle.make_params(**P, key_base=k), px)
+        g = {key: b[key][k].cpu().numpy()[px] for key in KEYS}
+        ok = ~r["near_crit"]
+        _say(f"  pair {k}: {int((~ok).sum())} of {ok.size} exempt, {int((r['polarity'] != 0).sum())} events, "
+             f"{r['n_paths'].mean():.0f} paths per pixel")
+        assert (~ok).sum() <= 0.01 * ok.size
+        np.testing.assert_array_equal(g["polarity"][ok], r["polarity"][ok])
+        np.testing.assert_array_equal(g["n_paths"][ok], r["n_paths"][ok])
+        same = g["n_paths"] == r["n_paths"]
+        for key in ("mean", "var", "mean_radiance"):
+            err = np.abs(g[key][same] - r[key][same]) / np.maximum(1.0, np.abs(r[key][same]))
+            assert err.max(initial=0.0) <= 1e-4, key
+
+
 def test_single_frame_key_base_matches_oracle(rend):
     P = dict(scenes.TINY_PARAMS)
     sc = scenes.tiny_box(width=24, height=20)
