@@ -224,7 +224,7 @@ struct TRay {
     float okx, oky, okz;    // origin permuted into the watertight frame
     float Sx, Sy, Sz;       // shear constants
     uint32_t kperm;         // kx | ky << 2 | kz << 4
-    uint32_t onx, ony, onz; // byte offsets of the near-plane rows of a 4-wide node
+    uint32_t onx, ony, onz; // byte offsets of the near planes of a 4-wide node
 };
 
 __device__ __forceinline__ float safe_dir(float d)
@@ -245,11 +245,18 @@ __device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx
     r.nox = -(ox * r.ix);
     r.noy = -(oy * r.iy);
     r.noz = -(oz * r.iz);
-    // Near planes: lo rows for a positive direction component, hi rows for
-    // a negative one; the far row of an axis is the other row of its pair.
+    // Near planes: lo planes for a positive direction component, hi planes
+    // for a negative one; the far planes of an axis are the other half of
+    // its pair.
+#if EVRT_HALF_NODES
+    r.onx = r.ix < 0.0f ? 24u : 16u;
+    r.ony = r.iy < 0.0f ? 40u : 32u;
+    r.onz = r.iz < 0.0f ? 56u : 48u;
+#else
     r.onx = r.ix < 0.0f ? 16u : 0u;
     r.ony = r.iy < 0.0f ? 48u : 32u;
     r.onz = r.iz < 0.0f ? 80u : 64u;
+#endif
     const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
     int kz = 0;
     float m = ax;
@@ -326,6 +333,52 @@ __device__ __forceinline__ void box4(const TRay &r, float4 nx, float4 fx, float4
     EVRT_SLOT(w, 3)
 #undef EVRT_SLOT
 }
+
+#if EVRT_HALF_NODES
+__device__ __forceinline__ float half_lo(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+__device__ __forceinline__ float half_hi(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+// The same slab test on FP16 planes stored as offsets from the node origin
+// o: with B = o * inv - origin * inv (one fused product per axis), a plane
+// o + h enters as fma(h, inv, B), the FP16-to-FP32 conversion folded into
+// a mixed-precision FMA.  near/far hold the four children's planes of one
+// axis (child 2j in the low half of word j).  The second rounding (of B)
+// is far inside the host's box padding; the offsets are rounded outward.
+__device__ __forceinline__ void box4h(const TRay &r, float4 org, uint2 nx, uint2 fx, uint2 ny, uint2 fy,
+                                      uint2 nz, uint2 fz, float tmin, float tfar, uint32_t (&k)[4])
+{
+    const float bx = __builtin_fmaf(org.x, r.ix, r.nox);
+    const float by = __builtin_fmaf(org.y, r.iy, r.noy);
+    const float bz = __builtin_fmaf(org.z, r.iz, r.noz);
+#define EVRT_SLOT(w, H, j)                                                                           \
+    {                                                                                                \
+        const float tn = fmaxf(fmaxf(fmaxf(__builtin_fmaf(H(nx.w), r.ix, bx), __builtin_fmaf(H(ny.w), r.iy, by)), \
+                                     __builtin_fmaf(H(nz.w), r.iz, bz)), tmin);                      \
+        const float tf = fminf(fminf(fminf(__builtin_fmaf(H(fx.w), r.ix, bx), __builtin_fmaf(H(fy.w), r.iy, by)), \
+                                     __builtin_fmaf(H(fz.w), r.iz, bz)), tfar);                      \
+        k[j] = slot_key(tn, tf, j);                                                                  \
+    }
+    EVRT_SLOT(x, half_lo, 0)
+    EVRT_SLOT(x, half_hi, 1)
+    EVRT_SLOT(y, half_lo, 2)
+    EVRT_SLOT(y, half_hi, 3)
+#undef EVRT_SLOT
+}
+
+// Near and far words of one axis from its whole plane row [lo01 lo23 hi01
+// hi23]; `neg` selects the hi planes as near ones.
+__device__ __forceinline__ void split_row(uint4 row, bool neg, uint2 &n, uint2 &f)
+{
+    n = neg ? make_uint2(row.z, row.w) : make_uint2(row.x, row.y);
+    f = neg ? make_uint2(row.x, row.y) : make_uint2(row.z, row.w);
+}
+#endif
 
 // Traversal block shape: kTB threads, a top treelet of kLdsNodes nodes per
 // instant staged in LDS, and a per-lane stack whose first kStackLds entries
@@ -420,20 +473,13 @@ __device__ __forceinline__ void stack_push(int &sp, int32_t v, lds_u32 *lds_stac
     ++sp;
 }
 
-// Ordered descent through one 4-wide node given its near/far plane rows and
-// child references: go to the nearest hit child and push the other hit
+// Ordered descent through one 4-wide node given its children's sort keys
+// and references: go to the nearest hit child and push the other hit
 // children farthest first, or pop when none is hit.  Returns false when the
 // stack is empty (traversal complete).
-__device__ __forceinline__ bool visit_node(Trav &T, float4 nx, float4 fx, float4 ny, float4 fy, float4 nz,
-                                           float4 fz, float4 refs, lds_u32 *lds_stack, int32_t *spill)
+__device__ __forceinline__ bool visit_node(Trav &T, uint32_t (&k)[4], float4 refs, lds_u32 *lds_stack,
+                                           int32_t *spill)
 {
-    uint32_t k[4];
-    // An empty statement that takes the reference row as an input: the row
-    // is then loaded with the plane rows instead of being sunk into the hit
-    // branch, which would add a dependent memory round trip to most visits
-    // (134.6 vs 137.0 ms per sensor frame).
-    asm volatile("" ::"v"(refs.x), "v"(refs.y), "v"(refs.z), "v"(refs.w));
-    box4(T.r, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
     int32_t c[4] = {__float_as_int(refs.x), __float_as_int(refs.y), __float_as_int(refs.z), __float_as_int(refs.w)};
     // Sorting network on (key, reference) pairs; misses sort last.
 #define EVRT_CSWAP(a, b)                                   \
@@ -486,6 +532,67 @@ __device__ __forceinline__ float4 row_at(const float4 *base, uint32_t off)
     return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
+// An empty statement that takes the reference row as an input: the row is
+// then loaded with the plane rows instead of being sunk into the hit branch,
+// which would add a dependent memory round trip to most visits (134.6 vs
+// 137.0 ms per sensor frame).
+__device__ __forceinline__ void keep_loaded(float4 refs)
+{
+    asm volatile("" ::"v"(refs.x), "v"(refs.y), "v"(refs.z), "v"(refs.w));
+}
+
+// Sort keys and child references of the 4-wide node at byte offset b of
+// the global node array.
+__device__ __forceinline__ float4 node_keys(const Trav &T, const float4 *nodes, uint32_t b, uint32_t (&k)[4])
+{
+#if EVRT_HALF_NODES
+    const float4 org = row_at(nodes, b);
+    const float4 refs = row_at(nodes, b + 64u);
+    keep_loaded(refs);
+#if EVRT_HALF_ROWS
+    uint2 nx, fx, ny, fy, nz, fz;
+    split_row(__builtin_bit_cast(uint4, row_at(nodes, b + 16u)), T.r.onx & 8u, nx, fx);
+    split_row(__builtin_bit_cast(uint4, row_at(nodes, b + 32u)), T.r.ony & 8u, ny, fy);
+    split_row(__builtin_bit_cast(uint4, row_at(nodes, b + 48u)), T.r.onz & 8u, nz, fz);
+#else
+    const char *c = reinterpret_cast<const char *>(nodes) + b;
+    const uint2 nx = *reinterpret_cast<const uint2 *>(c + T.r.onx), fx = *reinterpret_cast<const uint2 *>(c + (T.r.onx ^ 8u));
+    const uint2 ny = *reinterpret_cast<const uint2 *>(c + T.r.ony), fy = *reinterpret_cast<const uint2 *>(c + (T.r.ony ^ 8u));
+    const uint2 nz = *reinterpret_cast<const uint2 *>(c + T.r.onz), fz = *reinterpret_cast<const uint2 *>(c + (T.r.onz ^ 8u));
+#endif
+    box4h(T.r, org, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
+#else
+    const float4 refs = row_at(nodes, b + 96u);
+    keep_loaded(refs);
+    box4(T.r, row_at(nodes, b + T.r.onx), row_at(nodes, b + (T.r.onx ^ 16u)), row_at(nodes, b + T.r.ony),
+         row_at(nodes, b + (T.r.ony ^ 16u)), row_at(nodes, b + T.r.onz), row_at(nodes, b + (T.r.onz ^ 16u)), T.tmin,
+         T.tfar, k);
+#endif
+    return refs;
+}
+
+// The same for a node of the LDS treelet starting at p.
+__device__ __forceinline__ float4 node_keys_lds(const Trav &T, const lds_f32 *p, uint32_t (&k)[4])
+{
+#if EVRT_HALF_NODES
+    const float4 org = lds_load4(p);
+    const float4 refs = lds_load4(p + 16);
+    keep_loaded(refs);
+    const lds_u32 *q = reinterpret_cast<const lds_u32 *>(p);
+    const uint2 nx = make_uint2(q[T.r.onx / 4], q[T.r.onx / 4 + 1]), fx = make_uint2(q[(T.r.onx ^ 8u) / 4], q[(T.r.onx ^ 8u) / 4 + 1]);
+    const uint2 ny = make_uint2(q[T.r.ony / 4], q[T.r.ony / 4 + 1]), fy = make_uint2(q[(T.r.ony ^ 8u) / 4], q[(T.r.ony ^ 8u) / 4 + 1]);
+    const uint2 nz = make_uint2(q[T.r.onz / 4], q[T.r.onz / 4 + 1]), fz = make_uint2(q[(T.r.onz ^ 8u) / 4], q[(T.r.onz ^ 8u) / 4 + 1]);
+    box4h(T.r, org, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
+#else
+    const float4 refs = lds_load4(p + 24);
+    keep_loaded(refs);
+    box4(T.r, lds_load4(p + T.r.onx / 4), lds_load4(p + (T.r.onx ^ 16u) / 4), lds_load4(p + T.r.ony / 4),
+         lds_load4(p + (T.r.ony ^ 16u) / 4), lds_load4(p + T.r.onz / 4), lds_load4(p + (T.r.onz ^ 16u) / 4), T.tmin,
+         T.tfar, k);
+#endif
+    return refs;
+}
+
 // Tests the triangles of leaf `ref`: closest-hit keeps the lexicographic
 // minimum (t, primitive) in T.tfar / T.best_p; ANY returns true at the
 // first accepted hit.
@@ -534,20 +641,18 @@ __device__ __forceinline__ bool traverse_step(Trav &T, const Geo &g, lds_u32 *ld
         while (live && T.ref >= 0 && (uint32_t)T.ref < n_lds) {
             const lds_f32 *p = g.lds + 32 * T.ref;
             if (COUNT) ++visits;
-            live = visit_node(T, lds_load4(p + T.r.onx / 4), lds_load4(p + (T.r.onx ^ 16u) / 4),
-                              lds_load4(p + T.r.ony / 4), lds_load4(p + (T.r.ony ^ 16u) / 4),
-                              lds_load4(p + T.r.onz / 4), lds_load4(p + (T.r.onz ^ 16u) / 4), lds_load4(p + 24),
-                              lds_stack, spill);
+            uint32_t k[4];
+            const float4 refs = node_keys_lds(T, p, k);
+            live = visit_node(T, k, refs, lds_stack, spill);
         }
     }
     while (live && T.ref >= 0 && (!LDS || (uint32_t)T.ref >= n_lds)) {
         // 32-bit byte offsets: the host keeps node arrays below 4 GiB.
         const uint32_t b = (uint32_t)T.ref << 7;
         if (COUNT) ++visits;
-        live = visit_node(T, row_at(g.nodes, b + T.r.onx), row_at(g.nodes, b + (T.r.onx ^ 16u)),
-                          row_at(g.nodes, b + T.r.ony), row_at(g.nodes, b + (T.r.ony ^ 16u)),
-                          row_at(g.nodes, b + T.r.onz), row_at(g.nodes, b + (T.r.onz ^ 16u)), row_at(g.nodes, b + 96u),
-                          lds_stack, spill);
+        uint32_t k[4];
+        const float4 refs = node_keys(T, g.nodes, b, k);
+        live = visit_node(T, k, refs, lds_stack, spill);
     }
     if (!live) return false;
     // A pop in the global loop can return a treelet node: not a leaf yet.
@@ -600,11 +705,9 @@ __device__ __forceinline__ bool traverse_step_spec(Trav &T, const Geo &g, lds_u3
         if (node) {
             const uint32_t b = (uint32_t)T.ref << 7;
             if (COUNT) ++visits;
-            if (!visit_node(T, row_at(g.nodes, b + T.r.onx), row_at(g.nodes, b + (T.r.onx ^ 16u)),
-                            row_at(g.nodes, b + T.r.ony), row_at(g.nodes, b + (T.r.ony ^ 16u)),
-                            row_at(g.nodes, b + T.r.onz), row_at(g.nodes, b + (T.r.onz ^ 16u)),
-                            row_at(g.nodes, b + 96u), lds_stack, spill))
-                T.ref = kEmptyRef;
+            uint32_t k[4];
+            const float4 refs = node_keys(T, g.nodes, b, k);
+            if (!visit_node(T, k, refs, lds_stack, spill)) T.ref = kEmptyRef;
         }
     }
     // Lanes leave the compiled loop at different iterations; taking `leaf`

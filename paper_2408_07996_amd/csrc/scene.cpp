@@ -176,6 +176,43 @@ float bvh_padding(const SceneDesc &sd, const HostInstant &a, const HostInstant &
 }
 
 // ---------------------------------------------------------------------------
+// FP16 plane offsets.  Offsets from a node's origin are >= 0; they are
+// rounded outward to normal IEEE binary16 values or zero (no subnormals, so
+// the result does not depend on the device's FP16 denormal mode):
+// half_up(x) is the smallest such value >= x, half_down(x) the largest <= x.
+
+static uint16_t half_bits(double v)
+{
+    // v is zero or a normal binary16 value.
+    if (v == 0.0) return 0;
+    int e = 0;
+    const double f = std::frexp(v, &e);  // v = f 2^e, f in [0.5, 1)
+    const uint32_t mant = (uint32_t)std::lround((2.0 * f - 1.0) * 1024.0);
+    return (uint16_t)((uint32_t)(e - 1 + 15) << 10 | mant);
+}
+
+static uint16_t half_directed(double x, bool up)
+{
+    if (!(x >= 0.0)) fail(EVRT_E_INVALID, "negative or non-finite FP16 plane offset");
+    if (x < 0x1p-14) return up && x > 0.0 ? half_bits(0x1p-14) : 0;
+    int e = 0;
+    std::frexp(x, &e);
+    const double q = std::ldexp(1.0, e - 11);  // spacing of halves in [2^(e-1), 2^e)
+    const double v = (up ? std::ceil(x / q) : std::floor(x / q)) * q;
+    if (v > 65504.0) fail(EVRT_E_UNSUPPORTED, "node extent above 65504 units, the FP16 plane range");
+    return half_bits(v);
+}
+
+static double half_value(uint16_t b)
+{
+    const uint32_t E = (b >> 10) & 0x1fu, mant = b & 0x3ffu;
+    const double sign = (b & 0x8000u) ? -1.0 : 1.0;
+    if (E == 0x1f) return mant ? NAN : sign * INFINITY;
+    if (E == 0) return sign * std::ldexp((double)mant, -24);
+    return sign * std::ldexp(1.0 + (double)mant / 1024.0, (int)E - 15);
+}
+
+// ---------------------------------------------------------------------------
 // Binned SAH binary BVH, collapsed into a 4-wide BVH.
 
 namespace {
@@ -467,11 +504,44 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
             }
         }
         float4 *o = &h.nodes[8 * i];
+#if EVRT_HALF_NODES
+        // Row 0: the node's origin (lowest child plane per axis); rows 1-3:
+        // per axis the four children's lower planes then their upper planes,
+        // FP16 offsets from the origin rounded outward (even child in the
+        // low half); row 4: references.
+        float org[3];
+        for (int c = 0; c < 3; ++c) {
+            org[c] = INFINITY;
+            for (int j = 0; j < k; ++j) org[c] = std::min(org[c], lo[c][j]);
+        }
+        o[0] = make_float4(org[0], org[1], org[2], 0.0f);
+        for (int c = 0; c < 3; ++c) {
+            uint32_t w[4];
+            for (int jj = 0; jj < 2; ++jj) {
+                uint16_t lq[2], hq[2];
+                for (int b = 0; b < 2; ++b) {
+                    const int j = 2 * jj + b;
+                    if (j < k) {
+                        lq[b] = half_directed((double)lo[c][j] - (double)org[c], false);
+                        hq[b] = half_directed((double)hi[c][j] - (double)org[c], true);
+                    } else {
+                        lq[b] = kHalfPosInf;
+                        hq[b] = kHalfNegInf;
+                    }
+                }
+                w[jj] = (uint32_t)lq[0] | ((uint32_t)lq[1] << 16);
+                w[2 + jj] = (uint32_t)hq[0] | ((uint32_t)hq[1] << 16);
+            }
+            o[1 + c] = make_float4(u2f(w[0]), u2f(w[1]), u2f(w[2]), u2f(w[3]));
+        }
+        o[4] = make_float4(u2f(ref[0]), u2f(ref[1]), u2f(ref[2]), u2f(ref[3]));
+#else
         for (int c = 0; c < 3; ++c) {
             o[2 * c] = make_float4(lo[c][0], lo[c][1], lo[c][2], lo[c][3]);
             o[2 * c + 1] = make_float4(hi[c][0], hi[c][1], hi[c][2], hi[c][3]);
         }
         o[6] = make_float4(u2f(ref[0]), u2f(ref[1]), u2f(ref[2]), u2f(ref[3]));
+#endif
     }
     h.root = 0;
     h.depth = depth;
@@ -523,9 +593,33 @@ std::string check_bvh(const HostInstant &h, float pad)
         const uint32_t depth = it.depth + 1;
         max_depth = std::max(max_depth, depth);
         const float4 *n = &h.nodes[8 * (size_t)it.ref];
+#if EVRT_HALF_NODES
+        // Decode: plane = origin + FP16 offset, exactly in FP64.
+        float lo_buf[3][4], hi_buf[3][4];
+        const float org[3] = {n[0].x, n[0].y, n[0].z};
+        for (int c = 0; c < 3; ++c) {
+            const float *row = &n[1 + c].x;
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t wl = f2u(row[j >> 1]), wh = f2u(row[2 + (j >> 1)]);
+                const uint16_t bl = (uint16_t)((j & 1) ? wl >> 16 : wl & 0xffffu);
+                const uint16_t bh = (uint16_t)((j & 1) ? wh >> 16 : wh & 0xffffu);
+                // Decoded planes enclose the exact boxes; the FP32 rounding
+                // here only tightens the check (down for lo, up for hi).
+                const double dl = (double)org[c] + half_value(bl), dh = (double)org[c] + half_value(bh);
+                lo_buf[c][j] = bl == kHalfPosInf ? INFINITY : (float)dl;
+                hi_buf[c][j] = bh == kHalfNegInf ? -INFINITY : (float)dh;
+                if (bl != kHalfPosInf && (double)lo_buf[c][j] < dl) lo_buf[c][j] = std::nextafter(lo_buf[c][j], INFINITY);
+                if (bh != kHalfNegInf && (double)hi_buf[c][j] > dh) hi_buf[c][j] = std::nextafter(hi_buf[c][j], -INFINITY);
+            }
+        }
+        const float *lo[3] = {lo_buf[0], lo_buf[1], lo_buf[2]};
+        const float *hi[3] = {hi_buf[0], hi_buf[1], hi_buf[2]};
+        const float *rf = &n[4].x;
+#else
         const float *lo[3] = {&n[0].x, &n[2].x, &n[4].x};
         const float *hi[3] = {&n[1].x, &n[3].x, &n[5].x};
         const float *rf = &n[6].x;
+#endif
         int used = 0;
         for (int j = 0; j < 4; ++j) {
             const bool empty = lo[0][j] == INFINITY;
@@ -545,7 +639,12 @@ std::string check_bvh(const HostInstant &h, float pad)
             st.push_back(ci);
         }
         if (used < 2) return "inner node with fewer than two children";
+#if EVRT_HALF_NODES
+        for (int rr = 5; rr < 8; ++rr)
+            if (n[rr].x != 0.0f || n[rr].y != 0.0f || n[rr].z != 0.0f || n[rr].w != 0.0f) return "padding row not zero";
+#else
         if (n[7].x != 0.0f || n[7].y != 0.0f || n[7].z != 0.0f || n[7].w != 0.0f) return "padding row not zero";
+#endif
     }
     for (uint32_t p = 0; p < nt; ++p)
         if (seen[p] != 1) return "primitive missing or duplicated";
