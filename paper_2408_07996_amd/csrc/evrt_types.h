@@ -15,11 +15,7 @@ constexpr float kShadowScale = 0.9999f;  // shadow segment ends short of the lig
 #ifndef EVRT_HALF_NODES
 #define EVRT_HALF_NODES 1
 #endif
-// FP16 nodes: load each axis's whole plane row and select near/far in
-// registers (1), or load the near and far halves at per-ray offsets (0).
-#ifndef EVRT_HALF_ROWS
-#define EVRT_HALF_ROWS 1
-#endif
+
 constexpr uint16_t kHalfPosInf = 0x7c00u, kHalfNegInf = 0xfc00u;
 constexpr float kInvPi = 0.318309886183790671538f;
 constexpr double kTwoPi = 6.283185307179586476925;

@@ -249,9 +249,9 @@ __device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx
     // for a negative one; the far planes of an axis are the other half of
     // its pair.
 #if EVRT_HALF_NODES
-    r.onx = r.ix < 0.0f ? 24u : 16u;
-    r.ony = r.iy < 0.0f ? 40u : 32u;
-    r.onz = r.iz < 0.0f ? 56u : 48u;
+    r.onx = r.ix < 0.0f ? 40u : 32u;
+    r.ony = r.iy < 0.0f ? 64u : 56u;
+    r.onz = r.iz < 0.0f ? 88u : 80u;
 #else
     r.onx = r.ix < 0.0f ? 16u : 0u;
     r.ony = r.iy < 0.0f ? 48u : 32u;
@@ -371,13 +371,6 @@ __device__ __forceinline__ void box4h(const TRay &r, float4 org, uint2 nx, uint2
 #undef EVRT_SLOT
 }
 
-// Near and far words of one axis from its whole plane row [lo01 lo23 hi01
-// hi23]; `neg` selects the hi planes as near ones.
-__device__ __forceinline__ void split_row(uint4 row, bool neg, uint2 &n, uint2 &f)
-{
-    n = neg ? make_uint2(row.z, row.w) : make_uint2(row.x, row.y);
-    f = neg ? make_uint2(row.x, row.y) : make_uint2(row.z, row.w);
-}
 #endif
 
 // Traversal block shape: kTB threads, a top treelet of kLdsNodes nodes per
@@ -532,6 +525,14 @@ __device__ __forceinline__ float4 row_at(const float4 *base, uint32_t off)
     return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
+// Four words at a 32-bit byte offset that is a multiple of 8 (global
+// vector loads need only 4-byte alignment).
+typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ u32x4a words_at(const float4 *base, uint32_t off)
+{
+    return *reinterpret_cast<const u32x4a *>(reinterpret_cast<const char *>(base) + off);
+}
+
 // An empty statement that takes the reference row as an input: the row is
 // then loaded with the plane rows instead of being sunk into the hit branch,
 // which would add a dependent memory round trip to most visits (134.6 vs
@@ -546,27 +547,27 @@ __device__ __forceinline__ void keep_loaded(float4 refs)
 __device__ __forceinline__ float4 node_keys(const Trav &T, const float4 *nodes, uint32_t b, uint32_t (&k)[4])
 {
 #if EVRT_HALF_NODES
+    // An axis's planes are stored as [lo01 lo23 hi01 hi23 lo01 lo23]; one
+    // 16 B load at the ray's offset returns its near words then its far
+    // words.  All five loads are issued before the statement that pins the
+    // reference row, which would otherwise order the plane loads after it.
     const float4 org = row_at(nodes, b);
-    const float4 refs = row_at(nodes, b + 64u);
+    const u32x4a rx = words_at(nodes, b + T.r.onx);
+    const u32x4a ry = words_at(nodes, b + T.r.ony);
+    const u32x4a rz = words_at(nodes, b + T.r.onz);
+    const float4 refs = row_at(nodes, b + 16u);
     keep_loaded(refs);
-#if EVRT_HALF_ROWS
-    uint2 nx, fx, ny, fy, nz, fz;
-    split_row(__builtin_bit_cast(uint4, row_at(nodes, b + 16u)), T.r.onx & 8u, nx, fx);
-    split_row(__builtin_bit_cast(uint4, row_at(nodes, b + 32u)), T.r.ony & 8u, ny, fy);
-    split_row(__builtin_bit_cast(uint4, row_at(nodes, b + 48u)), T.r.onz & 8u, nz, fz);
-#else
-    const char *c = reinterpret_cast<const char *>(nodes) + b;
-    const uint2 nx = *reinterpret_cast<const uint2 *>(c + T.r.onx), fx = *reinterpret_cast<const uint2 *>(c + (T.r.onx ^ 8u));
-    const uint2 ny = *reinterpret_cast<const uint2 *>(c + T.r.ony), fy = *reinterpret_cast<const uint2 *>(c + (T.r.ony ^ 8u));
-    const uint2 nz = *reinterpret_cast<const uint2 *>(c + T.r.onz), fz = *reinterpret_cast<const uint2 *>(c + (T.r.onz ^ 8u));
-#endif
+    const uint2 nx = make_uint2(rx.x, rx.y), fx = make_uint2(rx.z, rx.w);
+    const uint2 ny = make_uint2(ry.x, ry.y), fy = make_uint2(ry.z, ry.w);
+    const uint2 nz = make_uint2(rz.x, rz.y), fz = make_uint2(rz.z, rz.w);
     box4h(T.r, org, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
 #else
+    const float4 nx = row_at(nodes, b + T.r.onx), fx = row_at(nodes, b + (T.r.onx ^ 16u));
+    const float4 ny = row_at(nodes, b + T.r.ony), fy = row_at(nodes, b + (T.r.ony ^ 16u));
+    const float4 nz = row_at(nodes, b + T.r.onz), fz = row_at(nodes, b + (T.r.onz ^ 16u));
     const float4 refs = row_at(nodes, b + 96u);
     keep_loaded(refs);
-    box4(T.r, row_at(nodes, b + T.r.onx), row_at(nodes, b + (T.r.onx ^ 16u)), row_at(nodes, b + T.r.ony),
-         row_at(nodes, b + (T.r.ony ^ 16u)), row_at(nodes, b + T.r.onz), row_at(nodes, b + (T.r.onz ^ 16u)), T.tmin,
-         T.tfar, k);
+    box4(T.r, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
 #endif
     return refs;
 }
@@ -576,19 +577,21 @@ __device__ __forceinline__ float4 node_keys_lds(const Trav &T, const lds_f32 *p,
 {
 #if EVRT_HALF_NODES
     const float4 org = lds_load4(p);
-    const float4 refs = lds_load4(p + 16);
-    keep_loaded(refs);
     const lds_u32 *q = reinterpret_cast<const lds_u32 *>(p);
-    const uint2 nx = make_uint2(q[T.r.onx / 4], q[T.r.onx / 4 + 1]), fx = make_uint2(q[(T.r.onx ^ 8u) / 4], q[(T.r.onx ^ 8u) / 4 + 1]);
-    const uint2 ny = make_uint2(q[T.r.ony / 4], q[T.r.ony / 4 + 1]), fy = make_uint2(q[(T.r.ony ^ 8u) / 4], q[(T.r.ony ^ 8u) / 4 + 1]);
-    const uint2 nz = make_uint2(q[T.r.onz / 4], q[T.r.onz / 4 + 1]), fz = make_uint2(q[(T.r.onz ^ 8u) / 4], q[(T.r.onz ^ 8u) / 4 + 1]);
+    const uint32_t ox = T.r.onx / 4, oy = T.r.ony / 4, oz = T.r.onz / 4;
+    const uint2 nx = make_uint2(q[ox], q[ox + 1]), fx = make_uint2(q[ox + 2], q[ox + 3]);
+    const uint2 ny = make_uint2(q[oy], q[oy + 1]), fy = make_uint2(q[oy + 2], q[oy + 3]);
+    const uint2 nz = make_uint2(q[oz], q[oz + 1]), fz = make_uint2(q[oz + 2], q[oz + 3]);
+    const float4 refs = lds_load4(p + 4);
+    keep_loaded(refs);
     box4h(T.r, org, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
 #else
+    const float4 nx = lds_load4(p + T.r.onx / 4), fx = lds_load4(p + (T.r.onx ^ 16u) / 4);
+    const float4 ny = lds_load4(p + T.r.ony / 4), fy = lds_load4(p + (T.r.ony ^ 16u) / 4);
+    const float4 nz = lds_load4(p + T.r.onz / 4), fz = lds_load4(p + (T.r.onz ^ 16u) / 4);
     const float4 refs = lds_load4(p + 24);
     keep_loaded(refs);
-    box4(T.r, lds_load4(p + T.r.onx / 4), lds_load4(p + (T.r.onx ^ 16u) / 4), lds_load4(p + T.r.ony / 4),
-         lds_load4(p + (T.r.ony ^ 16u) / 4), lds_load4(p + T.r.onz / 4), lds_load4(p + (T.r.onz ^ 16u) / 4), T.tmin,
-         T.tfar, k);
+    box4(T.r, nx, fx, ny, fy, nz, fz, T.tmin, T.tfar, k);
 #endif
     return refs;
 }
@@ -2234,7 +2237,7 @@ void launch_batch_pair_items(hipStream_t s, const uint32_t *act, uint32_t nA, ui
 size_t batch_sort_temp_bytes(uint32_t n_items)
 {
     size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr, n_items, 0, 32);
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr, n_items, 0, 32);
     return bytes;
 }
 

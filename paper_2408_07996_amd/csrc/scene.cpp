@@ -505,16 +505,21 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
         }
         float4 *o = &h.nodes[8 * i];
 #if EVRT_HALF_NODES
-        // Row 0: the node's origin (lowest child plane per axis); rows 1-3:
-        // per axis the four children's lower planes then their upper planes,
-        // FP16 offsets from the origin rounded outward (even child in the
-        // low half); row 4: references.
+        // Row 0: the node's origin (lowest child plane per axis); row 1:
+        // references; from byte 32, per axis six words [lo01 lo23 hi01
+        // hi23 lo01 lo23]: the children's lower then upper planes as FP16
+        // offsets from the origin rounded outward (child 2j in the low half
+        // of word j), the lower ones repeated so that one 16 B load at word
+        // 0 or 2 returns an axis's near then far planes for either sign of
+        // the ray direction; bytes 104-127 zero.
         float org[3];
         for (int c = 0; c < 3; ++c) {
             org[c] = INFINITY;
             for (int j = 0; j < k; ++j) org[c] = std::min(org[c], lo[c][j]);
         }
         o[0] = make_float4(org[0], org[1], org[2], 0.0f);
+        o[1] = make_float4(u2f(ref[0]), u2f(ref[1]), u2f(ref[2]), u2f(ref[3]));
+        float *words = &o[2].x;
         for (int c = 0; c < 3; ++c) {
             uint32_t w[4];
             for (int jj = 0; jj < 2; ++jj) {
@@ -532,9 +537,9 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
                 w[jj] = (uint32_t)lq[0] | ((uint32_t)lq[1] << 16);
                 w[2 + jj] = (uint32_t)hq[0] | ((uint32_t)hq[1] << 16);
             }
-            o[1 + c] = make_float4(u2f(w[0]), u2f(w[1]), u2f(w[2]), u2f(w[3]));
+            const uint32_t row[6] = {w[0], w[1], w[2], w[3], w[0], w[1]};
+            for (int q = 0; q < 6; ++q) words[6 * c + q] = u2f(row[q]);
         }
-        o[4] = make_float4(u2f(ref[0]), u2f(ref[1]), u2f(ref[2]), u2f(ref[3]));
 #else
         for (int c = 0; c < 3; ++c) {
             o[2 * c] = make_float4(lo[c][0], lo[c][1], lo[c][2], lo[c][3]);
@@ -597,14 +602,16 @@ std::string check_bvh(const HostInstant &h, float pad)
         // Decode: plane = origin + FP16 offset, exactly in FP64.
         float lo_buf[3][4], hi_buf[3][4];
         const float org[3] = {n[0].x, n[0].y, n[0].z};
+        const float *words = &n[2].x;
         for (int c = 0; c < 3; ++c) {
-            const float *row = &n[1 + c].x;
+            const float *row = words + 6 * c;
+            if (f2u(row[4]) != f2u(row[0]) || f2u(row[5]) != f2u(row[1])) return "repeated lower planes differ";
             for (int j = 0; j < 4; ++j) {
                 const uint32_t wl = f2u(row[j >> 1]), wh = f2u(row[2 + (j >> 1)]);
                 const uint16_t bl = (uint16_t)((j & 1) ? wl >> 16 : wl & 0xffffu);
                 const uint16_t bh = (uint16_t)((j & 1) ? wh >> 16 : wh & 0xffffu);
                 // Decoded planes enclose the exact boxes; the FP32 rounding
-                // here only tightens the check (down for lo, up for hi).
+                // here only tightens the check (up for lo, down for hi).
                 const double dl = (double)org[c] + half_value(bl), dh = (double)org[c] + half_value(bh);
                 lo_buf[c][j] = bl == kHalfPosInf ? INFINITY : (float)dl;
                 hi_buf[c][j] = bh == kHalfNegInf ? -INFINITY : (float)dh;
@@ -614,7 +621,7 @@ std::string check_bvh(const HostInstant &h, float pad)
         }
         const float *lo[3] = {lo_buf[0], lo_buf[1], lo_buf[2]};
         const float *hi[3] = {hi_buf[0], hi_buf[1], hi_buf[2]};
-        const float *rf = &n[4].x;
+        const float *rf = &n[1].x;
 #else
         const float *lo[3] = {&n[0].x, &n[2].x, &n[4].x};
         const float *hi[3] = {&n[1].x, &n[3].x, &n[5].x};
@@ -640,8 +647,9 @@ std::string check_bvh(const HostInstant &h, float pad)
         }
         if (used < 2) return "inner node with fewer than two children";
 #if EVRT_HALF_NODES
-        for (int rr = 5; rr < 8; ++rr)
-            if (n[rr].x != 0.0f || n[rr].y != 0.0f || n[rr].z != 0.0f || n[rr].w != 0.0f) return "padding row not zero";
+        if (f2u(n[0].w) != 0u) return "origin row padding not zero";
+        for (int q = 26; q < 32; ++q)
+            if (f2u((&n[0].x)[q]) != 0u) return "node padding not zero";
 #else
         if (n[7].x != 0.0f || n[7].y != 0.0f || n[7].z != 0.0f || n[7].w != 0.0f) return "padding row not zero";
 #endif
