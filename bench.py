@@ -435,7 +435,12 @@ def main() -> int:
     fps = args.steps / elapsed
     print(f"[bench] adaptive {1000 * elapsed / args.steps:.1f} ms/frame", file=sys.stderr, flush=True)
     if args.kernel_only:
-        print(json.dumps(dict(frames_per_s=fps, ms_per_step=1000 * elapsed / args.steps)))
+        # The last frame's schedule, for reading a kernel trace of this run.
+        nr = min(64, stats["rounds"])
+        print(json.dumps(dict(frames_per_s=fps, ms_per_step=1000 * elapsed / args.steps,
+                              rounds=stats["rounds"], active_after_round=list(stats["active_after_round"][:nr]),
+                              paths=stats["paths"], camera_rays=stats["camera_rays"],
+                              extension_rays=stats["extension_rays"], shadow_rays=stats["shadow_rays"])))
         return 0
 
     # Work counts of the same (deterministic) frame for the roofline.
