@@ -80,6 +80,7 @@ struct HostInstant {
     int32_t root = kEmptyRef;
     uint32_t n_lds = 0;
     uint32_t depth = 0;          // inner levels of the 4-wide tree
+    float plane_scale = 1.0f;    // power of two dividing stored node origins and plane offsets
     double sah_cost = 0.0;       // SAH cost of the binary tree
 };
 

@@ -56,6 +56,7 @@ struct DevInstant {
     int32_t root;            // root reference (kEmptyRef: no geometry)
     uint32_t n_nodes, n_lds, n_emit;
     float emit_S;            // sum over emitters of area * Le
+    float plane_scale;       // power of two: node origins and FP16 plane offsets are stored divided by it
     DevCamera cam;
 };
 

@@ -235,7 +235,10 @@ __device__ __forceinline__ float safe_dir(float d)
 // Watertight ray frame (Woop, Benthin, Wald 2013): z = axis of the largest
 // |d| (ties to the lower axis), x and y cyclic after it, swapped when
 // d_z < 0; shear Sx = d_x / d_z, Sy = d_y / d_z, Sz = 1 / d_z.
-__device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx, float dy, float dz)
+// plane_scale: the node array's power-of-two plane scale; the reciprocal
+// direction is multiplied by it (exactly) after the origin terms are formed.
+__device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx, float dy, float dz,
+                                          float plane_scale)
 {
     TRay r;
     // Reciprocals for the box test only (culling, covered by the padding).
@@ -245,6 +248,13 @@ __device__ __forceinline__ TRay make_tray(float ox, float oy, float oz, float dx
     r.nox = -(ox * r.ix);
     r.noy = -(oy * r.iy);
     r.noz = -(oz * r.iz);
+#if EVRT_HALF_NODES
+    r.ix *= plane_scale;
+    r.iy *= plane_scale;
+    r.iz *= plane_scale;
+#else
+    (void)plane_scale;
+#endif
     // Near planes: lo planes for a positive direction component, hi planes
     // for a negative one; the far planes of an axis are the other half of
     // its pair.
@@ -418,6 +428,7 @@ struct Geo {
     const lds_f32 *lds;
     uint32_t n_lds;
     int32_t root;
+    float scale;  // the node array's plane scale
 };
 
 __device__ __forceinline__ Geo make_geo(const DevScene &sc, uint32_t inst, const lds_f32 *lds)
@@ -427,14 +438,16 @@ __device__ __forceinline__ Geo make_geo(const DevScene &sc, uint32_t inst, const
     g.tris = inst ? sc.inst[1].tris : sc.inst[0].tris;
     g.n_lds = inst ? sc.inst[1].n_lds : sc.inst[0].n_lds;
     g.root = inst ? sc.inst[1].root : sc.inst[0].root;
+    g.scale = inst ? sc.inst[1].plane_scale : sc.inst[0].plane_scale;
     g.lds = lds;
     return g;
 }
 
-__device__ __forceinline__ void trav_begin(Trav &T, int32_t root, float ox, float oy, float oz, float dx,
+__device__ __forceinline__ void trav_begin(Trav &T, const Geo &g, float ox, float oy, float oz, float dx,
                                            float dy, float dz, float tmin, float tmax, uint32_t skip)
 {
-    T.r = make_tray(ox, oy, oz, dx, dy, dz);
+    const int32_t root = g.root;
+    T.r = make_tray(ox, oy, oz, dx, dy, dz, g.scale);
     T.tmin = tmin;
     T.tmax = tmax;
     T.tfar = tmax;
@@ -933,7 +946,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
         if (j != ~0u) {
             cur = pt.base + j;
             const float4 o = q.o[cur], d = q.d[cur];
-            trav_begin(T, g.root, o.x, o.y, o.z, d.x, d.y, d.z, kRayTmin, INFINITY, q.skip[cur]);
+            trav_begin(T, g, o.x, o.y, o.z, d.x, d.y, d.z, kRayTmin, INFINITY, q.skip[cur]);
             busy = T.ref != kEmptyRef;
             if (!busy) hit[cur] = make_float2(T.tfar, bitsf(T.best_p));
         }
@@ -1036,7 +1049,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
                 const float4 o = sq.o[e];
                 const float4 w = sq.dir[slot * sq.cap + e];
                 const uint32_t meta = sq.meta[e];
-                trav_begin(T, g.root, o.x, o.y, o.z, w.x, w.y, w.z, kRayTmin, w.w, meta & ~kInstBit);
+                trav_begin(T, g, o.x, o.y, o.z, w.x, w.y, w.z, kRayTmin, w.w, meta & ~kInstBit);
                 ++rays;
                 tracing = T.ref != kEmptyRef;
                 if (!tracing) {
@@ -1958,7 +1971,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(EVRT_TRACE_
     for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
         const float4 o = q.o[i], d = q.d[i];
         Trav T;
-        trav_begin(T, g.root, o.x, o.y, o.z, d.x, d.y, d.z, tminmax[2 * i], tminmax[2 * i + 1], q.skip[i]);
+        trav_begin(T, g, o.x, o.y, o.z, d.x, d.y, d.z, tminmax[2 * i], tminmax[2 * i + 1], q.skip[i]);
         traverse<ANY, false>(T, g, (lds_u32 *)s_stack + threadIdx.x, visits, tests);
         if (ANY) {
             p_out[i] = T.best_p != kNoPrim ? 1u : 0u;

@@ -141,6 +141,7 @@ static void upload_instant(evrt_ctx *c, DevInstantBufs &bi, hipStream_t s)
     v.tris = bi.tris.as<const float4>();
     v.prim = bi.prim.as<const float4>();
     v.root = h.root;
+    v.plane_scale = h.plane_scale;
     v.n_nodes = (uint32_t)(h.nodes.size() / 8);
     v.n_lds = h.n_lds;
     v.cam = h.cam;

@@ -194,12 +194,13 @@ static uint16_t half_bits(double v)
 static uint16_t half_directed(double x, bool up)
 {
     if (!(x >= 0.0)) fail(EVRT_E_INVALID, "negative or non-finite FP16 plane offset");
+    // (Offsets reach at most 2^15 with the tree's plane scale.)
     if (x < 0x1p-14) return up && x > 0.0 ? half_bits(0x1p-14) : 0;
     int e = 0;
     std::frexp(x, &e);
     const double q = std::ldexp(1.0, e - 11);  // spacing of halves in [2^(e-1), 2^e)
     const double v = (up ? std::ceil(x / q) : std::floor(x / q)) * q;
-    if (v > 65504.0) fail(EVRT_E_UNSUPPORTED, "node extent above 65504 units, the FP16 plane range");
+    if (v > 65504.0) fail(EVRT_E_UNSUPPORTED, "FP16 plane offset out of range");
     return half_bits(v);
 }
 
@@ -479,6 +480,22 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
         }
     }
     h.nodes.assign(8 * order.size(), make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+#if EVRT_HALF_NODES
+    // One power-of-two scale s = 2^e for the whole tree: origins are stored
+    // as origin / s and plane offsets as offset / s, so that the widest node
+    // (the root) spans at most 2^15 FP16 units; the kernels scale each ray's
+    // reciprocal direction by s once, which leaves every product unchanged.
+    // e = 0 unless the scene is wider than 2^15 units.
+    int plane_exp = 0;
+    {
+        const Box &rb = B.nodes[broot].box;
+        double ext = 0.0;
+        for (int c = 0; c < 3; ++c)
+            ext = std::max(ext, (double)pad_up(rb.hi[c], pad) - (double)pad_down(rb.lo[c], pad));
+        while (std::ldexp(ext, -plane_exp) > 32768.0) ++plane_exp;
+    }
+    h.plane_scale = std::ldexp(1.0f, plane_exp);
+#endif
     uint32_t depth = 0;
     for (size_t i = 0; i < order.size(); ++i) {
         depth = std::max(depth, wdepth[order[i]]);
@@ -517,7 +534,12 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
             org[c] = INFINITY;
             for (int j = 0; j < k; ++j) org[c] = std::min(org[c], lo[c][j]);
         }
-        o[0] = make_float4(org[0], org[1], org[2], 0.0f);
+        float org_s[3];
+        for (int c = 0; c < 3; ++c) {
+            org_s[c] = std::ldexp(org[c], -plane_exp);
+            if (std::ldexp(org_s[c], plane_exp) != org[c]) fail(EVRT_E_UNSUPPORTED, "node origin not exact under the plane scale");
+        }
+        o[0] = make_float4(org_s[0], org_s[1], org_s[2], 0.0f);
         o[1] = make_float4(u2f(ref[0]), u2f(ref[1]), u2f(ref[2]), u2f(ref[3]));
         float *words = &o[2].x;
         for (int c = 0; c < 3; ++c) {
@@ -527,8 +549,8 @@ void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad)
                 for (int b = 0; b < 2; ++b) {
                     const int j = 2 * jj + b;
                     if (j < k) {
-                        lq[b] = half_directed((double)lo[c][j] - (double)org[c], false);
-                        hq[b] = half_directed((double)hi[c][j] - (double)org[c], true);
+                        lq[b] = half_directed(std::ldexp((double)lo[c][j] - (double)org[c], -plane_exp), false);
+                        hq[b] = half_directed(std::ldexp((double)hi[c][j] - (double)org[c], -plane_exp), true);
                     } else {
                         lq[b] = kHalfPosInf;
                         hq[b] = kHalfNegInf;
@@ -601,6 +623,7 @@ std::string check_bvh(const HostInstant &h, float pad)
 #if EVRT_HALF_NODES
         // Decode: plane = origin + FP16 offset, exactly in FP64.
         float lo_buf[3][4], hi_buf[3][4];
+        const double sc = (double)h.plane_scale;
         const float org[3] = {n[0].x, n[0].y, n[0].z};
         const float *words = &n[2].x;
         for (int c = 0; c < 3; ++c) {
@@ -612,7 +635,7 @@ std::string check_bvh(const HostInstant &h, float pad)
                 const uint16_t bh = (uint16_t)((j & 1) ? wh >> 16 : wh & 0xffffu);
                 // Decoded planes enclose the exact boxes; the FP32 rounding
                 // here only tightens the check (up for lo, down for hi).
-                const double dl = (double)org[c] + half_value(bl), dh = (double)org[c] + half_value(bh);
+                const double dl = ((double)org[c] + half_value(bl)) * sc, dh = ((double)org[c] + half_value(bh)) * sc;
                 lo_buf[c][j] = bl == kHalfPosInf ? INFINITY : (float)dl;
                 hi_buf[c][j] = bh == kHalfNegInf ? -INFINITY : (float)dh;
                 if (bl != kHalfPosInf && (double)lo_buf[c][j] < dl) lo_buf[c][j] = std::nextafter(lo_buf[c][j], INFINITY);

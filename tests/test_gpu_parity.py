@@ -93,6 +93,39 @@ def test_trace_rays_match_oracle(rend, torch_cuda, seed):
             assert bad == 0
 
 
+@pytest.mark.parametrize("extent,size", [(3.0e4, 6.0e3), (1.0e7, 2.0e6), (500.0, 1.0e-5)])
+def test_trace_rays_match_oracle_scaled_scenes(rend, torch_cuda, extent, size):
+    """Scenes wider than the FP16 plane range (a plane scale of 2^1 and
+    2^10 in the node array) and tiny triangles far from the origin: ray
+    queries stay bit-exact."""
+    sc = scenes.triangle_soup(300, seed=7, extent=extent, size=size, moving=True)
+    rend.set_scene(sc)
+    rng = np.random.default_rng(71)
+    n = 2000
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        for inst, t in ((0, 0.0), (1, 1.0)):
+            _say(f"trace_rays scaled extent={extent} t={t}")
+            tri, _ = f.world_tris(inst)
+            o, d = _rays_for(tri, rng, n, 1.5 * extent)
+            tmin = np.full(n, 1e-4 * max(1.0, extent / 100.0), np.float32)
+            tmax = np.full(n, np.inf, np.float32)
+            skip = np.full(n, ev.NO_PRIM, np.uint32)
+            rays = np.concatenate([o, tmin[:, None], d, tmax[:, None]], axis=1)
+            tt, pp = rend.trace_rays(t, rays, skip)
+            anyh = rend.trace_rays(t, rays, skip, any_hit=True)
+            tt, pp, anyh = tt.cpu().numpy(), pp.cpu().numpy().view(np.uint32), anyh.cpu().numpy()
+            bad = hits = 0
+            for k in range(n):
+                hit, t_ref, p_ref = f.closest_hit(inst, o[k], d[k], tmin=tmin[k], tmax=tmax[k], brute=True)
+                hits += hit
+                if p_ref != pp[k] or (hit and t_ref != tt[k]):
+                    bad += 1
+                if bool(anyh[k]) != f.any_hit(inst, o[k], d[k], tmin=tmin[k], tmax=tmax[k], brute=True):
+                    bad += 1
+            assert bad == 0
+            assert hits > n // 50
+
+
 # ---------------------------------------------------------------------------
 # Per-path radiance.
 

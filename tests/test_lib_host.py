@@ -150,7 +150,14 @@ def test_library_t_quantile_closed_forms():
 @pytest.mark.parametrize("make", [lambda: scenes.triangle_soup(2000, seed=3, moving=True, emitters=5),
                                   lambda: scenes.tiny_box(), lambda: scenes.furnace(0.5, 1.0),
                                   lambda: scenes.empty(), lambda: scenes.plane_point_light(),
-                                  lambda: scenes.single_triangle()])
+                                  lambda: scenes.single_triangle(),
+                                  # Wider than the FP16 plane range: the tree takes a plane
+                                  # scale of 2^1 and of 2^10 (the check decodes with it).
+                                  lambda: scenes.triangle_soup(500, seed=4, extent=3.0e4, size=6.0e3),
+                                  lambda: scenes.triangle_soup(500, seed=5, extent=1.0e7, size=2.0e6, moving=True),
+                                  # Tiny triangles far from the origin: offsets below the
+                                  # smallest normal FP16 value round to 0 or 2^-14.
+                                  lambda: scenes.triangle_soup(300, seed=6, extent=500.0, size=1.0e-5)])
 def test_bvh_structure_on_host(host_ctx, make):
     sc = make()
     host_ctx.set_scene(sc)
