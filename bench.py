@@ -335,6 +335,42 @@ def bench_batch(ev, scenes, args) -> dict:
     return out
 
 
+def bench_stress(ev, scenes, args) -> dict:
+    """Stress workload (1920x1080 city of 4.32M triangles, camera flying and
+    50 boxes moving every frame, depth 12, schedule 64/64/4096, C = 0.2,
+    alpha = 0.001): K consecutive pairs in one batch call (one geometry
+    instant per frame, built on host threads), with the per-pair figures
+    and the host build time."""
+    import torch
+    P = scenes.CITY_PARAMS
+    K = args.stress_pairs
+    sc = scenes.city(n_frames=max(K + 1, 2))
+    r = ev.Renderer(0)
+    r.set_scene(sc)
+    o = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    times = [float(k) for k in range(K + 1)]
+    print(f"[bench] stress batch of {K} pairs", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b = r.render_event_batch(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], o,
+                             extras=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    st = r.frame_stats()
+    rays = st["camera_rays"] + st["extension_rays"] + st["shadow_rays"]
+    npth = b["n_paths"].cpu().numpy()
+    out = dict(workload=f"city: {sc.width}x{sc.height}, {sc.n_tri_world} triangles, {K} consecutive pairs, "
+                        f"moving camera and 50 moving boxes, spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}, "
+                        f"depth {P['max_depth']}, C {P['C']}, alpha {P['alpha']}",
+               pairs=K, batch_s=tb, s_per_pair=tb / K, pairs_per_s=K / tb, rays_per_s=rays / tb,
+               host_build_s=st["ms_build"] / 1000.0, rounds=st["rounds"], paths=st["paths"],
+               mean_paths_per_pixel=float(npth.mean()),
+               events_per_pair=float((b["polarity"].cpu().numpy() != 0).sum(axis=1).mean()))
+    r.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,7 +388,8 @@ def main() -> int:
                     help="traversal blocks per CU of the sensor frame (0: occupancy max)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
-    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny", "sensitivity"),
+    ap.add_argument("--stress-pairs", type=int, default=8, help="pairs of the stress workload (--only stress)")
+    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny", "sensitivity", "stress"),
                     default="all",
                     help="which workloads to run (the headline is the frame workload)")
     ap.add_argument("--batch-pairs", type=int, default=64, help="pairs of the frame-batch workload")
@@ -377,9 +414,11 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.only in ("diff", "batch", "video", "tiny", "sensitivity"):
+    if args.only in ("diff", "batch", "video", "tiny", "sensitivity", "stress"):
         res = {"metric": "next-row workloads", "next_rows": {}}
-        if args.only == "sensitivity":
+        if args.only == "stress":
+            res["next_rows"]["stress"] = bench_stress(ev, scenes, args)
+        elif args.only == "sensitivity":
             res["sensitivity"] = bench_sensitivity(ev, scenes, args.C)
         elif args.only == "diff":
             res["next_rows"]["differentiation"] = bench_diff(ev, scenes)
