@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "d7dbf72abf184e0e5f69ff20c7ee6fe028a6ff792b43495a958b7f09706d49e0",
-           "bytes_per_launch": 526711303.2,
-           "counters": {"k_trace_closest": {"valu_busy": 0.867, "valu_lane_utilization": 0.601}, "k_trace_shadow": {"valu_busy": 0.705, "valu_lane_utilization": 0.600}, "k_shade": {"valu_busy": 0.485, "valu_lane_utilization": 0.640}}}
+TRAFFIC = {"sources_sha256": "f8927dfeb2683a5745759c8a209acc1d7dc94114c9410b85ac9f450828f3e1a4",
+           "bytes_per_launch": 526564719.0,
+           "counters": {"k_trace_closest": {"valu_busy": 0.873, "valu_lane_utilization": 0.601}, "k_trace_shadow": {"valu_busy": 0.713, "valu_lane_utilization": 0.600}, "k_shade": {"valu_busy": 0.486, "valu_lane_utilization": 0.640}}}
 
 
 def kernel_sources_digest() -> str:
