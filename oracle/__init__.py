@@ -33,6 +33,11 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
+def luminance(r: float, g: float, b: float) -> float:
+    """The oracle's luminance of linear RGB (Rec. 709), FP32."""
+    return float(lib().evo_luminance(float(r), float(g), float(b)))
+
+
 class _SceneDesc(ctypes.Structure):
     _fields_ = [
         ("n_mat", ctypes.c_uint32), ("albedo", _f32p), ("emission", _f32p),
@@ -46,6 +51,7 @@ class _SceneDesc(ctypes.Structure):
         ("cam_nkeys", ctypes.c_uint32), ("cam_t", _f64p), ("cam_elu", _f64p),
         ("env_res", ctypes.c_uint32), ("env", _f32p),
         ("lens_radius", ctypes.c_float), ("focus_dist", ctypes.c_float),
+        ("albedo_rgb", _f32p), ("emission_rgb", _f32p), ("pl_rgb", _f32p),
     ]
 
 
@@ -95,6 +101,8 @@ def lib():
     L = ctypes.CDLL(_LIB_PATH)
     L.evo_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     L.evo_u01.argtypes = [ctypes.c_uint32]
+    L.evo_luminance.argtypes = [ctypes.c_float] * 3
+    L.evo_luminance.restype = ctypes.c_float
     L.evo_u01.restype = ctypes.c_float
     for name, nargs in (("evo_t_cdf", 2), ("evo_t_ppf", 2), ("evo_ibeta", 3)):
         fn = getattr(L, name)
@@ -280,6 +288,20 @@ class Frame:
         d.lens_radius = float(getattr(scene, "lens_radius", 0.0))
         d.focus_dist = float(getattr(scene, "focus_dist", 1.0))
         d.cam_elu = _ptr(cam_elu, ctypes.c_double)
+        alb3 = getattr(scene, "albedo_rgb", None)
+        if alb3 is not None:
+            alb3 = arr(alb3, np.float32).reshape(-1, 3)
+            emi3 = arr(scene.emission_rgb, np.float32).reshape(-1, 3)
+            if len(alb3) != len(albedo) or len(emi3) != len(albedo):
+                raise ValueError("RGB materials must match the material count")
+            d.albedo_rgb = _ptr(alb3, ctypes.c_float)
+            d.emission_rgb = _ptr(emi3, ctypes.c_float)
+            pl3 = getattr(scene, "pl_rgb", None)
+            if pl3 is not None:
+                pl3 = arr(pl3, np.float32).reshape(-1, 3)
+                if len(pl3) != len(pl_int):
+                    raise ValueError("RGB point-light intensities must match the light count")
+                d.pl_rgb = _ptr(pl3, ctypes.c_float)
         self._scene = L.evo_scene_new(ctypes.byref(d))
         self._keep = []
         self._frame = L.evo_frame_new(self._scene, float(t0), float(t1), int(bool(use_bvh)))

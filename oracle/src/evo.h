@@ -70,7 +70,16 @@ typedef struct {
     /* Thin lens (0: pinhole): aperture radius and the distance of the plane
      * in focus along the viewing direction. */
     float lens_radius, focus_dist;
+    /* RGB radiance (NULL: grey): per material albedo_rgb[n_mat][3] in
+     * [0, 1) and emission_rgb[n_mat][3] >= 0, per point light
+     * pl_rgb[n_plight][3] (NULL with RGB materials: the grey intensity in
+     * every channel).  albedo / emission are then ignored. */
+    const float *albedo_rgb, *emission_rgb, *pl_rgb;
 } evo_scene_desc;
+
+/* Luminance of linear RGB with the Rec. 709 primaries (ITU-R BT.709):
+ * Y = 0.2126 R + 0.7152 G + 0.0722 B, FP32 in that order. */
+float evo_luminance(float r, float g, float b);
 
 typedef struct {
     uint64_t seed;

@@ -132,6 +132,7 @@ int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau
     if (mb != 1 && mb != 2 && mb != 4 && mb != 8) return -1;
     if (spp == 0 || spp % mb != 0 || !(tau > 0.0) || p->max_depth > EVO_REC_MAX) return -1;
     if (p->mis) return -1; /* the gradient follows the estimator without MIS */
+    if (f->scene->d.albedo_rgb) return -1; /* ... and with grey radiance */
     if (!pixels) n_pixels = sd->width * sd->height;
     if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
     if (n_threads < 1) n_threads = 1;

@@ -43,6 +43,9 @@ typedef struct {
     float Sx, Sy, Sz;
 } evo_ray;
 
+/* Emitted radiance of material m used for emitter selection: Le, or the
+ * luminance of the RGB emission. */
+float evo__emission_y(const evo_scene_desc *d, uint32_t m);
 void evo__ray_setup(evo_ray *r, const float o[3], const float d[3]);
 int evo__tri_test(const evo_ray *r, const float *v, float *t_out);
 int evo__closest(const evo_frame *f, int instant, const evo_ray *r, float tmin, float tmax,

@@ -5,7 +5,13 @@
  * TEST INFRASTRUCTURE ONLY (see evo.h).
  *
  * Readings of the paper taken here (the paper leaves these open):
- *   - grey (scalar) radiance, so luminance Y = radiance;
+ *   - grey (scalar) radiance, so luminance Y = radiance; or, as an option,
+ *     linear RGB (Rec. 709 primaries) with the throughput carried per
+ *     channel and each contribution reduced to its luminance
+ *     Y = 0.2126 R + 0.7152 G + 0.0722 B when it is added to the path
+ *     (luminance is linear, so the path's Y is the sum); emitters are then
+ *     picked in proportion to A_j Y(Le_j) and Russian roulette survives
+ *     with min(1, largest throughput channel); the environment stays grey;
  *   - next-event estimation to area emitters chosen with probability
  *     proportional to A_j * Le_j, without multiple importance sampling;
  *   - cosine-weighted Lambertian sampling and Russian roulette with
@@ -146,7 +152,11 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
     float d[3], o[3];
     evo_camera_ray(f, p, pixel, instant, sample, o, d);
 
+    /* RGB radiance: the throughput per channel (b3), every contribution
+     * reduced to its luminance when it is added to L. */
+    const int rgb = sd->albedo_rgb != NULL;
     float L = 0.0f, beta = 1.0f;
+    float b3[3] = {1.0f, 1.0f, 1.0f};
     float pb_prev = 0.0f; /* solid-angle pdf of the direction sampled at the
                              previous vertex (cosine: cos / pi) */
     uint32_t skip = EVO_NO_PRIM;
@@ -162,14 +172,24 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
         if (!evo__closest(f, instant, &ray, RAY_TMIN, INFINITY, skip, brute, &t, &prim)) {
             /* Leaves the scene: the environment's radiance (found by this
              * direction only; light samples do not sample it). */
-            if (sd->env_res) L = L + beta * evo_env_radiance(f, d);
+            if (sd->env_res) {
+                const float Lenv = evo_env_radiance(f, d);
+                if (rgb) L = L + evo_luminance(b3[0] * Lenv, b3[1] * Lenv, b3[2] * Lenv);
+                else L = L + beta * Lenv;
+            }
             break;
         }
         float P[3];
         for (int c = 0; c < 3; ++c) P[c] = o[c] + t * d[c];
         const float *n = I->nrm + 3 * (size_t)prim;
         const uint32_t m = I->mat[prim];
-        const float alb = sd->albedo[m], Le = sd->emission[m];
+        const float *alb3 = rgb ? sd->albedo_rgb + 3 * (size_t)m : NULL;
+        const float *Le3 = rgb ? sd->emission_rgb + 3 * (size_t)m : NULL;
+        /* Grey: albedo and emission; RGB: the largest albedo channel (the
+         * surface reflects when it is > 0) and the luminance of the
+         * emission. */
+        const float alb = rgb ? fmaxf(alb3[0], fmaxf(alb3[1], alb3[2])) : sd->albedo[m];
+        const float Le = rgb ? evo_luminance(Le3[0], Le3[1], Le3[2]) : sd->emission[m];
         const float cosi = dot3(n, d);
         float ns[3];
         for (int c = 0; c < 3; ++c) ns[c] = cosi < 0.0f ? n[c] : -n[c];
@@ -181,7 +201,7 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
          * have sampled this point, in solid angle at the previous vertex:
          * p_light = P_j / A_j * r^2 / cos_y = Le r^2 / (S cos_y). */
         if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !p->nee || p->mis)) {
-            float term = beta * Le;
+            float term = rgb ? evo_luminance(b3[0] * Le3[0], b3[1] * Le3[1], b3[2] * Le3[2]) : beta * Le;
             if (depth > 1 && p->nee) {
                 const float pl = (Le * (t * t)) / (I->emit_S * (-cosi));
                 const float ratio = pl / pb_prev;
@@ -205,6 +225,9 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
         uint32_t r0[4];
         rng4(p, pixel, sample, instant, depth, 0, r0);
         const float fr = alb * INV_PI_F; /* Lambertian BRDF a / pi */
+        float fr3[3] = {0.0f, 0.0f, 0.0f};
+        if (rgb)
+            for (int c = 0; c < 3; ++c) fr3[c] = alb3[c] * INV_PI_F;
 
         if (p->nee) {
             float Dd = 0.0f;
@@ -237,13 +260,26 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
                             /* beta * (a/pi) * Le_j * cx * cy / r^2 / (P_j / A_j)
                              * with P_j = A_j Le_j / S, i.e. the emitter terms
                              * collapse to S. */
-                            float cval = ((((beta * fr) * cx) * cy) * I->emit_S) / r2;
+                            float cval;
+                            if (rgb) {
+                                /* Per channel the grey estimate times
+                                 * Le_j,c / Y(Le_j): the emitter was picked
+                                 * in proportion to A_j Y(Le_j). */
+                                const float *Lq = sd->emission_rgb + 3 * (size_t)I->mat[q];
+                                const float Yq = evo_luminance(Lq[0], Lq[1], Lq[2]);
+                                float c3[3];
+                                for (int c = 0; c < 3; ++c)
+                                    c3[c] = (((((b3[c] * fr3[c]) * (Lq[c] / Yq)) * cx) * cy) * I->emit_S) / r2;
+                                cval = evo_luminance(c3[0], c3[1], c3[2]);
+                            } else {
+                                cval = ((((beta * fr) * cx) * cy) * I->emit_S) / r2;
+                            }
                             if (p->mis && depth < p->max_depth) {
                                 /* Power heuristic against the cosine-sampling
                                  * pdf of the same direction; the last vertex
                                  * samples no direction, so its light sample
                                  * keeps the full weight. */
-                                const float Lej = sd->emission[I->mat[q]];
+                                const float Lej = evo__emission_y(sd, I->mat[q]);
                                 const float pl = (Lej * r2) / (I->emit_S * cy);
                                 const float ratio = (cx * INV_PI_F) / pl;
                                 cval = cval * (1.0f / (1.0f + ratio * ratio));
@@ -269,16 +305,29 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
                 evo_ray sr;
                 evo__ray_setup(&sr, P, wi);
                 if (evo__any(f, instant, &sr, RAY_TMIN, rl * SHADOW_SCALE, prim, brute)) continue;
-                float cval = (((beta * fr) * sd->pl_intensity[k]) * cx) / r2;
+                float cval;
+                if (rgb) {
+                    float c3[3];
+                    for (int c = 0; c < 3; ++c) {
+                        const float Ik = sd->pl_rgb ? sd->pl_rgb[3 * (size_t)k + c] : sd->pl_intensity[k];
+                        c3[c] = (((b3[c] * fr3[c]) * Ik) * cx) / r2;
+                    }
+                    cval = evo_luminance(c3[0], c3[1], c3[2]);
+                } else {
+                    cval = (((beta * fr) * sd->pl_intensity[k]) * cx) / r2;
+                }
                 Dd = Dd + cval;
             }
             L = L + Dd;
         }
         if (depth == p->max_depth) break;
         if (depth >= p->rr_start_depth) {
-            const float q = fminf(1.0f, beta);
+            /* RGB: survival min(1, largest throughput channel). */
+            const float q = fminf(1.0f, rgb ? fmaxf(b3[0], fmaxf(b3[1], b3[2])) : beta);
             if (evo_u01(r0[3]) >= q) break;
             beta = beta / q;
+            if (rgb)
+                for (int c = 0; c < 3; ++c) b3[c] = b3[c] / q;
         }
 
         /* Cosine-weighted direction about ns; sin/cos are the correctly
@@ -302,6 +351,8 @@ static float path_radiance(const evo_frame *f, const evo_params *p, uint32_t pix
             o[c] = P[c];
         }
         beta = beta * alb;
+        if (rgb)
+            for (int c = 0; c < 3; ++c) b3[c] = b3[c] * alb3[c];
         skip = prim;
     }
     return L;

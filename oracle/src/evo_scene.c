@@ -35,6 +35,18 @@ static void *dup_bytes(const void *src, size_t n)
     return p;
 }
 
+float evo_luminance(float r, float g, float b)
+{
+    return (0.2126f * r + 0.7152f * g) + 0.0722f * b;
+}
+
+float evo__emission_y(const evo_scene_desc *d, uint32_t m)
+{
+    if (!d->albedo_rgb) return d->emission[m];
+    const float *e = d->emission_rgb + 3 * (size_t)m;
+    return evo_luminance(e[0], e[1], e[2]);
+}
+
 evo_scene *evo_scene_new(const evo_scene_desc *d)
 {
     evo_scene *s = (evo_scene *)calloc(1, sizeof(*s));
@@ -55,6 +67,9 @@ evo_scene *evo_scene_new(const evo_scene_desc *d)
     s->d.cam_t = dup_bytes(d->cam_t, sizeof(double) * d->cam_nkeys);
     s->d.cam_elu = dup_bytes(d->cam_elu, sizeof(double) * 9 * d->cam_nkeys);
     s->d.env = dup_bytes(d->env, sizeof(float) * 6 * (size_t)d->env_res * d->env_res);
+    s->d.albedo_rgb = d->albedo_rgb ? dup_bytes(d->albedo_rgb, sizeof(float) * 3 * d->n_mat) : NULL;
+    s->d.emission_rgb = d->albedo_rgb ? dup_bytes(d->emission_rgb, sizeof(float) * 3 * d->n_mat) : NULL;
+    s->d.pl_rgb = d->albedo_rgb && d->pl_rgb ? dup_bytes(d->pl_rgb, sizeof(float) * 3 * d->n_plight) : NULL;
     return s;
 }
 
@@ -66,6 +81,7 @@ void evo_scene_free(evo_scene *s)
     free((void *)s->d.inst_mesh); free((void *)s->d.inst_key_off); free((void *)s->d.key_t);
     free((void *)s->d.key_xform); free((void *)s->d.pl_pos); free((void *)s->d.pl_intensity);
     free((void *)s->d.cam_t); free((void *)s->d.cam_elu); free((void *)s->d.env);
+    free((void *)s->d.albedo_rgb); free((void *)s->d.emission_rgb); free((void *)s->d.pl_rgb);
     free(s);
 }
 
@@ -147,17 +163,18 @@ static void build_instant(const evo_scene *s, double t, evo_instant *I, int use_
 
     /* Emitter table: triangles with Le > 0, in primitive order.  Power
      * w_j = A_j * Le_j (FP32), prefix sums and total S in FP64 in that
-     * order, cdf_j = (float)(prefix_j / S), last entry exactly 1. */
+     * order, cdf_j = (float)(prefix_j / S), last entry exactly 1.  With RGB
+     * radiance Le_j is the luminance of the emission. */
     I->n_emit = 0;
     for (uint32_t p = 0; p < nt; ++p)
-        if (d->emission[I->mat[p]] > 0.0f) ++I->n_emit;
+        if (evo__emission_y(d, I->mat[p]) > 0.0f) ++I->n_emit;
     I->emit_prim = (uint32_t *)malloc(sizeof(uint32_t) * (I->n_emit ? I->n_emit : 1));
     I->emit_cdf = (float *)malloc(sizeof(float) * (I->n_emit ? I->n_emit : 1));
     double *pref = (double *)malloc(sizeof(double) * (I->n_emit ? I->n_emit : 1));
     double S = 0.0;
     uint32_t j = 0;
     for (uint32_t p = 0; p < nt; ++p) {
-        float le = d->emission[I->mat[p]];
+        float le = evo__emission_y(d, I->mat[p]);
         if (le > 0.0f) {
             float w = I->area[p] * le;
             S += (double)w;

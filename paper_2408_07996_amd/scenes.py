@@ -52,6 +52,13 @@ class Scene:
     env: Optional[np.ndarray] = None
     lens_radius: float = 0.0
     focus_dist: float = 1.0
+    # RGB radiance (None: grey): per material albedo_rgb [n_mat, 3] in
+    # [0, 1) and emission_rgb [n_mat, 3] >= 0 (linear Rec. 709 primaries),
+    # optional per point light pl_rgb [n_plight, 3] (None: the grey
+    # intensity in every channel).  albedo / emission are then unused.
+    albedo_rgb: Optional[np.ndarray] = None
+    emission_rgb: Optional[np.ndarray] = None
+    pl_rgb: Optional[np.ndarray] = None
 
     @property
     def n_tri_world(self) -> int:
@@ -704,6 +711,23 @@ def triangle_soup(n_tri: int, seed: int = 0, extent: float = 2.0, size: float = 
         b.static(d)
     b.set_camera(width, height, 45.0, [0.0], [[0.0, 0.0, 6.0, 0, 0, 0, 0, 1, 0]])
     return b.build()
+
+
+def colorize(sc: Scene, seed: int = 0, spread: float = 0.5) -> Scene:
+    """The same scene with RGB radiance: each material's albedo and emission
+    scaled per channel by factors in [1 - spread, 1 + spread] (albedo
+    clamped below 1), each point light's intensity likewise."""
+    rng = np.random.default_rng(seed)
+    n = len(sc.albedo)
+    fa = rng.uniform(1.0 - spread, 1.0 + spread, size=(n, 3))
+    fe = rng.uniform(1.0 - spread, 1.0 + spread, size=(n, 3))
+    out = dataclasses.replace(sc)
+    out.albedo_rgb = np.minimum(np.asarray(sc.albedo, np.float64)[:, None] * fa, 0.99).astype(np.float32)
+    out.emission_rgb = (np.asarray(sc.emission, np.float64)[:, None] * fe).astype(np.float32)
+    if len(sc.pl_intensity):
+        fl = rng.uniform(1.0 - spread, 1.0 + spread, size=(len(sc.pl_intensity), 3))
+        out.pl_rgb = (np.asarray(sc.pl_intensity, np.float64)[:, None] * fl).astype(np.float32)
+    return out
 
 
 def empty(width: int = 8, height: int = 8) -> Scene:
