@@ -181,6 +181,39 @@ def bench_video(ev, scenes) -> dict:
     return out
 
 
+def bench_rgb(ev, scenes, steps: int = 3) -> dict:
+    """The sensor workload with RGB radiance (materials and lights coloured
+    per channel by scenes.colorize): adaptive event frames/s and rays/s,
+    next to the grey frame of the headline."""
+    import torch
+    P = scenes.SENSOR_PARAMS
+    sc = scenes.colorize(scenes.sensor(), seed=1)
+    r = ev.Renderer(0)
+    r.set_scene(sc)
+    o = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+             minibatch=P["minibatch"], log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    print("[bench] RGB sensor frame", file=sys.stderr, flush=True)
+
+    def frame():
+        return r.render_event_frame(0.0, 1.0, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], o,
+                                    extras=False)
+    frame()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        out = frame()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    st = r.frame_stats()
+    rays = st["camera_rays"] + st["extension_rays"] + st["shadow_rays"]
+    res = dict(workload="sensor workload with RGB materials and lights", frames_per_s=1.0 / dt,
+               ms_per_frame=1000.0 * dt, rays_per_s=rays / dt, rounds=st["rounds"],
+               mean_paths_per_pixel=float(out["n_paths"].cpu().numpy().mean()),
+               events=int((out["polarity"].cpu().numpy() != 0).sum()))
+    r.close()
+    return res
+
+
 def bench_tiny(ev, scenes, steps: int = 20) -> dict:
     """The tiny workload (64x64, 24 triangles, depth 4, schedule 16/16/256,
     C = 0.2, alpha = 0.01): adaptive event frames/s on the GPU, where launch
@@ -389,7 +422,8 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
     ap.add_argument("--stress-pairs", type=int, default=8, help="pairs of the stress workload (--only stress)")
-    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny", "sensitivity", "stress"),
+    ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny", "sensitivity", "stress",
+                                       "rgb"),
                     default="all",
                     help="which workloads to run (the headline is the frame workload)")
     ap.add_argument("--batch-pairs", type=int, default=64, help="pairs of the frame-batch workload")
@@ -414,9 +448,11 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.only in ("diff", "batch", "video", "tiny", "sensitivity", "stress"):
+    if args.only in ("diff", "batch", "video", "tiny", "sensitivity", "stress", "rgb"):
         res = {"metric": "next-row workloads", "next_rows": {}}
-        if args.only == "stress":
+        if args.only == "rgb":
+            res["next_rows"]["rgb_frame"] = bench_rgb(ev, scenes)
+        elif args.only == "stress":
             res["next_rows"]["stress"] = bench_stress(ev, scenes, args)
         elif args.only == "sensitivity":
             res["sensitivity"] = bench_sensitivity(ev, scenes, args.C)
@@ -677,7 +713,8 @@ def main() -> int:
         res["tiny"] = bench_tiny(ev, scenes)
         res["next_rows"] = {"differentiation": bench_diff(ev, scenes),
                             "batching": bench_batch(ev, scenes, args),
-                            "sequential_video": bench_video(ev, scenes)}
+                            "sequential_video": bench_video(ev, scenes),
+                            "rgb_frame": bench_rgb(ev, scenes)}
     print(json.dumps(res), flush=True)
     return 0
 

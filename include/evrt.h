@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define EVRT_ABI_VERSION 5
+#define EVRT_ABI_VERSION 6
 
 enum {
     EVRT_OK = 0,
@@ -94,6 +94,24 @@ const char *evrt_last_error(const evrt_ctx *ctx);
 int evrt_scene_set_materials(evrt_ctx *ctx, const float *albedo, const float *emission,
                              uint32_t n_mat);
 
+/* RGB radiance (the paper's renderer is spectral; grey radiance is the
+ * default): n_mat Lambertian materials with albedo_rgb[n_mat][3] in [0, 1)
+ * and emission_rgb[n_mat][3] >= 0 per channel, linear Rec. 709 primaries.
+ * A path's throughput is carried per channel and every contribution it
+ * gathers is reduced to its luminance Y = 0.2126 R + 0.7152 G + 0.0722 B
+ * (FP32 in that order) when it is added, so the per-path radiance, and all
+ * statistics of the event decision (Sec. 3.2, Eq. 7: log-luminance), stay
+ * scalar.  Emitters are picked in proportion to area times the luminance
+ * of their emission; Russian roulette survives with min(1, largest
+ * throughput channel); the environment map stays grey (its radiance in
+ * every channel); grey point lights shine with their intensity in every
+ * channel.  Replaces evrt_scene_set_materials (and is replaced by it).
+ * The event-loss gradient refuses RGB scenes (EVRT_E_UNSUPPORTED).
+ * Errors: EVRT_E_INVALID for n_mat = 0, NULL arrays, an albedo channel
+ * outside [0, 1) or a negative or non-finite emission channel. */
+int evrt_scene_set_materials_rgb(evrt_ctx *ctx, const float *albedo_rgb, const float *emission_rgb,
+                                 uint32_t n_mat);
+
 /* Mesh `mesh_id` (ids must end up dense 0..n-1): nv object-space vertices
  * (xyz[nv][3]) and nt triangles (tri_idx[nt][3] into this mesh's vertices,
  * tri_mat[nt] material ids).  Replaces a mesh with the same id. */
@@ -116,6 +134,12 @@ int evrt_scene_set_instance(evrt_ctx *ctx, uint32_t inst_id, uint32_t mesh_id, u
  * intensity[n].  Reached through next-event estimation only. */
 int evrt_scene_set_point_lights(evrt_ctx *ctx, const float *pos_xyz, const float *intensity,
                                 uint32_t n);
+
+/* Point lights with RGB intensities intensity_rgb[n][3] (scenes with RGB
+ * materials only: the commit refuses them otherwise with EVRT_E_INVALID).
+ * Replaces evrt_scene_set_point_lights (and is replaced by it). */
+int evrt_scene_set_point_lights_rgb(evrt_ctx *ctx, const float *pos_xyz, const float *intensity_rgb,
+                                    uint32_t n);
 
 /* Pinhole camera: image width x height, vertical field of view vfov_deg,
  * keyframed (eye, look-at, up) eye_look_up[n_keys][9], interpolated like

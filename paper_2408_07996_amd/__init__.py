@@ -90,9 +90,11 @@ SIGNATURES = [
     ("evrt_destroy", None, [_c_p]),
     ("evrt_last_error", ctypes.c_char_p, [_c_p]),
     ("evrt_scene_set_materials", ctypes.c_int, [_c_p, _c_p, _c_p, _u32]),
+    ("evrt_scene_set_materials_rgb", ctypes.c_int, [_c_p, _c_p, _c_p, _u32]),
     ("evrt_scene_set_mesh", ctypes.c_int, [_c_p, _u32, _c_p, _u32, _c_p, _c_p, _u32]),
     ("evrt_scene_set_instance", ctypes.c_int, [_c_p, _u32, _u32, _u32, _c_p, _c_p]),
     ("evrt_scene_set_point_lights", ctypes.c_int, [_c_p, _c_p, _c_p, _u32]),
+    ("evrt_scene_set_point_lights_rgb", ctypes.c_int, [_c_p, _c_p, _c_p, _u32]),
     ("evrt_scene_set_camera", ctypes.c_int, [_c_p, _u32, _u32, ctypes.c_double, _u32, _c_p, _c_p]),
     ("evrt_scene_set_environment", ctypes.c_int, [_c_p, _c_p, _u32]),
     ("evrt_scene_set_lens", ctypes.c_int, [_c_p, ctypes.c_float, ctypes.c_float]),
@@ -222,6 +224,13 @@ class Renderer:
         e = np.ascontiguousarray(emission, np.float32)
         self._check(load_library().evrt_scene_set_materials(self._h, _np_ptr(a), _np_ptr(e), len(a)))
 
+    def scene_set_materials_rgb(self, albedo_rgb, emission_rgb) -> None:
+        a = np.ascontiguousarray(albedo_rgb, np.float32).reshape(-1, 3)
+        e = np.ascontiguousarray(emission_rgb, np.float32).reshape(-1, 3)
+        if len(a) != len(e):
+            raise ValueError("albedo_rgb and emission_rgb differ in length")
+        self._check(load_library().evrt_scene_set_materials_rgb(self._h, _np_ptr(a), _np_ptr(e), len(a)))
+
     def scene_set_mesh(self, mesh_id: int, xyz, tri_idx, tri_mat) -> None:
         v = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
         t = np.ascontiguousarray(tri_idx, np.uint32).reshape(-1, 3)
@@ -240,6 +249,13 @@ class Renderer:
         i = np.ascontiguousarray(intensity, np.float32).reshape(-1)
         self._check(load_library().evrt_scene_set_point_lights(self._h, _np_ptr(p), _np_ptr(i), len(i)))
 
+    def scene_set_point_lights_rgb(self, pos_xyz, intensity_rgb) -> None:
+        p = np.ascontiguousarray(pos_xyz, np.float32).reshape(-1, 3)
+        i = np.ascontiguousarray(intensity_rgb, np.float32).reshape(-1, 3)
+        if len(p) != len(i):
+            raise ValueError("positions and intensities differ in length")
+        self._check(load_library().evrt_scene_set_point_lights_rgb(self._h, _np_ptr(p), _np_ptr(i), len(i)))
+
     def scene_set_camera(self, width: int, height: int, vfov_deg: float, key_t, eye_look_up) -> None:
         kt = np.ascontiguousarray(key_t, np.float64).reshape(-1)
         e = np.ascontiguousarray(eye_look_up, np.float64).reshape(-1, 9)
@@ -255,7 +271,10 @@ class Renderer:
     def set_scene(self, sc) -> None:
         """Uploads a ``scenes.Scene`` (flat arrays) mesh by mesh and commits."""
         self.scene_reset()
-        self.scene_set_materials(sc.albedo, sc.emission)
+        if getattr(sc, "albedo_rgb", None) is not None:
+            self.scene_set_materials_rgb(sc.albedo_rgb, sc.emission_rgb)
+        else:
+            self.scene_set_materials(sc.albedo, sc.emission)
         off = sc.mesh_tri_off.astype(np.int64)
         for m in range(len(off) - 1):
             tri = sc.tri_idx[off[m]:off[m + 1]].astype(np.int64)
@@ -269,7 +288,10 @@ class Renderer:
         for i in range(len(sc.inst_mesh)):
             self.scene_set_instance(i, int(sc.inst_mesh[i]), sc.key_t[koff[i]:koff[i + 1]],
                                     sc.key_xform[koff[i]:koff[i + 1]])
-        self.scene_set_point_lights(sc.pl_pos, sc.pl_intensity)
+        if getattr(sc, "pl_rgb", None) is not None:
+            self.scene_set_point_lights_rgb(sc.pl_pos, sc.pl_rgb)
+        else:
+            self.scene_set_point_lights(sc.pl_pos, sc.pl_intensity)
         self.scene_set_camera(sc.width, sc.height, sc.vfov_deg, sc.cam_t, sc.cam_elu)
         env = getattr(sc, "env", None)
         if env is not None:

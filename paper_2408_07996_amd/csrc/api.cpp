@@ -212,6 +212,34 @@ int evrt_scene_set_materials(evrt_ctx *c, const float *albedo, const float *emis
         }
         c->pending.albedo.assign(albedo, albedo + n_mat);
         c->pending.emission.assign(emission, emission + n_mat);
+        c->pending.rgb = false;
+        c->pending.albedo3.clear();
+        c->pending.emission3.clear();
+        scene_changed(c);
+    });
+}
+
+int evrt_scene_set_materials_rgb(evrt_ctx *c, const float *albedo_rgb, const float *emission_rgb, uint32_t n_mat)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        if (n_mat == 0 || !albedo_rgb || !emission_rgb) fail(EVRT_E_INVALID, "need at least one material");
+        for (size_t i = 0; i < 3 * (size_t)n_mat; ++i) {
+            if (!(albedo_rgb[i] >= 0.0f && albedo_rgb[i] < 1.0f)) fail(EVRT_E_INVALID, "albedo must be in [0, 1)");
+            if (!(emission_rgb[i] >= 0.0f) || !std::isfinite(emission_rgb[i]))
+                fail(EVRT_E_INVALID, "emission must be finite and >= 0");
+        }
+        SceneDesc &p = c->pending;
+        p.rgb = true;
+        p.albedo3.assign(albedo_rgb, albedo_rgb + 3 * (size_t)n_mat);
+        p.emission3.assign(emission_rgb, emission_rgb + 3 * (size_t)n_mat);
+        p.albedo.resize(n_mat);
+        p.emission.resize(n_mat);
+        for (uint32_t i = 0; i < n_mat; ++i) {
+            const float *a = albedo_rgb + 3 * (size_t)i, *e = emission_rgb + 3 * (size_t)i;
+            p.albedo[i] = std::max(a[0], std::max(a[1], a[2]));
+            p.emission[i] = luminance(e[0], e[1], e[2]);
+        }
         scene_changed(c);
     });
 }
@@ -269,6 +297,29 @@ int evrt_scene_set_point_lights(evrt_ctx *c, const float *pos_xyz, const float *
                 fail(EVRT_E_INVALID, "point light intensity must be finite and >= 0");
         c->pending.pl_pos.assign(pos_xyz, pos_xyz + 3 * (size_t)n);
         c->pending.pl_int.assign(intensity, intensity + n);
+        c->pending.pl_int3.clear();
+        scene_changed(c);
+    });
+}
+
+int evrt_scene_set_point_lights_rgb(evrt_ctx *c, const float *pos_xyz, const float *intensity_rgb, uint32_t n)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        if (n && (!pos_xyz || !intensity_rgb)) fail(EVRT_E_INVALID, "NULL point light array");
+        if (n > 64) fail(EVRT_E_UNSUPPORTED, "at most 64 point lights");
+        need_finite(pos_xyz, 3 * (size_t)n, "point light positions");
+        for (size_t i = 0; i < 3 * (size_t)n; ++i)
+            if (!(intensity_rgb[i] >= 0.0f) || !std::isfinite(intensity_rgb[i]))
+                fail(EVRT_E_INVALID, "point light intensity must be finite and >= 0");
+        SceneDesc &p = c->pending;
+        p.pl_pos.assign(pos_xyz, pos_xyz + 3 * (size_t)n);
+        p.pl_int3.assign(intensity_rgb, intensity_rgb + 3 * (size_t)n);
+        p.pl_int.resize(n);
+        for (uint32_t i = 0; i < n; ++i) {
+            const float *v = intensity_rgb + 3 * (size_t)i;
+            p.pl_int[i] = luminance(v[0], v[1], v[2]);
+        }
         scene_changed(c);
     });
 }
@@ -360,7 +411,7 @@ static bool same_geometry(const SceneDesc &a, const SceneDesc &b)
         x.elu != y.elu)
         return false;
     // The lens radius enters the box padding.
-    return a.pl_pos == b.pl_pos && a.pl_int == b.pl_int && a.lens_radius == b.lens_radius;
+    return a.pl_pos == b.pl_pos && a.pl_int == b.pl_int && a.pl_int3 == b.pl_int3 && a.lens_radius == b.lens_radius;
 }
 
 int evrt_scene_commit(evrt_ctx *c)
@@ -369,6 +420,7 @@ int evrt_scene_commit(evrt_ctx *c)
         need_ctx(c);
         SceneDesc &p = c->pending;
         if (p.albedo.empty()) fail(EVRT_E_STATE, "materials not set");
+        if (!p.rgb && !p.pl_int3.empty()) fail(EVRT_E_INVALID, "RGB point lights need RGB materials");
         if (!p.cam.set) fail(EVRT_E_STATE, "camera not set");
         for (size_t i = 0; i < p.meshes.size(); ++i)
             if (!p.meshes[i].set) fail(EVRT_E_INVALID, "mesh ids are not dense: mesh " + std::to_string(i) + " missing");
@@ -405,6 +457,24 @@ int evrt_scene_commit(evrt_ctx *c)
             for (size_t i = 0; i < p.pl_int.size(); ++i)
                 pl[i] = make_float4(p.pl_pos[3 * i], p.pl_pos[3 * i + 1], p.pl_pos[3 * i + 2], p.pl_int[i]);
             c->plights.upload(pl.data(), pl.size() * sizeof(float4), nullptr);
+            if (p.rgb) {
+                // (albedo rgb, 0), (emission rgb, its luminance) per material;
+                // (intensity rgb, 0) per point light (grey lights: the
+                // intensity in every channel).
+                std::vector<float4> mr(2 * p.albedo.size());
+                for (size_t i = 0; i < p.albedo.size(); ++i) {
+                    const float *a = &p.albedo3[3 * i], *e = &p.emission3[3 * i];
+                    mr[2 * i] = make_float4(a[0], a[1], a[2], 0.0f);
+                    mr[2 * i + 1] = make_float4(e[0], e[1], e[2], p.emission[i]);
+                }
+                c->mat_rgb.upload(mr.data(), mr.size() * sizeof(float4), nullptr);
+                std::vector<float4> plr(pl.size(), make_float4(0, 0, 0, 0));
+                for (size_t i = 0; i < p.pl_int.size(); ++i)
+                    plr[i] = p.pl_int3.empty() ? make_float4(p.pl_int[i], p.pl_int[i], p.pl_int[i], 0.0f)
+                                               : make_float4(p.pl_int3[3 * i], p.pl_int3[3 * i + 1],
+                                                             p.pl_int3[3 * i + 2], 0.0f);
+                c->plights_rgb.upload(plr.data(), plr.size() * sizeof(float4), nullptr);
+            }
             if (p.env_res) c->env.upload(p.env.data(), p.env.size() * sizeof(float), nullptr);
             hip_check(hipStreamSynchronize(nullptr), "scene upload");
             if (materials_only) refresh_emitters(c);
@@ -594,6 +664,7 @@ int evrt_event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, 
         if (spp == 0 || spp % o.minibatch != 0) fail(EVRT_E_INVALID, "spp must be a positive multiple of minibatch");
         if (!out || !out->loss || !out->grad) fail(EVRT_E_INVALID, "NULL loss or gradient output");
         if (o.mis) fail(EVRT_E_UNSUPPORTED, "the gradient follows the estimator without MIS");
+        if (c->scene.rgb) fail(EVRT_E_UNSUPPORTED, "the gradient follows grey radiance");
         if (c->scene.albedo.size() > 2048) fail(EVRT_E_UNSUPPORTED, "more than 2048 materials");
         const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;
         if (2ull * npx * spp >= (1ull << 31)) fail(EVRT_E_UNSUPPORTED, "more than 2^31 paths");

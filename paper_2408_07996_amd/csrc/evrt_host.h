@@ -54,7 +54,12 @@ struct CameraDesc {
 };
 
 struct SceneDesc {
+    // Grey materials, or with RGB radiance the largest albedo channel and
+    // the emission's luminance (they drive the same decisions).
     std::vector<float> albedo, emission;
+    bool rgb = false;                       // RGB radiance
+    std::vector<float> albedo3, emission3;  // [n_mat][3] with RGB radiance
+    std::vector<float> pl_int3;             // [n][3] RGB point-light intensities (empty: grey)
     std::vector<MeshDesc> meshes;
     std::vector<InstanceDesc> instances;
     std::vector<float> pl_pos, pl_int;
@@ -121,6 +126,7 @@ double t_quantile(double p, uint32_t df);
 // run on two streams so that one piece's kernels fill the other's tails.
 struct LaneBufs {
     DevBuf q_o[2], q_d[2], q_skip[2], hit;
+    DevBuf q_bgb[2];  // RGB radiance: green and blue throughput of the ray queues
     DevBuf sh_o, sh_meta, sh_dir, sh_c;
     DevBuf rad;
     uint32_t queue_cap = 0, shadow_slots = 0;
@@ -165,6 +171,7 @@ struct evrt_ctx {
     std::map<double, std::shared_ptr<evrt::DevInstantBufs>> cache;
     std::vector<double> cache_order;
     evrt::DevBuf mat, plights, env;
+    evrt::DevBuf mat_rgb, plights_rgb;  // RGB radiance tables
     evrt::FrameBuffers fb;
     hipStream_t s2 = nullptr;                // second lane's stream (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;

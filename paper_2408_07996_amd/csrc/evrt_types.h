@@ -17,6 +17,13 @@ constexpr float kShadowScale = 0.9999f;  // shadow segment ends short of the lig
 #endif
 
 constexpr uint16_t kHalfPosInf = 0x7c00u, kHalfNegInf = 0xfc00u;
+
+// Luminance of linear RGB with the Rec. 709 primaries (ITU-R BT.709), FP32
+// operations in this order (built without contraction).
+__host__ __device__ inline float luminance(float r, float g, float b)
+{
+    return (0.2126f * r + 0.7152f * g) + 0.0722f * b;
+}
 constexpr float kInvPi = 0.318309886183790671538f;
 constexpr double kTwoPi = 6.283185307179586476925;
 constexpr uint32_t kInstBit = 0x80000000u;  // instant flag in queue path words
@@ -62,8 +69,13 @@ struct DevInstant {
 
 struct DevScene {
     DevInstant inst[2];
-    const float2 *mat;       // (albedo, emission)
+    const float2 *mat;       // (albedo, emission); RGB: (largest albedo channel, luminance of the emission)
     const float4 *plights;   // (position xyz, intensity)
+    // RGB radiance (rgb = 1): per material (albedo rgb, 0), (emission rgb,
+    // its luminance); per point light (intensity rgb, 0).
+    const float4 *mat_rgb;
+    const float4 *plights_rgb;
+    uint32_t rgb;
     const float *env;        // cube map [6][env_res][env_res] (env_res 0: none)
     uint32_t n_plights;
     uint32_t env_res;
@@ -110,11 +122,14 @@ constexpr uint32_t kPixMask = (1u << kPixBits) - 1u;
 constexpr uint32_t kMaxBatchFrames = 1u << (32 - kPixBits);
 
 // Ray queue (SoA of float4): o = (origin xyz, throughput beta),
-// d = (direction xyz, path word = p | instant << 31), skip = origin primitive.
+// d = (direction xyz, path word = p | instant << 31), skip = origin primitive;
+// with RGB radiance beta is the red channel and bgb the green and blue ones
+// (null otherwise).
 struct RayQueue {
     float4 *o;
     float4 *d;
     uint32_t *skip;
+    float2 *bgb;
 };
 
 // Shadow queue: one entry per shaded vertex with at least one shadow ray;

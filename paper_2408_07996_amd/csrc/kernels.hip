@@ -916,6 +916,7 @@ __global__ void k_raygen(Piece pc, DevScene sc, RenderParams rp, RayQueue q, uin
     q.o[p] = make_float4(ox, oy, oz, 1.0f);
     q.d[p] = make_float4(dx, dy, dz, bitsf(p | (inst << 31)));
     q.skip[p] = kNoPrim;
+    if (q.bgb) q.bgb[p] = make_float2(1.0f, 1.0f);
     pc.rad[a * pc.rs_a + ii * pc.rs_i + s] = 0.0f;
 }
 
@@ -1142,6 +1143,26 @@ __device__ __forceinline__ float point_light_slot(const DevScene &sc, uint32_t k
     return (((beta * fr) * L.w) * cx) / r2;
 }
 
+// The same for RGB radiance: per channel throughput b3, BRDF fr3 and the
+// light's intensity, reduced to luminance.
+__device__ __forceinline__ float point_light_slot_rgb(const DevScene &sc, uint32_t k, float Px, float Py,
+                                                      float Pz, float nsx, float nsy, float nsz,
+                                                      float3 b3, float3 fr3, float4 &dir)
+{
+    const float4 L = sc.plights[k];
+    const float wx = L.x - Px, wy = L.y - Py, wz = L.z - Pz;
+    const float r2 = dot3f(wx, wy, wz, wx, wy, wz);
+    if (!(r2 > 0.0f)) return 0.0f;
+    const float rl = sqrtf(r2);
+    const float wix = wx / rl, wiy = wy / rl, wiz = wz / rl;
+    const float cx = dot3f(nsx, nsy, nsz, wix, wiy, wiz);
+    if (!(cx > 0.0f)) return 0.0f;
+    dir = make_float4(wix, wiy, wiz, rl * kShadowScale);
+    const float4 I = sc.plights_rgb[k];
+    return luminance((((b3.x * fr3.x) * I.x) * cx) / r2, (((b3.y * fr3.y) * I.y) * cx) / r2,
+                     (((b3.z * fr3.z) * I.z) * cx) / r2);
+}
+
 // Shading of vertex `depth` for every queued ray: emission, next-event
 // estimation (area emitters picked in proportion to area * Le, uniform
 // point on the triangle; point lights), Russian roulette, cosine-weighted
@@ -1193,7 +1214,7 @@ __device__ __forceinline__ float env_radiance(const DevScene &sc, float dx, floa
     return sc.env[((size_t)face * N + j) * N + i];
 }
 
-template <bool ADJ>
+template <bool ADJ, bool RGB>
 __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, RenderParams rp, RayQueue qin,
                                                const uint32_t *cnt_in, const float2 *hit,
                                                RayQueue qout, uint32_t *cnt_out, ShadowQueue sq,
@@ -1213,6 +1234,12 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
         const bool valid = j < pt.n;
         const uint32_t i = pt.base + (valid ? j : 0u);
         const float4 o = qin.o[i], d = qin.d[i];
+        // RGB: the throughput per channel (red in o.w).
+        float3 b3 = make_float3(0.0f, 0.0f, 0.0f), b3v = b3, fr3 = b3;
+        if (RGB && valid) {
+            const float2 bg = qin.bgb[i];
+            b3 = make_float3(o.w, bg.x, bg.y);
+        }
         // hit_log (per-vertex slice, by path id): the replay reads the hit the
         // logging forward pass wrote instead of a traced one.
         float2 h;
@@ -1238,7 +1265,8 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
             const uint32_t s = p - qq * pc.bp;
             const uint32_t ii = fdiv(pc.div_nA, qq);
             const uint32_t rm = (qq - ii * pc.nA) * pc.rs_a + ii * pc.rs_i + s;
-            pc.rad[rm] = pc.rad[rm] + o.w * env_radiance(sc, d.x, d.y, d.z);
+            const float Lenv = env_radiance(sc, d.x, d.y, d.z);
+            pc.rad[rm] = pc.rad[rm] + (RGB ? luminance(b3.x * Lenv, b3.y * Lenv, b3.z * Lenv) : o.w * Lenv);
         }
         if (prim != kNoPrim) {
             pword = fbits(d.w);
@@ -1260,14 +1288,21 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
             Pz = o.z + t * d.z;
             const float4 pr = inst ? sc.inst[1].prim[prim] : sc.inst[0].prim[prim];
             const float2 mt = sc.mat[fbits(pr.w)];
+            // RGB: mt holds the largest albedo channel and the emission's
+            // luminance, which drive the same decisions as grey values.
             const float alb = mt.x, Le = mt.y;
+            float4 A3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), E3 = A3;
+            if (RGB) {
+                A3 = sc.mat_rgb[2 * fbits(pr.w)];
+                E3 = sc.mat_rgb[2 * fbits(pr.w) + 1];
+            }
             const float cosi = dot3f(pr.x, pr.y, pr.z, d.x, d.y, d.z);
             nsx = cosi < 0.0f ? pr.x : -pr.x;
             nsy = cosi < 0.0f ? pr.y : -pr.y;
             nsz = cosi < 0.0f ? pr.z : -pr.z;
             if (ADJ) w = adj.W[((size_t)pixel * 2 + inst) * adj.m + sample / adj.mb];
             if (Le > 0.0f && cosi < 0.0f && (depth == 1 || !rp.nee || rp.mis)) {
-                float term = beta * Le;
+                float term = RGB ? luminance(b3.x * E3.x, b3.y * E3.y, b3.z * E3.z) : beta * Le;
                 if (depth > 1 && rp.nee) {
                     // MIS: this emitter point was reached by the cosine-sampled
                     // direction of the previous vertex, whose pdf cos / pi is
@@ -1293,6 +1328,10 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
                 const uint4 r0 = rng_block(rp, pixel, sample, q, depth, 0);
                 fr = alb * kInvPi;
                 beta_v = beta;
+                if (RGB) {
+                    fr3 = make_float3(A3.x * kInvPi, A3.y * kInvPi, A3.z * kInvPi);
+                    b3v = b3;
+                }
                 if (rp.nee) {
                     const uint32_t n_emit = inst ? sc.inst[1].n_emit : sc.inst[0].n_emit;
                     if (n_emit > 0) {
@@ -1321,7 +1360,18 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
                             const float cy = -dot3f(en.x, en.y, en.z, wix, wiy, wiz);
                             if (cx > 0.0f && cy > 0.0f) {
                                 const float S = inst ? sc.inst[1].emit_S : sc.inst[0].emit_S;
-                                c0 = ((((beta * fr) * cx) * cy) * S) / r2;
+                                if (RGB) {
+                                    // Per channel the grey estimate times
+                                    // Le_j,c / Y(Le_j) (emitters are picked
+                                    // by luminance power), then luminance.
+                                    const float4 *P = inst ? sc.inst[1].prim : sc.inst[0].prim;
+                                    const float4 Lq = sc.mat_rgb[2 * fbits(P[fbits(en.w)].w) + 1];
+                                    c0 = luminance(((((b3.x * fr3.x) * (Lq.x / Lq.w)) * cx) * cy) * S / r2,
+                                                   ((((b3.y * fr3.y) * (Lq.y / Lq.w)) * cx) * cy) * S / r2,
+                                                   ((((b3.z * fr3.z) * (Lq.z / Lq.w)) * cx) * cy) * S / r2);
+                                } else {
+                                    c0 = ((((beta * fr) * cx) * cy) * S) / r2;
+                                }
                                 if (rp.mis && depth < rp.max_depth) {
                                     // MIS against the cosine-sampling pdf of the
                                     // same direction; the last vertex samples no
@@ -1341,14 +1391,20 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
                     want_shadow = c0 > 0.0f;
                     for (uint32_t k = 0; k < sc.n_plights; ++k) {
                         float4 dk;
-                        want_shadow |= point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta, fr, dk) > 0.0f;
+                        want_shadow |= (RGB ? point_light_slot_rgb(sc, k, Px, Py, Pz, nsx, nsy, nsz, b3, fr3, dk)
+                                            : point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta, fr, dk)) > 0.0f;
                     }
                 }
                 bool cont = depth < rp.max_depth;
                 if (cont && depth >= rp.rr_start) {
-                    const float qs = fminf(1.0f, beta);
-                    if (u01(r0.w) >= qs) cont = false;
-                    else beta = beta / qs;
+                    // RGB: survival min(1, largest throughput channel).
+                    const float qs = fminf(1.0f, RGB ? fmaxf(b3.x, fmaxf(b3.y, b3.z)) : beta);
+                    if (u01(r0.w) >= qs) {
+                        cont = false;
+                    } else {
+                        beta = beta / qs;
+                        if (RGB) b3 = make_float3(b3.x / qs, b3.y / qs, b3.z / qs);
+                    }
                 }
                 if (cont) {
                     const uint4 r1 = rng_block(rp, pixel, sample, q, depth, 1);
@@ -1369,6 +1425,7 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
                     ndy = (ty * lx + by * ly) + nsy * lz;
                     ndz = (tz * lx + bz * ly) + nsz * lz;
                     beta = beta * alb;
+                    if (RGB) b3 = make_float3(b3.x * A3.x, b3.y * A3.y, b3.z * A3.z);
                     want_ext = true;
                 }
             }
@@ -1403,13 +1460,15 @@ __global__ __launch_bounds__(kShadeTB) void k_shade(Piece pc, DevScene sc, Rende
             if (c0 > 0.0f) sq.dir[se] = d0;
             for (uint32_t k = 0; k < sc.n_plights; ++k) {
                 float4 dk = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                const float ck = point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta_v, fr, dk);
+                const float ck = RGB ? point_light_slot_rgb(sc, k, Px, Py, Pz, nsx, nsy, nsz, b3v, fr3, dk)
+                                     : point_light_slot(sc, k, Px, Py, Pz, nsx, nsy, nsz, beta_v, fr, dk);
                 sq.c[(k + 1) * sq.cap + se] = ck;
                 if (ck > 0.0f) sq.dir[(k + 1) * sq.cap + se] = dk;
             }
         }
         if (want_ext) {
-            qout.o[xe] = make_float4(Px, Py, Pz, beta);
+            qout.o[xe] = make_float4(Px, Py, Pz, RGB ? b3.x : beta);
+            if (RGB) qout.bgb[xe] = make_float2(b3.y, b3.z);
             qout.d[xe] = make_float4(ndx, ndy, ndz, bitsf(pword));
             qout.skip[xe] = prim;
         }
@@ -2178,11 +2237,14 @@ void launch_shade(hipStream_t s, uint32_t blocks, const Piece &pc, const DevScen
 {
     // threads: a multiple of 64 up to kShadeTB (the kernel is block-size agnostic).
     if (adj)
-        hipLaunchKernelGGL(k_shade<true>, dim3(blocks), dim3(threads), 2 * adj->n_mat * sizeof(double), s, pc, sc,
-                           rp, qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj, hit_log);
+        hipLaunchKernelGGL((k_shade<true, false>), dim3(blocks), dim3(threads), 2 * adj->n_mat * sizeof(double), s,
+                           pc, sc, rp, qin, cnt_in, hit, qout, cnt_out, sq, cnt_sh, depth, *adj, hit_log);
+    else if (sc.rgb)
+        hipLaunchKernelGGL((k_shade<false, true>), dim3(blocks), dim3(threads), 0, s, pc, sc, rp, qin, cnt_in, hit,
+                           qout, cnt_out, sq, cnt_sh, depth, Adjoint{}, hit_log);
     else
-        hipLaunchKernelGGL(k_shade<false>, dim3(blocks), dim3(threads), 0, s, pc, sc, rp, qin, cnt_in, hit, qout,
-                           cnt_out, sq, cnt_sh, depth, Adjoint{}, hit_log);
+        hipLaunchKernelGGL((k_shade<false, false>), dim3(blocks), dim3(threads), 0, s, pc, sc, rp, qin, cnt_in, hit,
+                           qout, cnt_out, sq, cnt_sh, depth, Adjoint{}, hit_log);
 }
 
 void launch_accumulate(hipStream_t s, const Piece &pc, const RenderParams &rp, uint32_t *wf_n,
@@ -2338,7 +2400,7 @@ void kernel_occupancy(int *trace_blocks_per_cu, int *shade_blocks_per_cu)
     int a = 0, b = 0, c = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_trace_closest<false, false>, kTB, 0) != hipSuccess) a = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_trace_shadow<false, false, false>, kTB, 0) != hipSuccess) b = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade<false>, kShadeTB, 0) != hipSuccess) c = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_shade<false, false>, kShadeTB, 0) != hipSuccess) c = 1;
     *trace_blocks_per_cu = std::max(1, std::min(a, b));
     *shade_blocks_per_cu = std::max(1, c);
 }

@@ -207,6 +207,9 @@ DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBu
     sc.inst[1].n_lds = std::min(sc.inst[1].n_lds, lds_nodes);
     sc.mat = c->mat.as<const float2>();
     sc.plights = c->plights.as<const float4>();
+    sc.rgb = c->scene.rgb ? 1u : 0u;
+    sc.mat_rgb = c->scene.rgb ? c->mat_rgb.as<const float4>() : nullptr;
+    sc.plights_rgb = c->scene.rgb ? c->plights_rgb.as<const float4>() : nullptr;
     sc.n_plights = (uint32_t)c->scene.pl_int.size();
     sc.env = c->env.as<const float>();
     sc.env_res = c->scene.env_res;
@@ -339,7 +342,13 @@ static void trace_piece(evrt_ctx *c, const Piece &pc, const DevScene &sc, const 
     uint32_t *cnt = ln ? fb.cnt1.as<uint32_t>() : fb.cnt.as<uint32_t>();
     unsigned long long *stat = fb.stat.as<unsigned long long>();
     RayQueue q[2];
-    for (int k = 0; k < 2; ++k) q[k] = RayQueue{L.q_o[k].as<float4>(), L.q_d[k].as<float4>(), L.q_skip[k].as<uint32_t>()};
+    for (int k = 0; k < 2; ++k) {
+        q[k] = RayQueue{L.q_o[k].as<float4>(), L.q_d[k].as<float4>(), L.q_skip[k].as<uint32_t>(), nullptr};
+        if (sc.rgb) {
+            L.q_bgb[k].ensure(sizeof(float2) * (size_t)L.queue_cap);
+            q[k].bgb = L.q_bgb[k].as<float2>();
+        }
+    }
     ShadowQueue sq{L.sh_o.as<float4>(), L.sh_meta.as<uint32_t>(), L.sh_dir.as<float4>(), L.sh_c.as<float>(),
                    L.queue_cap};
     launch_raygen(s, pc, sc, rp, q[0], cnt);

@@ -50,7 +50,7 @@ def _batch_vs_pairs(rend, sc, P, times, **kw):
 
 
 @pytest.mark.parametrize("variant", ["default", "small_pieces", "split_samples", "fixed", "two_tailed", "mb8",
-                                     "key_base"])
+                                     "key_base", "rgb"])
 def test_batch_equals_single_pairs(rend, variant):
     P = dict(scenes.TINY_PARAMS)
     kw = {}
@@ -67,6 +67,8 @@ def test_batch_equals_single_pairs(rend, variant):
     elif variant == "key_base":
         kw = dict(key_base=300)
     sc = scenes.panning(scenes.tiny_box(width=32, height=24), 5, 2.0)
+    if variant == "rgb":
+        sc = scenes.colorize(sc, seed=9)
     _say(f"batch variant {variant}")
     b, pb, pp = _batch_vs_pairs(rend, sc, P, [0.0, 1.0, 2.0, 3.0, 4.0], **kw)
     # shared frames are traced once: fewer camera rays than the pairs
@@ -191,9 +193,12 @@ def test_moving_batch_equals_single_pairs(rend, variant):
     assert rend.frame_stats()["rounds"] >= 1
 
 
-def test_moving_batch_matches_oracle(rend):
+@pytest.mark.parametrize("rgb", [False, True])
+def test_moving_batch_matches_oracle(rend, rgb):
     P = dict(scenes.TINY_PARAMS)
     sc = scenes.moving_panning(24, 20, 4)
+    if rgb:
+        sc = scenes.colorize(sc, seed=11)
     rend.set_scene(sc)
     times = [0.0, 1.0, 2.0, 3.0]
     b = rend.render_event_batch(times, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], _opts(P))

@@ -144,6 +144,13 @@ PATH_CASES = {
     "lens_env": (lambda: scenes.lens_env(width=32, height=24), {**scenes.TINY_PARAMS, "max_depth": 5}, 0.0, 1.0),
     "lens_env_mis_nojitter": (lambda: scenes.lens_env(width=32, height=24),
                               {**scenes.TINY_PARAMS, "max_depth": 5, "mis": 1, "jitter": 0}, 0.0, 1.0),
+    # RGB radiance: per-channel throughput, luminance of every contribution.
+    "tiny_box_rgb": (lambda: scenes.colorize(scenes.tiny_box(), seed=2), scenes.TINY_PARAMS, 0.0, 1.0),
+    "soup_lights_rgb_mis": (lambda: scenes.colorize(scenes.triangle_soup(600, seed=5, moving=True, emitters=8,
+                                                                         width=24, height=20), seed=4),
+                            {**scenes.TINY_PARAMS, "max_depth": 5, "seed": 0x123456789, "mis": 1}, 0.0, 1.0),
+    "lens_env_rgb": (lambda: scenes.colorize(scenes.lens_env(width=32, height=24), seed=6),
+                     {**scenes.TINY_PARAMS, "max_depth": 5, "rr_start_depth": 2}, 0.0, 1.0),
 }
 
 
@@ -154,6 +161,8 @@ def test_render_paths_bit_exact(rend, torch_cuda, case):
     if case.startswith("soup_lights"):
         b_pos = np.array([[0.5, 3.0, 1.0], [-2.0, 1.0, 2.5]], np.float32)
         sc.pl_pos, sc.pl_intensity = b_pos, np.array([4.0, 2.5], np.float32)
+        if sc.albedo_rgb is not None:
+            sc.pl_rgb = np.array([[4.0, 1.0, 2.0], [0.5, 2.5, 6.0]], np.float32)
     rend.set_scene(sc)
     npx = sc.width * sc.height
     pixels = np.unique(np.concatenate([np.arange(0, npx, 7), [0, npx - 1]])).astype(np.uint32)
@@ -294,9 +303,10 @@ def _compare(g, r, pixels, C):
 
 @pytest.mark.parametrize("variant", ["default", "fixed", "ref_full", "two_tailed", "mean_only", "mb1", "mb8",
                                      "lds_treelet", "small_pieces", "split_samples", "welch", "welch_two_tailed",
-                                     "welch_ref_full", "mis", "normality", "normality_split"])
+                                     "welch_ref_full", "mis", "normality", "normality_split", "rgb",
+                                     "rgb_split"])
 def test_tiny_frame_parity(rend, torch_cuda, variant):
-    sc = scenes.tiny_box()
+    sc = scenes.colorize(scenes.tiny_box(), seed=7) if variant.startswith("rgb") else scenes.tiny_box()
     rend.set_scene(sc)
     params = dict(scenes.TINY_PARAMS)
     if variant == "fixed":
@@ -329,6 +339,8 @@ def test_tiny_frame_parity(rend, torch_cuda, variant):
         params["normality_alpha"] = 0.05
     elif variant == "normality_split":
         params.update(normality_alpha=0.05, ray_batch=512)   # moments over split sample ranges
+    elif variant == "rgb_split":
+        params.update(ray_batch=512, mis=1)
     _say(f"tiny frame variant={variant}")
     g, st = _frame(rend, sc, params, 0.0, 1.0)
     with oracle.Frame(sc, 0.0, 1.0) as f:

@@ -49,9 +49,12 @@ def _video_parity(g, v, pixels=None):
     return pol, npth
 
 
-def test_video_matches_oracle(rend):
+@pytest.mark.parametrize("rgb", [False, True])
+def test_video_matches_oracle(rend, rgb):
     P = dict(scenes.TINY_PARAMS)
     sc = scenes.tiny_box(width=24, height=20)
+    if rgb:
+        sc = scenes.colorize(sc, seed=13)
     rend.set_scene(sc)
     g = rend.render_event_video(TIMES, P["C"], P["alpha"], P["spp_init"], P["spp_batch"], P["spp_max"], _opts(P))
     v = oracle.render_video(sc, TIMES, oracle.make_params(**P))

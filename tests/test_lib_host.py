@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
     bound = {s[0] for s in ev.SIGNATURES}
     assert set(names) == bound
-    assert L.evrt_abi_version() == 5
+    assert L.evrt_abi_version() == 6
 
 
 def test_default_opts():
@@ -183,3 +183,45 @@ def test_bvh_structure_sensor_scene(host_ctx):
     # SAH cost in units of root-box traversals: a sane tree is far below
     # the brute-force cost n_tri.
     assert info["sah_cost"] < 200
+
+
+def test_rgb_scene_validation(host_ctx):
+    """RGB materials and point lights: channel ranges, lengths, RGB lights
+    only with RGB materials; an RGB scene commits and builds on the host
+    (emitters by luminance)."""
+    r = host_ctx
+    with pytest.raises(ev.EvrtError) as e:
+        r.scene_set_materials_rgb([[0.5, 1.0, 0.2]], [[0, 0, 0]])       # albedo channel >= 1
+    assert e.value.code == ev.EVRT_E_INVALID
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_materials_rgb([[0.5, 0.5, 0.2]], [[0, -1.0, 0]])
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_materials_rgb([[0.5, 0.5, 0.2]], [[0, np.inf, 0]])
+    with pytest.raises(ev.EvrtError):
+        r.scene_set_point_lights_rgb([[0, 1, 0]], [[1.0, -2.0, 0.5]])
+    sc = scenes.colorize(scenes.tiny_box(), seed=3)
+    r.set_scene(sc)
+    info = r.scene_info_at(0.0)
+    assert info["n_emit"] == 2
+    # RGB point lights with grey materials are refused at commit.
+    sc_grey = scenes.plane_point_light()
+    r.set_scene(sc_grey)
+    r.scene_set_point_lights_rgb(sc_grey.pl_pos, [[1.0, 2.0, 3.0]])
+    with pytest.raises(ev.EvrtError) as e:
+        r.scene_commit()
+    assert e.value.code == ev.EVRT_E_INVALID and "RGB" in str(e.value)
+    # ... and accepted once the materials are RGB.
+    r.scene_set_materials_rgb([[0.7, 0.2, 0.4]], [[0, 0, 0]])
+    r.scene_commit()
+
+
+def test_gradient_refuses_rgb(host_ctx):
+    r = host_ctx
+    r.set_scene(scenes.colorize(scenes.tiny_box(), seed=1))
+    L = ev.load_library()
+    o = ev.default_opts()
+    dummy = ctypes.c_void_p(16)
+    out = ev.DiffOut(dummy, dummy, None, None, None)
+    rc = L.evrt_event_loss_grad(r._h, 0.0, 1.0, 0.2, 0.05, 16, ctypes.byref(o), ctypes.byref(out), None)
+    assert rc == ev.EVRT_E_UNSUPPORTED
+    assert "grey" in L.evrt_last_error(r._h).decode()
