@@ -109,7 +109,8 @@ void camera_at(const SceneDesc &sd, double t, DevCamera &out);
 bool instances_static(const SceneDesc &sd, const double *times, uint32_t n);
 // True when every instance's keys hold one transform (no motion at all).
 bool scene_static(const SceneDesc &sd);
-// BVH2 over out.tri (binned SAH), LDS treelet of up to n_lds_max nodes first.
+// 4-wide BVH over out.tri (a binned-SAH binary tree collapsed two levels
+// at a time), breadth-first treelet of up to n_lds_max nodes first.
 void build_bvh(HostInstant &h, uint32_t n_lds_max, float pad);
 // Validates structural invariants of a built BVH; returns an empty string
 // when they hold.

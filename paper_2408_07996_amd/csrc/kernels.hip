@@ -1,14 +1,15 @@
 // kernels.hip -- gfx950 kernels of the adaptive event renderer.
 //
-// Wavefront path tracer for one piece of a sampling round (raygen, BVH2
-// closest-hit and any-hit traversal, shading with next-event estimation
-// and Russian roulette), the per-pixel FP64 Welford accumulator of the
-// mini-batch log-luminance, and the fused t-test / decision kernel with
-// wave-ballot compaction of the pixels that stay undecided.
+// Wavefront path tracer for one piece of a sampling round (raygen, 4-wide
+// BVH closest-hit and any-hit traversal, shading with next-event
+// estimation and Russian roulette, grey or RGB radiance), the per-pixel
+// FP64 Welford accumulator of the mini-batch log-luminance, and the fused
+// t-test / decision kernel with wave-ballot compaction of the pixels that
+// stay undecided.
 //
 // Floating point: the whole file is compiled without FMA contraction; the
 // only fused multiply-adds are the explicit ones in the (conservative) box
-// test.  Path arithmetic is FP32 in the order documented next to each
+// test, some of them mixed-precision (FP16 plane offsets).  Path arithmetic is FP32 in the order documented next to each
 // step; sin, cos and log are evaluated in FP64 (sin/cos rounded to FP32)
 // and statistics are FP64.
 #include <algorithm>
