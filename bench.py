@@ -51,8 +51,8 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "f8927dfeb2683a5745759c8a209acc1d7dc94114c9410b85ac9f450828f3e1a4",
-           "bytes_per_launch": 526564719.0,
+TRAFFIC = {"sources_sha256": "88abd59b08f46e79e873bb91cc82e02dee705557f886d6fb529c1316946d355f",
+           "bytes_per_launch": 526820590.0,
            "counters": {"k_trace_closest": {"valu_busy": 0.873, "valu_lane_utilization": 0.601}, "k_trace_shadow": {"valu_busy": 0.713, "valu_lane_utilization": 0.600}, "k_shade": {"valu_busy": 0.486, "valu_lane_utilization": 0.640}}}
 
 

@@ -414,15 +414,15 @@ def test_lens_env_frame_parity(rend, torch_cuda, variant):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("C", [0.15, 0.3])
-def test_sensor_subset_parity(rend, torch_cuda, C):
+@pytest.mark.parametrize("C,rgb", [(0.15, False), (0.3, False), (0.15, True)])
+def test_sensor_subset_parity(rend, torch_cuda, C, rgb):
     """The sensor workload (640x480, ~98k triangles, depth 8, 64/16/1024)
     at full size in the benchmark's launch configuration, compared on every
-    8th pixel in x and y (4,800 pixels)."""
-    sc = scenes.sensor()
+    8th pixel in x and y (4,800 pixels); also with RGB radiance."""
+    sc = scenes.colorize(scenes.sensor(), seed=1) if rgb else scenes.sensor()
     rend.set_scene(sc)
     params = {**scenes.SENSOR_PARAMS, "C": C}
-    _say(f"sensor frame C={C}")
+    _say(f"sensor frame C={C} rgb={rgb}")
     t = time.time()
     g, st = _frame(rend, sc, params, 0.0, 1.0)
     _say(f"  gpu frame {time.time() - t:.2f}s rounds={st['rounds']}")
