@@ -431,7 +431,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every pixel and sample is "
-              "independent, so a multi-GPU run would shard pixels, which this build does not do.",
+              "independent, so a multi-GPU run would shard pixels, which this renderer does not do.",
               file=sys.stderr)
         return 2
 

@@ -46,7 +46,7 @@ enum {
     EVRT_E_NOMEM = -2,       /* host or device allocation failed              */
     EVRT_E_DEVICE = -3,      /* HIP runtime error or no device in the context */
     EVRT_E_STATE = -4,       /* call out of order (e.g. render before commit) */
-    EVRT_E_UNSUPPORTED = -5  /* valid request that this build does not serve  */
+    EVRT_E_UNSUPPORTED = -5  /* valid request that the library does not serve */
 };
 
 /* Sampling modes (Sec. 3.2 and its ablation). */
