@@ -11,6 +11,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <future>
+#include <map>
 #include <thread>
 
 #include "evrt_host.h"
@@ -681,13 +683,69 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
 // full count fills the reference slot of every pixel; each later frame k is
 // sampled adaptively against the pixel's reference (frame keys key_base + k)
 // and replaces it where the frame fires an event.  Outputs frame-major.
+// Host builds of the instants a frame loop needs next, on worker threads
+// while the calling thread drives the device: at most `depth` frames ahead
+// (geometry that moves; a static scene shares one instant).  take() uploads
+// and caches a frame's instant, waiting for its build if needed; the
+// destructor waits for builds still running (their results are dropped).
+class InstantPrefetch {
+public:
+    InstantPrefetch(evrt_ctx *c, const double *times, uint32_t n, uint32_t depth)
+        : c_(c), times_(times), n_(n), depth_(c->static_geom ? 0u : depth)
+    {
+    }
+
+    std::shared_ptr<DevInstantBufs> take(uint32_t k, hipStream_t s, double *ms_build)
+    {
+        launch_upto(std::min(n_, k + 1 + depth_));
+        const double t = times_[k];
+        auto it = inflight_.find(t);
+        if (it == inflight_.end()) return get_instant(c_, t, s, ms_build);
+        const auto t0 = std::chrono::steady_clock::now();
+        std::shared_ptr<DevInstantBufs> bi = it->second.get();  // rethrows a build's error
+        inflight_.erase(it);
+        upload_instant(c_, *bi, s);
+        cache_insert(c_, t, bi);
+        if (ms_build)
+            *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return bi;
+    }
+
+private:
+    void launch_upto(uint32_t end)
+    {
+        for (; next_ < end; ++next_) {
+            const double t = times_[next_];
+            if (c_->cache.count(t) || inflight_.count(t)) continue;
+            const evrt_ctx *cc = c_;
+            inflight_[t] = std::async(std::launch::async, [cc, t] {
+                auto bi = std::make_shared<DevInstantBufs>();
+                build_host_instant(cc, t, bi->host);
+                return bi;
+            });
+        }
+    }
+
+    evrt_ctx *c_;
+    const double *times_;
+    uint32_t n_, depth_;
+    uint32_t next_ = 0;
+    std::map<double, std::future<std::shared_ptr<DevInstantBufs>>> inflight_;
+};
+
 void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, float alpha, uint32_t spp_init,
                   uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o, const evrt_frame_out &out,
                   hipStream_t s)
 {
     const auto wall0 = std::chrono::steady_clock::now();
     std::memset(&c->stats, 0, sizeof(c->stats));
-    auto g0 = get_instant(c, times[0], s, &c->stats.ms_build);
+    // The next frames' geometry is built on host threads while the device
+    // renders (a frame's host build costs about as much as its tracing on
+    // the sensor scene).  The cache keeps the frames in flight.
+    const uint32_t ahead = std::min(8u, std::max(1u, std::thread::hardware_concurrency() / 2));
+    c->cache_cap = std::max<size_t>(c->cache_cap, (size_t)ahead + 3);
+    InstantPrefetch pre(c, times, n_frames, ahead);
+    auto g0 = pre.take(0, s, &c->stats.ms_build);
     const DevScene sc0 = make_dev_scene(c, *g0, *g0, o.lds_nodes);
     const RenderParams rp0 = make_params(c, o);
     const uint32_t npx = sc0.width * sc0.height;
@@ -700,7 +758,7 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
     Profiler prof{c, o.profile != 0, 0, {}};
     trace_range(c, fb.act0.as<uint32_t>(), npx, 1, 0, 0, spp_max, sc0, rp0, o, s, prof);
     for (uint32_t k = 1; k < n_frames; ++k) {
-        auto gk = get_instant(c, times[k], s, &c->stats.ms_build);
+        auto gk = pre.take(k, s, &c->stats.ms_build);
         const DevScene sc = make_dev_scene(c, *gk, *gk, o.lds_nodes);
         evrt_render_opts ok = o;
         ok.key_base = o.key_base + k - 1;  // the second instant is frame key_base + k
