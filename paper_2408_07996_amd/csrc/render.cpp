@@ -199,6 +199,18 @@ void get_instants(evrt_ctx *c, const double *times, uint32_t n, hipStream_t s, d
         *ms_build += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
 }
 
+// The instants of a pair; two that both need building are built on two
+// host threads at once.
+static std::pair<std::shared_ptr<DevInstantBufs>, std::shared_ptr<DevInstantBufs>>
+get_pair(evrt_ctx *c, double t0, double t1, hipStream_t s, double *ms_build)
+{
+    const double tt[2] = {t0, t1};
+    get_instants(c, tt, 2, s, ms_build);
+    auto ga = get_instant(c, t0, s, ms_build);
+    auto gb = get_instant(c, t1, s, ms_build);
+    return {ga, gb};
+}
+
 DevScene make_dev_scene(evrt_ctx *c, const DevInstantBufs &a, const DevInstantBufs &b, uint32_t lds_nodes)
 {
     DevScene sc{};
@@ -655,8 +667,7 @@ void render_frame(evrt_ctx *c, double t0, double t1, float C, float alpha, uint3
 {
     const auto wall0 = std::chrono::steady_clock::now();
     std::memset(&c->stats, 0, sizeof(c->stats));
-    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
-    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    auto [ga, gb] = get_pair(c, t0, t1, s, &c->stats.ms_build);
     const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
     const uint32_t npx = sc.width * sc.height;
@@ -1090,8 +1101,7 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
                   uint32_t spp, const evrt_render_opts &o, float *L_out, hipStream_t s)
 {
     std::memset(&c->stats, 0, sizeof(c->stats));
-    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
-    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    auto [ga, gb] = get_pair(c, t0, t1, s, &c->stats.ms_build);
     const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
     trace_paths(c, sc, rp, o, n_pixels, pixels, spp, L_out, nullptr, s);
@@ -1105,8 +1115,7 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
                      const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s)
 {
     std::memset(&c->stats, 0, sizeof(c->stats));
-    auto ga = get_instant(c, t0, s, &c->stats.ms_build);
-    auto gb = get_instant(c, t1, s, &c->stats.ms_build);
+    auto [ga, gb] = get_pair(c, t0, t1, s, &c->stats.ms_build);
     const uint32_t npx = c->scene.cam.width * c->scene.cam.height;
     const uint32_t n_mat = (uint32_t)c->scene.albedo.size();
     const uint32_t mb = o.minibatch, m = spp / mb;
