@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <numeric>
 
 #include "evrt_host.h"
@@ -265,7 +266,16 @@ struct Builder {
     static constexpr uint32_t kLeafTarget = EVRT_LEAF_TARGET;
     static constexpr uint32_t kSahDepthLimit = 32;
 
-    int32_t build(uint32_t b, uint32_t e, uint32_t depth)
+    int32_t build(uint32_t b, uint32_t e, uint32_t depth) { return build_into(nodes, b, e, depth); }
+
+    // Subtrees of at least kParallelTris triangles in the top kParallelDepth
+    // levels build their left half on another host thread, into a vector of
+    // its own appended afterwards (ids shifted); the tree is the same as a
+    // serial build's, only its node numbering differs.
+    static constexpr uint32_t kParallelTris = 1u << 15;
+    static constexpr uint32_t kParallelDepth = 5;
+
+    int32_t build_into(std::vector<BNode> &nodes, uint32_t b, uint32_t e, uint32_t depth)
     {
         const int32_t id = (int32_t)nodes.size();
         nodes.emplace_back();
@@ -354,8 +364,27 @@ struct Builder {
                 return cx < cy || (cx == cy && x < y);
             });
         }
-        const int32_t l = build(b, mid, depth + 1);
-        const int32_t r = build(mid, e, depth + 1);
+        int32_t l, r;
+        if (n >= kParallelTris && depth < kParallelDepth) {
+            std::vector<BNode> left;
+            auto fut = std::async(std::launch::async, [this, &left, b, mid, depth] {
+                return build_into(left, b, mid, depth + 1);
+            });
+            r = build_into(nodes, mid, e, depth + 1);
+            const int32_t l_local = fut.get();
+            const int32_t off = (int32_t)nodes.size();
+            for (BNode nd : left) {
+                if (nd.count == 0) {
+                    nd.child[0] += off;
+                    nd.child[1] += off;
+                }
+                nodes.push_back(nd);
+            }
+            l = l_local + off;
+        } else {
+            l = build_into(nodes, b, mid, depth + 1);
+            r = build_into(nodes, mid, e, depth + 1);
+        }
         nodes[id].child[0] = l;
         nodes[id].child[1] = r;
         return id;
