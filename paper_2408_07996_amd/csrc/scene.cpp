@@ -4,6 +4,7 @@
 // a binned-SAH binary BVH collapsed into a 4-wide BVH whose top treelet is
 // laid out first for LDS staging.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <future>
@@ -274,6 +275,14 @@ struct Builder {
     // serial build's, only its node numbering differs.
     static constexpr uint32_t kParallelTris = 1u << 15;
     static constexpr uint32_t kParallelDepth = 5;
+    // Extra builder threads of the whole process at once (instants may be
+    // built on several host threads themselves).
+    static constexpr int kMaxBuildThreads = 16;
+    static std::atomic<int> &build_threads()
+    {
+        static std::atomic<int> n{0};
+        return n;
+    }
 
     int32_t build_into(std::vector<BNode> &nodes, uint32_t b, uint32_t e, uint32_t depth)
     {
@@ -365,9 +374,17 @@ struct Builder {
             });
         }
         int32_t l, r;
+        bool par = false;
         if (n >= kParallelTris && depth < kParallelDepth) {
+            if (build_threads().fetch_add(1) < kMaxBuildThreads) par = true;
+            else build_threads().fetch_sub(1);
+        }
+        if (par) {
             std::vector<BNode> left;
             auto fut = std::async(std::launch::async, [this, &left, b, mid, depth] {
+                struct Release {
+                    ~Release() { build_threads().fetch_sub(1); }
+                } release;
                 return build_into(left, b, mid, depth + 1);
             });
             r = build_into(nodes, mid, e, depth + 1);
