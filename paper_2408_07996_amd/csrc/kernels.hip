@@ -355,12 +355,14 @@ __device__ __forceinline__ float half_hi(uint32_t w)
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
 }
 
-// The same slab test on FP16 planes stored as offsets from the node origin
-// o: with B = o * inv - origin * inv (one fused product per axis), a plane
-// o + h enters as fma(h, inv, B), the FP16-to-FP32 conversion folded into
-// a mixed-precision FMA.  near/far hold the four children's planes of one
-// axis (child 2j in the low half of word j).  The second rounding (of B)
-// is far inside the host's box padding; the offsets are rounded outward.
+// The same slab test on FP16 planes stored as offsets h from the node
+// origin p: with B = p inv - o inv (o the ray origin; one fused product per
+// axis), the plane p + h enters as fma(h, inv, B), the FP16-to-FP32
+// conversion folded into a mixed-precision FMA.  (p, h and inv carry the
+// tree's power-of-two plane scale, which cancels exactly.)  near/far hold
+// the four children's planes of one axis (child 2j in the low half of word
+// j).  The second rounding (of B) is far inside the host's box padding;
+// the offsets are rounded outward.
 __device__ __forceinline__ void box4h(const TRay &r, float4 org, uint2 nx, uint2 fx, uint2 ny, uint2 fy,
                                       uint2 nz, uint2 fz, float tmin, float tfar, uint32_t (&k)[4])
 {
