@@ -632,6 +632,7 @@ def main() -> int:
                       speedup_equal_quality=s_eq2, quality=q2)
 
     cpu = None
+    oracle_match = None
     if not args.no_cpu:
         import oracle
         host = host_cpu()
@@ -641,8 +642,20 @@ def main() -> int:
         print(f"[bench] CPU oracle on {len(px)} pixels, {threads} threads", file=sys.stderr, flush=True)
         with oracle.Frame(sc, 0.0, 1.0) as f:
             tc = time.perf_counter()
-            f.render(oracle.make_params(**P), px, threads=threads)
+            ro = f.render(oracle.make_params(**P), px, threads=threads)
             t_cpu = time.perf_counter() - tc
+        # The timed frame against the oracle on the same pixels: decisions
+        # within the exemption band of a critical value may go either way.
+        ok = ~ro["near_crit"]
+        g_pol = adaptive_map.reshape(-1)[px]
+        g_n = adaptive_paths.reshape(-1)[px]
+        g_mean = out["mean"].cpu().numpy().reshape(-1, 2)[px]
+        same_n = g_n == ro["n_paths"]
+        mean_err = np.abs(g_mean[same_n] - ro["mean"][same_n]) / np.maximum(1.0, np.abs(ro["mean"][same_n]))
+        oracle_match = dict(pixels=int(len(px)), exempt=int((~ok).sum()),
+                            polarity_mismatch=int((g_pol[ok] != ro["polarity"][ok]).sum()),
+                            n_paths_mismatch=int((g_n[ok] != ro["n_paths"][ok]).sum()),
+                            max_mean_rel_err=float(mean_err.max(initial=0.0)))
         s_per_frame = t_cpu * sc.n_pixels / len(px)
         # The tiny workload's full frame, not extrapolated.
         tiny = scenes.tiny_box()
@@ -711,6 +724,7 @@ def main() -> int:
             "counters": counters,
         },
         "cpu_baseline": cpu,
+        "oracle_match": oracle_match,
         "paper_context": PAPER_CONTEXT,
         "scene_build_and_warmup_s": build_ms,
     }
