@@ -241,13 +241,24 @@ def bench_tiny(ev, scenes, steps: int = 20) -> dict:
 
     dt, out, st = run(ev.MODE_ADAPTIVE_1T)
     dtf, _, _ = run(ev.MODE_FIXED)
+    # The timed frame against the oracle's full frame.
+    import oracle
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        ro = f.render(oracle.make_params(**P), threads=min(HOST_SHARE_THREADS, os.cpu_count() or 1))
+    ok = ~ro["near_crit"]
+    g_pol = out["polarity"].cpu().numpy()
+    g_n = out["n_paths"].cpu().numpy()
+    match = dict(pixels=int(sc.n_pixels), exempt=int((~ok).sum()),
+                 polarity_mismatch=int((g_pol[ok] != ro["polarity"][ok]).sum()),
+                 n_paths_mismatch=int((g_n[ok] != ro["n_paths"][ok]).sum()))
     rays = st["camera_rays"] + st["extension_rays"] + st["shadow_rays"]
     res = dict(workload=f"tiny: {sc.width}x{sc.height}, {sc.n_tri_world} triangles, depth {P['max_depth']}, "
                         f"spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}, C {P['C']}",
                frames_per_s=1.0 / dt, ms_per_frame=1000.0 * dt, rounds=st["rounds"], rays_per_s=rays / dt,
                fixed_frames_per_s=1.0 / dtf, speedup_vs_fixed_spp_max=dtf / dt,
                stop_evidence=stop_evidence(out["n_paths"].cpu().numpy(), out["polarity"].cpu().numpy(),
-                                           P["spp_init"], P["spp_max"]))
+                                           P["spp_init"], P["spp_max"]),
+               oracle_match=match)
     r.close()
     return res
 
