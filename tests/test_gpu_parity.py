@@ -126,6 +126,52 @@ def test_trace_rays_match_oracle_scaled_scenes(rend, torch_cuda, extent, size):
             assert hits > n // 50
 
 
+@pytest.mark.parametrize("y,scale", [(0.0, 1.0), (1000.0, 1.0), (0.0, 5e4)])
+def test_trace_rays_match_oracle_flat_grid(rend, torch_cuda, y, scale):
+    """A flat grid (every box of zero height before padding), near and far
+    from the origin and wider than the FP16 range: ray queries bit-exact."""
+    n = 24
+    b = scenes.SceneBuilder()
+    m = b.material(0.5)
+    xs = np.linspace(-scale, scale, n + 1)
+    v = np.array([[x, y, z] for z in xs for x in xs], np.float32)
+    t = []
+    for j in range(n):
+        for i in range(n):
+            a = j * (n + 1) + i
+            t += [[a, a + 1, a + n + 2], [a, a + n + 2, a + n + 1]]
+    b.static(b.mesh(v, np.array(t), m))
+    b.set_camera(8, 8, 40.0, [0.0], [[0, y + 3 * scale, 3 * scale, 0, y, 0, 0, 1, 0]])
+    sc = b.build()
+    rend.set_scene(sc)
+    rng = np.random.default_rng(91)
+    k = 3000
+    o = np.stack([rng.uniform(-1.2 * scale, 1.2 * scale, k), y + rng.uniform(-scale, scale, k),
+                  rng.uniform(-1.2 * scale, 1.2 * scale, k)], 1).astype(np.float32)
+    tgt = np.stack([rng.uniform(-scale, scale, k), np.full(k, y), rng.uniform(-scale, scale, k)], 1)
+    d = np.where(rng.random((k, 1)) < 0.7, tgt - o, rng.normal(size=(k, 3)))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    tmin = np.full(k, 1e-4 * max(1.0, scale), np.float32)
+    tmax = np.full(k, np.inf, np.float32)
+    skip = np.full(k, ev.NO_PRIM, np.uint32)
+    rays = np.concatenate([o, tmin[:, None], d, tmax[:, None]], axis=1)
+    _say(f"trace_rays flat grid y={y} scale={scale}")
+    tt, pp = rend.trace_rays(0.0, rays, skip)
+    anyh = rend.trace_rays(0.0, rays, skip, any_hit=True)
+    tt, pp, anyh = tt.cpu().numpy(), pp.cpu().numpy().view(np.uint32), anyh.cpu().numpy()
+    bad = hits = 0
+    with oracle.Frame(sc, 0.0, 0.0) as f:
+        for i in range(k):
+            hit, t_ref, p_ref = f.closest_hit(0, o[i], d[i], tmin=tmin[i], tmax=tmax[i], brute=True)
+            hits += hit
+            if p_ref != pp[i] or (hit and t_ref != tt[i]):
+                bad += 1
+            if bool(anyh[i]) != f.any_hit(0, o[i], d[i], tmin=tmin[i], tmax=tmax[i], brute=True):
+                bad += 1
+    assert bad == 0
+    assert hits > k // 4
+
+
 # ---------------------------------------------------------------------------
 # Per-path radiance.
 

@@ -225,3 +225,34 @@ def test_gradient_refuses_rgb(host_ctx):
     rc = L.evrt_event_loss_grad(r._h, 0.0, 1.0, 0.2, 0.05, 16, ctypes.byref(o), ctypes.byref(out), None)
     assert rc == ev.EVRT_E_UNSUPPORTED
     assert "grey" in L.evrt_last_error(r._h).decode()
+
+
+def _flat_grid(n=40, y=0.0, scale=1.0):
+    """n x n quads in the plane y (every box flat in y)."""
+    b = scenes.SceneBuilder()
+    m = b.material(0.5)
+    xs = np.linspace(-scale, scale, n + 1)
+    v = np.array([[x, y, z] for z in xs for x in xs], np.float32)
+    t = []
+    for j in range(n):
+        for i in range(n):
+            a = j * (n + 1) + i
+            t += [[a, a + 1, a + n + 2], [a, a + n + 2, a + n + 1]]
+    b.static(b.mesh(v, np.array(t), m))
+    b.set_camera(8, 8, 40.0, [0.0], [[0, 3 * scale, 3 * scale, 0, 0, 0, 0, 1, 0]])
+    return b.build()
+
+
+@pytest.mark.parametrize("make", [lambda: _flat_grid(), lambda: _flat_grid(y=1000.0),
+                                  lambda: _flat_grid(scale=1e-3), lambda: _flat_grid(scale=5e4),
+                                  lambda: scenes.triangle_soup(800, seed=9, extent=1e-3, size=1e-4),
+                                  lambda: scenes.triangle_soup(800, seed=10, extent=3e6, size=1.0)])
+def test_bvh_structure_flat_and_extreme_scales(host_ctx, make):
+    """Flat boxes (zero extent on one axis), scenes far from the origin,
+    tiny and huge extents: the host build encodes every plane within the
+    FP16 range (with the tree's plane scale) and the structural check, which
+    decodes the planes, holds."""
+    sc = make()
+    host_ctx.set_scene(sc)
+    info = host_ctx.scene_info_at(0.0)
+    assert info["n_tri"] == sc.n_tri_world and info["n_nodes"] >= 1
