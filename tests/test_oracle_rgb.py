@@ -46,11 +46,16 @@ def test_rgb_furnace_nee_off_is_exact(D):
     p = oracle.make_params(nee=0, max_depth=D, rr_start_depth=D + 10)
     expect = float(W709 @ (Le * (1 - a ** D) / (1 - a)))
     with oracle.Frame(sc, 0, 0) as f:
-        L = _all_paths(f, p, range(0, 144, 7), 64).astype(np.float64)
-    err = np.abs(L - expect) / expect
-    # As for the grey furnace: the rare corner leak loses light, never adds.
-    assert (err <= 1e-5).mean() > 0.995
-    assert (L <= expect * (1 + 1e-5)).all()
+        L = _all_paths(f, p, range(144), 512).astype(np.float64)
+    exact = np.abs(L - expect) <= 1e-5 * expect
+    # As for the grey furnace, every other path left the box through a
+    # corner gap after j < D vertices and carries the first j terms.
+    partial = np.array([float(W709 @ (Le * (1 - a ** j) / (1 - a))) for j in range(1, D)])
+    for v in L[~exact]:
+        assert np.abs(partial - v).min() <= 1e-5 * expect, v
+    assert (~exact).sum() <= 1e-3 * L.size
+    if D == 1:
+        assert exact.all()
 
 
 def test_rgb_furnace_nee_and_roulette_unbiased():
@@ -221,8 +226,11 @@ def test_rgb_roulette_survival_is_largest_channel():
         L = _all_paths(f, p, range(64), 128).astype(np.float64).reshape(-1)
     is_low = np.abs(L - low) <= 1e-5 * low
     is_high = np.abs(L - high) <= 1e-5 * high
-    # (the rare corner leak of the furnace aside)
-    assert (is_low | is_high).mean() > 0.995
+    # Any other path left the box through a corner gap after its first
+    # vertex and carries Y(Le) alone (about 1e-4 of the paths).
+    gap = np.abs(L - float(W709 @ Le)) <= 1e-5 * low
+    assert (is_low | is_high | gap).all()
+    assert gap.sum() <= 1e-3 * len(L)
     frac = is_high.sum() / (is_low | is_high).sum()
     assert abs(frac - q) < 4 * math.sqrt(q * (1 - q) / len(L)), frac
 
