@@ -337,7 +337,12 @@ int evrt_get_frame_stats(const evrt_ctx *ctx, evrt_frame_stats *out);
  * dz, tmax); skip: device uint32[n] primitive to ignore (0xffffffff: none)
  * or NULL.  any_hit = 0: t_out[i] = closest distance and prim_out[i] = its
  * primitive, (tmax, 0xffffffff) when nothing is hit; any_hit = 1: prim_out[i]
- * = 1 if anything is hit in (tmin, tmax) else 0, t_out unused (may be NULL). */
+ * = 1 if anything is hit in (tmin, tmax) else 0, t_out unused (may be NULL).
+ * Results are exact (the lexicographic minimum over all triangles) for ray
+ * origins within the scene's coordinate range (the largest |coordinate| of
+ * its vertices, camera eye and point lights at time t): the BVH's box
+ * padding, a fixed fraction of that range, covers the rounding of the box
+ * test for such rays only; an origin far outside it may miss hits. */
 int evrt_trace_rays(evrt_ctx *ctx, double t, uint32_t n, const float *rays,
                     const uint32_t *skip, int any_hit, float *t_out, uint32_t *prim_out,
                     void *stream);
