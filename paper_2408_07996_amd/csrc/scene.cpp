@@ -168,11 +168,17 @@ float bvh_padding(const SceneDesc &sd, const HostInstant &a, const HostInstant &
     float mx = 0.0f;
     for (float v : a.tri) mx = std::max(mx, std::fabs(v));
     for (float v : b.tri) mx = std::max(mx, std::fabs(v));
-    // Ray origins on a thin lens lie within its radius of the eye.
+    // Ray origins on a thin lens lie within its radius of the eye.  The eye
+    // moves on straight segments between the camera keys, so the keys bound
+    // it at every time: one BVH serves all times of a scene whose instances
+    // do not move.
     for (int c = 0; c < 3; ++c) {
         mx = std::max(mx, std::fabs(a.cam.eye[c]) + sd.lens_radius);
         mx = std::max(mx, std::fabs(b.cam.eye[c]) + sd.lens_radius);
     }
+    for (size_t k = 0; 9 * k + 2 < sd.cam.elu.size(); ++k)
+        for (int c = 0; c < 3; ++c)
+            mx = std::max(mx, (float)std::fabs(sd.cam.elu[9 * k + c]) + sd.lens_radius);
     for (float v : sd.pl_pos) mx = std::max(mx, std::fabs(v));
     return std::ldexp(mx + 1.0f, -16);
 }

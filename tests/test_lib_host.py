@@ -1,6 +1,7 @@
 """Host-side checks of libevrt.so that need no GPU: exported symbols,
 argument validation on a host-only context, the critical-value quantile."""
 import ctypes
+import dataclasses
 import math
 import os
 import re
@@ -169,6 +170,20 @@ def test_bvh_structure_on_host(host_ctx, make):
         else:
             assert info["n_nodes"] == 0 and info["depth"] == 0  # the root is one leaf
         assert info["depth"] <= 32
+
+
+def test_box_padding_covers_every_camera_key(host_ctx):
+    """A scene whose instances do not move shares one BVH for all times, so
+    its box padding, 2^-16 (largest |coordinate| + 1), covers the eye at
+    every camera key, not only the eye at the time of the build."""
+    sc = scenes.tiny_box()
+    far = np.array(sc.cam_elu[0], np.float64)
+    far[:3] = (0.0, 1.0, 5000.0)
+    sc = dataclasses.replace(sc, cam_t=np.array([0.0, 1.0]), cam_elu=np.stack([sc.cam_elu[0], far]))
+    host_ctx.set_scene(sc)
+    pads = [host_ctx.scene_info_at(t)["box_pad"] for t in (0.0, 0.5, 1.0)]
+    assert pads[0] == pads[1] == pads[2]
+    assert pads[0] >= 2.0 ** -16 * 5001.0
 
 
 @pytest.mark.slow
