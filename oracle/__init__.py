@@ -122,6 +122,9 @@ def lib():
                                   ctypes.c_float, ctypes.c_uint32, ctypes.c_int, _f32p, _u32p]
     L.evo_any_hit.argtypes = [ctypes.c_void_p, ctypes.c_int, _f32p, _f32p, ctypes.c_float,
                               ctypes.c_float, ctypes.c_uint32, ctypes.c_int]
+    L.evo_ray_queries.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, _f32p, _f32p, _f32p, _f32p,
+                                  _u32p, ctypes.c_int, ctypes.c_int, _f32p, _u32p]
+    L.evo_ray_queries.restype = None
     L.evo_path_radiance.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32,
                                     ctypes.c_int, ctypes.c_uint32]
     L.evo_path_radiance.restype = ctypes.c_float
@@ -355,6 +358,24 @@ class Frame:
         return bool(lib().evo_any_hit(self._frame, int(instant), _ptr(o, ctypes.c_float),
                                       _ptr(d, ctypes.c_float), float(tmin), float(tmax), int(skip),
                                       int(bool(brute))))
+
+    def ray_queries(self, instant, o, d, tmin, tmax, skip, any_hit=False, brute=False):
+        """closest_hit (t, primitive arrays) or any_hit (0/1 array) for n rays
+        at once: o, d [n, 3]; tmin, tmax, skip [n]."""
+        o = np.ascontiguousarray(o, np.float32).reshape(-1, 3)
+        d = np.ascontiguousarray(d, np.float32).reshape(-1, 3)
+        n = len(o)
+        tmin = np.ascontiguousarray(np.broadcast_to(np.asarray(tmin, np.float32), (n,)))
+        tmax = np.ascontiguousarray(np.broadcast_to(np.asarray(tmax, np.float32), (n,)))
+        skip = np.ascontiguousarray(np.broadcast_to(np.asarray(skip, np.uint32), (n,)))
+        assert d.shape == o.shape
+        t = np.zeros(n, np.float32)
+        p = np.zeros(n, np.uint32)
+        lib().evo_ray_queries(self._frame, int(instant), n, _ptr(o, ctypes.c_float), _ptr(d, ctypes.c_float),
+                              _ptr(tmin, ctypes.c_float), _ptr(tmax, ctypes.c_float), _ptr(skip, ctypes.c_uint32),
+                              int(bool(any_hit)), int(bool(brute)), _ptr(t, ctypes.c_float),
+                              _ptr(p, ctypes.c_uint32))
+        return p if any_hit else (t, p)
 
     def camera_ray(self, params: Params, pixel: int, instant: int, sample: int):
         """(origin, unit direction) of a path sample's camera ray."""

@@ -141,6 +141,12 @@ int evo_closest_hit(const evo_frame *f, int instant, const float o[3], const flo
                     float *t_out, uint32_t *prim_out);
 int evo_any_hit(const evo_frame *f, int instant, const float o[3], const float d[3],
                 float tmin, float tmax, uint32_t skip, int brute);
+/* The two queries above for n rays (o, d: [n][3]; tmin, tmax, skip: [n]):
+ * any = 0 stores the closest (t, primitive), any = 1 stores 1 or 0 in
+ * prim_out (t_out unused). */
+void evo_ray_queries(const evo_frame *f, int instant, uint32_t n, const float *o, const float *d,
+                     const float *tmin, const float *tmax, const uint32_t *skip, int any, int brute,
+                     float *t_out, uint32_t *prim_out);
 
 float evo_path_radiance(const evo_frame *f, const evo_params *p, uint32_t pixel,
                         int instant, uint32_t sample);

@@ -389,3 +389,18 @@ int evo_any_hit(const evo_frame *f, int instant, const float o[3], const float d
     evo__ray_setup(&r, o, d);
     return evo__any(f, instant, &r, tmin, tmax, skip, brute);
 }
+
+void evo_ray_queries(const evo_frame *f, int instant, uint32_t n, const float *o, const float *d,
+                     const float *tmin, const float *tmax, const uint32_t *skip, int any, int brute,
+                     float *t_out, uint32_t *prim_out)
+{
+    for (uint32_t i = 0; i < n; ++i) {
+        if (any) {
+            prim_out[i] = (uint32_t)evo_any_hit(f, instant, o + 3 * (size_t)i, d + 3 * (size_t)i, tmin[i], tmax[i],
+                                                skip[i], brute);
+        } else {
+            evo_closest_hit(f, instant, o + 3 * (size_t)i, d + 3 * (size_t)i, tmin[i], tmax[i], skip[i], brute,
+                            &t_out[i], &prim_out[i]);
+        }
+    }
+}

@@ -40,6 +40,34 @@ def test_bvh_equals_brute_force(seed):
                             == f.any_hit(inst, o[k], d[k], tmax=tmax, skip=skip, brute=False))
 
 
+def test_bvh_equals_brute_force_million_rays():
+    """The oracle's BVH against its brute force on 10^6 rays (the batched
+    query): 250,000 random and 250,000 aimed at vertices and edge midpoints
+    per instant of a moving 300-triangle soup, a third of them skipping a
+    primitive; closest hits bit for bit, any-hit answers under random tmax."""
+    sc = scenes.triangle_soup(300, seed=7, moving=True)
+    rng = np.random.default_rng(107)
+    n = 250_000
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        for inst in (0, 1):
+            tri, _ = f.world_tris(inst)
+            pts = np.concatenate([tri.reshape(-1, 3), 0.5 * (tri[:, 0] + tri[:, 1])])
+            o1, d1 = _random_rays(rng, n)
+            o2, d2 = _random_rays(rng, n, targets=pts)
+            o, d = np.concatenate([o1, o2]), np.concatenate([d1, d2])
+            skip = np.where(np.arange(2 * n) % 3 == 0, rng.integers(0, 300, 2 * n), oracle.NO_PRIM).astype(np.uint32)
+            tmin = np.full(2 * n, 1e-4, np.float32)
+            ta, pa = f.ray_queries(inst, o, d, tmin, np.inf, skip, brute=True)
+            tb, pb = f.ray_queries(inst, o, d, tmin, np.inf, skip, brute=False)
+            np.testing.assert_array_equal(pa, pb)
+            np.testing.assert_array_equal(ta.view(np.uint32), tb.view(np.uint32))
+            assert 0.1 < (pa != oracle.NO_PRIM).mean() < 0.9
+            tmax = rng.uniform(0.5, 6.0, 2 * n).astype(np.float32)
+            aa = f.ray_queries(inst, o, d, tmin, tmax, skip, any_hit=True, brute=True)
+            ab = f.ray_queries(inst, o, d, tmin, tmax, skip, any_hit=True, brute=False)
+            np.testing.assert_array_equal(aa, ab)
+
+
 def _closed_sphere(subdiv=2):
     b = scenes.SceneBuilder()
     m = b.material(0.5)
