@@ -93,6 +93,36 @@ def test_trace_rays_match_oracle(rend, torch_cuda, seed):
             assert bad == 0
 
 
+def test_trace_rays_match_oracle_million_rays(rend, torch_cuda):
+    """10^6 ray queries (500,000 per instant of a moving 400-triangle soup,
+    half aimed at vertices and edge midpoints, 30 % with a finite tmax and
+    30 % skipping a primitive) against the oracle's brute force: closest
+    hits and any-hit answers bit for bit."""
+    sc = scenes.triangle_soup(400, seed=2, moving=True)
+    rend.set_scene(sc)
+    rng = np.random.default_rng(52)
+    n = 500_000
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        for inst, t in ((0, 0.0), (1, 1.0)):
+            _say(f"trace_rays million t={t}")
+            tri, _ = f.world_tris(inst)
+            o, d = _rays_for(tri, rng, n, 3.0)
+            tmin = np.full(n, 1e-4, np.float32)
+            tmax = np.where(rng.random(n) < 0.3, rng.uniform(0.5, 5, n), np.inf).astype(np.float32)
+            skip = np.where(rng.random(n) < 0.3, rng.integers(0, 400, n), ev.NO_PRIM).astype(np.uint32)
+            rays = np.concatenate([o, tmin[:, None], d, tmax[:, None]], axis=1)
+            tt, pp = rend.trace_rays(t, rays, skip)
+            anyh = rend.trace_rays(t, rays, skip, any_hit=True)
+            tt, pp, anyh = tt.cpu().numpy(), pp.cpu().numpy().view(np.uint32), anyh.cpu().numpy()
+            t_ref, p_ref = f.ray_queries(inst, o, d, tmin, tmax, skip, brute=True)
+            a_ref = f.ray_queries(inst, o, d, tmin, tmax, skip, any_hit=True, brute=True)
+            np.testing.assert_array_equal(pp, p_ref)
+            hit = p_ref != ev.NO_PRIM
+            np.testing.assert_array_equal(tt[hit].view(np.uint32), t_ref[hit].view(np.uint32))
+            np.testing.assert_array_equal(anyh.astype(np.uint32) != 0, a_ref != 0)
+            assert 0.1 < hit.mean() < 0.9
+
+
 @pytest.mark.parametrize("extent,size", [(3.0e4, 6.0e3), (1.0e7, 2.0e6), (500.0, 1.0e-5)])
 def test_trace_rays_match_oracle_scaled_scenes(rend, torch_cuda, extent, size):
     """Scenes wider than the FP16 plane range (a plane scale of 2^1 and
