@@ -490,6 +490,29 @@ def test_lens_env_frame_parity(rend, torch_cuda, variant):
 
 
 @pytest.mark.slow
+def test_largest_frame_parity(rend, torch_cuda):
+    """The largest image the library accepts, 16384 x 16384 = 2^28 pixels
+    (tiny box scene, spp 8/8/16, depth 2): every 256th pixel in x and y
+    (4,096 pixels, sampled on the device) against the oracle."""
+    w = h = 16384
+    sc = scenes.tiny_box(width=w, height=h)
+    rend.set_scene(sc)
+    params = {**scenes.TINY_PARAMS, "spp_init": 8, "spp_batch": 8, "spp_max": 16, "max_depth": 2}
+    _say("largest frame 16384x16384")
+    t = time.time()
+    out = rend.render_event_frame(0.0, 1.0, params["C"], params["alpha"], params["spp_init"], params["spp_batch"],
+                                  params["spp_max"], opts=_opts_from(params))
+    px = scenes.subset_every(w, h, 256)
+    idx = torch_cuda.from_numpy(px.astype(np.int64)).cuda()
+    g = {k: v[idx].cpu().numpy() for k, v in out.items()}
+    del out
+    _say(f"  gpu frame {time.time() - t:.2f}s rounds={rend.frame_stats()['rounds']}")
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        r = f.render(oracle.make_params(**params), px)
+    _compare(g, r, np.arange(len(px)), params["C"])
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("C,rgb", [(0.15, False), (0.3, False), (0.15, True)])
 def test_sensor_subset_parity(rend, torch_cuda, C, rgb):
     """The sensor workload (640x480, ~98k triangles, depth 8, 64/16/1024)

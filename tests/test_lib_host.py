@@ -172,6 +172,15 @@ def test_bvh_structure_on_host(host_ctx, make):
         assert info["depth"] <= 32
 
 
+def test_image_size_limit(host_ctx):
+    """2^28 pixels is the largest image: 16384 x 16384 commits, one more
+    column is refused before any work."""
+    host_ctx.set_scene(scenes.tiny_box(width=16384, height=16384))
+    with pytest.raises(ev.EvrtError) as e:
+        host_ctx.set_scene(scenes.tiny_box(width=16385, height=16384))
+    assert e.value.code == ev.EVRT_E_UNSUPPORTED
+
+
 def test_box_padding_covers_every_camera_key(host_ctx):
     """A scene whose instances do not move shares one BVH for all times, so
     its box padding, 2^-16 (largest |coordinate| + 1), covers the eye at
