@@ -490,6 +490,31 @@ def test_lens_env_frame_parity(rend, torch_cuda, variant):
 
 
 @pytest.mark.slow
+def test_largest_sample_counts(rend, torch_cuda):
+    """Fixed-count frames of a 4 x 4 tiny box at 2^22 paths per pixel and
+    instant against the oracle (pixel 5), and at the largest count, 2^24
+    (sample ranges split over pieces): the counts, and mean logL within 5
+    standard errors of the 2^22 result."""
+    sc = scenes.tiny_box(width=4, height=4)
+    rend.set_scene(sc)
+    res = {}
+    for spp in (1 << 22, 1 << 24):
+        params = {**scenes.TINY_PARAMS, "spp_init": spp, "spp_batch": 16, "spp_max": spp, "mode": ev.MODE_FIXED}
+        _say(f"fixed frame at {spp} paths per pixel")
+        g, _ = _frame(rend, sc, params, 0.0, 1.0)
+        assert (g["n_paths"].astype(np.int64) == spp).all()
+        res[spp] = g
+    params = {**scenes.TINY_PARAMS, "spp_init": 1 << 22, "spp_batch": 16, "spp_max": 1 << 22, "mode": ev.MODE_FIXED}
+    px = np.array([5], np.uint32)
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        r = f.render(oracle.make_params(**params), px)
+    _compare(res[1 << 22], r, px, params["C"])
+    m22, m24 = res[1 << 22]["mean"], res[1 << 24]["mean"]
+    se = np.sqrt(res[1 << 22]["var"] / ((1 << 22) // params["minibatch"]))
+    assert (np.abs(m24 - m22) <= 5 * se + 1e-12).all()
+
+
+@pytest.mark.slow
 def test_largest_frame_parity(rend, torch_cuda):
     """The largest image the library accepts, 16384 x 16384 = 2^28 pixels
     (tiny box scene, spp 8/8/16, depth 2): every 256th pixel in x and y
