@@ -319,6 +319,61 @@ def bench_sensitivity(ev, scenes, C: float = 0.15) -> dict:
     return dict(workload=f"sensor, C {C}, spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}", rows=rows)
 
 
+def bench_scene_variants(ev, scenes, C: float = 0.15) -> dict:
+    """Where the equal-quality speed-up comes from: the sensor workload and
+    variants of it with one moving sphere instead of twenty and with a
+    uniform grey sky as extra light (fewer dark, noisy pixels).  Per
+    variant: adaptive and fixed spp_max frame times, S_paper, polarity F1
+    of the adaptive map against a 4 x spp_max fixed reference, N_eq and
+    S_eq, and the stop evidence with its bound."""
+    import torch
+    P = scenes.SENSOR_PARAMS
+    base = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
+                log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
+    rows = []
+    for name, kw in (("twenty moving spheres", {}), ("one moving sphere", dict(n_moving=1)),
+                     ("sky 1.0", dict(sky=1.0)), ("one moving sphere, sky 1.0", dict(n_moving=1, sky=1.0)),
+                     ("one moving sphere, sky 3.0", dict(n_moving=1, sky=3.0))):
+        print(f"[bench] scene variant: {name}", file=sys.stderr, flush=True)
+        r = ev.Renderer(0)
+        r.set_scene(scenes.sensor(**kw))
+
+        def timed(mode, spp_max, reps=2):
+            args = (0.0, 1.0, C, P["alpha"], min(P["spp_init"], spp_max), P["spp_batch"], spp_max,
+                    dict(base, mode=mode))
+            out = r.render_event_frame(*args, extras=False)
+            torch.cuda.synchronize()
+            if reps == 0:
+                return 0.0, out
+            t = time.perf_counter()
+            for _ in range(reps):
+                out = r.render_event_frame(*args, extras=False)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps, out
+
+        ta, out = timed(ev.MODE_ADAPTIVE_1T, P["spp_max"], reps=3)
+        tf, _ = timed(ev.MODE_FIXED, P["spp_max"])
+        _, ref = timed(ev.MODE_FIXED, 4 * P["spp_max"], reps=0)
+        ref_map = ref["polarity"].cpu().numpy()
+        amap = out["polarity"].cpu().numpy()
+        f1 = polarity_f1(amap, ref_map)
+        ladder, n_eq = {}, None
+        for n in (64, 128, 256, 512, 1024, 2048):
+            tn, fo = timed(ev.MODE_FIXED, n, reps=1)
+            ladder[n] = (tn, polarity_f1(fo["polarity"].cpu().numpy(), ref_map))
+            if ladder[n][1] >= f1:
+                n_eq = n
+                break
+        se = stop_evidence(out["n_paths"].cpu().numpy().astype(np.int64), amap, P["spp_init"], P["spp_max"])
+        rows.append(dict(variant=name, ms_adaptive=1000 * ta, ms_fixed_spp_max=1000 * tf,
+                         speedup_vs_fixed_spp_max=tf / ta, f1_adaptive=f1, reference_events=int((ref_map != 0).sum()), n_eq=n_eq,
+                         speedup_equal_quality=(ladder[n_eq][0] / ta) if n_eq else None,
+                         f1_fixed={str(k): v[1] for k, v in ladder.items()}, stop_evidence=se))
+        r.close()
+    return dict(workload=f"sensor and variants, C {C}, spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}",
+                rows=rows)
+
+
 def bench_batch(ev, scenes, args) -> dict:
     """Frame-batch workload (1280x720, 977,290 triangles, camera panning
     0.5 degrees per frame, schedule 16/16/2048, depth 8): K consecutive pairs
@@ -434,7 +489,7 @@ def main() -> int:
                     help="first copy a buffer of this many MiB on the device (counter calibration)")
     ap.add_argument("--stress-pairs", type=int, default=8, help="pairs of the stress workload (--only stress)")
     ap.add_argument("--only", choices=("all", "frame", "diff", "batch", "video", "tiny", "sensitivity", "stress",
-                                       "rgb"),
+                                       "rgb", "variants"),
                     default="all",
                     help="which workloads to run (the headline is the frame workload)")
     ap.add_argument("--batch-pairs", type=int, default=64, help="pairs of the frame-batch workload")
@@ -459,9 +514,11 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.only in ("diff", "batch", "video", "tiny", "sensitivity", "stress", "rgb"):
+    if args.only in ("diff", "batch", "video", "tiny", "sensitivity", "stress", "rgb", "variants"):
         res = {"metric": "next-row workloads", "next_rows": {}}
-        if args.only == "rgb":
+        if args.only == "variants":
+            res["scene_variants"] = bench_scene_variants(ev, scenes, args.C)
+        elif args.only == "rgb":
             res["next_rows"]["rgb_frame"] = bench_rgb(ev, scenes)
         elif args.only == "stress":
             res["next_rows"]["stress"] = bench_stress(ev, scenes, args)

@@ -284,7 +284,8 @@ def heightfield_y(x, z, phi1: float, phi2: float):
 
 
 def sensor(seed: int = 0, width: int = 640, height: int = 480, n_spheres: int = 20,
-           grid: int = 190, subdiv: int = 3) -> Scene:
+           grid: int = 190, subdiv: int = 3, n_moving: Optional[int] = None,
+           sky: Optional[float] = None) -> Scene:
     """640x480: a 190x190-quad displaced floor on [-4, 4]^2 (72,200 triangles,
     h = 0.05 sin(1.7x + phi1) cos(2.3z + phi2)), 20 icospheres (subdivision 3,
     1,280 triangles each) of radius U[0.1, 0.5] resting on the floor at
@@ -292,7 +293,11 @@ def sensor(seed: int = 0, width: int = 640, height: int = 480, n_spheres: int = 
     at y = 4 facing down (Le = 10).  Between t = 0 and t = 1 every sphere
     moves rigidly by a translation U[-0.02, 0.02]^3 and a rotation of U[0, 2]
     degrees about a random axis through its centre.  Static camera at
-    (0, 2.5, 7) looking at (0, 0.3, 0), 40 degree vertical field of view."""
+    (0, 2.5, 7) looking at (0, 0.3, 0), 40 degree vertical field of view.
+    Variants: only the first n_moving spheres move (the others keep their
+    t = 0 placement; the random draws are the same), and a uniform grey sky
+    of radiance `sky` (an environment map) lights the scene besides the
+    three lights."""
     rng = np.random.default_rng(seed)
     phi1, phi2 = rng.uniform(0, 2 * math.pi, size=2)
     b = SceneBuilder()
@@ -311,7 +316,7 @@ def sensor(seed: int = 0, width: int = 640, height: int = 480, n_spheres: int = 
     ft = np.stack([np.stack([v00, v01, v11], 1), np.stack([v00, v11, v10], 1)], 1).reshape(-1, 3)
     b.static(b.mesh(fv, ft, floor_m))
     sv, st = icosphere(subdiv)
-    for _ in range(n_spheres):
+    for k in range(n_spheres):
         m = b.material(rng.uniform(0.1, 0.9))
         mesh = b.mesh(sv, st, m)
         r = rng.uniform(0.1, 0.5)
@@ -321,14 +326,20 @@ def sensor(seed: int = 0, width: int = 640, height: int = 480, n_spheres: int = 
         axis = rng.normal(size=3)
         ang = math.radians(rng.uniform(0.0, 2.0))
         rot = rotation_axis_angle(axis, ang)
-        b.instance(mesh, [0.0, 1.0], [compose(np.eye(3), c, r), compose(rot, c + dt, r)])
+        if n_moving is None or k < n_moving:
+            b.instance(mesh, [0.0, 1.0], [compose(np.eye(3), c, r), compose(rot, c + dt, r)])
+        else:
+            b.instance(mesh, [0.0], [compose(np.eye(3), c, r)])
     light_m = b.material(0.0, 10.0)
     for (lx, lz) in ((-2.0, -1.0), (0.0, 1.0), (2.0, -0.5)):
         lv, lt = oriented_quad([(lx - 0.5, 4.0, lz - 0.5), (lx + 0.5, 4.0, lz - 0.5),
                                 (lx + 0.5, 4.0, lz + 0.5), (lx - 0.5, 4.0, lz + 0.5)], (0, -1, 0))
         b.static(b.mesh(lv, lt, light_m))
     b.set_camera(width, height, 40.0, [0.0], [[0, 2.5, 7.0, 0, 0.3, 0, 0, 1, 0]])
-    return b.build()
+    sc = b.build()
+    if sky is not None:
+        sc.env = np.full((6, 8, 8), sky, np.float32)
+    return sc
 
 
 def diff_scene(seed: int = 0, width: int = 256, height: int = 256, floor_n: int = 50,
