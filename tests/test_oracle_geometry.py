@@ -215,3 +215,20 @@ def test_pinhole_camera_directions():
         o = cam["eye"]
         hit, t, _ = f.closest_hit(0, o, np.float32([0, 0, -1]))
         assert hit and abs(t - 5.0) < 1e-6
+
+
+def test_sensor_scene_variants():
+    """scenes.sensor(n_moving=1, sky=s): the same scene at t = 0, at t = 1
+    only the first sphere has moved (the floor comes first, then the spheres
+    of 1,280 triangles each), and a uniform sky of radiance s."""
+    a = scenes.sensor()
+    b = scenes.sensor(n_moving=1, sky=2.0)
+    assert a.env is None and b.env.shape == (6, 8, 8) and (b.env == 2.0).all()
+    floor, sphere = 190 * 190 * 2, 1280
+    with oracle.Frame(a, 0.0, 1.0) as fa, oracle.Frame(b, 0.0, 1.0) as fb:
+        a0, a1 = fa.world_tris(0)[0], fa.world_tris(1)[0]
+        b0, b1 = fb.world_tris(0)[0], fb.world_tris(1)[0]
+    np.testing.assert_array_equal(a0, b0)
+    np.testing.assert_array_equal(b1[:floor + sphere], a1[:floor + sphere])
+    np.testing.assert_array_equal(b1[floor + sphere:], b0[floor + sphere:])
+    assert not np.array_equal(a1[floor + sphere:floor + 20 * sphere], a0[floor + sphere:floor + 20 * sphere])
