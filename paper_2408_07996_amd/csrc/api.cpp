@@ -548,11 +548,11 @@ int evrt_render_event_video(evrt_ctx *c, uint32_t n_frames, const double *times,
         validate_opts(o);
         if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
         if (n_frames < 2) fail(EVRT_E_INVALID, "n_frames must be at least 2");
+        if ((uint64_t)o.key_base + n_frames > (1u << 24)) fail(EVRT_E_INVALID, "key_base + n_frames above 2^24");
         if (!times) fail(EVRT_E_INVALID, "NULL times");
         for (uint32_t k = 0; k < n_frames; ++k)
             if (!std::isfinite(times[k])) fail(EVRT_E_INVALID, "times must be finite");
         validate_frame_args(o, C, alpha, spp_init, spp_batch, spp_max, out);
-        if ((uint64_t)o.key_base + n_frames > (1u << 24)) fail(EVRT_E_INVALID, "key_base + n_frames above 2^24");
         need_device(c);
         render_video(c, n_frames, times, C, alpha, spp_init, spp_batch, spp_max, o, *out,
                      static_cast<hipStream_t>(stream));
@@ -571,14 +571,15 @@ int evrt_render_event_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, 
         validate_opts(o);
         if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
         if (n_pairs == 0) fail(EVRT_E_INVALID, "n_pairs must be positive");
+        // Counts first: times[] is only read once n_pairs is known to be sane.
+        if (n_pairs + 1ull > kMaxBatchFrames) fail(EVRT_E_UNSUPPORTED, "more than 2047 pairs in one batch");
+        if ((uint64_t)o.key_base + n_pairs > (1u << 24)) fail(EVRT_E_INVALID, "key_base + n_pairs above 2^24");
         if (!times) fail(EVRT_E_INVALID, "NULL times");
-        for (uint32_t k = 0; k <= n_pairs; ++k)
+        for (uint32_t k = 0; k < n_pairs + 1; ++k)
             if (!std::isfinite(times[k])) fail(EVRT_E_INVALID, "times must be finite");
         validate_frame_args(o, C, alpha, spp_init, spp_batch, spp_max, out);
         if (o.ref_mode != EVRT_REF_LOCKSTEP) fail(EVRT_E_UNSUPPORTED, "frame batches sample in lock step only");
         if (o.normality_alpha > 0.0f) fail(EVRT_E_UNSUPPORTED, "frame batches do not run the normality pre-test");
-        if (n_pairs + 1 > kMaxBatchFrames) fail(EVRT_E_UNSUPPORTED, "more than 2047 pairs in one batch");
-        if ((uint64_t)o.key_base + n_pairs > (1u << 24)) fail(EVRT_E_INVALID, "key_base + n_pairs above 2^24");
         const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;
         if (npx > kPixMask + 1ull) fail(EVRT_E_UNSUPPORTED, "more than 2^21 pixels per frame in a batch");
         if ((n_pairs + 1ull) * npx >= (1ull << 31)) fail(EVRT_E_UNSUPPORTED, "more than 2^31 (frame, pixel) items");

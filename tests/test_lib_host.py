@@ -125,6 +125,30 @@ def test_render_argument_validation_before_device_work(host_ctx):
     assert rc == ev.EVRT_E_DEVICE and "host-only" in msg
 
 
+def test_batch_and_video_counts_checked_before_times_are_read(host_ctx):
+    """Absurd pair and frame counts are refused before the times array is
+    read (a two-entry array stands in for a caller's short buffer)."""
+    r = host_ctx
+    r.set_scene(scenes.tiny_box())
+    L = ev.load_library()
+    times = (ctypes.c_double * 2)(0.0, 1.0)
+    o = ev.default_opts()
+    dummy = ctypes.c_void_p(16)
+    fo = ev.FrameOut(dummy, dummy, dummy, dummy, None, None, None)
+    for n in (0xFFFFFFFF, 0xFFFFFFFE, 1 << 20, 2048):
+        rc = L.evrt_render_event_batch(r._h, n, ctypes.cast(times, ctypes.c_void_p), 0.2, 0.01, 16, 16, 256,
+                                       ctypes.byref(o), ctypes.byref(fo), None)
+        assert rc == ev.EVRT_E_UNSUPPORTED and "pairs" in L.evrt_last_error(r._h).decode()
+    for n in (0xFFFFFFFF, (1 << 24) + 1):
+        rc = L.evrt_render_event_video(r._h, n, ctypes.cast(times, ctypes.c_void_p), 0.2, 0.01, 16, 16, 256,
+                                       ctypes.byref(o), ctypes.byref(fo), None)
+        assert rc == ev.EVRT_E_INVALID and "n_frames" in L.evrt_last_error(r._h).decode()
+    # Sane counts go on to the device check of the host-only context.
+    rc = L.evrt_render_event_batch(r._h, 1, ctypes.cast(times, ctypes.c_void_p), 0.2, 0.01, 16, 16, 256,
+                                   ctypes.byref(o), ctypes.byref(fo), None)
+    assert rc == ev.EVRT_E_DEVICE
+
+
 def test_null_context_is_rejected():
     L = ev.load_library()
     assert L.evrt_scene_commit(None) == ev.EVRT_E_INVALID
