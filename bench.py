@@ -319,7 +319,12 @@ def bench_sensitivity(ev, scenes, C: float = 0.15) -> dict:
     return dict(workload=f"sensor, C {C}, spp {P['spp_init']}/{P['spp_batch']}/{P['spp_max']}", rows=rows)
 
 
-def bench_scene_variants(ev, scenes, C: float = 0.15) -> dict:
+SCENE_VARIANTS = (("twenty moving spheres", {}), ("one moving sphere", dict(n_moving=1)), ("sky 1.0", dict(sky=1.0)),
+                  ("one moving sphere, sky 1.0", dict(n_moving=1, sky=1.0)),
+                  ("one moving sphere, sky 3.0", dict(n_moving=1, sky=3.0)))
+
+
+def bench_scene_variants(ev, scenes, C: float = 0.15, names=None) -> dict:
     """Where the equal-quality speed-up comes from: the sensor workload and
     variants of it with one moving sphere instead of twenty and with a
     uniform grey sky as extra light (fewer dark, noisy pixels).  Per
@@ -331,9 +336,9 @@ def bench_scene_variants(ev, scenes, C: float = 0.15) -> dict:
     base = dict(seed=P["seed"], max_depth=P["max_depth"], rr_start_depth=P["rr_start_depth"],
                 log_eps=P["log_eps"], nee=P["nee"], jitter=P["jitter"])
     rows = []
-    for name, kw in (("twenty moving spheres", {}), ("one moving sphere", dict(n_moving=1)),
-                     ("sky 1.0", dict(sky=1.0)), ("one moving sphere, sky 1.0", dict(n_moving=1, sky=1.0)),
-                     ("one moving sphere, sky 3.0", dict(n_moving=1, sky=3.0))):
+    for name, kw in SCENE_VARIANTS:
+        if names is not None and name not in names:
+            continue
         print(f"[bench] scene variant: {name}", file=sys.stderr, flush=True)
         r = ev.Renderer(0)
         r.set_scene(scenes.sensor(**kw))
@@ -803,6 +808,9 @@ def main() -> int:
                             "batching": bench_batch(ev, scenes, args),
                             "sequential_video": bench_video(ev, scenes),
                             "rgb_frame": bench_rgb(ev, scenes)}
+        # Where the equal-quality ceiling comes from (all five variants:
+        # --only variants).
+        res["scene_variants"] = bench_scene_variants(ev, scenes, P["C"], names=("one moving sphere", "sky 1.0"))
     print(json.dumps(res), flush=True)
     return 0
 
