@@ -47,7 +47,7 @@ def _opts_from(params: dict, **kw):
     d = dict(params)
     d.update(kw)
     keys = ("seed", "max_depth", "rr_start_depth", "minibatch", "log_eps", "nee", "jitter", "mode",
-            "df_mode", "ref_mode", "lds_nodes", "ray_batch", "mis", "normality_alpha")
+            "df_mode", "ref_mode", "lds_nodes", "ray_batch", "mis", "normality_alpha", "key_base")
     return {k: d[k] for k in keys if k in d}
 
 
@@ -423,6 +423,23 @@ def test_tiny_frame_parity(rend, torch_cuda, variant):
         r = f.render(oracle.make_params(**{k: v for k, v in params.items() if k not in ("lds_nodes", "ray_batch")}))
     _compare(g, r, np.arange(sc.n_pixels), params["C"])
     assert st["rounds"] >= 1 and st["camera_rays"] > 0
+
+
+def test_same_instant_key_gives_identical_statistics(rend, torch_cuda):
+    """Instant 1 of a frame keyed k and instant 0 of one keyed k + 1 at the
+    same time draw the same random numbers: bitwise equal statistics on the
+    GPU (fixed count), equal to the oracle's."""
+    sc = scenes.tiny_box(width=24, height=20)
+    rend.set_scene(sc)
+    P = dict(scenes.TINY_PARAMS, mode=ev.MODE_FIXED, spp_max=64)
+    ga, _ = _frame(rend, sc, P, 0.5, 0.5, key_base=3)
+    gb, _ = _frame(rend, sc, P, 0.5, 0.5, key_base=4)
+    for k in ("mean", "var", "mean_radiance"):
+        np.testing.assert_array_equal(ga[k][:, 1], gb[k][:, 0])
+    assert (ga["mean"][:, 0] != ga["mean"][:, 1]).mean() > 0.5
+    with oracle.Frame(sc, 0.5, 0.5) as f:
+        r = f.render(oracle.make_params(**P, key_base=3))
+    _compare(ga, r, np.arange(sc.n_pixels), P["C"])
 
 
 def test_tiny_frame_invariants_and_determinism(rend, torch_cuda):
