@@ -134,6 +134,8 @@ def lib():
     L.evo_event_loss.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double,
                                  ctypes.c_double, ctypes.c_uint32, _u32p, ctypes.c_uint32, ctypes.c_int,
                                  _f64p, _f64p, _f64p, _f64p, _f64p]
+    L.evo_delta_vjp.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32, _f64p, _u32p,
+                                ctypes.c_uint32, ctypes.c_int, _f64p, _f64p, _f64p, _f64p]
     L.evo_paths_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint32,
                                   _u32p, _u8p, _u32p, _f32p, ctypes.c_int]
     L.evo_decide.argtypes = [_f64p, ctypes.c_uint32, _f64p, ctypes.c_uint32, ctypes.c_float,
@@ -439,6 +441,29 @@ class Frame:
         if rc != 0:
             raise ValueError("invalid event-loss parameters")
         return dict(loss=float(loss[0]), grad_albedo=ga, grad_emission=ge, loss_px=lpx, delta=dpx)
+
+    def delta_vjp(self, params: Params, spp: int, g, pixels: Optional[np.ndarray] = None,
+                  threads: int = 0) -> Dict[str, np.ndarray]:
+        """sum_p g_p Delta_p over the listed pixels (every pixel when None)
+        and its gradient with respect to every material's albedo and
+        emission (FP64), with Delta the per-pixel log-luminance difference at
+        spp paths per pixel and instant."""
+        nm = len(self.scene.albedo)
+        n = self.scene.width * self.scene.height if pixels is None else len(pixels)
+        px = None if pixels is None else np.ascontiguousarray(pixels, np.uint32)
+        g = np.ascontiguousarray(g, np.float64)
+        assert g.shape == (n,)
+        val = np.zeros(1)
+        ga = np.zeros(nm)
+        ge = np.zeros(nm)
+        dpx = np.zeros(n)
+        rc = lib().evo_delta_vjp(self._frame, ctypes.byref(params), int(spp), _ptr(g, ctypes.c_double),
+                                 None if px is None else _ptr(px, ctypes.c_uint32), n, int(threads),
+                                 _ptr(val, ctypes.c_double), _ptr(ga, ctypes.c_double), _ptr(ge, ctypes.c_double),
+                                 _ptr(dpx, ctypes.c_double))
+        if rc != 0:
+            raise ValueError("invalid parameters")
+        return dict(value=float(val[0]), grad_albedo=ga, grad_emission=ge, delta=dpx)
 
     def paths(self, params: Params, pixel, instant, sample, threads: int = 0) -> np.ndarray:
         """Per-path radiance for arrays of (pixel, instant, sample)."""

@@ -189,6 +189,15 @@ int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau
                    const uint32_t *pixels, uint32_t n_pixels, int n_threads, double *loss,
                    double *grad_albedo, double *grad_emission, double *loss_px, double *delta_px);
 
+/* Vector-Jacobian product through the per-pixel differences Delta above:
+ * for weights g (one per listed pixel, the derivative dL/dDelta of an outer
+ * function L) value = sum_p g_p Delta_p and its gradient with respect to
+ * every material's albedo and emitted radiance, by the same path replay.
+ * Outputs may be NULL. */
+int evo_delta_vjp(const evo_frame *f, const evo_params *p, uint32_t spp, const double *g, const uint32_t *pixels,
+                  uint32_t n_pixels, int n_threads, double *value, double *grad_albedo, double *grad_emission,
+                  double *delta_px);
+
 /* Sequential event video (Algorithm 1 over n_frames frames): pairs[k - 1]
  * is the frame of instants (t_{k-1}, t_k); frame 0 at spp_max is the first
  * reference of every pixel, frame k is sampled adaptively against the

@@ -18,6 +18,11 @@
  *   dmu_i        = (1/m) sum_k (1/(Y_{i,k} + eps)) (1/mb) sum_{s in k} dL_s.
  * Gradients are reported for materials with albedo > 0 (albedo) and with
  * emission > 0 (emission); the sampler never produces the other terms.
+ *
+ * The same replay gives the gradient of any outer function of the
+ * per-pixel differences: with caller weights g_p = dL/dDelta_p the
+ * "loss" is sum_p g_p Delta_p and sigmoid(z)/tau * sign(Delta) above is
+ * replaced by g_p (evo_delta_vjp).
  */
 #include "evo_internal.h"
 
@@ -50,6 +55,7 @@ typedef struct {
     const evo_frame *f;
     const evo_params *p;
     double C, tau;
+    const double *upstream;    /* per listed pixel dL/dDelta, or NULL: the smoothed loss */
     uint32_t spp;
     const uint32_t *pixels;
     uint32_t n_pixels;
@@ -87,12 +93,19 @@ static void *diff_worker(void *arg)
             mu[i] = sum / (double)m;
         }
         const double delta = mu[1] - mu[0];
-        const double z = (fabs(delta) - j->C) / j->tau;
-        loss += softplus(z);
-        if (j->loss_px) j->loss_px[k] = softplus(z);
+        double g;
+        if (j->upstream) {
+            g = j->upstream[k];
+            loss += g * delta;
+            if (j->loss_px) j->loss_px[k] = g * delta;
+        } else {
+            const double z = (fabs(delta) - j->C) / j->tau;
+            loss += softplus(z);
+            if (j->loss_px) j->loss_px[k] = softplus(z);
+            const double sgn = delta > 0.0 ? 1.0 : (delta < 0.0 ? -1.0 : 0.0);
+            g = sigmoid(z) / j->tau * sgn;
+        }
         if (j->delta_px) j->delta_px[k] = delta;
-        const double sgn = delta > 0.0 ? 1.0 : (delta < 0.0 ? -1.0 : 0.0);
-        const double g = sigmoid(z) / j->tau * sgn;
         if (g == 0.0) continue;
         for (int i = 0; i < 2; ++i) {
             for (uint32_t s = 0; s < spp; ++s) {
@@ -123,14 +136,15 @@ static void *diff_worker(void *arg)
     return NULL;
 }
 
-int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau, uint32_t spp,
-                   const uint32_t *pixels, uint32_t n_pixels, int n_threads, double *loss,
-                   double *grad_albedo, double *grad_emission, double *loss_px, double *delta_px)
+static int loss_grad(const evo_frame *f, const evo_params *p, double C, double tau, const double *upstream,
+                     uint32_t spp, const uint32_t *pixels, uint32_t n_pixels, int n_threads, double *loss,
+                     double *grad_albedo, double *grad_emission, double *loss_px, double *delta_px)
 {
     const evo_scene_desc *sd = &f->scene->d;
     const uint32_t mb = p->minibatch;
     if (mb != 1 && mb != 2 && mb != 4 && mb != 8) return -1;
-    if (spp == 0 || spp % mb != 0 || !(tau > 0.0) || p->max_depth > EVO_REC_MAX) return -1;
+    if (spp == 0 || spp % mb != 0 || p->max_depth > EVO_REC_MAX) return -1;
+    if (!upstream && !(tau > 0.0)) return -1;
     if (p->mis) return -1; /* the gradient follows the estimator without MIS */
     if (f->scene->d.albedo_rgb) return -1; /* ... and with grey radiance */
     if (!pixels) n_pixels = sd->width * sd->height;
@@ -142,6 +156,7 @@ int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau
     job.p = p;
     job.C = C;
     job.tau = tau;
+    job.upstream = upstream;
     job.spp = spp;
     job.pixels = pixels;
     job.n_pixels = n_pixels;
@@ -160,4 +175,21 @@ int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau
     if (grad_emission) memcpy(grad_emission, job.ge, sizeof(double) * sd->n_mat);
     free(job.ga);
     return 0;
+}
+
+int evo_event_loss(const evo_frame *f, const evo_params *p, double C, double tau, uint32_t spp,
+                   const uint32_t *pixels, uint32_t n_pixels, int n_threads, double *loss,
+                   double *grad_albedo, double *grad_emission, double *loss_px, double *delta_px)
+{
+    return loss_grad(f, p, C, tau, NULL, spp, pixels, n_pixels, n_threads, loss, grad_albedo, grad_emission,
+                     loss_px, delta_px);
+}
+
+int evo_delta_vjp(const evo_frame *f, const evo_params *p, uint32_t spp, const double *g, const uint32_t *pixels,
+                  uint32_t n_pixels, int n_threads, double *value, double *grad_albedo, double *grad_emission,
+                  double *delta_px)
+{
+    if (!g) return -1;
+    return loss_grad(f, p, 0.0, 1.0, g, spp, pixels, n_pixels, n_threads, value, grad_albedo, grad_emission,
+                     NULL, delta_px);
 }

@@ -152,3 +152,43 @@ def test_gradient_matches_central_differences_on_the_diff_workload():
             vals.append((float(arr[m]), loss_of(dataclasses.replace(sc, albedo=arr))["loss"]))
         fd = (vals[0][1] - vals[1][1]) / (vals[0][0] - vals[1][0])
         assert g["grad_albedo"][m] == pytest.approx(fd, rel=1e-2, abs=1e-3 * scale), (m, g["grad_albedo"][m], fd)
+
+
+def test_delta_vjp_matches_central_differences_and_the_loss_gradient():
+    """The vector-Jacobian product through the per-pixel log-luminance
+    difference: value = sum_p g_p Delta_p for seeded weights g; its albedo
+    gradient against central differences of the value (h = 1e-3, roulette
+    off, one emitter), its Delta equal to the loss's Delta, and with g the
+    loss's own dL/dDelta it reproduces the loss gradient."""
+    sc = scenes.tiny_box(width=16, height=12)
+    P = oracle.make_params(max_depth=3, rr_start_depth=99)
+    spp = 32
+    n = sc.width * sc.height
+    g = np.random.default_rng(5).normal(size=n)
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        v = f.delta_vjp(P, spp, g)
+        lo = f.event_loss(P, 0.2, 0.05, spp)
+    np.testing.assert_array_equal(v["delta"], lo["delta"])
+    assert v["value"] == pytest.approx(float(np.dot(g, v["delta"])), rel=1e-12)
+    scale = np.abs(v["grad_albedo"]).max()
+    assert scale > 0
+    for m in range(len(sc.albedo)):
+        if sc.albedo[m] <= 0:
+            continue
+        vals = []
+        for sgn in (1, -1):
+            arr = np.array(sc.albedo, np.float32)
+            arr[m] = np.float32(arr[m] + sgn * 1e-3)
+            with oracle.Frame(dataclasses.replace(sc, albedo=arr), 0.0, 1.0) as f:
+                vals.append((float(arr[m]), f.delta_vjp(P, spp, g)["value"]))
+        fd = (vals[0][1] - vals[1][1]) / (vals[0][0] - vals[1][0])
+        assert v["grad_albedo"][m] == pytest.approx(fd, rel=1e-2, abs=1e-3 * scale), m
+    # The loss's own weights: sigmoid((|Delta| - C) / tau) / tau * sign(Delta).
+    d = lo["delta"]
+    z = (np.abs(d) - 0.2) / 0.05
+    w = 1.0 / (1.0 + np.exp(-z)) / 0.05 * np.sign(d)
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        v2 = f.delta_vjp(P, spp, w)
+    np.testing.assert_allclose(v2["grad_albedo"], lo["grad_albedo"], rtol=1e-9, atol=1e-12 * scale)
+    np.testing.assert_allclose(v2["grad_emission"], lo["grad_emission"], rtol=1e-9,
+                               atol=1e-12 * np.abs(lo["grad_emission"]).max())
