@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define EVRT_ABI_VERSION 6
+#define EVRT_ABI_VERSION 7
 
 enum {
     EVRT_OK = 0,
@@ -437,6 +437,24 @@ typedef struct {
 
 int evrt_event_loss_grad(evrt_ctx *ctx, double t0, double t1, float C, float tau, uint32_t spp,
                          const evrt_render_opts *opts, const evrt_diff_out *out, void *stream);
+
+/* The per-pixel log-luminance difference Delta of evrt_event_loss_grad
+ * (Eq. 3 and 7: mu_1 - mu_0 at spp paths per pixel and instant) and a
+ * vector-Jacobian product through it, for an outer function L of the
+ * differences whose derivative the caller gives: grad_delta, device
+ * double[width * height], g_p = dL/dDelta_p.  Writes
+ *   out->loss            [1] sum_p g_p Delta_p
+ *   out->grad            [2 * n_mat] its derivative with respect to every
+ *                        albedo, then every emission (same replay, same
+ *                        reporting rule as evrt_event_loss_grad)
+ *   out->loss_px, delta  g_p Delta_p and Delta per pixel, or NULL
+ *   out->replay_mismatch as in evrt_event_loss_grad, or NULL.
+ * grad_delta = NULL computes Delta only (out->delta required; no replay;
+ * nothing else written), the forward half of an autograd step.
+ * Errors as evrt_event_loss_grad (without C and tau); NULL loss or grad with
+ * grad_delta set, or NULL delta without it: EVRT_E_INVALID. */
+int evrt_delta_vjp(evrt_ctx *ctx, double t0, double t1, uint32_t spp, const evrt_render_opts *opts,
+                   const double *grad_delta, const evrt_diff_out *out, void *stream);
 
 /* Host-side build of the scene at time t (world triangles and the 4-wide
  * BVH, no device work) with a structural check of the BVH: every primitive

@@ -21,7 +21,8 @@ from typing import Dict, Optional
 import numpy as np
 
 __all__ = ["Renderer", "EvrtError", "default_opts", "load_library", "MODE_ADAPTIVE_1T", "MODE_FIXED",
-           "MODE_ADAPTIVE_2T", "MODE_MEAN_ONLY", "DF_STUDENT", "DF_WELCH", "REF_LOCKSTEP", "REF_FULL"]
+           "MODE_ADAPTIVE_2T", "MODE_MEAN_ONLY", "DF_STUDENT", "DF_WELCH", "REF_LOCKSTEP", "REF_FULL",
+           "event_loss", "log_luminance_delta"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # EVRT_LIBRARY may point at another build of the same library (tuning runs).
@@ -122,6 +123,8 @@ SIGNATURES = [
     ("evrt_event_loss_grad", ctypes.c_int,
      [_c_p, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float, _u32, ctypes.POINTER(RenderOpts),
       ctypes.POINTER(DiffOut), _c_p]),
+    ("evrt_delta_vjp", ctypes.c_int,
+     [_c_p, ctypes.c_double, ctypes.c_double, _u32, ctypes.POINTER(RenderOpts), _c_p, ctypes.POINTER(DiffOut), _c_p]),
     ("evrt_scene_info_at", ctypes.c_int, [_c_p, ctypes.c_double, ctypes.POINTER(SceneInfo)]),
     ("evrt_t_quantile", ctypes.c_double, [ctypes.c_double, _u32]),
 ]
@@ -470,6 +473,36 @@ class Renderer:
             res.update(loss_px=lpx, delta=dpx)
         return res
 
+    def delta_vjp(self, t0: float, t1: float, spp: int, grad_delta=None, opts=None, stream=None) -> Dict:
+        """The per-pixel log-luminance difference Delta [H*W] at spp paths
+        per pixel and instant and, with grad_delta (dL/dDelta per pixel, any
+        float tensor or array of H*W values), value = sum g Delta and its
+        path-replay gradient: grad_albedo, grad_emission [n_mat],
+        replay_mismatch [1] (float64 device tensors).  Without grad_delta
+        only Delta is computed (no replay)."""
+        import torch
+        o = self._opts(opts)
+        dev = torch.device("cuda", self.device)
+        n_mat = len(self.scene.albedo)
+        npx = self.scene.width * self.scene.height
+        delta = torch.empty(npx, dtype=torch.float64, device=dev)
+        if grad_delta is None:
+            out = DiffOut(None, None, None, _dptr(delta), None)
+            self._check(load_library().evrt_delta_vjp(self._h, float(t0), float(t1), int(spp), ctypes.byref(o), None,
+                                                      ctypes.byref(out), _stream_ptr(stream)))
+            return dict(delta=delta)
+        g = torch.as_tensor(grad_delta).to(device=dev, dtype=torch.float64).reshape(-1).contiguous()
+        if g.numel() != npx:
+            raise ValueError(f"grad_delta needs {npx} values, got {g.numel()}")
+        val = torch.empty(1, dtype=torch.float64, device=dev)
+        grad = torch.empty(2 * n_mat, dtype=torch.float64, device=dev)
+        mism = torch.empty(1, dtype=torch.int32, device=dev)
+        out = DiffOut(_dptr(val), _dptr(grad), None, _dptr(delta), _dptr(mism))
+        self._check(load_library().evrt_delta_vjp(self._h, float(t0), float(t1), int(spp), ctypes.byref(o),
+                                                  _dptr(g), ctypes.byref(out), _stream_ptr(stream)))
+        return dict(value=val, delta=delta, grad_albedo=grad[:n_mat], grad_emission=grad[n_mat:],
+                    replay_mismatch=mism)
+
     def decide_stats(self, x0, x1, C: float, alpha: float, mode: int = MODE_ADAPTIVE_1T,
                      df_mode: int = DF_STUDENT, want_p: bool = False, stream=None):
         """Decision kernels on caller log-luminance samples [n, m] (float64).
@@ -521,6 +554,49 @@ def _event_loss_function():
 
     _EVENT_LOSS_FN = EventLoss
     return EventLoss
+
+
+_DELTA_FN = None
+
+
+def _delta_function():
+    global _DELTA_FN
+    if _DELTA_FN is not None:
+        return _DELTA_FN
+    import torch
+
+    class LogLuminanceDelta(torch.autograd.Function):
+        """Delta(albedo, emission) per pixel of Renderer.delta_vjp; the
+        backward pass is the path-replay vector-Jacobian product with the
+        incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, albedo, emission, renderer, t0, t1, spp, opts):
+            ctx.mats = (albedo.detach().cpu().numpy(), emission.detach().cpu().numpy())
+            renderer.set_materials(*ctx.mats)
+            ctx.renderer, ctx.args = renderer, (t0, t1, spp, opts)
+            ctx.dev = (albedo.device, albedo.dtype, emission.device, emission.dtype)
+            d = renderer.delta_vjp(t0, t1, spp, None, opts)["delta"]
+            return d.to(device=albedo.device, dtype=albedo.dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            t0, t1, spp, opts = ctx.args
+            ctx.renderer.set_materials(*ctx.mats)  # the forward's materials
+            r = ctx.renderer.delta_vjp(t0, t1, spp, g.detach(), opts)
+            ad, at, ed, et = ctx.dev
+            return (r["grad_albedo"].to(ad, at), r["grad_emission"].to(ed, et), None, None, None, None, None)
+
+    _DELTA_FN = LogLuminanceDelta
+    return LogLuminanceDelta
+
+
+def log_luminance_delta(renderer: "Renderer", albedo, emission, t0: float, t1: float, spp: int, opts=None):
+    """Differentiable per-pixel difference of mean log-luminance between t1
+    and t0 (a flat tensor of H*W values) with the given per-material albedo
+    and emission tensors; gradients of any function of it flow to both by
+    path replay (the backward pass sets the forward's materials again)."""
+    return _delta_function().apply(albedo, emission, renderer, t0, t1, spp, opts)
 
 
 def event_loss(renderer: "Renderer", albedo, emission, t0: float, t1: float, C: float, tau: float,

@@ -674,6 +674,39 @@ int evrt_event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, 
     });
 }
 
+int evrt_delta_vjp(evrt_ctx *c, double t0, double t1, uint32_t spp, const evrt_render_opts *opts,
+                   const double *grad_delta, const evrt_diff_out *out, void *stream)
+{
+    return guarded(c, [&] {
+        need_ctx(c);
+        evrt_render_opts o;
+        if (opts) o = *opts;
+        else evrt_default_opts(&o);
+        validate_opts(o);
+        if (!c->committed) fail(EVRT_E_STATE, "scene not committed");
+        if (!std::isfinite(t0) || !std::isfinite(t1)) fail(EVRT_E_INVALID, "t0 and t1 must be finite");
+        if (spp == 0 || spp % o.minibatch != 0) fail(EVRT_E_INVALID, "spp must be a positive multiple of minibatch");
+        if (!out) fail(EVRT_E_INVALID, "NULL output");
+        if (grad_delta && (!out->loss || !out->grad)) fail(EVRT_E_INVALID, "NULL value or gradient output");
+        if (!grad_delta && !out->delta) fail(EVRT_E_INVALID, "NULL delta output (grad_delta NULL computes Delta only)");
+        if (o.mis) fail(EVRT_E_UNSUPPORTED, "the gradient follows the estimator without MIS");
+        if (c->scene.rgb) fail(EVRT_E_UNSUPPORTED, "the gradient follows grey radiance");
+        if (c->scene.albedo.size() > 2048) fail(EVRT_E_UNSUPPORTED, "more than 2048 materials");
+        const uint64_t npx = (uint64_t)c->scene.cam.width * c->scene.cam.height;
+        if (2ull * npx * spp >= (1ull << 31)) fail(EVRT_E_UNSUPPORTED, "more than 2^31 paths");
+        need_device(c);
+        evrt_diff_out d = *out;
+        if (!grad_delta) {
+            d.loss = nullptr;
+            d.grad = nullptr;
+            d.loss_px = nullptr;
+            d.replay_mismatch = nullptr;
+        }
+        event_loss_grad(c, t0, t1, 0.0f, 1.0f, spp, o, d, static_cast<hipStream_t>(stream), grad_delta,
+                        grad_delta == nullptr);
+    });
+}
+
 int evrt_decide_stats(evrt_ctx *c, const double *x0, const double *x1, uint32_t n_pixels, uint32_t m, float C,
                       float alpha, uint8_t mode, uint8_t df_mode, double *t_out, uint8_t *stop_out,
                       int8_t *polarity_out, double *p_out, void *stream)

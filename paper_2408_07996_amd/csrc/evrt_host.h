@@ -221,7 +221,11 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
 void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, float alpha, uint32_t spp_init,
                   uint32_t spp_batch, uint32_t spp_max, const evrt_render_opts &o, const evrt_frame_out &out,
                   hipStream_t s);
+// upstream: the caller's dL/dDelta per pixel for a product through Delta
+// (null: the smoothed event loss with C and tau); delta_only: Delta (and the
+// forward statistics) without the replay.
 void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint32_t spp,
-                     const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s);
+                     const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s,
+                     const double *upstream = nullptr, bool delta_only = false);
 void validate_opts(const evrt_render_opts &o);
 }  // namespace evrt

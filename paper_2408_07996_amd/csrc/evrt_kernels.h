@@ -119,8 +119,11 @@ void launch_hook_decide(hipStream_t s, const double *x0, const double *x1, uint3
 // Event loss and its gradient: zeroing, per-pixel statistics and weights,
 // path-replay adjoint (g = [albedo gradients | emission gradients]).
 void launch_diff_zero(hipStream_t s, double *loss, double *g, uint32_t n_g, uint32_t *mismatch);
+// Per pixel: Delta, the loss term and the weight of every mini-batch;
+// upstream (null: the smoothed event loss) holds the caller's dL/dDelta.
 void launch_diff_stats(hipStream_t s, uint32_t npx, uint32_t spp, uint32_t mb, double log_eps, double C,
-                       double tau, const float *L, double *W, double *loss, double *loss_px, double *delta_px);
+                       double tau, const double *upstream, const float *L, double *W, double *loss,
+                       double *loss_px, double *delta_px);
 void launch_diff_compare(hipStream_t s, uint64_t n, const float *a, const float *b, uint32_t *mismatch);
 
 // Sequential video: current-frame slots cleared / references replaced at

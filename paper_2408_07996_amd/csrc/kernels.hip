@@ -2090,7 +2090,7 @@ __global__ void k_diff_zero(double *loss, double *g, uint32_t n_g, uint32_t *mis
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_g) g[i] = 0.0;
     if (i == 0) {
-        *loss = 0.0;
+        if (loss) *loss = 0.0;
         if (mismatch) *mismatch = 0;
     }
 }
@@ -2101,8 +2101,8 @@ __global__ void k_diff_zero(double *loss, double *g, uint32_t n_g, uint32_t *mis
 // and the weight of every mini-batch in the gradient,
 // W = +-sigmoid(z) sign(Delta) / tau / m / mb / (Y_k + eps) (+ at t1).
 __global__ __launch_bounds__(256) void k_diff_stats(uint32_t npx, uint32_t spp, uint32_t mb, double log_eps,
-                                                    double C, double tau, const float *L, double *W,
-                                                    double *loss, double *loss_px, double *delta_px)
+                                                    double C, double tau, const double *upstream, const float *L,
+                                                    double *W, double *loss, double *loss_px, double *delta_px)
 {
     __shared__ double s_sum[256];
     const uint32_t px = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2117,12 +2117,20 @@ __global__ __launch_bounds__(256) void k_diff_stats(uint32_t npx, uint32_t spp, 
             mu[i] = sum / (double)m;
         }
         const double delta = mu[1] - mu[0];
-        const double z = (fabs(delta) - C) / tau;
-        lp = softplus_d(z);
+        // dL/dDelta: the smoothed loss's, or the caller's for a product
+        // through Delta (then L = sum g Delta).
+        double g;
+        if (upstream) {
+            g = upstream[px];
+            lp = g * delta;
+        } else {
+            const double z = (fabs(delta) - C) / tau;
+            lp = softplus_d(z);
+            const double sgn = delta > 0.0 ? 1.0 : (delta < 0.0 ? -1.0 : 0.0);
+            g = sigmoid_d(z) / tau * sgn;
+        }
         if (loss_px) loss_px[px] = lp;
         if (delta_px) delta_px[px] = delta;
-        const double sgn = delta > 0.0 ? 1.0 : (delta < 0.0 ? -1.0 : 0.0);
-        const double g = sigmoid_d(z) / tau * sgn;
         for (uint32_t i = 0; i < 2; ++i) {
             const float *src = L + ((size_t)px * 2 + i) * spp;
             double *dst = W + ((size_t)px * 2 + i) * m;
@@ -2136,7 +2144,7 @@ __global__ __launch_bounds__(256) void k_diff_stats(uint32_t npx, uint32_t spp, 
         if (threadIdx.x < h) s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && s_sum[0] != 0.0) atomicAdd(loss, s_sum[0]);
+    if (threadIdx.x == 0 && loss && s_sum[0] != 0.0) atomicAdd(loss, s_sum[0]);
 }
 
 // Replay check: count of path radiances of the replay that differ (bitwise)
@@ -2363,10 +2371,11 @@ void launch_diff_zero(hipStream_t s, double *loss, double *g, uint32_t n_g, uint
 }
 
 void launch_diff_stats(hipStream_t s, uint32_t npx, uint32_t spp, uint32_t mb, double log_eps, double C,
-                       double tau, const float *L, double *W, double *loss, double *loss_px, double *delta_px)
+                       double tau, const double *upstream, const float *L, double *W, double *loss,
+                       double *loss_px, double *delta_px)
 {
-    hipLaunchKernelGGL(k_diff_stats, dim3((npx + 255) / 256), dim3(256), 0, s, npx, spp, mb, log_eps, C, tau, L,
-                       W, loss, loss_px, delta_px);
+    hipLaunchKernelGGL(k_diff_stats, dim3((npx + 255) / 256), dim3(256), 0, s, npx, spp, mb, log_eps, C, tau,
+                       upstream, L, W, loss, loss_px, delta_px);
 }
 
 void launch_diff_compare(hipStream_t s, uint64_t n, const float *a, const float *b, uint32_t *mismatch)

@@ -1112,7 +1112,8 @@ void render_paths(evrt_ctx *c, double t0, double t1, uint32_t n_pixels, const ui
 // forward path radiances of every pixel (the wavefront renderer), per-pixel
 // statistics and mini-batch weights, then the path-replay adjoint.
 void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint32_t spp,
-                     const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s)
+                     const evrt_render_opts &o, const evrt_diff_out &out, hipStream_t s, const double *upstream,
+                     bool delta_only)
 {
     std::memset(&c->stats, 0, sizeof(c->stats));
     auto [ga, gb] = get_pair(c, t0, t1, s, &c->stats.ms_build);
@@ -1128,7 +1129,7 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
     }
     fb.diff_L.ensure(sizeof(float) * 2 * (size_t)npx * spp);
     fb.diff_W.ensure(sizeof(double) * 2 * (size_t)npx * m);
-    launch_diff_zero(s, out.loss, out.grad, 2 * n_mat, out.replay_mismatch);
+    launch_diff_zero(s, out.loss, out.grad, out.grad ? 2 * n_mat : 0u, out.replay_mismatch);
     const DevScene sc = make_dev_scene(c, *ga, *gb, o.lds_nodes);
     const RenderParams rp = make_params(c, o);
     // Ray log: the forward pass keeps every ray's closest hit (8 bytes per
@@ -1143,7 +1144,7 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
     hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     const uint64_t room =
         std::min<uint64_t>(kMaxRayLog, fb.diff_hitlog.bytes + fb.diff_vislog.bytes + free_b / 2);
-    const bool use_log = !o.replay_retrace && log_n * (8 + (vis_ok ? 4 : 0)) <= room;
+    const bool use_log = !delta_only && !o.replay_retrace && log_n * (8 + (vis_ok ? 4 : 0)) <= room;
     RayLog log{};
     if (use_log) {
         fb.diff_hitlog.ensure(sizeof(float2) * log_n);
@@ -1155,8 +1156,13 @@ void event_loss_grad(evrt_ctx *c, double t0, double t1, float C, float tau, uint
     }
     trace_paths(c, sc, rp, o, npx, fb.diff_px.as<uint32_t>(), spp, fb.diff_L.as<float>(), nullptr, s,
                 use_log ? &log : nullptr);
-    launch_diff_stats(s, npx, spp, mb, (double)o.log_eps, (double)C, (double)tau, fb.diff_L.as<float>(),
+    launch_diff_stats(s, npx, spp, mb, (double)o.log_eps, (double)C, (double)tau, upstream, fb.diff_L.as<float>(),
                       fb.diff_W.as<double>(), out.loss, out.loss_px, out.delta);
+    if (delta_only) {
+        read_stats(c, s);
+        hip_check(hipGetLastError(), "delta launch");
+        return;
+    }
     // Adjoint: the same pieces again with the gradient terms of every vertex,
     // then every replayed path radiance against the forward one.
     fb.diff_R.ensure(sizeof(float) * 2 * (size_t)npx * spp);

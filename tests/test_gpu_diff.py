@@ -132,6 +132,68 @@ def test_autograd_matches_central_differences():
         assert ga[m] == pytest.approx(fd, rel=1e-2, abs=1e-3 * scale), m
 
 
+@pytest.mark.parametrize("variant", ["default", "retrace"])
+def test_delta_vjp_matches_oracle(variant):
+    """The product through the per-pixel log-luminance difference with
+    seeded weights g: Delta, sum g Delta and its gradient against the
+    oracle's; Delta alone (no replay) equal to it."""
+    import torch
+    sc = scenes.diff_scene(width=32, height=24)
+    P = dict(scenes.DIFF_PARAMS, spp=32)
+    if variant == "retrace":
+        P["replay_retrace"] = 1
+    rend = ev.Renderer(0)
+    rend.set_scene(sc)
+    g = np.random.default_rng(9).normal(size=sc.width * sc.height)
+    _say(f"gpu delta vjp {variant}")
+    r = rend.delta_vjp(0.0, 1.0, P["spp"], torch.tensor(g), _opts(P))
+    d_only = rend.delta_vjp(0.0, 1.0, P["spp"], None, _opts(P))["delta"].cpu().numpy()
+    with oracle.Frame(sc, 0.0, 1.0) as f:
+        o = f.delta_vjp(_oracle_params(P), P["spp"], g)
+    assert int(r["replay_mismatch"].cpu()[0]) == 0
+    np.testing.assert_allclose(r["delta"].cpu().numpy(), o["delta"], rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(d_only, r["delta"].cpu().numpy())
+    assert float(r["value"].cpu()[0]) == pytest.approx(o["value"], rel=1e-10, abs=1e-12)
+    for k in ("grad_albedo", "grad_emission"):
+        a, b = r[k].cpu().numpy(), o[k]
+        scale = max(np.abs(b).max(), 1e-300)
+        assert scale > 1e-300
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * scale, err_msg=k)
+
+
+def test_log_luminance_delta_autograd():
+    """log_luminance_delta through torch.autograd: the gradient of a
+    quadratic function of Delta equals the library's product with its
+    derivative 2 Delta, and the first entries against central differences
+    of the function (roulette off)."""
+    import torch
+    sc = scenes.tiny_box(width=16, height=12)
+    P = dict(scenes.DIFF_PARAMS, spp=32, max_depth=3, rr_start_depth=99)
+    rend = ev.Renderer(0)
+    rend.set_scene(sc)
+    a = torch.tensor(np.asarray(sc.albedo), dtype=torch.float64, requires_grad=True)
+    e = torch.tensor(np.asarray(sc.emission), dtype=torch.float64, requires_grad=True)
+    d = ev.log_luminance_delta(rend, a, e, 0.0, 1.0, P["spp"], _opts(P))
+    (d * d).sum().backward()
+    r = rend.delta_vjp(0.0, 1.0, P["spp"], 2.0 * d.detach(), _opts(P))
+    np.testing.assert_allclose(a.grad.numpy(), r["grad_albedo"].cpu().numpy(), rtol=1e-12)
+    np.testing.assert_allclose(e.grad.numpy(), r["grad_emission"].cpu().numpy(), rtol=1e-12)
+    ga = a.grad.numpy()
+    scale = np.abs(ga).max()
+    assert scale > 0
+    base_a = np.asarray(sc.albedo, np.float32)
+    for m in np.nonzero(base_a > 0)[0][:3]:
+        vals = []
+        for sgn in (1, -1):
+            aa = base_a.copy()
+            aa[m] = np.float32(aa[m] + sgn * 1e-3)
+            dd = ev.log_luminance_delta(rend, torch.tensor(aa, dtype=torch.float64),
+                                        torch.tensor(np.asarray(sc.emission)), 0.0, 1.0, P["spp"], _opts(P))
+            vals.append((float(aa[m]), float((dd * dd).sum())))
+        fd = (vals[0][1] - vals[1][1]) / (vals[0][0] - vals[1][0])
+        assert ga[m] == pytest.approx(fd, rel=1e-2, abs=1e-3 * scale), m
+
+
 @pytest.mark.slow
 def test_event_loss_gradient_full_workload():
     # 256x256, 9,648 triangles, 32 albedos, 4 emitters, 256 paths per pixel

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
     bound = {s[0] for s in ev.SIGNATURES}
     assert set(names) == bound
-    assert L.evrt_abi_version() == 6
+    assert L.evrt_abi_version() == 7
 
 
 def test_default_opts():
