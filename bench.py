@@ -433,7 +433,11 @@ def bench_batch(ev, scenes, args) -> dict:
                         f"depth {P['max_depth']}, C {P['C']}",
                pairs=K, batch_s=tb, pair_loop_s=tp, speedup=tp / tb, identical_to_pair_loop=same,
                batch_pairs_per_s=K / tb, batch_rays_per_s=rays_b / tb, pair_loop_rays_per_s=rays_p / tp,
-               sample_share_bound=2.0 * K / (K + 1), mean_paths_per_pixel=float(npth.mean()),
+               sample_share_bound=2.0 * K / (K + 1),
+               # The work the sharing saves: a shared frame is traced to the
+               # larger of its two pairs' counts, so fewer rays than 2K/(K+1).
+               loop_over_batch_rays=rays_p / max(1.0, float(rays_b)),
+               mean_paths_per_pixel=float(npth.mean()),
                events_per_pair=float((b["polarity"].cpu().numpy() != 0).sum(axis=1).mean()), autotune=tuned)
     r.close()
     return out
