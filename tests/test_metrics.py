@@ -49,35 +49,35 @@ def test_autotune_calibration_spp():
     assert calibration_spp(8, 8, minibatch=8) % 8 == 0
 
 
-def test_autotune_prefers_more_work_in_flight_on_ties():
+def test_autotune_prefers_more_work_in_flight_on_ties(monkeypatch):
     """Shapes within 2 % of the fastest count as tied; the tie goes to the
-    larger batch, then the more blocks per CU."""
+    larger batch, then the more blocks per CU.  The fake renderer advances a
+    virtual clock that the tuner reads, so the test does not depend on how
+    precisely the host sleeps."""
+    import types
+    import sys
+
     import paper_2408_07996_amd.autotune as at
+
+    clock = [0.0]
 
     class FakeRenderer:
         scene = None
 
-        def __init__(self, times):
-            self.times, self.calls, self.cur = times, 0, None
-
         def render_event_frame(self, t0, t1, C, a, s0, s1, s2, o, extras=False):
-            import time as _t
-            key = (o.get("ray_batch"), o.get("trace_blocks_per_cu"))
-            if key in self.times:
-                _t.sleep(self.times[key])
+            clock[0] += times.get((o.get("ray_batch"), o.get("trace_blocks_per_cu")), 0.0)
 
     times = {(1 << 24, 4): 0.140, (1 << 25, 4): 0.120, (1 << 26, 4): 0.100, (1 << 26, 8): 0.1005,
              (1 << 24, 8): 0.150, (1 << 25, 8): 0.130}
-    import types, sys
+    monkeypatch.setattr(at.time, "perf_counter", lambda: clock[0])
     fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None))
-    saved = sys.modules.get("torch")
-    sys.modules["torch"] = fake_torch
-    try:
-        r = at.autotune(FakeRenderer(times), 0.0, 1.0, {}, spp=32, ray_batch=(1 << 24, 1 << 25, 1 << 26),
-                        blocks_per_cu=(4, 8), repeats=2)
-    finally:
-        if saved is not None:
-            sys.modules["torch"] = saved
-        else:
-            del sys.modules["torch"]
+    monkeypatch.setitem(sys.modules, "torch", fake_torch)
+    r = at.autotune(FakeRenderer(), 0.0, 1.0, {}, spp=32, ray_batch=(1 << 24, 1 << 25, 1 << 26),
+                    blocks_per_cu=(4, 8), repeats=2)
     assert (r["opts"]["ray_batch"], r["opts"]["trace_blocks_per_cu"]) == (1 << 26, 8)
+    assert [round(t, 4) for _, _, t in r["table"]] == [0.14, 0.15, 0.12, 0.13, 0.1, 0.1005]
+    # Outside the tie band the fastest shape wins.
+    times[(1 << 26, 8)] = 0.103
+    r = at.autotune(FakeRenderer(), 0.0, 1.0, {}, spp=32, ray_batch=(1 << 24, 1 << 25, 1 << 26),
+                    blocks_per_cu=(4, 8), repeats=2)
+    assert (r["opts"]["ray_batch"], r["opts"]["trace_blocks_per_cu"]) == (1 << 26, 4)
