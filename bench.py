@@ -138,11 +138,28 @@ def bench_diff(ev, scenes, steps: int = 3) -> dict:
         g = r.event_loss_grad(0.0, 1.0, P["C"], P["tau"], P["spp"], o)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / steps
+    # The product through the per-pixel difference (seeded weights), and
+    # the difference alone (the forward half of autograd).
+    w = torch.tensor(np.random.default_rng(0).normal(size=sc.width * sc.height), dtype=torch.float64)
+    v = r.delta_vjp(0.0, 1.0, P["spp"], w, o)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        v = r.delta_vjp(0.0, 1.0, P["spp"], w, o)
+    torch.cuda.synchronize()
+    dv = (time.perf_counter() - t) / steps
+    t = time.perf_counter()
+    for _ in range(steps):
+        r.delta_vjp(0.0, 1.0, P["spp"], None, o)
+    torch.cuda.synchronize()
+    dd = (time.perf_counter() - t) / steps
     paths = 2 * 2 * sc.width * sc.height * P["spp"]
     out = dict(workload=f"{sc.width}x{sc.height}, {sc.n_tri_world} triangles, {len(sc.albedo)} materials, "
                         f"{P['spp']} paths per pixel and instant, depth {P['max_depth']}",
                grad_evals_per_s=1.0 / dt, ms_per_grad=1000.0 * dt, path_evals_per_s=paths / dt,
-               loss=float(g["loss"].cpu()[0]), replay_mismatch=int(g["replay_mismatch"].cpu()[0]))
+               loss=float(g["loss"].cpu()[0]), replay_mismatch=int(g["replay_mismatch"].cpu()[0]),
+               ms_per_delta_vjp=1000.0 * dv, ms_per_delta_forward=1000.0 * dd,
+               delta_vjp_replay_mismatch=int(v["replay_mismatch"].cpu()[0]))
     r.close()
     return out
 
