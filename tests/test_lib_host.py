@@ -275,6 +275,34 @@ def test_gradient_refuses_rgb(host_ctx):
     assert "grey" in L.evrt_last_error(r._h).decode()
 
 
+def test_delta_vjp_argument_validation(host_ctx):
+    """evrt_delta_vjp: a product needs the value and gradient outputs, Delta
+    alone needs the delta output; bad counts and MIS or RGB scenes are
+    refused before any device work; valid calls reach the device check."""
+    r = host_ctx
+    r.set_scene(scenes.tiny_box())
+    L = ev.load_library()
+    o = ev.default_opts()
+    dummy = ctypes.c_void_p(16)
+
+    def rc(grad, out, spp=16, opts=o):
+        code = L.evrt_delta_vjp(r._h, 0.0, 1.0, spp, ctypes.byref(opts), grad, ctypes.byref(out), None)
+        return code, L.evrt_last_error(r._h).decode()
+
+    assert rc(dummy, ev.DiffOut(None, dummy, None, dummy, None))[0] == ev.EVRT_E_INVALID
+    assert rc(dummy, ev.DiffOut(dummy, None, None, dummy, None))[0] == ev.EVRT_E_INVALID
+    code, msg = rc(None, ev.DiffOut(dummy, dummy, None, None, None))
+    assert code == ev.EVRT_E_INVALID and "delta" in msg
+    assert rc(dummy, ev.DiffOut(dummy, dummy, None, None, None), spp=6)[0] == ev.EVRT_E_INVALID
+    assert rc(dummy, ev.DiffOut(dummy, dummy, None, None, None), opts=ev.default_opts(mis=1))[0] == \
+        ev.EVRT_E_UNSUPPORTED
+    assert rc(dummy, ev.DiffOut(dummy, dummy, None, None, None))[0] == ev.EVRT_E_DEVICE
+    assert rc(None, ev.DiffOut(None, None, None, dummy, None))[0] == ev.EVRT_E_DEVICE
+    r.set_scene(scenes.colorize(scenes.tiny_box(), seed=1))
+    code, msg = rc(dummy, ev.DiffOut(dummy, dummy, None, None, None))
+    assert code == ev.EVRT_E_UNSUPPORTED and "grey" in msg
+
+
 def _flat_grid(n=40, y=0.0, scale=1.0):
     """n x n quads in the plane y (every box flat in y)."""
     b = scenes.SceneBuilder()
