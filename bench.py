@@ -51,9 +51,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
 # traversal kernels.  They hold for the kernel sources they were taken with
 # and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "10d2e5f36d2a42c3cada9ec2d6393e54724afe0c47b8aa2eff2b09fa2a45813c",
-           "bytes_per_launch": 526583335.0,
-           "counters": {"k_trace_closest": {"valu_busy": 0.868, "valu_lane_utilization": 0.601}, "k_trace_shadow": {"valu_busy": 0.714, "valu_lane_utilization": 0.600}, "k_shade": {"valu_busy": 0.487, "valu_lane_utilization": 0.640}}}
+TRAFFIC = {"sources_sha256": "2883268fd1cd1af154f771e8d830f1e92f3e6f9749a0fc11b00e98994910fa82",
+           "bytes_per_launch": 526874623.6,
+           "counters": {"k_trace_closest": {"valu_busy": 0.874, "valu_lane_utilization": 0.601}, "k_trace_shadow": {"valu_busy": 0.709, "valu_lane_utilization": 0.600}, "k_shade": {"valu_busy": 0.487, "valu_lane_utilization": 0.640}}}
 
 
 def kernel_sources_digest() -> str:

@@ -299,7 +299,11 @@ int evrt_render_event_video(evrt_ctx *ctx, uint32_t n_frames, const double *time
  * the host) and kept on the device, and each round traces each frame's
  * items with its own geometry; lock-step sampling only (ref_mode LOCKSTEP);
  * at most 2047 pairs and 2^21 pixels.  Outputs as for one frame, pair-major:
- * entry k * width * height + pixel (x2 arrays: two per entry). */
+ * entry k * width * height + pixel (x2 arrays: two per entry).  With the
+ * environment variable EVRT_LOG_ROUNDS set to anything but "0" when the
+ * library first reads it, each round prints one progress line to stderr
+ * (items traced, sample range, undecided entries, seconds since the call
+ * began). */
 int evrt_render_event_batch(evrt_ctx *ctx, uint32_t n_pairs, const double *times, float C, float alpha,
                             uint32_t spp_init, uint32_t spp_batch, uint32_t spp_max,
                             const evrt_render_opts *opts, const evrt_frame_out *out, void *stream);

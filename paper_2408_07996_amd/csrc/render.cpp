@@ -10,6 +10,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <future>
 #include <map>
@@ -793,6 +795,18 @@ void render_video(evrt_ctx *c, uint32_t n_frames, const double *times, float C, 
     c->stats.ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
 }
 
+// With EVRT_LOG_ROUNDS set to anything but "0" in the environment, a batch
+// prints one line per round to stderr, so that a call of many minutes shows
+// how far it has got.  Read once per process.
+static bool log_rounds()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("EVRT_LOG_ROUNDS");
+        return v != nullptr && *v != '\0' && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
 // A batch of consecutive pairs (times[k], times[k+1]), k < n_pairs, of a
 // scene whose geometry is the same at every time (the camera may move).
 // Frame f is keyed as key_base + f, so pair k equals render_frame of
@@ -1013,6 +1027,13 @@ void render_batch(evrt_ctx *c, uint32_t n_pairs, const double *times, float C, f
         const uint32_t next = c->h_pinned[0];
         if (r < 64) c->stats.active_after_round[r] = next;
         c->stats.rounds = r + 1;
+        if (log_rounds()) {
+            std::fprintf(stderr, "evrt: batch round %u: %u items over samples [%u, %u) in %u checkpoints, "
+                         "%u of %u (pair, pixel) entries still undecided, %.1f s\n", r, n_items, n_prev, hi,
+                         dc.n_checks, next, nA,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count());
+            std::fflush(stderr);
+        }
         std::swap(act_in, act_out);
         nA = next;
         if (nA == 0 || dc.final_round) break;
