@@ -49,16 +49,19 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # and the VALU busy fraction (SQ_ACTIVE_INST_VALU x 4 cycles over 1024 SIMDs
 # and the dispatches' GRBM_GUI_ACTIVE, which sums the 8 XCDs) and VALU lane
 # utilization (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) of the
-# traversal kernels.  They hold for the kernel sources they were taken with
-# and are reported as null for any others.
-TRAFFIC = {"sources_sha256": "2883268fd1cd1af154f771e8d830f1e92f3e6f9749a0fc11b00e98994910fa82",
-           "bytes_per_launch": 526874623.6,
-           "counters": {"k_trace_closest": {"valu_busy": 0.874, "valu_lane_utilization": 0.601}, "k_trace_shadow": {"valu_busy": 0.709, "valu_lane_utilization": 0.600}, "k_shade": {"valu_busy": 0.487, "valu_lane_utilization": 0.640}}}
+# traversal kernels.  They hold for the kernel sources and build flags they
+# were taken with and are reported as null for any others.
+TRAFFIC = {"sources_sha256": "05cdcfa7b1ef8436525e1bb15435d32d097feb3725fd1b84c2c38949a92ff974",
+           "bytes_per_launch": 526307510.5,
+           "counters": {"k_trace_closest": {"valu_busy": 0.874, "valu_lane_utilization": 0.601}, "k_trace_shadow": {"valu_busy": 0.713, "valu_lane_utilization": 0.602}, "k_shade": {"valu_busy": 0.504, "valu_lane_utilization": 0.634}}}
 
 
 def kernel_sources_digest() -> str:
+    """Digest of the kernel sources and of the build script (its compiler
+    flags change the kernels too)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2408_07996_amd", "csrc", "*"))):
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2408_07996_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "paper_2408_07996_amd", "build.py")]:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())

@@ -2,7 +2,8 @@
 
 Every HIP translation unit is compiled for gfx950 only, without FMA
 contraction (the renderer's FP32 path arithmetic follows a written
-operation order) and without packed-FP32 instruction selection.
+operation order), without packed-FP32 instruction selection, and with the
+device's ILP-first instruction scheduler.
 """
 from __future__ import annotations
 
@@ -22,6 +23,10 @@ COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # The device scheduler that favours instruction-level parallelism over
+    # occupancy: the trace kernels hold 8 waves per SIMD either way (64
+    # VGPRs), and their loads are then issued further ahead of their uses.
+    "-Xarch_device", "-mllvm=-misched=gcn-max-ilp",
     "-Wall", "-Wno-unused-function",
 ]
 
